@@ -1,0 +1,256 @@
+/*
+ * kn.h -- C ABI of libkn: exact evaluation of the Jones polynomial V_K(t(q))
+ * by contracting the tensor network of the q-state Potts model with
+ * anisotropic complex interactions (PACI) on the signed Tait graph of a knot
+ * diagram (Meichanetzidis & Kourtis, arXiv:1807.02119).
+ *
+ * Pipeline and where each call sits in the paper:
+ *   kn_build_tait      diagram -> bicoloured regions -> signed Tait graph G,
+ *                      writhe w, Tait number tau                    (Sec. II)
+ *   kn_plan_create     Reidemeister-I/II simplification (Sec. III.A), the
+ *                      tensor network G_T with the q x q interaction matrices
+ *                      absorbed into the vertex COPY tensors (Sec. III, Eq. 5),
+ *                      and a greedy pairwise contraction order (Sec. III)
+ *   kn_contract        full contraction of G_T on the GPU -> Z(q)
+ *                      (Eqs. 2-3, Eq. 6)
+ *   kn_contract_backward  d log Z / d J_e for every edge coupling
+ *   kn_jones           V = A(q) Z (Eq. 4)
+ *   kn_batch_*         many knots (and q values) in one persistent launch
+ *
+ * Conventions shared by every call:
+ *   - Status codes: every call returns kn_status; nothing aborts or throws.
+ *     Validation failures return KN_E_INVALID and leave *out == NULL.
+ *   - Input arrays are borrowed for the duration of the call only.
+ *   - Handles (kn_tait, kn_plan, kn_batch) are host objects owned by the
+ *     caller and released with their *_free; *_free(NULL) is a no-op.
+ *     Plans and batches are immutable after creation and may be shared by
+ *     threads and streams.
+ *   - Device buffers (workspace, couplings, outputs) are caller-owned device
+ *     memory on the current HIP device; "stream" is a hipStream_t passed as
+ *     void* (NULL = the null stream).  Device calls are asynchronous on that
+ *     stream; HIP launch/copy failures return KN_E_DEVICE.
+ *   - Complex numbers are interleaved (re, im) doubles.
+ *   - q must be in [2, 8]; other values return KN_E_UNSUPPORTED.
+ */
+#ifndef KN_H
+#define KN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KN_OK = 0,
+  KN_E_INVALID = -1,     /* malformed argument or diagram */
+  KN_E_NOMEM = -2,       /* host allocation failed */
+  KN_E_BUDGET = -3,      /* plan exceeds the memory budget / workspace too small */
+  KN_E_DEVICE = -4,      /* HIP runtime error */
+  KN_E_NUMERIC = -5,     /* non-finite input or result */
+  KN_E_UNSUPPORTED = -6  /* q out of range, or plan/call combination not supported */
+} kn_status;
+
+typedef struct kn_tait kn_tait;
+typedef struct kn_plan kn_plan;
+typedef struct kn_batch kn_batch;
+
+/* A complex number with a separate power-of-two exponent:
+   value = (re + i*im) * 2^exp2.  Results are normalised so that
+   max(|re|, |im|) lies in [0.5, 1) unless the value is zero. */
+typedef struct {
+  double re, im;
+  int64_t exp2;
+} kn_scalar;
+
+/* ------------------------------------------------------------------ Sec. II
+ * kn_build_tait: signed Tait graph of a knot diagram given as a PD code.
+ *   n      number of crossings (n == 0: the crossingless unknot).
+ *   pd     int32[4n]; pd[4i..4i+3] = (a, b, c, d): the arcs at crossing i
+ *          counter-clockwise from the incoming under-arc a.  Arcs are labelled
+ *          0..2n-1 consecutively along the orientation (arc k runs from the
+ *          k-th to the (k+1)-th crossing visit), so c == a+1 (mod 2n), and the
+ *          over-strand satisfies b == d+1 (positive crossing) or d == b+1
+ *          (negative crossing).
+ *   signs  int8[n] twist signs (+1 right-handed) or NULL to read them from
+ *          the labels; required when n == 1 (the labels are ambiguous).
+ *   outer_arc, outer_side
+ *          the region taken as unbounded (coloured white, Sec. II): the region
+ *          on the left (outer_side 0) or right (1) of arc outer_arc where it
+ *          leaves its crossing.  outer_arc < 0 selects arc 0, left.  Either
+ *          choice gives the same V (the two Tait graphs are planar duals).
+ * Errors: KN_E_INVALID for labels out of range / not used exactly twice,
+ * labels inconsistent with one oriented closed curve, or a non-planar code
+ * (region count != n + 2).
+ */
+kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* signs,
+                        int32_t outer_arc, int32_t outer_side, kn_tait** out);
+/* n_vertices = black regions (n_v), n_edges = crossings, writhe w = sum of
+   twist signs, tait_number tau = sum of Tait signs (Sec. II).  Any pointer may
+   be NULL. */
+kn_status kn_tait_info(const kn_tait* g, int32_t* n_vertices, int32_t* n_edges,
+                       int32_t* writhe, int32_t* tait_number);
+/* Edge k is crossing k: uv[2k], uv[2k+1] are its black regions (equal for a
+   loop), eps[k] its Tait sign.  uv: int32[2*n_edges], eps: int8[n_edges]. */
+kn_status kn_tait_edges(const kn_tait* g, int32_t* uv, int8_t* eps);
+void kn_tait_free(kn_tait* g);
+
+/* ------------------------------------------------------------------ Sec. III
+ * Planning: simplification, absorption, contraction order, memory layout.
+ *
+ * strategy   0: greedy pairwise order minimising size(C) - size(A) - size(B)
+ *               over tensors indexed by spins (default);
+ *            1: greedy by the rank of the result (the paper's "cheapest
+ *               contraction in terms of the resulting degree");
+ * precision  0: complex128 (FP64) tensors; 1: complex64 (FP32) tensors with
+ *               FP32 accumulation, exponents and normalisation kept in
+ *               int64 / FP64.
+ * simplify   bit 0: Reidemeister I (loops and degree-1 vertices);
+ *            bit 1: Reidemeister II (parallel edges of opposite Tait sign;
+ *                   only valid for the Jones couplings).  Parallel edges are
+ *                   always merged into one q x q matrix (elementwise product).
+ *            Default (opts == NULL): 3.
+ * jones_only 1: the plan may only be contracted with the Jones couplings
+ *               (J == NULL); required for simplify bit 1.  0: any couplings.
+ * mem_budget_bytes  0 = no limit; otherwise a plan whose workspace exceeds it
+ *               returns KN_E_BUDGET (and still fills *out so that its
+ *               statistics can be read, see kn_plan_info).
+ * tile_outputs      outputs per tile for steps split across workgroups
+ *               (0 = default); big_step_macs: complex multiply-adds above
+ *               which a step is split into tiles (0 = default).
+ */
+typedef struct {
+  int32_t strategy;
+  int32_t precision;
+  int32_t simplify;
+  int32_t jones_only;
+  uint64_t mem_budget_bytes;
+  int32_t tile_outputs;
+  int32_t big_step_macs_log2;
+} kn_plan_opts;
+
+/* Statistics of a plan (algorithmic, from the plan itself).
+ *   n_steps            pairwise contractions
+ *   n_vertex_tensors   tensors built from absorbed edge matrices
+ *   log2_max_entries   log2 of the largest tensor (entries)
+ *   flops              8 * sum over steps of |batch|*|M|*|N|*|K| (complex MAC = 8)
+ *   bytes              sum over steps of s*(|A| + |B| + |C|), s = 16 (c128) or 8 (c64)
+ *   workspace_bytes    device workspace kn_contract needs
+ *   delta_h_paper      max vertex degree over the graph minors of the paper's
+ *                      edge-contraction greedy on the simplified graph (Sec. III)
+ *   n_edges_simplified edges left after simplification and merging
+ *   n_vertices_simplified */
+typedef struct {
+  int32_t n_steps;
+  int32_t n_vertex_tensors;
+  double log2_max_entries;
+  double flops;
+  double bytes;
+  uint64_t workspace_bytes;
+  uint64_t image_bytes;
+  int32_t delta_h_paper;
+  int32_t n_edges_simplified;
+  int32_t n_vertices_simplified;
+  int32_t n_tasks;
+  int32_t n_components;
+  int32_t max_rank;
+} kn_plan_stats;
+
+/* Build a plan for q.  opts == NULL selects the defaults above (Jones-only,
+   full simplification, complex128, greedy size order). */
+kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_opts* opts, kn_plan** out);
+kn_status kn_plan_info(const kn_plan* p, kn_plan_stats* out);
+void kn_plan_free(kn_plan* p);
+/* Read-only view of the plan's device image (the bytes kn_contract copies to
+   the device; layout private to this library version), for inspection tools
+   and tests.  *data stays valid until kn_plan_free. */
+kn_status kn_plan_image(const kn_plan* p, const void** data, size_t* bytes);
+/* The plan's contraction order, for inspection: step k contracts tensors
+   ab[2k], ab[2k+1] (ids: 0..n_vertex_tensors-1 are vertex tensors, id
+   n_vertex_tensors + k is the result of step k).  ab: int32[2*n_steps]. */
+kn_status kn_plan_steps(const kn_plan* p, int32_t* ab);
+
+/* ------------------------------------------------------------------ Eqs. 2-3, 6
+ * kn_contract: Z(q) of the plan's knot, computed on the GPU.
+ *   J          device array of 2*n_edges doubles: complex coupling J_e for every
+ *              ORIGINAL Tait edge (edge order of kn_tait_edges), interaction
+ *              matrix T_e = 1 + (exp(J_e) - 1) * delta.  NULL = the Jones
+ *              couplings exp(J_e) = -t(q)^(-eps_e) (Sec. II).  Non-NULL with a
+ *              jones_only plan returns KN_E_UNSUPPORTED.
+ *   workspace  device memory of at least plan workspace_bytes, 256-byte
+ *              aligned; its contents on entry do not matter and are
+ *              overwritten (the plan's device image is copied into it).
+ *   z_dev      device pointer to one kn_scalar receiving Z.  On an internal
+ *              device error Z is written as NaN.
+ * The call enqueues a host-to-device copy of the plan image, one clear kernel
+ * and one persistent contraction kernel on `stream` and returns. */
+kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
+                      size_t workspace_bytes, void* stream, kn_scalar* z_dev);
+
+/* d log Z / d J_e (holomorphic derivative) for every ORIGINAL edge, written to
+ * grad_dev (device, 2*n_edges doubles).  Runs its own forward sweep (the
+ * intermediates are recomputed, nothing from a previous kn_contract is
+ * needed); z_dev receives Z as in kn_contract.  The plan must not be
+ * jones_only if J is non-NULL.  workspace must hold kn_plan_info's
+ * workspace_bytes of a plan created with the same options; the backward sweep
+ * needs the extra room reported by kn_backward_workspace. */
+kn_status kn_backward_workspace(const kn_plan* p, uint64_t* bytes);
+kn_status kn_contract_backward(const kn_plan* p, const double* J, void* workspace,
+                               size_t workspace_bytes, void* stream,
+                               kn_scalar* z_dev, double* grad_dev);
+
+/* ------------------------------------------------------------------ Eq. 4
+ * V = A(q) Z with A(q) = (-t^{1/2} - t^{-1/2})^{-n_v-1} (-t^{3/4})^{w} t^{tau/4},
+ * all fractional powers taken from the principal fourth root of t (Eq. 1).
+ * n_v, w and tau are those of the ORIGINAL Tait graph `g`.  Outputs are host
+ * scalars; v_re/v_im overflow to +-inf when |V| exceeds double range, in which
+ * case log2_abs_v (nullable) and arg_v (nullable) still carry V exactly. */
+kn_status kn_jones(int32_t q, const kn_tait* g, const kn_scalar* z_host, double* v_re,
+                   double* v_im, double* log2_abs_v, double* arg_v);
+/* t(q) of Eq. 1 with principal square roots. */
+kn_status kn_jones_variable(int32_t q, double* t_re, double* t_im);
+
+/* ------------------------------------------------------------------ batches
+ * A batch contracts many plans (any mix of knots, q and sizes) in one
+ * persistent kernel launch.  All plans must share one precision.
+ * kn_batch_create builds the combined task list on the host; kn_batch_upload
+ * copies its device image into the workspace (once); kn_batch_contract only
+ * launches kernels (a clear kernel and the persistent kernel), so it can be
+ * captured in a hipGraph and replayed.
+ *   J    NULL (Jones couplings for every knot) or a device array holding, for
+ *        knot i, 2*n_edges(i) doubles at offset 2*edge_offset(i) (see
+ *        kn_batch_edge_offset).  A non-NULL J needs no jones_only plans.
+ *   z_dev  device array of n kn_scalar, one per plan, in input order. */
+typedef struct {
+  uint64_t workspace_bytes;
+  uint64_t image_bytes;
+  int32_t n_tasks;
+  int32_t n_knots;
+  double flops;
+  double bytes;
+  int64_t total_edges;
+  int32_t grid;
+} kn_batch_stats;
+kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_batch** out);
+kn_status kn_batch_info(const kn_batch* b, kn_batch_stats* out);
+kn_status kn_batch_edge_offset(const kn_batch* b, int32_t i, int64_t* off);
+kn_status kn_batch_upload(const kn_batch* b, void* workspace, size_t workspace_bytes, void* stream);
+kn_status kn_batch_contract(const kn_batch* b, const double* J, void* workspace,
+                            size_t workspace_bytes, void* stream, kn_scalar* z_dev);
+/* Read-only view of the batch's device image (see kn_plan_image). */
+kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes);
+/* Override the persistent grid size (workgroups) of later kn_batch_contract
+   calls; 0 restores the default (derived from the device's CU count). */
+kn_status kn_batch_set_grid(kn_batch* b, int32_t grid);
+void kn_batch_free(kn_batch* b);
+
+/* Human-readable name of a status code (static string). */
+const char* kn_status_string(kn_status s);
+/* Library version string (static). */
+const char* kn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KN_H */

@@ -1,0 +1,85 @@
+// internal.h -- host-side objects behind the opaque handles of kn.h.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kn.h"
+#include "program.h"
+
+struct kn_tait {
+  int32_t n_vertices = 0;
+  std::vector<int32_t> uv;    // 2 per edge (edge k = crossing k)
+  std::vector<int8_t> eps;    // Tait sign per edge
+  std::vector<int8_t> twist;  // twist sign per crossing
+  int32_t writhe = 0;
+  int32_t tau = 0;
+};
+
+namespace kn {
+
+// One pairwise contraction C = A . B over spin groups.
+struct PStep {
+  int32_t a, b, c;
+  std::vector<int32_t> bs, ms, ns, ks;  // batch, rows (A only), cols (B only), contracted
+};
+
+struct PTensor {
+  std::vector<int32_t> spins;  // storage order, first = most significant
+  int64_t off = 0;             // arena offset (entries), knot-local
+  int64_t size = 1;            // q^rank
+};
+
+struct PVertex {
+  int32_t tensor;
+  int32_t center;               // spin of the vertex itself
+  bool keep_center;
+  std::vector<int32_t> nbr;     // neighbour spins, slot order
+  std::vector<int32_t> medge;   // merged edge per slot (knot-local)
+};
+
+// Everything about one knot's contraction, in knot-local ids.
+struct PlanKnot {
+  int32_t q = 3;
+  double t_re = 0, t_im = 0;
+  int32_t precision = 0;
+  bool jones_only = true;
+  int32_t n_edges = 0;                          // original Tait edges
+  std::vector<int8_t> eps;                      // original Tait signs
+  std::vector<std::vector<int32_t>> medges;     // members of each merged edge
+  std::vector<Factor> factors;                  // simplification factors
+  int32_t n_iso = 0;                            // isolated spins
+  std::vector<PTensor> tensors;                 // vertex tensors, then step outputs
+  std::vector<PVertex> vtx;
+  std::vector<PStep> steps;
+  std::vector<int32_t> comps;                   // final scalar tensor per component
+  int64_t arena_elems = 0;
+  int32_t tile = 256;
+  int32_t big_log2 = 16;
+  std::vector<uint8_t> big;                     // per step: split into tiles
+};
+
+// Build the device image for a list of knots (a batch of one or more).
+// out_slot of knot i is i.  Returns the image bytes; header filled in.
+std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots);
+
+int64_t elem_bytes(int32_t precision);
+
+}  // namespace kn
+
+struct kn_plan {
+  kn::PlanKnot k;
+  kn_plan_stats stats{};
+  std::vector<uint8_t> image;  // single-knot device image
+  uint64_t bwd_workspace = 0;
+};
+
+struct kn_batch {
+  std::vector<uint8_t> image;
+  kn_batch_stats stats{};
+  std::vector<int64_t> edge_offset;
+  int32_t precision = 0;
+  bool jones_only = false;
+  int32_t grid_override = 0;
+};

@@ -1,0 +1,550 @@
+// plan.cpp -- from a signed Tait graph to a contraction plan for the PACI
+// tensor network G_T (Sec. III of arXiv:1807.02119).
+//
+// 1. Simplification (Sec. III.A).  Loops (v, v) are removed; each leaves the
+//    constant factor x_e = e^{J_e} because sigma_v == sigma_v always.  Parallel
+//    edges are merged into one q x q matrix (elementwise product of the
+//    interaction matrices, merged weight x_m = prod x_e).  With the Jones
+//    couplings a merged class with as many + as - Tait signs has x_m = 1, an
+//    all-ones matrix that couples nothing: that is the Reidemeister-II
+//    "unpoke" and the edge is dropped.  A vertex of degree 1 (a spike) is
+//    summed out: sum_b T(a, b) = x_m + q - 1 for every a, a constant factor.
+//    A vertex of degree 0 contributes a factor q.
+// 2. Tensor network (Sec. III, Eq. 5).  Every vertex carries a COPY tensor;
+//    instead of materialising it, each merged edge matrix is absorbed into one
+//    endpoint, so that a vertex tensor is indexed by spins:
+//      F_v(s_v, s_w1, ..., s_wk) = prod_j T_{v wj}(s_v, s_wj).
+//    Edges are oriented out of the endpoint that comes first in a
+//    minimum-degree (degeneracy) order, which bounds k by the degeneracy of
+//    the planar graph (<= 5).  A vertex spin that no other tensor mentions is
+//    summed at build time.
+// 3. Contraction order (Sec. III, "greedy").  Tensors that share a spin are
+//    contracted pairwise; a spin is summed when the two operands are its last
+//    holders, otherwise it stays as a batch index.  Each step is a batched
+//    complex GEMM C[b,m,n] = sum_k A[b,m,k] B[b,k,n].  The greedy key is the
+//    growth size(C) - size(A) - size(B) (strategy 0) or the rank of C
+//    (strategy 1), ties broken by the flop count and then tensor ids.
+// 4. Memory: first-fit arena over the tensors' live ranges.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <queue>
+#include <set>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace kn {
+
+int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
+
+namespace {
+
+struct Simplified {
+  int32_t n_spins = 0;                          // remaining spins (renumbered)
+  std::vector<std::pair<int32_t, int32_t>> e;   // merged edges (spin ids)
+  std::vector<int32_t> e_medge;                 // merged-edge id of each remaining edge
+  // paper-model edge multiplicity of each remaining edge (for delta_h_paper)
+  std::vector<int32_t> e_mult;
+};
+
+// Simplification of Sec. III.A; fills k.medges, k.factors, k.n_iso.
+Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& k) {
+  const int32_t nv = g.n_vertices;
+  const int32_t ne = (int32_t)g.eps.size();
+  bool r1 = flags & 1, r2 = (flags & 2) && jones_only;
+  // merge parallel classes; loops become factors (or stay as loops when R-I
+  // is off: they are still constants, a loop never couples two spins)
+  std::map<std::pair<int32_t, int32_t>, int32_t> cls;
+  std::vector<std::pair<int32_t, int32_t>> ends;
+  for (int32_t e = 0; e < ne; ++e) {
+    int32_t u = g.uv[2 * e], v = g.uv[2 * e + 1];
+    if (u == v) {
+      k.factors.push_back({FAC_LOOP, e});
+      continue;
+    }
+    auto key = std::make_pair(std::min(u, v), std::max(u, v));
+    auto it = cls.find(key);
+    int32_t id;
+    if (it == cls.end()) {
+      id = (int32_t)k.medges.size();
+      cls.emplace(key, id);
+      k.medges.emplace_back();
+      ends.push_back(key);
+    } else {
+      id = it->second;
+    }
+    k.medges[id].push_back(e);
+  }
+  (void)r1;
+  const int32_t nm = (int32_t)k.medges.size();
+  std::vector<uint8_t> alive_e(nm, 1);
+  std::vector<int32_t> mult(nm);
+  for (int32_t m = 0; m < nm; ++m) {
+    int32_t s = 0;
+    for (int32_t e : k.medges[m]) s += g.eps[e];
+    mult[m] = r2 ? std::abs(s) : (int32_t)k.medges[m].size();
+    if (r2 && s == 0) alive_e[m] = 0;  // Reidemeister II: x_m = 1
+  }
+  // adjacency over live merged edges
+  std::vector<std::vector<int32_t>> inc(nv);
+  for (int32_t m = 0; m < nm; ++m)
+    if (alive_e[m]) {
+      inc[ends[m].first].push_back(m);
+      inc[ends[m].second].push_back(m);
+    }
+  std::vector<int32_t> deg(nv);
+  for (int32_t v = 0; v < nv; ++v) deg[v] = (int32_t)inc[v].size();
+  std::vector<uint8_t> alive_v(nv, 1);
+  if (flags & 1) {
+    // Reidemeister I on spikes: peel degree-1 vertices repeatedly
+    std::vector<int32_t> stack;
+    for (int32_t v = 0; v < nv; ++v)
+      if (deg[v] == 1) stack.push_back(v);
+    while (!stack.empty()) {
+      int32_t v = stack.back();
+      stack.pop_back();
+      if (!alive_v[v] || deg[v] != 1) continue;
+      int32_t m = -1;
+      for (int32_t x : inc[v])
+        if (alive_e[x]) { m = x; break; }
+      if (m < 0) continue;
+      alive_e[m] = 0;
+      k.factors.push_back({FAC_LEAF, m});
+      alive_v[v] = 0;
+      int32_t w = ends[m].first == v ? ends[m].second : ends[m].first;
+      deg[v] = 0;
+      if (--deg[w] == 1) stack.push_back(w);
+    }
+  }
+  // isolated vertices and renumbering
+  Simplified s;
+  std::vector<int32_t> sid(nv, -1);
+  for (int32_t v = 0; v < nv; ++v) {
+    if (!alive_v[v]) continue;
+    if (deg[v] == 0) {
+      k.n_iso++;
+      continue;
+    }
+    sid[v] = s.n_spins++;
+  }
+  for (int32_t m = 0; m < nm; ++m)
+    if (alive_e[m]) {
+      s.e.emplace_back(sid[ends[m].first], sid[ends[m].second]);
+      s.e_medge.push_back(m);
+      s.e_mult.push_back(mult[m]);
+    }
+  return s;
+}
+
+// Max degree over the minors of the paper's greedy edge contraction on the
+// multigraph (each merged edge counted with its multiplicity).
+int32_t paper_delta_h(const Simplified& s) {
+  const int32_t n = s.n_spins;
+  std::vector<std::unordered_map<int32_t, int32_t>> adj(n);
+  std::vector<int32_t> deg(n, 0);
+  for (size_t i = 0; i < s.e.size(); ++i) {
+    auto [u, v] = s.e[i];
+    int32_t w = std::max(1, s.e_mult[i]);
+    adj[u][v] += w;
+    adj[v][u] += w;
+    deg[u] += w;
+    deg[v] += w;
+  }
+  int32_t best = 0;
+  for (int32_t v = 0; v < n; ++v) best = std::max(best, deg[v]);
+  std::vector<uint8_t> alive(n, 1);
+  while (true) {
+    // cheapest edge contraction: smallest resulting degree
+    int32_t bu = -1, bv = -1, bd = 0;
+    for (int32_t u = 0; u < n; ++u) {
+      if (!alive[u]) continue;
+      for (auto& [v, m] : adj[u]) {
+        if (v <= u) continue;
+        int32_t d = deg[u] + deg[v] - 2 * m;
+        if (bu < 0 || d < bd) { bu = u; bv = v; bd = d; }
+      }
+    }
+    if (bu < 0) break;
+    // merge bv into bu
+    int32_t m_uv = adj[bu][bv];
+    adj[bu].erase(bv);
+    adj[bv].erase(bu);
+    deg[bu] -= m_uv;
+    deg[bv] -= m_uv;
+    for (auto& [w, m] : adj[bv]) {
+      adj[w].erase(bv);
+      adj[w][bu] += m;
+      adj[bu][w] += m;
+    }
+    deg[bu] += deg[bv];
+    adj[bv].clear();
+    alive[bv] = 0;
+    best = std::max(best, deg[bu]);
+  }
+  return best;
+}
+
+struct Cand {
+  double k1, k2;
+  int32_t a, b;
+  bool operator<(const Cand& o) const {  // max-heap: "less" = worse
+    if (k1 != o.k1) return k1 > o.k1;
+    if (k2 != o.k2) return k2 > o.k2;
+    if (a != o.a) return a > o.a;
+    return b > o.b;
+  }
+};
+
+}  // namespace
+
+// Build tensors, order and arena for one knot.  Returns KN_OK or an error.
+kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
+                    kn_plan_stats& st) {
+  k.q = q;
+  k.precision = o.precision;
+  k.jones_only = o.jones_only != 0;
+  k.n_edges = (int32_t)g.eps.size();
+  k.eps = g.eps;
+  k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
+  k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
+  {
+    double qq = q;
+    if (q < 4) {
+      k.t_re = (qq - 2.0) / 2.0;
+      k.t_im = std::sqrt(qq * (4.0 - qq)) / 2.0;
+    } else {
+      k.t_re = (qq - 2.0 + std::sqrt(qq * (qq - 4.0))) / 2.0;
+      k.t_im = 0.0;
+    }
+  }
+  Simplified s = simplify(g, o.simplify, k.jones_only, k);
+  const int32_t n = s.n_spins;
+  st.n_edges_simplified = (int32_t)s.e.size();
+  st.n_vertices_simplified = n;
+  st.delta_h_paper = paper_delta_h(s);
+
+  // ---- absorption: orient edges by a minimum-degree elimination order
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> adj(n);  // (nbr, medge)
+  for (size_t i = 0; i < s.e.size(); ++i) {
+    auto [u, v] = s.e[i];
+    adj[u].emplace_back(v, s.e_medge[i]);
+    adj[v].emplace_back(u, s.e_medge[i]);
+  }
+  std::vector<int32_t> deg(n), pos(n, -1);
+  int32_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = (int32_t)adj[v].size();
+    maxd = std::max(maxd, deg[v]);
+  }
+  {
+    std::vector<std::vector<int32_t>> bucket(maxd + 1);
+    for (int32_t v = 0; v < n; ++v) bucket[deg[v]].push_back(v);
+    int32_t placed = 0, d = 0;
+    while (placed < n) {
+      d = std::max(0, d - 1);
+      while (d <= maxd && bucket[d].empty()) ++d;
+      int32_t v = bucket[d].back();
+      bucket[d].pop_back();
+      if (pos[v] >= 0 || deg[v] != d) continue;
+      pos[v] = placed++;
+      for (auto& [w, m] : adj[v])
+        if (pos[w] < 0) {
+          --deg[w];
+          bucket[deg[w]].push_back(w);
+        }
+    }
+  }
+  // out-edges of v: to neighbours placed later
+  std::vector<int32_t> holders(n, 0);
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> outs(n);
+  for (int32_t v = 0; v < n; ++v)
+    for (auto& [w, m] : adj[v])
+      if (pos[w] > pos[v]) outs[v].emplace_back(w, m);
+  for (int32_t v = 0; v < n; ++v) {
+    std::sort(outs[v].begin(), outs[v].end());
+    if (!outs[v].empty()) holders[v]++;
+    for (auto& [w, m] : outs[v]) holders[w]++;
+  }
+  // vertex tensors
+  for (int32_t v = 0; v < n; ++v) {
+    bool has = !outs[v].empty();
+    if (!has && holders[v] == 1) has = true;  // lone holder elsewhere: add [v] of ones
+    if (!has) continue;
+    PVertex pv;
+    pv.tensor = (int32_t)k.tensors.size();
+    pv.center = v;
+    int32_t cnt = holders[v] + (outs[v].empty() ? 1 : 0);
+    pv.keep_center = cnt >= 2;
+    PTensor t;
+    if (pv.keep_center) t.spins.push_back(v);
+    for (auto& [w, m] : outs[v]) {
+      pv.nbr.push_back(w);
+      pv.medge.push_back(m);
+      t.spins.push_back(w);
+    }
+    if (pv.nbr.size() > 7) return KN_E_UNSUPPORTED;  // planar graphs give <= 5
+    k.vtx.push_back(pv);
+    k.tensors.push_back(std::move(t));
+  }
+  const int32_t n_vt = (int32_t)k.tensors.size();
+  st.n_vertex_tensors = n_vt;
+
+  // ---- greedy pairwise order over spin-indexed tensors
+  std::vector<int32_t> cnt(n, 0);
+  std::vector<std::vector<int32_t>> hold(n);
+  std::vector<uint8_t> alive(n_vt, 1);
+  for (int32_t t = 0; t < n_vt; ++t)
+    for (int32_t sp : k.tensors[t].spins) {
+      cnt[sp]++;
+      hold[sp].push_back(t);
+    }
+  for (int32_t sp = 0; sp < n; ++sp)
+    if (cnt[sp] == 1) return KN_E_INVALID;  // private spin left: planner bug guard
+  std::vector<double> qpow(64);
+  qpow[0] = 1;
+  for (int i = 1; i < 64; ++i) qpow[i] = qpow[i - 1] * q;
+  auto cost = [&](int32_t a, int32_t b, Cand& c) {
+    const auto& A = k.tensors[a].spins;
+    const auto& B = k.tensors[b].spins;
+    int32_t uni = (int32_t)A.size(), kk = 0;
+    for (int32_t x : B) {
+      bool inA = std::find(A.begin(), A.end(), x) != A.end();
+      if (!inA) uni++;
+      else if (cnt[x] == 2) kk++;
+    }
+    int32_t rc = uni - kk;
+    if (o.strategy == 1) c.k1 = rc;
+    else c.k1 = qpow[std::min(rc, 63)] - qpow[A.size()] - qpow[B.size()];
+    c.k2 = qpow[std::min(uni, 63)];
+    c.a = std::min(a, b);
+    c.b = std::max(a, b);
+  };
+  std::priority_queue<Cand> pq;
+  auto push_pairs = [&](int32_t a) {
+    std::vector<int32_t> seen;
+    for (int32_t sp : k.tensors[a].spins)
+      for (int32_t b : hold[sp]) {
+        if (b == a || !alive[b]) continue;
+        if (std::find(seen.begin(), seen.end(), b) != seen.end()) continue;
+        seen.push_back(b);
+        Cand c;
+        cost(a, b, c);
+        pq.push(c);
+      }
+  };
+  for (int32_t t = 0; t < n_vt; ++t) push_pairs(t);
+  while (!pq.empty()) {
+    Cand c = pq.top();
+    pq.pop();
+    if (!alive[c.a] || !alive[c.b]) continue;
+    // recompute: counts may have changed since the candidate was pushed
+    Cand fresh;
+    cost(c.a, c.b, fresh);
+    if (fresh.k1 != c.k1 || fresh.k2 != c.k2) {
+      pq.push(fresh);
+      continue;
+    }
+    int32_t a = c.a, b = c.b;
+    // put the larger operand first (rows come from A)
+    if (k.tensors[b].spins.size() > k.tensors[a].spins.size()) std::swap(a, b);
+    const auto A = k.tensors[a].spins;
+    const auto B = k.tensors[b].spins;
+    PStep stp;
+    stp.a = a;
+    stp.b = b;
+    for (int32_t x : A) {
+      bool inB = std::find(B.begin(), B.end(), x) != B.end();
+      if (!inB) stp.ms.push_back(x);
+      else if (cnt[x] == 2) stp.ks.push_back(x);
+      else stp.bs.push_back(x);
+    }
+    for (int32_t x : B)
+      if (std::find(A.begin(), A.end(), x) == A.end()) stp.ns.push_back(x);
+    PTensor ct;
+    for (int32_t x : stp.bs) ct.spins.push_back(x);
+    for (int32_t x : stp.ms) ct.spins.push_back(x);
+    for (int32_t x : stp.ns) ct.spins.push_back(x);
+    int32_t cid = (int32_t)k.tensors.size();
+    stp.c = cid;
+    for (int32_t x : stp.ks) cnt[x] = 0;
+    for (int32_t x : stp.bs) cnt[x]--;
+    alive[a] = alive[b] = 0;
+    alive.push_back(1);
+    for (int32_t x : ct.spins) hold[x].push_back(cid);
+    k.tensors.push_back(std::move(ct));
+    k.steps.push_back(std::move(stp));
+    push_pairs(cid);
+  }
+  for (int32_t t = 0; t < (int32_t)k.tensors.size(); ++t)
+    if (alive[t]) {
+      if (!k.tensors[t].spins.empty()) return KN_E_INVALID;  // guard
+      k.comps.push_back(t);
+    }
+  st.n_components = (int32_t)k.comps.size();
+  st.n_steps = (int32_t)k.steps.size();
+
+  // ---- sizes, statistics, tile decisions
+  const int64_t es = elem_bytes(o.precision);
+  double flops = 0, bytes = 0, maxlog = 0;
+  int32_t maxrank = 0;
+  for (auto& t : k.tensors) {
+    int32_t r = (int32_t)t.spins.size();
+    maxrank = std::max(maxrank, r);
+    double sz = qpow[std::min(r, 63)];
+    if (sz > 2147483647.0) {
+      st.max_rank = r;
+      st.log2_max_entries = r * std::log2((double)q);
+      return KN_E_BUDGET;
+    }
+    t.size = (int64_t)sz;
+    maxlog = std::max(maxlog, std::log2(sz));
+  }
+  k.big.assign(k.steps.size(), 0);
+  for (size_t i = 0; i < k.steps.size(); ++i) {
+    auto& sp = k.steps[i];
+    double nb = qpow[sp.bs.size()], nm = qpow[sp.ms.size()], nn = qpow[sp.ns.size()],
+           nk = qpow[sp.ks.size()];
+    flops += 8.0 * nb * nm * nn * nk;
+    bytes += es * double(k.tensors[sp.a].size + k.tensors[sp.b].size + k.tensors[sp.c].size);
+    double macs = nb * nm * nn * nk;
+    k.big[i] = macs >= std::ldexp(1.0, k.big_log2) ? 1 : 0;
+  }
+  st.flops = flops;
+  st.bytes = bytes;
+  st.log2_max_entries = maxlog;
+  st.max_rank = maxrank;
+
+  // ---- arena: first fit over live ranges, in execution order
+  {
+    const int64_t align = 16;  // entries
+    std::map<int64_t, int64_t> free_blk;  // off -> len
+    int64_t top = 0;
+    auto alloc = [&](int64_t len) {
+      len = (len + align - 1) / align * align;
+      for (auto it = free_blk.begin(); it != free_blk.end(); ++it)
+        if (it->second >= len) {
+          int64_t off = it->first, rem = it->second - len;
+          free_blk.erase(it);
+          if (rem) free_blk.emplace(off + len, rem);
+          return off;
+        }
+      // extend: merge with a free block touching the top
+      if (!free_blk.empty()) {
+        auto last = std::prev(free_blk.end());
+        if (last->first + last->second == top) {
+          int64_t off = last->first;
+          free_blk.erase(last);
+          top = off + len;
+          return off;
+        }
+      }
+      int64_t off = top;
+      top += len;
+      return off;
+    };
+    auto release = [&](int64_t off, int64_t len) {
+      len = (len + align - 1) / align * align;
+      auto it = free_blk.emplace(off, len).first;
+      auto nx = std::next(it);
+      if (nx != free_blk.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_blk.erase(nx);
+      }
+      if (it != free_blk.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+          pv->second += it->second;
+          free_blk.erase(it);
+        }
+      }
+    };
+    for (int32_t t = 0; t < n_vt; ++t) k.tensors[t].off = alloc(k.tensors[t].size);
+    for (auto& sp : k.steps) {
+      k.tensors[sp.c].off = alloc(k.tensors[sp.c].size);
+      release(k.tensors[sp.a].off, k.tensors[sp.a].size);
+      release(k.tensors[sp.b].off, k.tensors[sp.b].size);
+    }
+    k.arena_elems = std::max<int64_t>(top, 16);
+  }
+  return KN_OK;
+}
+
+}  // namespace kn
+
+static kn_plan_opts default_opts() {
+  kn_plan_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.strategy = 0;
+  o.precision = 0;
+  o.simplify = 3;
+  o.jones_only = 1;
+  o.mem_budget_bytes = 0;
+  o.tile_outputs = 0;
+  o.big_step_macs_log2 = 0;
+  return o;
+}
+
+extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_opts* opts,
+                                    kn_plan** out) {
+  if (!out) return KN_E_INVALID;
+  *out = nullptr;
+  if (!g) return KN_E_INVALID;
+  if (q < 2 || q > 8) return KN_E_UNSUPPORTED;
+  kn_plan_opts o = opts ? *opts : default_opts();
+  if (o.strategy < 0 || o.strategy > 1 || o.precision < 0 || o.precision > 1 ||
+      o.simplify < 0 || o.simplify > 3 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
+      o.big_step_macs_log2 > 40)
+    return KN_E_INVALID;
+  if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
+  kn_plan* p = new (std::nothrow) kn_plan();
+  if (!p) return KN_E_NOMEM;
+  kn_status rc;
+  try {
+    rc = kn::make_plan(*g, q, o, p->k, p->stats);
+    if (rc == KN_OK) {
+      std::vector<const kn::PlanKnot*> one{&p->k};
+      p->image = kn::build_image(one);
+      const auto* h = reinterpret_cast<const kn::ImgHeader*>(p->image.data());
+      p->stats.workspace_bytes = (uint64_t)h->workspace_bytes;
+      p->stats.image_bytes = (uint64_t)h->image_bytes;
+      p->stats.n_tasks = h->n_tasks;
+      if (o.mem_budget_bytes && p->stats.workspace_bytes > o.mem_budget_bytes) rc = KN_E_BUDGET;
+    }
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return KN_E_NOMEM;
+  }
+  if (rc == KN_OK || rc == KN_E_BUDGET) {
+    *out = p;
+    return rc;
+  }
+  delete p;
+  return rc;
+}
+
+extern "C" kn_status kn_plan_info(const kn_plan* p, kn_plan_stats* out) {
+  if (!p || !out) return KN_E_INVALID;
+  *out = p->stats;
+  return KN_OK;
+}
+
+extern "C" kn_status kn_plan_image(const kn_plan* p, const void** data, size_t* bytes) {
+  if (!p || !data || !bytes) return KN_E_INVALID;
+  *data = p->image.empty() ? nullptr : p->image.data();
+  *bytes = p->image.size();
+  return KN_OK;
+}
+
+extern "C" kn_status kn_plan_steps(const kn_plan* p, int32_t* ab) {
+  if (!p || !ab) return KN_E_INVALID;
+  for (size_t i = 0; i < p->k.steps.size(); ++i) {
+    ab[2 * i] = p->k.steps[i].a;
+    ab[2 * i + 1] = p->k.steps[i].b;
+  }
+  return KN_OK;
+}
+
+extern "C" void kn_plan_free(kn_plan* p) { delete p; }

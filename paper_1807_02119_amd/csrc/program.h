@@ -1,0 +1,120 @@
+// program.h -- layout of the device program ("image") that the host planner
+// writes and the persistent contraction kernel reads.
+//
+// An image describes the full contraction of one or more tensor networks G_T
+// (one per knot, Sec. III of arXiv:1807.02119): the vertex tensors built from
+// absorbed edge matrices, the pairwise contraction steps, and a list of tasks
+// that workgroups take in order from a global ticket.  Everything is plain
+// old data addressed by byte offsets from the start of the image, so the
+// image can be copied to the device verbatim.
+//
+// Workspace layout (device): [ image | runtime state | tensor arena ], each
+// part 256-byte aligned; offsets are recorded in the header.
+#pragma once
+#include <stdint.h>
+
+namespace kn {
+
+constexpr int32_t kMagic = 0x4b4e4731;  // "KNG1"
+constexpr int32_t kBlock = 256;         // threads per workgroup of the engine
+
+enum TaskKind : int32_t {
+  // One workgroup runs, in order: the knot's setup (edge weights + vertex
+  // tensors) if flags&1, steps [first, first+count) entirely, and the knot's
+  // final reduction to Z if flags&2.
+  TASK_SERIAL = 0,
+  // One tile (outputs [count*tile, (count+1)*tile)) of step `first`.
+  TASK_TILE = 1,
+};
+
+enum TaskFlags : int32_t { TF_SETUP = 1, TF_FINAL = 2 };
+
+enum FactorKind : int32_t {
+  FAC_LOOP = 0,  // loop edge e: factor x_e (original edge id)
+  FAC_LEAF = 1,  // degree-1 vertex on merged edge m: factor x_m + q - 1
+};
+
+struct ImgHeader {
+  int32_t magic;
+  int32_t precision;  // 0 complex128, 1 complex64
+  int32_t n_tasks, n_knots, n_tensors, n_steps;
+  int32_t n_vtx, n_medges, n_members, n_factors;
+  int32_t n_tables, n_deps;
+  int32_t n_edges;   // original edges over all knots
+  int32_t tile;      // outputs per tile
+  int64_t o_tasks, o_deps, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
+  int64_t o_medges, o_members, o_factors, o_tables, o_eps, o_comps;
+  int64_t image_bytes;
+  // runtime state (relative to the workspace base)
+  int64_t state_off, state_bytes;
+  int64_t o_tstate;   // TensorState[n_tensors] (relative to state)
+  int64_t o_weights;  // complex128 x_e per original edge, then x_m per merged edge
+  // tensor arena (relative to the workspace base), in complex entries
+  int64_t arena_off, arena_elems;
+  int64_t workspace_bytes;
+};
+
+struct TaskDesc {
+  int32_t kind, knot;
+  int32_t first, count;
+  int32_t flags;
+  int32_t dep_off, n_deps;  // tensor ids whose producers must have finished
+  int32_t sig_off, n_sig;   // tensor ids whose `done` counter this task bumps
+};
+
+struct KnotDesc {
+  double t_re, t_im;        // Jones variable t(q) (Eq. 1)
+  int32_t q;
+  int32_t edge_off, n_edges;      // original edges (global index range)
+  int32_t medge_off, n_medges;    // merged edges
+  int32_t vtx_off, n_vtx;         // vertex tensors
+  int32_t factor_off, n_factors;  // simplification factors
+  int32_t comp_off, n_comps;      // final (scalar) tensor of each component
+  int32_t n_iso;                  // isolated vertices: factor q each
+  int32_t out_slot;               // index into the kn_scalar output array
+  int32_t step_off, n_steps;
+};
+
+struct TensorDesc {
+  int64_t off;     // complex entries from the arena base
+  int32_t size;    // entries
+  int32_t target;  // producer work units (1, or the producing step's tiles)
+};
+
+struct StepDesc {
+  int32_t a, b, c;          // tensor ids: C = A . B
+  int32_t nb, nm, nn, nk;   // batch, rows, cols, contracted extents
+  int32_t tab;              // tables: tAb[nb] tAm[nm] tAk[nk] tBb[nb] tBk[nk] tBn[nn]
+  int32_t n_tiles;          // 0 for steps run inside a serial task
+  int32_t tile;             // outputs per tile (tiled steps)
+};
+
+struct VtxDesc {
+  int32_t tensor;      // tensor id
+  int32_t n_slots;     // neighbour spins (absorbed edges)
+  int32_t slot_off;    // merged-edge id (knot-local) per neighbour slot
+  int32_t keep_center; // 1: the vertex's own spin is the leading index;
+                       // 0: it is private to this tensor and summed at build
+};
+
+struct MEdge {
+  int32_t member_off, n_members;  // original edge ids (knot-local)
+};
+
+struct Factor {
+  int32_t kind, id;
+};
+
+// Per-tensor runtime state.
+struct TensorState {
+  int32_t shift;  // frexp exponent of max(|re|,|im|) over the raw entries
+                  // (INT32_MIN until written / for an all-zero tensor)
+  int32_t done;   // finished producer work units
+  int64_t exp2;   // true tensor = raw * 2^exp2
+};
+
+constexpr int32_t kShiftNone = (-2147483647 - 1);
+
+inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+}  // namespace kn

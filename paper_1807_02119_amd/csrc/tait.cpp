@@ -1,0 +1,182 @@
+// tait.cpp -- knot diagram (PD code) -> signed Tait graph (Sec. II of
+// arXiv:1807.02119).
+//
+// Regions of the diagram are found by walking corners: the wedge at crossing
+// i between slots k and k+1 (counter-clockwise) is corner 4i+k.  Leaving
+// crossing i along slot k, corner 4i+k lies on the left; at the far end of
+// that arc (crossing j, slot p) the same region continues in corner
+// 4j+((p+3)&3).  Regions on the two sides of an arc get opposite colours; the
+// unbounded region is white (Sec. II).  Black regions are the Tait vertices,
+// every crossing joins its two black corners, and the Tait sign is +1 iff the
+// region left of the outgoing over-strand is black.
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace {
+
+// Slot of the outgoing over-arc: b for a positive crossing, d for a negative.
+inline int out_over_slot(int sign) { return sign > 0 ? 1 : 3; }
+
+}  // namespace
+
+extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* signs,
+                                   int32_t outer_arc, int32_t outer_side, kn_tait** out) {
+  if (!out) return KN_E_INVALID;
+  *out = nullptr;
+  if (n < 0 || (n > 0 && !pd) || n > (1 << 26)) return KN_E_INVALID;
+  if (outer_side != 0 && outer_side != 1) return KN_E_INVALID;
+  kn_tait* g = new (std::nothrow) kn_tait();
+  if (!g) return KN_E_NOMEM;
+  if (n == 0) {
+    // a single circle: its inside is the one black region
+    g->n_vertices = 1;
+    *out = g;
+    return KN_OK;
+  }
+  if (n == 1 && !signs) {
+    delete g;
+    return KN_E_INVALID;
+  }
+  const int32_t m = 2 * n;
+  try {
+    // every arc label used exactly twice; record its two slots
+    std::vector<int32_t> first(m, -1), second(m, -1);
+    for (int32_t s = 0; s < 4 * n; ++s) {
+      int32_t lab = pd[s];
+      if (lab < 0 || lab >= m) { delete g; return KN_E_INVALID; }
+      if (first[lab] < 0) first[lab] = s;
+      else if (second[lab] < 0) second[lab] = s;
+      else { delete g; return KN_E_INVALID; }
+    }
+    for (int32_t lab = 0; lab < m; ++lab)
+      if (second[lab] < 0) { delete g; return KN_E_INVALID; }
+
+    // crossing signs and orientation consistency: each label must be the
+    // outgoing arc of one slot and the incoming arc of another
+    g->twist.resize(n);
+    std::vector<int32_t> n_in(m, 0), n_out(m, 0);
+    for (int32_t i = 0; i < n; ++i) {
+      const int32_t* x = pd + 4 * i;
+      int sg;
+      if (signs) {
+        sg = signs[i] > 0 ? 1 : (signs[i] < 0 ? -1 : 0);
+        if (!sg) { delete g; return KN_E_INVALID; }
+      } else {
+        bool pos = (x[1] - x[3] - 1) % m == 0;
+        bool neg = (x[3] - x[1] - 1) % m == 0;
+        if (pos == neg) { delete g; return KN_E_INVALID; }
+        sg = pos ? 1 : -1;
+      }
+      if (((x[2] - x[0] - 1) % m + m) % m != 0) { delete g; return KN_E_INVALID; }
+      int oo = out_over_slot(sg), oi = oo ^ 2;
+      if ((((x[oo] - x[oi] - 1) % m) + m) % m != 0 && n > 1) { delete g; return KN_E_INVALID; }
+      g->twist[i] = (int8_t)sg;
+      n_in[x[0]]++;
+      n_out[x[2]]++;
+      n_in[x[oi]]++;
+      n_out[x[oo]]++;
+    }
+    for (int32_t lab = 0; lab < m; ++lab)
+      if (n_in[lab] != 1 || n_out[lab] != 1) { delete g; return KN_E_INVALID; }
+
+    // region tracing over corners
+    const int32_t nc = 4 * n;
+    std::vector<int32_t> region(nc, -1);
+    int32_t nreg = 0;
+    for (int32_t c0 = 0; c0 < nc; ++c0) {
+      if (region[c0] >= 0) continue;
+      int32_t c = c0;
+      while (region[c] < 0) {
+        region[c] = nreg;
+        int32_t lab = pd[c];  // slot c: leave along it
+        int32_t far = (first[lab] == c) ? second[lab] : first[lab];
+        c = (far & ~3) | ((far + 3) & 3);
+      }
+      if (c != c0) { delete g; return KN_E_INVALID; }
+      ++nreg;
+    }
+    if (nreg != n + 2) { delete g; return KN_E_INVALID; }  // not a plane diagram
+
+    // two-colouring by breadth-first search across arcs
+    std::vector<std::vector<int32_t>> adj(nreg);
+    for (int32_t c = 0; c < nc; ++c) {
+      int32_t other = (c & ~3) | ((c + 3) & 3);  // across slot c
+      adj[region[c]].push_back(region[other]);
+      adj[region[other]].push_back(region[c]);
+    }
+    int32_t arc = outer_arc < 0 ? 0 : outer_arc;
+    if (arc >= m) { delete g; return KN_E_INVALID; }
+    // the slot where `arc` leaves its crossing
+    int32_t leave = -1;
+    for (int32_t s : {first[arc], second[arc]}) {
+      int32_t i = s >> 2, k = s & 3;
+      if (k == 2 || k == out_over_slot(g->twist[i])) leave = s;
+    }
+    if (leave < 0) { delete g; return KN_E_INVALID; }
+    int32_t outer_corner = outer_side == 0 ? leave : ((leave & ~3) | ((leave + 3) & 3));
+    std::vector<int8_t> colour(nreg, -1);  // 0 white, 1 black
+    std::vector<int32_t> queue;
+    queue.reserve(nreg);
+    colour[region[outer_corner]] = 0;
+    queue.push_back(region[outer_corner]);
+    for (size_t h = 0; h < queue.size(); ++h) {
+      int32_t r = queue[h];
+      for (int32_t s : adj[r]) {
+        if (colour[s] < 0) {
+          colour[s] = (int8_t)(1 - colour[r]);
+          queue.push_back(s);
+        } else if (colour[s] == colour[r]) {
+          delete g;
+          return KN_E_INVALID;
+        }
+      }
+    }
+    std::vector<int32_t> vid(nreg, -1);
+    int32_t nv = 0;
+    for (int32_t r = 0; r < nreg; ++r)
+      if (colour[r] == 1) vid[r] = nv++;
+    g->n_vertices = nv;
+    g->uv.resize(2 * n);
+    g->eps.resize(n);
+    int32_t w = 0, tau = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t oo = out_over_slot(g->twist[i]);
+      bool left_black = colour[region[4 * i + oo]] == 1;
+      // the black corners are the odd ones (1, 3) or the even ones (0, 2)
+      int32_t k0 = left_black ? 1 : 0;
+      g->uv[2 * i] = vid[region[4 * i + k0]];
+      g->uv[2 * i + 1] = vid[region[4 * i + k0 + 2]];
+      g->eps[i] = (int8_t)(left_black ? 1 : -1);
+      w += g->twist[i];
+      tau += g->eps[i];
+    }
+    g->writhe = w;
+    g->tau = tau;
+  } catch (const std::bad_alloc&) {
+    delete g;
+    return KN_E_NOMEM;
+  }
+  *out = g;
+  return KN_OK;
+}
+
+extern "C" kn_status kn_tait_info(const kn_tait* g, int32_t* n_vertices, int32_t* n_edges,
+                                  int32_t* writhe, int32_t* tait_number) {
+  if (!g) return KN_E_INVALID;
+  if (n_vertices) *n_vertices = g->n_vertices;
+  if (n_edges) *n_edges = (int32_t)g->eps.size();
+  if (writhe) *writhe = g->writhe;
+  if (tait_number) *tait_number = g->tau;
+  return KN_OK;
+}
+
+extern "C" kn_status kn_tait_edges(const kn_tait* g, int32_t* uv, int8_t* eps) {
+  if (!g) return KN_E_INVALID;
+  if (uv && !g->uv.empty()) std::memcpy(uv, g->uv.data(), g->uv.size() * sizeof(int32_t));
+  if (eps && !g->eps.empty()) std::memcpy(eps, g->eps.data(), g->eps.size());
+  return KN_OK;
+}
+
+extern "C" void kn_tait_free(kn_tait* g) { delete g; }

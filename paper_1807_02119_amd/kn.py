@@ -1,0 +1,378 @@
+"""Python binding of libkn (ctypes).  Argument marshalling only: every step of
+the evaluation runs in the C++ planner and the HIP kernels of libkn.so.
+
+PyTorch supplies device memory (workspaces, outputs, couplings) and streams.
+The names mirror the C ABI in ``include/kn.h``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkn.so")
+
+KN_OK = 0
+STATUS = {0: "KN_OK", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_BUDGET",
+          -4: "KN_E_DEVICE", -5: "KN_E_NUMERIC", -6: "KN_E_UNSUPPORTED"}
+
+
+class KnError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("simplify", ctypes.c_int32), ("jones_only", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
+                ("big_step_macs_log2", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("n_vertex_tensors", ctypes.c_int32),
+                ("log2_max_entries", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64),
+                ("image_bytes", ctypes.c_uint64), ("delta_h_paper", ctypes.c_int32),
+                ("n_edges_simplified", ctypes.c_int32), ("n_vertices_simplified", ctypes.c_int32),
+                ("n_tasks", ctypes.c_int32), ("n_components", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
+                ("n_tasks", ctypes.c_int32), ("n_knots", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("total_edges", ctypes.c_int64), ("grid", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Scalar(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double), ("exp2", ctypes.c_int64)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+PI32 = ctypes.POINTER(ctypes.c_int32)
+PI8 = ctypes.POINTER(ctypes.c_int8)
+PD = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "kn_build_tait": (I32, [I32, PI32, PI8, I32, I32, ctypes.POINTER(P)]),
+    "kn_tait_info": (I32, [P, PI32, PI32, PI32, PI32]),
+    "kn_tait_edges": (I32, [P, PI32, PI8]),
+    "kn_tait_free": (None, [P]),
+    "kn_plan_create": (I32, [P, I32, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]),
+    "kn_plan_info": (I32, [P, ctypes.POINTER(PlanStats)]),
+    "kn_plan_steps": (I32, [P, PI32]),
+    "kn_plan_image": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+    "kn_plan_free": (None, [P]),
+    "kn_contract": (I32, [P, P, P, ctypes.c_size_t, P, P]),
+    "kn_backward_workspace": (I32, [P, ctypes.POINTER(ctypes.c_uint64)]),
+    "kn_contract_backward": (I32, [P, P, P, ctypes.c_size_t, P, P, P]),
+    "kn_jones": (I32, [I32, P, ctypes.POINTER(Scalar), PD, PD, PD, PD]),
+    "kn_jones_variable": (I32, [I32, PD, PD]),
+    "kn_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
+    "kn_batch_info": (I32, [P, ctypes.POINTER(BatchStats)]),
+    "kn_batch_edge_offset": (I32, [P, I32, ctypes.POINTER(ctypes.c_int64)]),
+    "kn_batch_upload": (I32, [P, P, ctypes.c_size_t, P]),
+    "kn_batch_contract": (I32, [P, P, P, ctypes.c_size_t, P, P]),
+    "kn_batch_set_grid": (I32, [P, I32]),
+    "kn_batch_image": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+    "kn_batch_free": (None, [P]),
+    "kn_status_string": (ctypes.c_char_p, [I32]),
+    "kn_version": (ctypes.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libkn.so (building it first if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                from . import build
+                build.build()
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != KN_OK:
+        raise KnError(code, where)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(PI32)
+
+
+class Tait:
+    """Signed Tait graph of a PD code (kn_build_tait)."""
+
+    def __init__(self, pd, signs=None, outer_arc: int = -1, outer_side: int = 0):
+        L = lib()
+        pd = np.ascontiguousarray(np.asarray(pd, dtype=np.int32).reshape(-1))
+        n = pd.size // 4
+        sg = None
+        if signs is not None:
+            sg = np.ascontiguousarray(np.asarray(signs, dtype=np.int8))
+        h = P()
+        rc = L.kn_build_tait(n, pd.ctypes.data_as(PI32) if n else None,
+                             sg.ctypes.data_as(PI8) if sg is not None else None,
+                             outer_arc, outer_side, ctypes.byref(h))
+        _check(rc, "kn_build_tait")
+        self._h = h
+        nv, ne, w, t = I32(), I32(), I32(), I32()
+        _check(L.kn_tait_info(h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(w),
+                              ctypes.byref(t)), "kn_tait_info")
+        self.n_vertices, self.n_edges, self.writhe, self.tait_number = nv.value, ne.value, w.value, t.value
+
+    def edges(self):
+        uv = np.zeros(2 * self.n_edges, np.int32)
+        eps = np.zeros(self.n_edges, np.int8)
+        _check(lib().kn_tait_edges(self._h, uv.ctypes.data_as(PI32), eps.ctypes.data_as(PI8)),
+               "kn_tait_edges")
+        return uv.reshape(-1, 2), eps
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.kn_tait_free(h)
+            self._h = None
+
+
+class Plan:
+    """Contraction plan for one knot at one q (kn_plan_create)."""
+
+    def __init__(self, tait: Tait, q: int, strategy=0, precision=0, simplify=None,
+                 jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
+                 allow_budget=False):
+        L = lib()
+        if simplify is None:
+            simplify = 3 if jones_only else 1
+        o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
+                     tile_outputs, big_step_macs_log2)
+        h = P()
+        rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
+        self._h = h if h.value else None
+        self.status = rc
+        if rc != KN_OK and not (allow_budget and rc == -3 and h.value):
+            if h.value:
+                L.kn_plan_free(h)
+                self._h = None
+            raise KnError(rc, "kn_plan_create")
+        self.tait = tait
+        self.q = q
+        self.precision = precision
+        self.jones_only = jones_only
+        st = PlanStats()
+        _check(L.kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
+        self.stats = st.as_dict()
+
+    @property
+    def workspace_bytes(self):
+        return int(self.stats["workspace_bytes"])
+
+    def steps(self):
+        n = self.stats["n_steps"]
+        ab = np.zeros(2 * max(n, 1), np.int32)
+        _check(lib().kn_plan_steps(self._h, ab.ctypes.data_as(PI32)), "kn_plan_steps")
+        return ab[:2 * n].reshape(-1, 2)
+
+    def image(self) -> bytes:
+        """Copy of the plan's device image (kn_plan_image)."""
+        d, n = P(), ctypes.c_size_t()
+        _check(lib().kn_plan_image(self._h, ctypes.byref(d), ctypes.byref(n)), "kn_plan_image")
+        return ctypes.string_at(d, n.value) if n.value else b""
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.kn_plan_free(h)
+            self._h = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def scalars_from_device(z):
+    """(n, 3) float64 device tensor of kn_scalar -> list of (complex mantissa, exp2)."""
+    a = z.detach().cpu().numpy().reshape(-1, 3)
+    ex = a.view(np.int64)[:, 2]
+    return [(complex(a[i, 0], a[i, 1]), int(ex[i])) for i in range(a.shape[0])]
+
+
+def alloc_scalars(n, device="cuda"):
+    torch = _torch()
+    return torch.empty((n, 3), dtype=torch.float64, device=device)
+
+
+def alloc_workspace(nbytes, device="cuda"):
+    torch = _torch()
+    return torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned_ptr(ws):
+    p = ws.data_ptr()
+    return (p + 255) & ~255, ws.numel() - ((p + 255 & ~255) - p)
+
+
+def contract(plan: Plan, J=None, workspace=None, stream=None, z=None):
+    """Z of the plan's knot on the GPU (kn_contract).  Returns the (1, 3)
+    float64 device tensor holding the kn_scalar; see scalars_from_device."""
+    if workspace is None:
+        workspace = alloc_workspace(plan.workspace_bytes)
+    if z is None:
+        z = alloc_scalars(1)
+    ptr, nbytes = _aligned_ptr(workspace)
+    jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+    rc = lib().kn_contract(plan._h, jp, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream),
+                           ctypes.c_void_p(z.data_ptr()))
+    _check(rc, "kn_contract")
+    return z
+
+
+def backward_workspace_bytes(plan: Plan) -> int:
+    v = ctypes.c_uint64()
+    _check(lib().kn_backward_workspace(plan._h, ctypes.byref(v)), "kn_backward_workspace")
+    return int(v.value)
+
+
+def contract_backward(plan: Plan, J=None, workspace=None, stream=None, z=None, grad=None):
+    """d log Z / d J_e for every original edge (kn_contract_backward).
+    Returns (z, grad) device tensors; grad is (n_edges, 2) float64."""
+    torch = _torch()
+    if workspace is None:
+        workspace = alloc_workspace(backward_workspace_bytes(plan))
+    if z is None:
+        z = alloc_scalars(1)
+    if grad is None:
+        grad = torch.empty((plan.tait.n_edges, 2), dtype=torch.float64, device="cuda")
+    ptr, nbytes = _aligned_ptr(workspace)
+    jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+    rc = lib().kn_contract_backward(plan._h, jp, ctypes.c_void_p(ptr), nbytes,
+                                    _stream_ptr(stream), ctypes.c_void_p(z.data_ptr()),
+                                    ctypes.c_void_p(grad.data_ptr()))
+    _check(rc, "kn_contract_backward")
+    return z, grad
+
+
+def jones(q: int, tait: Tait, z_mant: complex, z_exp2: int):
+    """V = A(q) Z (kn_jones).  Returns (V, log2|V|, arg V)."""
+    s = Scalar(z_mant.real, z_mant.imag, z_exp2)
+    vr, vi, l2, ar = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().kn_jones(q, tait._h, ctypes.byref(s), ctypes.byref(vr), ctypes.byref(vi),
+                          ctypes.byref(l2), ctypes.byref(ar)), "kn_jones")
+    return complex(vr.value, vi.value), l2.value, ar.value
+
+
+def jones_variable(q: int) -> complex:
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().kn_jones_variable(q, ctypes.byref(a), ctypes.byref(b)), "kn_jones_variable")
+    return complex(a.value, b.value)
+
+
+class Batch:
+    """Many plans contracted in one persistent launch (kn_batch_*)."""
+
+    def __init__(self, plans):
+        L = lib()
+        self.plans = list(plans)
+        arr = (P * len(self.plans))(*[p._h for p in self.plans])
+        h = P()
+        _check(L.kn_batch_create(arr, len(self.plans), ctypes.byref(h)), "kn_batch_create")
+        self._h = h
+        st = BatchStats()
+        _check(L.kn_batch_info(h, ctypes.byref(st)), "kn_batch_info")
+        self.stats = st.as_dict()
+        self.workspace = None
+
+    @property
+    def workspace_bytes(self):
+        return int(self.stats["workspace_bytes"])
+
+    def edge_offset(self, i):
+        v = ctypes.c_int64()
+        _check(lib().kn_batch_edge_offset(self._h, i, ctypes.byref(v)), "kn_batch_edge_offset")
+        return int(v.value)
+
+    def image(self) -> bytes:
+        d, n = P(), ctypes.c_size_t()
+        _check(lib().kn_batch_image(self._h, ctypes.byref(d), ctypes.byref(n)), "kn_batch_image")
+        return ctypes.string_at(d, n.value)
+
+    def set_grid(self, grid: int):
+        _check(lib().kn_batch_set_grid(self._h, grid), "kn_batch_set_grid")
+
+    def upload(self, workspace=None, stream=None):
+        if workspace is None:
+            workspace = alloc_workspace(self.workspace_bytes)
+        ptr, nbytes = _aligned_ptr(workspace)
+        _check(lib().kn_batch_upload(self._h, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream)),
+               "kn_batch_upload")
+        self.workspace = workspace
+        return workspace
+
+    def contract(self, J=None, stream=None, z=None):
+        if self.workspace is None:
+            self.upload(stream=stream)
+        if z is None:
+            z = alloc_scalars(len(self.plans))
+        ptr, nbytes = _aligned_ptr(self.workspace)
+        jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+        _check(lib().kn_batch_contract(self._h, jp, ctypes.c_void_p(ptr), nbytes,
+                                       _stream_ptr(stream), ctypes.c_void_p(z.data_ptr())),
+               "kn_batch_contract")
+        return z
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.kn_batch_free(h)
+            self._h = None
+
+
+def status_string(code: int) -> str:
+    return lib().kn_status_string(code).decode()
+
+
+def version() -> str:
+    return lib().kn_version().decode()
+
+
+def z_to_log(z_mant: complex, z_exp2: int):
+    """(log2|Z|, arg Z) of a mantissa/exponent pair."""
+    if z_mant == 0:
+        return -math.inf, 0.0
+    return math.log2(abs(z_mant)) + z_exp2, math.atan2(z_mant.imag, z_mant.real)

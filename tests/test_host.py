@@ -1,0 +1,254 @@
+"""Host-side checks of libkn (no GPU): the C ABI loads and exports every
+declared symbol, the C++ Tait builder agrees with the oracle's, the planner's
+device program evaluates to the oracle's Z when executed by the CPU model of
+the engine, Eq. 4 normalisation, and error handling."""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import jones as ojones
+from oracle import potts
+from paper_1807_02119_amd import gen, kn
+from tests import image_model
+from tests.oracle_helpers import oracle_tait, oracle_z, rel_err
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "kn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kn_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = kn.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(kn.EXPORTED)
+    assert "gfx950" in kn.version()
+
+
+def _same_graph_up_to_relabelling(t, o):
+    """C++ and oracle Tait graphs are equal up to a renaming of the vertices.
+
+    Edges are labelled (edge k is crossing k) in both, so a vertex is named by
+    the set of edges incident to it; the two graphs agree iff these sets do."""
+    uv, eps = t.edges()
+    assert t.n_vertices == o.n_vertices
+    assert list(eps) == list(o.eps)
+
+    def signature(nv, edges):
+        inc = [set() for _ in range(nv)]
+        for k, (a, b) in enumerate(edges):
+            inc[a].add(k)
+            inc[b].add(k)
+        return sorted(tuple(sorted(x)) for x in inc)
+
+    return signature(t.n_vertices, [tuple(e) for e in uv]) == signature(o.n_vertices, o.edges)
+
+
+@pytest.mark.parametrize("outer_side", [0, 1])
+def test_tait_graph_matches_oracle(outer_side):
+    ds = [gen.trefoil(), gen.figure_eight()] + [gen.lattice_knot((41, k), 3, 150) for k in range(25)]
+    rng = np.random.default_rng(2)
+    ds += [gen.random_grid_diagram(rng, 9) for _ in range(5)]
+    for d in ds:
+        if d.n < 2:
+            continue
+        t = kn.Tait(d.pd, outer_side=outer_side)
+        o = oracle_tait(d, outer_left=(outer_side == 0))
+        assert (t.writhe, t.tait_number) == (o.writhe, o.tait_number)
+        assert _same_graph_up_to_relabelling(t, o)
+        # same partition function on the two edge lists (q = 3)
+        uv, eps = t.edges()
+        x = potts.jones_weights(eps, ojones.t_of_q(3))
+        z1 = potts.partition_function(t.n_vertices, [tuple(e) for e in uv], x, 3)
+        z2 = potts.partition_function(o.n_vertices, o.edges, x, 3)
+        assert rel_err(z1[0] * 2.0 ** (z1[1] - z2[1]), z2[0]) < 1e-12
+
+
+def test_tait_single_crossing_and_unknot():
+    for over_first in (False, True):
+        for s in (1, -1):
+            d = gen.add_kink(gen.UNKNOT, 0, over_first, s)
+            t = kn.Tait(d.pd, d.signs)
+            o = oracle_tait(d)
+            assert (t.n_vertices, t.writhe, t.tait_number) == (o.n_vertices, o.writhe, o.tait_number)
+    t = kn.Tait(np.zeros((0, 4), np.int32))
+    assert (t.n_vertices, t.n_edges, t.writhe, t.tait_number) == (1, 0, 0, 0)
+
+
+def test_tait_rejects_malformed_codes():
+    good = gen.trefoil().pd
+    with pytest.raises(kn.KnError) as e:
+        kn.Tait(np.array([[0, 1, 2, 3]]))  # one crossing without signs
+    assert e.value.code == -1
+    bad = good.copy()
+    bad[0, 0] = 99  # label out of range
+    with pytest.raises(kn.KnError):
+        kn.Tait(bad)
+    bad = good.copy()
+    bad[0, 1], bad[0, 3] = bad[0, 3], bad[0, 1]  # label used twice on one side
+    bad[1, 1] = bad[0, 1]
+    with pytest.raises(kn.KnError):
+        kn.Tait(bad)
+    # a non-planar code: swap two arcs between crossings
+    bad = good.copy()
+    bad[0, 1], bad[1, 1] = bad[1, 1], bad[0, 1]
+    with pytest.raises(kn.KnError):
+        kn.Tait(bad)
+
+
+def _model_z(plan, J=None):
+    (zm, ze), = image_model.run(plan.image(), J)
+    return zm, ze
+
+
+def _check_model(d, q, **kw):
+    t = kn.Tait(d.pd, d.signs if d.n == 1 else None)
+    p = kn.Plan(t, q, **kw)
+    zm, ze = _model_z(p)
+    tg, m, e = oracle_z(d, q)
+    assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, q, kw)
+
+
+def test_plan_model_tiny_config():
+    for d, q in gen.config_knots("tiny", 0):
+        _check_model(d, q)
+
+
+@pytest.mark.parametrize("q", [2, 3, 5, 6, 8])
+def test_plan_model_many_q(q):
+    for k in range(6):
+        _check_model(gen.lattice_knot((43, k), 30, 120), q)
+
+
+def test_plan_model_tiled_and_options():
+    for k in range(4):
+        d = gen.lattice_knot((44, k), 60, 160)
+        for kw in (dict(big_step_macs_log2=4, tile_outputs=8),
+                   dict(big_step_macs_log2=6, tile_outputs=100),
+                   dict(simplify=0, jones_only=True),
+                   dict(simplify=1, jones_only=True),
+                   dict(simplify=1, jones_only=False),
+                   dict(strategy=1)):
+            _check_model(d, 3, **kw)
+
+
+def test_plan_model_general_couplings():
+    rng = np.random.default_rng(7)
+    for k in range(5):
+        d = gen.lattice_knot((45, k), 20, 90)
+        t = kn.Tait(d.pd)
+        p = kn.Plan(t, 3, jones_only=False)
+        J = rng.normal(scale=0.5, size=2 * t.n_edges)
+        zm, ze = _model_z(p, J)
+        uv, eps = t.edges()
+        x = np.exp(J[0::2] + 1j * J[1::2])
+        m, e = potts.partition_function(t.n_vertices, [tuple(a) for a in uv], x, 3)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+
+
+def test_batch_image_model():
+    knots = gen.config_knots("batched", 0, count=24)
+    plans = [kn.Plan(kn.Tait(d.pd), q, big_step_macs_log2=(8 if i % 3 == 0 else 0))
+             for i, (d, q) in enumerate(knots)]
+    b = kn.Batch(plans)
+    out = image_model.run(b.image())
+    for (d, q), (zm, ze) in zip(knots, out):
+        tg, m, e = oracle_z(d, q)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+    assert b.edge_offset(0) == 0
+    assert b.edge_offset(1) == plans[0].tait.n_edges
+
+
+def test_plan_statistics_and_invariants():
+    for k in range(8):
+        d = gen.lattice_knot((46, k), 100, 300)
+        t = kn.Tait(d.pd)
+        p = kn.Plan(t, 3)
+        s = p.stats
+        im = image_model.Image(p.image())
+        # every step is a pairwise contraction of live tensors; each consumed once
+        steps = p.steps()
+        assert len(steps) == s["n_steps"]
+        consumed = set()
+        n_vt = s["n_vertex_tensors"]
+        for i, (a, b) in enumerate(steps):
+            assert a != b and a < n_vt + i and b < n_vt + i
+            assert a not in consumed and b not in consumed
+            consumed |= {a, b}
+        # flops and bytes add up over the steps
+        fl = sum(8.0 * int(x["nb"]) * int(x["nm"]) * int(x["nn"]) * int(x["nk"]) for x in im.steps)
+        assert fl == pytest.approx(s["flops"])
+        by = sum(16.0 * (int(im.tensors[x["a"]]["size"]) + int(im.tensors[x["b"]]["size"]) +
+                         int(im.tensors[x["c"]]["size"])) for x in im.steps)
+        assert by == pytest.approx(s["bytes"])
+        assert s["n_components"] >= 1
+        assert s["max_rank"] <= 30
+        assert s["log2_max_entries"] == pytest.approx(
+            max(math.log2(int(x["size"])) for x in im.tensors))
+
+
+def test_plan_errors():
+    t = kn.Tait(gen.trefoil().pd)
+    for q in (0, 1, 9, 100):
+        with pytest.raises(kn.KnError) as e:
+            kn.Plan(t, q)
+        assert e.value.code == -6
+    with pytest.raises(kn.KnError) as e:
+        kn.Plan(t, 3, simplify=3, jones_only=False)  # R-II needs Jones couplings
+    assert e.value.code == -1
+    d = gen.lattice_knot((47, 0), 150, 250)
+    big = kn.Tait(d.pd)
+    with pytest.raises(kn.KnError) as e:
+        kn.Plan(big, 3, mem_budget_bytes=1024)
+    assert e.value.code == -3
+    p = kn.Plan(big, 3, mem_budget_bytes=1024, allow_budget=True)
+    assert p.stats["workspace_bytes"] > 1024
+
+
+def test_jones_normalisation_matches_oracle():
+    rng = np.random.default_rng(9)
+    t = kn.Tait(gen.figure_eight().pd)
+    for q in range(2, 9):
+        for _ in range(5):
+            zm = complex(rng.uniform(0.5, 1) * rng.choice([-1, 1]), rng.uniform(-1, 1))
+            ze = int(rng.integers(-300, 300))
+            v, l2, ar = kn.jones(q, t, zm, ze)
+            vo, l2o = ojones.jones_value(q, t.n_vertices, t.writhe, t.tait_number, zm, ze)
+            assert abs(l2 - l2o) < 1e-11
+            ph = ar - math.atan2(vo.imag, vo.real) if vo != 0 else 0
+            assert abs(math.remainder(ph, 2 * math.pi)) < 1e-11
+    # t(q) of Eq. 1
+    for q in range(2, 9):
+        assert abs(kn.jones_variable(q) - ojones.t_of_q(q)) < 1e-14
+    with pytest.raises(kn.KnError):
+        kn.jones_variable(9)
+    with pytest.raises(kn.KnError) as e:
+        kn.jones(3, t, complex(math.nan, 0), 0)
+    assert e.value.code == -5
+
+
+def test_jones_large_knot_phase_exact():
+    # phase reduction in integers: same V for huge (n_v, w, tau) offsets that
+    # differ by a full period of the phase
+    t = kn.Tait(gen.trefoil().pd)
+    v, l2, ar = kn.jones(3, t, 0.5 + 0j, 0)
+    vo, l2o = ojones.jones_value(3, t.n_vertices, t.writhe, t.tait_number, 0.5 + 0j, 0)
+    assert abs(v - vo) < 1e-14 * abs(vo) + 1e-300
+
+
+def test_status_strings():
+    for c in range(-6, 1):
+        assert kn.status_string(c)
