@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Throughput of exact Jones-polynomial evaluation V_K(t(3)) on one MI355X.
+
+Workload: seeded lattice-walk knot diagrams with 200-600 raw crossings
+(``paper_1807_02119_amd.gen``, workload ``q3_200_600``), q = 3
+(t = e^{i pi/3}), complex128.  One step = the whole pipeline for one batch of
+knots: signed Tait graphs and plans on the host thread pool (kn_plan_many),
+the batch device program (kn_batch_create + upload), the persistent GPU
+contraction of every tensor network (kn_batch_contract) and the
+normalisation V = A(q) Z (kn_jones_many).  The PD codes (the input) are
+generated before timing.
+
+Printed: one JSON line.  ``value`` is knots/s of the whole step; the line
+also carries the GPU contraction alone (events around the persistent
+kernel), the complex64 path with its error against complex128, the
+one-knot-per-call path, the roofline of the contraction kernel and the CPU
+oracle timed on a bounded sample of the same knots.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "knots/s + achieved TFLOP/s for exact Z, q=3, 200–600 crossings; FP32 vs FP64"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256, help="knots per step")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0, help="host planning threads (0 = all)")
+    ap.add_argument("--kernel-reps", type=int, default=20,
+                    help="launches of the contraction kernel timed for the roofline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget for the CPU oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the one-knot-per-call comparison")
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("engine.hip", "program.h"):
+        with open(os.path.join(ROOT, "paper_1807_02119_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "engine_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = d.get(kernel)
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "knots are independent and would shard across GPUs with no communication, "
+              "but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1807_02119_amd import gen, kn
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    kn.lib()
+    q = 3
+    B = args.batch
+    knots = gen.config_knots("q3_200_600", args.seed, count=B)
+    pds = [np.ascontiguousarray(d.pd, dtype=np.int32) for d, _ in knots]
+    ncross = [d.n for d, _ in knots]
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- pipeline
+    state = {}
+
+    def step(precision=0):
+        taits, plans = kn.plan_many(pds, q, n_threads=args.threads, precision=precision)
+        batch = kn.Batch(plans)
+        need = batch.workspace_bytes
+        ws = state.get(("ws", precision))
+        if ws is None or ws.numel() < need + 256:
+            ws = kn.alloc_workspace(need)
+            state[("ws", precision)] = ws
+        z = state.get(("z", precision))
+        if z is None:
+            z = kn.alloc_scalars(B)
+            state[("z", precision)] = z
+        batch.upload(ws, stream)
+        batch.contract(stream=stream, z=z)
+        zh = z.cpu().numpy()  # synchronises
+        v, l2, ar = kn.jones_many(q, taits, zh)
+        return taits, plans, batch, zh, v, l2, ar
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        taits, plans, batch, zh, v, l2, ar = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms_step = 1e3 * float(np.mean(times))
+    value = B / (ms_step / 1e3)
+
+    # ---------------------------------------------------------------- GPU contraction alone
+    def time_kernel(batch, reps):
+        z = kn.alloc_scalars(B)
+        batch.contract(stream=stream, z=z)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            batch.contract(stream=stream, z=z)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, z
+
+    ms_gpu, z64 = time_kernel(batch, args.kernel_reps)
+    st = batch.stats
+    flops, bytes_alg = st["flops"], st["bytes"]
+    zh64 = z64.cpu().numpy()
+    assert np.array_equal(zh64, zh), "repeated launches must give identical bits"
+
+    # planning-only and GPU-only breakdown of one step
+    t0 = time.perf_counter()
+    kn.plan_many(pds, q, n_threads=args.threads)
+    ms_plan = 1e3 * (time.perf_counter() - t0)
+
+    roofline_gbs = bytes_alg / (ms_gpu * 1e-3) / 1e9
+    rec = measured_traffic("engine<double>")
+    traffic = None
+    if rec is not None:
+        traffic = rec["fetch_bytes"] + rec["write_bytes"]
+    roofline = {
+        "kernel": "kn::engine<double> (persistent contraction, batch launch)",
+        "bound": "hbm",
+        "achieved": round(roofline_gbs, 3),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": roofline_gbs / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": bytes_alg,
+        "flops_per_launch": flops,
+        "avg_launch_ms": ms_gpu,
+        "achieved_tflops": flops / (ms_gpu * 1e-3) / 1e12,
+        "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "knots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "q3_200_600: seeded lattice-walk knots, 200-600 raw crossings, q=3, "
+                        "complex128, whole pipeline (Tait graph, plan, device program, "
+                        "persistent GPU contraction, V = A Z) per batch",
+            "q": q,
+            "knots_per_step": B,
+            "crossings_min": int(min(ncross)),
+            "crossings_max": int(max(ncross)),
+            "crossings_mean": float(np.mean(ncross)),
+            "seed": args.seed,
+        },
+        "achieved_tflops": flops / (ms_step * 1e-3) / 1e12,
+        "host_plan_ms": ms_plan,
+        "gpu_contract": {
+            "ms_per_batch": ms_gpu,
+            "knots_per_s": B / (ms_gpu * 1e-3),
+            "tflops": flops / (ms_gpu * 1e-3) / 1e12,
+            "n_tasks": st["n_tasks"],
+        },
+        "roofline": roofline,
+    }
+
+    # ---------------------------------------------------------------- FP32 path
+    def rel_errs(za, zb):
+        ea = za.view(np.int64)[:, 2]
+        eb = zb.view(np.int64)[:, 2]
+        ma = za[:, 0] + 1j * za[:, 1]
+        mb = zb[:, 0] + 1j * zb[:, 1]
+        return np.abs(ma * np.exp2((ea - eb).astype(np.float64)) - mb) / np.abs(mb)
+
+    if not args.no_fp32:
+        for _ in range(max(1, args.warmup)):
+            step(precision=1)
+        t32 = []
+        for _ in range(max(1, args.steps // 2)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            taits32, plans32, batch32, zh32, v32, _, _ = step(precision=1)
+            t32.append(time.perf_counter() - t0)
+        ms32, _ = time_kernel(batch32, args.kernel_reps)
+        err = rel_errs(zh32, zh)
+        out["fp32"] = {
+            "dtype": "f32",
+            "knots_per_s": B / float(np.mean(t32)),
+            "gpu_contract_ms": ms32,
+            "gpu_knots_per_s": B / (ms32 * 1e-3),
+            "gpu_speedup_vs_fp64": ms_gpu / ms32,
+            "tflops": batch32.stats["flops"] / (ms32 * 1e-3) / 1e12,
+            "rel_err_vs_fp64_max": float(err.max()),
+            "rel_err_vs_fp64_median": float(np.median(err)),
+        }
+
+    # ---------------------------------------------------------------- one knot per call
+    if not args.no_single:
+        ws = kn.alloc_workspace(max(p.workspace_bytes for p in plans))
+        z1 = kn.alloc_scalars(1)
+        for p in plans[:4]:
+            kn.contract(p, workspace=ws, stream=stream, z=z1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in plans:
+            kn.contract(p, workspace=ws, stream=stream, z=z1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["one_at_a_time"] = {
+            "knots_per_s": B / dt,
+            "ms_per_knot": 1e3 * dt / B,
+            "batched_gpu_speedup": (dt * 1e3) / ms_gpu,
+        }
+
+    # ---------------------------------------------------------------- CPU oracle baseline
+    if not args.no_cpu_baseline:
+        from oracle import diagram, jones, potts
+
+        t_cpu = 0.0
+        n_done = 0
+        worst = 0.0
+        for i, (d, _) in enumerate(knots):
+            t0 = time.perf_counter()
+            tg = diagram.tait_graph(d.pd)
+            x = potts.jones_weights(tg.eps, jones.t_of_q(q))
+            mo, eo = potts.partition_function(tg.n_vertices, tg.edges, x, q)
+            jones.jones_value(q, tg.n_vertices, tg.writhe, tg.tait_number, mo, eo)
+            t_cpu += time.perf_counter() - t0
+            n_done += 1
+            m = complex(zh[i, 0], zh[i, 1])
+            e = int(zh.view(np.int64)[i, 2])
+            worst = max(worst, abs(m * 2.0 ** (e - eo) - mo) / abs(mo))
+            if t_cpu >= args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {
+            "value": n_done / t_cpu,
+            "unit": "knots/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {n_done} of the {B} knots of the step (same seed), numpy "
+                      f"complex128 min-fill variable elimination, single thread, "
+                      f"{t_cpu:.1f} s",
+            "gpu_vs_oracle_max_rel_err": worst,
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,9 +100,14 @@ void kn_tait_free(kn_tait* g);
  * Planning: simplification, absorption, contraction order, memory layout.
  *
  * strategy   0: greedy pairwise order minimising size(C) - size(A) - size(B)
- *               over tensors indexed by spins (default);
+ *               over tensors indexed by spins;
  *            1: greedy by the rank of the result (the paper's "cheapest
  *               contraction in terms of the resulting degree");
+ *            2: variable elimination in min-fill order, each spin's holders
+ *               contracted pairwise, smallest first;
+ *            3: auto (default) -- plans 0 and 2 are both built and the one
+ *               with the smaller modelled time (per step max(flops/peak,
+ *               bytes/HBM bandwidth) plus a fixed per-step latency) is kept;
  * precision  0: complex128 (FP64) tensors; 1: complex64 (FP32) tensors with
  *               FP32 accumulation, exponents and normalisation kept in
  *               int64 / FP64.
@@ -117,8 +122,14 @@ void kn_tait_free(kn_tait* g);
  *               returns KN_E_BUDGET (and still fills *out so that its
  *               statistics can be read, see kn_plan_info).
  * tile_outputs      outputs per tile for steps split across workgroups
- *               (0 = default); big_step_macs: complex multiply-adds above
- *               which a step is split into tiles (0 = default).
+ *               (0 = default); big_step_macs_log2: log2 of the complex
+ *               multiply-adds above which a step is split into tiles
+ *               (0 = default).
+ * paper_stats   1: also compute delta_h_paper (costs about as much as the
+ *               plan itself); 0: delta_h_paper = -1.
+ * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
+ *               (0 = default 32 KiB, at most 96 KiB).  All plans of a batch
+ *               are launched with the largest value any of them uses.
  */
 typedef struct {
   int32_t strategy;
@@ -128,6 +139,8 @@ typedef struct {
   uint64_t mem_budget_bytes;
   int32_t tile_outputs;
   int32_t big_step_macs_log2;
+  int32_t paper_stats;
+  int32_t lds_bytes;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).
@@ -158,7 +171,7 @@ typedef struct {
 } kn_plan_stats;
 
 /* Build a plan for q.  opts == NULL selects the defaults above (Jones-only,
-   full simplification, complex128, greedy size order). */
+   full simplification, complex128, auto order). */
 kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_opts* opts, kn_plan** out);
 kn_status kn_plan_info(const kn_plan* p, kn_plan_stats* out);
 void kn_plan_free(kn_plan* p);
@@ -211,6 +224,22 @@ kn_status kn_jones(int32_t q, const kn_tait* g, const kn_scalar* z_host, double*
 /* t(q) of Eq. 1 with principal square roots. */
 kn_status kn_jones_variable(int32_t q, double* t_re, double* t_im);
 
+/* ------------------------------------------------------------------ host runtime
+ * kn_plan_many: kn_build_tait + kn_plan_create for many knots on a pool of
+ * host threads (n_threads <= 0: one per hardware thread).  Knot i has
+ * n_crossings[i] crossings; its PD code starts at pd + 4*s_i and its signs
+ * (optional, NULL for all knots) at signs + s_i, s_i = sum of n_crossings[j]
+ * for j < i.  q[i] in [2, 8].  taits[i] / plans[i] receive handles owned by
+ * the caller (NULL where that knot failed; a plan over budget is still
+ * returned, as with kn_plan_create); status[i] (nullable) its status.
+ * Returns KN_OK if every knot succeeded, else the first failing status. */
+kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_t* pd,
+                       const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
+                       int32_t n_threads, kn_tait** taits, kn_plan** plans, kn_status* status);
+/* kn_jones for n knots: v (nullable) receives 2n doubles (re, im). */
+kn_status kn_jones_many(int32_t n, const int32_t* q, const kn_tait* const* g,
+                        const kn_scalar* z_host, double* v, double* log2_abs_v, double* arg_v);
+
 /* ------------------------------------------------------------------ batches
  * A batch contracts many plans (any mix of knots, q and sizes) in one
  * persistent kernel launch.  All plans must share one precision.
@@ -243,6 +272,11 @@ kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes);
 /* Override the persistent grid size (workgroups) of later kn_batch_contract
    calls; 0 restores the default (derived from the device's CU count). */
 kn_status kn_batch_set_grid(kn_batch* b, int32_t grid);
+/* Per-task timing of later kn_batch_contract calls: trace_dev (device, at
+   least 32 * n_tasks bytes; NULL switches tracing off) receives for task i the
+   record {int64 t_claim, t_start, t_end; int32 task, workgroup} in device
+   clock ticks (100 MHz): queue slot claimed, task available, task done. */
+kn_status kn_batch_set_trace(kn_batch* b, void* trace_dev, size_t bytes);
 void kn_batch_free(kn_batch* b);
 
 /* Human-readable name of a status code (static string). */

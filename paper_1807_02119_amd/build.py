@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkn.so")
 
-HOST_SOURCES = ["tait.cpp", "plan.cpp", "image.cpp", "jones.cpp"]
+HOST_SOURCES = ["tait.cpp", "plan.cpp", "image.cpp", "jones.cpp", "runtime.cpp"]
 HIP_SOURCES = ["engine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -61,7 +61,7 @@ def build(verbose: bool = False) -> str:
             if o.strip():
                 print(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,14 +1,15 @@
 // engine.hip -- GPU contraction of PACI tensor networks (Sec. III of
 // arXiv:1807.02119) for CDNA4 (gfx950).
 //
-// One persistent kernel executes the task list of a device program (see
-// program.h).  Workgroups take tasks in list order from a global ticket; a
-// task first waits until the tensors it reads are complete (per-tensor
-// completion counters, acquire at device scope), runs, then publishes what it
-// wrote (release at device scope) and bumps the counters of the tensors it
-// produced.  Because tasks are handed out in an order in which every
-// dependency precedes its consumer, the earliest unfinished task always has
-// its inputs and the queue cannot deadlock, whatever the grid size.
+// One persistent kernel executes the task groups of a device program (see
+// program.h).  Ready tasks sit in a device queue: a workgroup claims the next
+// queue slot, waits until a task id has been written there, runs the task,
+// and when it finishes the last task of a group it appends every task of the
+// knot's next group to the queue.  Completion is published with a release at
+// device scope and taken with an acquire before a task reads its inputs, so
+// data written on one XCD is visible on another.  Every task is enqueued
+// exactly once and only after its predecessors finished, so every claimed
+// slot is eventually filled and the kernel drains for any grid size.
 //
 // Work done by tasks:
 //   setup   edge weights x_e = e^{J_e} (or the Jones couplings -t^{-eps_e},
@@ -17,23 +18,26 @@
 //           with T = 1 + (x - 1) delta (Eqs. 3, 5); a vertex spin private to
 //           its tensor is summed here.
 //   step    C[b,m,n] = sum_k A[b,m,k] B[b,k,n] (one pairwise contraction of
-//           Eq. 6).  Operands are gathered through per-step offset tables, so
-//           the permutation that brings A and B into GEMM order is fused into
-//           the loads and never materialised.  Each tensor is stored as a raw
-//           mantissa array R with an int64 exponent e (true = R 2^e) and a
-//           shift s = frexp exponent of max(|Re|,|Im|) over R; the consumer
-//           multiplies by 2^-(sA+sB) while accumulating, so every product
-//           stays bounded by the contracted extent and Z never overflows.
+//           Eq. 6).  Operands are gathered through per-step offset tables
+//           (staged in LDS), so the permutation that brings A and B into GEMM
+//           order is fused into the loads and never materialised.  Tensors
+//           that live inside one serial task are kept in that workgroup's LDS.
+//           Each tensor is a raw mantissa array R with an int64 exponent e
+//           (true = R 2^e) and a shift s = frexp exponent of max(|Re|,|Im|)
+//           over R; the consumer scales by 2^-(sA+sB) while accumulating, so
+//           every product stays bounded by the contracted extent and Z never
+//           overflows.
 //   final   Z = prod over components of (scalar R 2^e) times the
 //           simplification factors (loops x_e, spikes x_m + q - 1) and q per
 //           isolated spin, renormalised after every product.
 #include <hip/hip_runtime.h>
 
 #include <climits>
-#include <cstdint>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <algorithm>
 #include <new>
 
 #include "internal.h"
@@ -48,7 +52,7 @@ struct alignas(2 * sizeof(T)) Cx {
 struct DevProg {
   const ImgHeader* h;
   const TaskDesc* tasks;
-  const int32_t* deps;
+  const GroupDesc* groups;
   const KnotDesc* knots;
   const TensorDesc* tens;
   const StepDesc* steps;
@@ -60,9 +64,11 @@ struct DevProg {
   const int32_t* tables;
   const int8_t* eps;
   const int32_t* comps;
+  int32_t* ctrl;
+  int32_t* queue;
+  int32_t* pending;
   TensorState* ts;
   Cx<double>* weights;  // x_e (n_edges) then x_m (n_medges)
-  int32_t* ctrl;        // [0] ticket, [1] error
 };
 
 __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
@@ -70,7 +76,7 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.h = reinterpret_cast<const ImgHeader*>(img);
   const ImgHeader& h = *p.h;
   p.tasks = reinterpret_cast<const TaskDesc*>(img + h.o_tasks);
-  p.deps = reinterpret_cast<const int32_t*>(img + h.o_deps);
+  p.groups = reinterpret_cast<const GroupDesc*>(img + h.o_groups);
   p.knots = reinterpret_cast<const KnotDesc*>(img + h.o_knots);
   p.tens = reinterpret_cast<const TensorDesc*>(img + h.o_tensors);
   p.steps = reinterpret_cast<const StepDesc*>(img + h.o_steps);
@@ -83,6 +89,8 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.eps = reinterpret_cast<const int8_t*>(img + h.o_eps);
   p.comps = reinterpret_cast<const int32_t*>(img + h.o_comps);
   p.ctrl = reinterpret_cast<int32_t*>(state);
+  p.queue = reinterpret_cast<int32_t*>(state + h.o_queue);
+  p.pending = reinterpret_cast<int32_t*>(state + h.o_pending);
   p.ts = reinterpret_cast<TensorState*>(state + h.o_tstate);
   p.weights = reinterpret_cast<Cx<double>*>(state + h.o_weights);
   return p;
@@ -106,6 +114,40 @@ __device__ inline void acc_mul(Cx<double>& z, int64_t& e, Cx<double> f) {
 
 __device__ inline int32_t shift_of(int32_t s) { return s == kShiftNone ? 0 : s; }
 
+// Tensor data: the workgroup's LDS arena or the global arena (generic pointer).
+template <class T>
+__device__ inline Cx<T>* tptr(const TensorDesc& d, Cx<T>* arena, Cx<T>* lds) {
+  return d.lds_off >= 0 ? lds + d.lds_off : arena + d.off;
+}
+
+// Tensor states: those produced by the running serial task are cached in LDS,
+// the rest live in global memory.
+struct States {
+  TensorState* g;
+  int32_t* sh;  // LDS
+  int64_t* ex;  // LDS
+  int32_t lo, len;
+  __device__ inline bool local(int32_t t) const { return (uint32_t)(t - lo) < (uint32_t)len; }
+  __device__ inline void get(int32_t t, int32_t& shift, int64_t& e) const {
+    if (local(t)) {
+      shift = sh[t - lo];
+      e = ex[t - lo];
+    } else {
+      shift = g[t].shift;
+      e = g[t].exp2;
+    }
+  }
+  __device__ inline void set(int32_t t, int32_t shift, int64_t e) const {
+    if (local(t)) {
+      sh[t - lo] = shift;
+      ex[t - lo] = e;
+    } else {
+      g[t].shift = shift;
+      g[t].exp2 = e;
+    }
+  }
+};
+
 // ------------------------------------------------------------------ reductions
 
 template <class T>
@@ -119,7 +161,6 @@ template <class T>
 __device__ inline T block_max(T v, T* red) {
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
   if (lane == 0) red[wv] = v;
   __syncthreads();
   T r = red[0];
@@ -131,7 +172,8 @@ __device__ inline T block_max(T v, T* red) {
 // ------------------------------------------------------------------ setup
 
 template <class T>
-__device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, const double* J) {
+__device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
+                           const double* J, const States& st) {
   const int tid = threadIdx.x;
   const ImgHeader& h = *p.h;
   Cx<double>* xe = p.weights + kd.edge_off;
@@ -168,53 +210,59 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, c
   for (int v = wv; v < kd.n_vtx; v += kBlock / 64) {
     const VtxDesc vd = p.vtx[kd.vtx_off + v];
     const TensorDesc td = p.tens[vd.tensor];
-    Cx<T>* out = arena + td.off;
+    Cx<T>* out = tptr<T>(td, arena, lds);
+    const int32_t* slot_me = p.vslot + vd.slot_off;
+    int32_t qn = 1;  // q^n_slots
+    for (int j = 0; j < vd.n_slots; ++j) qn *= q;
     for (int i = lane; i < td.size; i += 64) {
-      // digits: last neighbour slot fastest; the kept centre is the leading index
-      int rem = i;
-      int dig[8];
-      for (int j = vd.n_slots - 1; j >= 0; --j) {
-        dig[j] = rem % q;
-        rem /= q;
-      }
+      // digits of i: last neighbour slot fastest; a kept centre is the leading
+      // index (i / q^n_slots), a private centre is summed over
+      const int a_lo = vd.keep_center ? i / qn : 0;
+      const int a_hi = vd.keep_center ? a_lo + 1 : q;
       Cx<double> acc{0.0, 0.0};
-      const int a_lo = vd.keep_center ? rem : 0;
-      const int a_hi = vd.keep_center ? rem + 1 : q;
       for (int a = a_lo; a < a_hi; ++a) {
         Cx<double> prod{1.0, 0.0};
-        for (int j = 0; j < vd.n_slots; ++j)
-          if (dig[j] == a) prod = cmul(prod, xm[p.vslot[vd.slot_off + j]]);
+        int rem = i;
+        for (int j = vd.n_slots - 1; j >= 0; --j) {
+          const int d = rem % q;
+          rem /= q;
+          if (d == a) prod = cmul(prod, xm[slot_me[j]]);
+        }
         acc.re += prod.re;
         acc.im += prod.im;
       }
       out[i] = Cx<T>{(T)acc.re, (T)acc.im};
     }
-    if (lane == 0) {
-      p.ts[vd.tensor].shift = 0;  // entries are products of <= 8 weights: no scaling needed
-      p.ts[vd.tensor].exp2 = 0;
-    }
+    // entries are products of <= 8 weights: no scaling needed
+    if (lane == 0) st.set(vd.tensor, 0, 0);
   }
 }
 
 // ------------------------------------------------------------------ step
 
-// Computes outputs [o_begin, o_end) of step s; returns this thread's max |.|.
+// Lanes per output: enough to give every thread work, at most 64 (one
+// wavefront, reduced with shuffles) and at most the contracted extent.
+__device__ inline int32_t lanes_per_output(int64_t outs, int32_t nk) {
+  int32_t L = 1;
+  while (L < 64 && 2 * L <= nk && outs * L < kBlock) L *= 2;
+  return L;
+}
+
+// Outputs [o_begin, o_end) of C = A . B, each summed over k by L lanes of one
+// wavefront; returns this thread's max |.|.  Table pointers may point into
+// LDS or global memory.
 template <class T>
-__device__ T step_outputs(const DevProg& p, const StepDesc& s, Cx<T>* arena, int64_t o_begin,
-                          int64_t o_end, T scale) {
-  const TensorDesc A = p.tens[s.a], B = p.tens[s.b], C = p.tens[s.c];
-  const int32_t* tAb = p.tables + s.tab;
-  const int32_t* tAm = tAb + s.nb;
-  const int32_t* tAk = tAm + s.nm;
-  const int32_t* tBb = tAk + s.nk;
-  const int32_t* tBk = tBb + s.nb;
-  const int32_t* tBn = tBk + s.nk;
-  const Cx<T>* pa = arena + A.off;
-  const Cx<T>* pb = arena + B.off;
-  Cx<T>* pc = arena + C.off;
-  const int32_t nn = s.nn, mn = s.nm * s.nn, nk = s.nk;
+__device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict__ pb,
+                          Cx<T>* __restrict__ pc, const int32_t* tAb, const int32_t* tAm,
+                          const int32_t* tAk, const int32_t* tBb, const int32_t* tBk,
+                          const int32_t* tBn, int32_t nm, int32_t nn, int32_t nk,
+                          int64_t o_begin, int64_t o_end, T scale, int32_t L) {
+  const int32_t mn = nm * nn;
+  const int32_t lsub = threadIdx.x & (L - 1);
+  const int32_t slot = threadIdx.x / L;
+  const int32_t nslot = kBlock / L;
   T lmax = 0;
-  for (int64_t o = o_begin + threadIdx.x; o < o_end; o += kBlock) {
+  for (int64_t o = o_begin + slot; o < o_end; o += nslot) {
     const int32_t oi = (int32_t)o;
     const int32_t b = oi / mn;
     const int32_t r = oi - b * mn;
@@ -222,29 +270,41 @@ __device__ T step_outputs(const DevProg& p, const StepDesc& s, Cx<T>* arena, int
     const int32_t n = r - m * nn;
     const Cx<T>* ra = pa + tAb[b] + tAm[m];
     const Cx<T>* rb = pb + tBb[b] + tBn[n];
-    T cr = 0, ci = 0;
-    for (int32_t k = 0; k < nk; ++k) {
+    T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
+    int32_t k = lsub;
+    for (; k + 3 * L < nk; k += 4 * L) {
+      const Cx<T> x0 = ra[tAk[k]], x1 = ra[tAk[k + L]], x2 = ra[tAk[k + 2 * L]],
+                  x3 = ra[tAk[k + 3 * L]];
+      const Cx<T> y0 = rb[tBk[k]], y1 = rb[tBk[k + L]], y2 = rb[tBk[k + 2 * L]],
+                  y3 = rb[tBk[k + 3 * L]];
+      cr0 = fma(x0.re, y0.re, cr0); cr0 = fma(-x0.im, y0.im, cr0);
+      ci0 = fma(x0.re, y0.im, ci0); ci0 = fma(x0.im, y0.re, ci0);
+      cr1 = fma(x1.re, y1.re, cr1); cr1 = fma(-x1.im, y1.im, cr1);
+      ci1 = fma(x1.re, y1.im, ci1); ci1 = fma(x1.im, y1.re, ci1);
+      cr0 = fma(x2.re, y2.re, cr0); cr0 = fma(-x2.im, y2.im, cr0);
+      ci0 = fma(x2.re, y2.im, ci0); ci0 = fma(x2.im, y2.re, ci0);
+      cr1 = fma(x3.re, y3.re, cr1); cr1 = fma(-x3.im, y3.im, cr1);
+      ci1 = fma(x3.re, y3.im, ci1); ci1 = fma(x3.im, y3.re, ci1);
+    }
+    for (; k < nk; k += L) {
       const Cx<T> x = ra[tAk[k]];
       const Cx<T> y = rb[tBk[k]];
-      cr = fma(x.re, y.re, cr);
-      cr = fma(-x.im, y.im, cr);
-      ci = fma(x.re, y.im, ci);
-      ci = fma(x.im, y.re, ci);
+      cr0 = fma(x.re, y.re, cr0); cr0 = fma(-x.im, y.im, cr0);
+      ci0 = fma(x.re, y.im, ci0); ci0 = fma(x.im, y.re, ci0);
     }
-    cr *= scale;
-    ci *= scale;
-    pc[oi] = Cx<T>{cr, ci};
-    lmax = fmax(lmax, fmax(fabs(cr), fabs(ci)));
+    T cr = cr0 + cr1, ci = ci0 + ci1;
+    for (int32_t off = L >> 1; off >= 1; off >>= 1) {
+      cr += __shfl_xor(cr, off, 64);
+      ci += __shfl_xor(ci, off, 64);
+    }
+    if (lsub == 0) {
+      cr *= scale;
+      ci *= scale;
+      pc[oi] = Cx<T>{cr, ci};
+      lmax = fmax(lmax, fmax(fabs(cr), fabs(ci)));
+    }
   }
   return lmax;
-}
-
-template <class T>
-__device__ inline T step_scale(const DevProg& p, const StepDesc& s, int64_t& e_out) {
-  const TensorState sa = p.ts[s.a], sb = p.ts[s.b];
-  const int32_t sh = shift_of(sa.shift) + shift_of(sb.shift);
-  e_out = sa.exp2 + sb.exp2 + sh;
-  return (T)ldexp(1.0, -sh);
 }
 
 template <class T>
@@ -255,11 +315,116 @@ __device__ inline int32_t frexp_shift(T m) {
   return s;
 }
 
+// Scale 2^-(sA+sB) applied to the products, and the exponent of C.
+template <class T>
+__device__ inline T step_scale(const States& st, int32_t a, int32_t b, int64_t& e_out) {
+  int32_t sa, sb;
+  int64_t ea, eb;
+  st.get(a, sa, ea);
+  st.get(b, sb, eb);
+  const int32_t sh = shift_of(sa) + shift_of(sb);
+  e_out = ea + eb + sh;
+  return (T)ldexp(1.0, -sh);
+}
+
+// Serial steps [first, first + count): descriptors and gather tables are
+// staged in LDS one chunk at a time (tables of consecutive steps of a knot
+// are contiguous), then the chunk runs with no global round trip except the
+// operands that live in the global arena.
+template <class T>
+__device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, Cx<T>* arena,
+                             Cx<T>* lds, int32_t* s_tab, StepDesc* s_desc, const States& st,
+                             T* s_red) {
+  constexpr int32_t kDescWords = (int32_t)(sizeof(StepDesc) / 4);
+  int32_t s = first;
+  const int32_t end = first + count;
+  while (s < end) {
+    const int32_t nd = min(end - s, kDescBuf);
+    {
+      const int32_t* src = reinterpret_cast<const int32_t*>(p.steps + s);
+      int32_t* dst = reinterpret_cast<int32_t*>(s_desc);
+      for (int32_t i = threadIdx.x; i < nd * kDescWords; i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int32_t tab0 = s_desc[0].tab;
+    int32_t ce = 0, tab_end = 0;
+    for (int32_t j = 0; j < nd; ++j) {
+      const StepDesc& d = s_desc[j];
+      const int32_t e = d.tab + 2 * d.nb + d.nm + 2 * d.nk + d.nn - tab0;
+      if (e > kTabBuf) break;
+      ce = j + 1;
+      tab_end = e;
+    }
+    for (int32_t i = threadIdx.x; i < tab_end; i += kBlock) s_tab[i] = p.tables[tab0 + i];
+    __syncthreads();
+    for (int32_t j = 0; j < ce; ++j) {
+      const StepDesc d = s_desc[j];
+      const int32_t* tAb = s_tab + (d.tab - tab0);
+      const int32_t* tAm = tAb + d.nb;
+      const int32_t* tAk = tAm + d.nm;
+      const int32_t* tBb = tAk + d.nk;
+      const int32_t* tBk = tBb + d.nb;
+      const int32_t* tBn = tBk + d.nk;
+      int64_t ec;
+      const T scale = step_scale<T>(st, d.a, d.b, ec);
+      const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
+      const int32_t L = lanes_per_output(outs, d.nk);
+      T lm = step_outputs<T>(tptr<T>(p.tens[d.a], arena, lds), tptr<T>(p.tens[d.b], arena, lds),
+                             tptr<T>(p.tens[d.c], arena, lds), tAb, tAm, tAk, tBb, tBk, tBn,
+                             d.nm, d.nn, d.nk, 0, outs, scale, L);
+      lm = block_max<T>(lm, s_red);
+      if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
+      __syncthreads();
+    }
+    s += ce;
+  }
+}
+
+// One tile of a step split across workgroups.
+template <class T>
+__device__ void tile_step(const DevProg& p, int32_t si, int32_t tile_id, Cx<T>* arena,
+                          int32_t* s_tab, const States& st, T* s_red) {
+  const StepDesc s = p.steps[si];
+  const int32_t* g = p.tables + s.tab;
+  const int32_t* tAb = g;
+  const int32_t* tAm = tAb + s.nb;
+  const int32_t* tAk = tAm + s.nm;
+  const int32_t* tBb = tAk + s.nk;
+  const int32_t* tBk = tBb + s.nb;
+  const int32_t* tBn = tBk + s.nk;
+  // the contracted-index tables are read by every output: stage them
+  if (2 * s.nk <= kTabBuf) {
+    for (int32_t i = threadIdx.x; i < s.nk; i += kBlock) {
+      s_tab[i] = tAk[i];
+      s_tab[s.nk + i] = tBk[i];
+    }
+    tAk = s_tab;
+    tBk = s_tab + s.nk;
+  }
+  int64_t ec;
+  const T scale = step_scale<T>(st, s.a, s.b, ec);
+  const TensorDesc A = p.tens[s.a], B = p.tens[s.b], C = p.tens[s.c];
+  __syncthreads();
+  const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
+  const int64_t o0 = (int64_t)tile_id * s.tile;
+  const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
+  const int32_t L = lanes_per_output(o1 - o0, s.nk);
+  T lm = step_outputs<T>(arena + A.off, arena + B.off, arena + C.off, tAb, tAm, tAk, tBb, tBk,
+                         tBn, s.nm, s.nn, s.nk, o0, o1, scale, L);
+  lm = block_max<T>(lm, s_red);
+  if (threadIdx.x == 0) {
+    const int32_t sh = frexp_shift<T>(lm);
+    if (sh != kShiftNone)
+      __hip_atomic_fetch_max(&p.ts[s.c].shift, sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tile_id == 0) p.ts[s.c].exp2 = ec;
+  }
+}
+
 // ------------------------------------------------------------------ final
 
 template <class T>
-__device__ void knot_final(const DevProg& p, const KnotDesc& kd, const Cx<T>* arena,
-                           kn_scalar* zout) {
+__device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
+                           kn_scalar* zout, const States& st) {
   if (threadIdx.x != 0) return;
   const ImgHeader& h = *p.h;
   const Cx<double>* xe = p.weights + kd.edge_off;
@@ -268,8 +433,11 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, const Cx<T>* ar
   int64_t e = 0;
   for (int i = 0; i < kd.n_comps; ++i) {
     const int32_t t = p.comps[kd.comp_off + i];
-    const Cx<T> r = arena[p.tens[t].off];
-    e += p.ts[t].exp2;
+    const Cx<T> r = *tptr<T>(p.tens[t], arena, lds);
+    int32_t sh;
+    int64_t et;
+    st.get(t, sh, et);
+    e += et;
     acc_mul(z, e, Cx<double>{(double)r.re, (double)r.im});
   }
   for (int i = 0; i < kd.n_factors; ++i) {
@@ -280,7 +448,7 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, const Cx<T>* ar
   }
   for (int i = 0; i < kd.n_iso; ++i) acc_mul(z, e, Cx<double>{(double)kd.q, 0.0});
   kn_scalar out;
-  if (__hip_atomic_load(&p.ctrl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+  if (__hip_atomic_load(&p.ctrl[CTRL_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
     out.re = out.im = __builtin_nan("");
     out.exp2 = 0;
   } else {
@@ -293,100 +461,127 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, const Cx<T>* ar
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void clear_state(uint8_t* state, int32_t n_tensors, int64_t o_tstate) {
+// Reset the runtime state of an image: control words, ready queue seeded
+// with the knots' first groups, pending counters, tensor states.
+__global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict__ state) {
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(img);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 64) reinterpret_cast<int32_t*>(state)[i] = 0;
-  TensorState* ts = reinterpret_cast<TensorState*>(state + o_tstate);
-  if (i < n_tensors) {
+  int32_t* ctrl = reinterpret_cast<int32_t*>(state);
+  if (i < CTRL_WORDS) ctrl[i] = (i == CTRL_TAIL) ? h.n_roots : 0;
+  if (i < h.n_tasks) {
+    const int32_t* roots = reinterpret_cast<const int32_t*>(img + h.o_roots);
+    reinterpret_cast<int32_t*>(state + h.o_queue)[i] = i < h.n_roots ? roots[i] : -1;
+  }
+  if (i < h.n_groups) {
+    const GroupDesc* g = reinterpret_cast<const GroupDesc*>(img + h.o_groups);
+    reinterpret_cast<int32_t*>(state + h.o_pending)[i] = g[i].n_pred;
+  }
+  if (i < h.n_tensors) {
+    TensorState* ts = reinterpret_cast<TensorState*>(state + h.o_tstate);
     ts[i].shift = kShiftNone;
-    ts[i].done = 0;
+    ts[i].pad = 0;
     ts[i].exp2 = 0;
   }
 }
 
-// Bound on the wait for one dependency (sleep iterations, ~0.3 us each): a
-// dependency that is never satisfied (a planner bug) ends the task with the
-// error flag set instead of hanging the device.
+// Bound on the wait for a queue slot (sleep iterations): a slot that is never
+// filled (a planner bug) ends the kernel with the error flag set instead of
+// hanging the device.
 constexpr int32_t kSpinLimit = 1 << 24;
+
+extern __shared__ __align__(16) uint8_t kn_dyn_smem[];
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img,
                                                  uint8_t* __restrict__ state,
                                                  Cx<T>* __restrict__ arena,
                                                  const double* __restrict__ J,
-                                                 kn_scalar* __restrict__ zout) {
+                                                 kn_scalar* __restrict__ zout,
+                                                 TraceRec* __restrict__ trace) {
   __shared__ int32_t s_task;
+  __shared__ int32_t s_enq[3];
   __shared__ T s_red[kBlock / 64];
+  int32_t* s_tab = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsTab);
+  StepDesc* s_desc = reinterpret_cast<StepDesc*>(kn_dyn_smem + kLdsDesc);
+  int32_t* s_shift = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsShift);
+  int64_t* s_exp = reinterpret_cast<int64_t*>(kn_dyn_smem + kLdsExp);
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(kn_dyn_smem + kLdsArena);
   const DevProg p = make_prog(img, state);
   const int32_t n_tasks = p.h->n_tasks;
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) s_task = atomicAdd(&p.ctrl[0], 1);
-    __syncthreads();
-    const int32_t ti = s_task;
-    __syncthreads();
-    if (ti >= n_tasks) break;
-    const TaskDesc td = p.tasks[ti];
-    // ---- wait for inputs
+    int64_t t_claim = 0;
     if (tid == 0) {
-      for (int i = 0; i < td.n_deps; ++i) {
-        const int32_t d = p.deps[td.dep_off + i];
-        const int32_t target = p.tens[d].target;
-        int32_t spins = 0;
-        while (__hip_atomic_load(&p.ts[d].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               target) {
-          __builtin_amdgcn_s_sleep(8);
+      if (trace) t_claim = wall_clock64();
+      const int32_t slot = atomicAdd(&p.ctrl[CTRL_HEAD], 1);
+      int32_t t = -1;
+      if (slot < n_tasks) {
+        int32_t spins = 0, nap = 1;
+        while ((t = __hip_atomic_load(&p.queue[slot], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT)) < 0) {
+          if (nap < 16) {
+            __builtin_amdgcn_s_sleep(1);
+            ++nap;
+          } else {
+            __builtin_amdgcn_s_sleep(8);
+          }
           if (++spins > kSpinLimit) {
-            __hip_atomic_store(&p.ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&p.ctrl[CTRL_ERROR], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
         }
       }
+      s_task = t;
     }
     __syncthreads();
+    const int32_t ti = s_task;
+    __syncthreads();
+    if (ti < 0) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const KnotDesc kd = p.knots[td.knot];
+    const int64_t t_start = (trace && tid == 0) ? wall_clock64() : 0;
+    const TaskDesc td = p.tasks[ti];
     if (td.kind == TASK_SERIAL) {
+      const KnotDesc kd = p.knots[td.knot];
+      const States st{p.ts, s_shift, s_exp, td.state_lo, min(td.state_len, kStateCap)};
       if (td.flags & TF_SETUP) {
-        knot_setup<T>(p, kd, arena, J);
+        knot_setup<T>(p, kd, arena, lds, J, st);
         __syncthreads();
       }
-      for (int32_t si = td.first; si < td.first + td.count; ++si) {
-        const StepDesc s = p.steps[si];
-        int64_t ec;
-        const T scale = step_scale<T>(p, s, ec);
-        const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
-        T lm = step_outputs<T>(p, s, arena, 0, outs, scale);
-        lm = block_max<T>(lm, s_red);
-        if (tid == 0) {
-          p.ts[s.c].shift = frexp_shift<T>(lm);
-          p.ts[s.c].exp2 = ec;
-        }
-        __syncthreads();
+      serial_steps<T>(p, td.first, td.count, arena, lds, s_tab, s_desc, st, s_red);
+      if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, lds, zout, st);
+      // states of this task's tensors go back to global memory for later groups
+      for (int32_t i = tid; i < st.len; i += kBlock) {
+        p.ts[st.lo + i].shift = s_shift[i];
+        p.ts[st.lo + i].exp2 = s_exp[i];
       }
-      if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, zout);
     } else {
-      const StepDesc s = p.steps[td.first];
-      int64_t ec;
-      const T scale = step_scale<T>(p, s, ec);
-      const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
-      const int64_t o0 = (int64_t)td.count * s.tile;
-      const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
-      T lm = step_outputs<T>(p, s, arena, o0, o1, scale);
-      lm = block_max<T>(lm, s_red);
-      if (tid == 0) {
-        const int32_t sh = frexp_shift<T>(lm);
-        if (sh != kShiftNone)
-          __hip_atomic_fetch_max(&p.ts[s.c].shift, sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (td.count == 0) p.ts[s.c].exp2 = ec;
-      }
+      const States st{p.ts, s_shift, s_exp, 0, 0};
+      tile_step<T>(p, td.first, td.count, arena, s_tab, st, s_red);
     }
-    // ---- publish
+    // ---- publish; the last task of a group releases the knot's next group
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    for (int i = tid; i < td.n_sig; i += kBlock)
-      __hip_atomic_fetch_add(&p.ts[p.deps[td.sig_off + i]].done, 1, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      s_enq[0] = 0;
+      const int32_t next = p.groups[td.group].next;
+      if (next >= 0 && __hip_atomic_fetch_add(&p.pending[next], -1, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        const GroupDesc g = p.groups[next];
+        s_enq[0] = g.n_tasks;
+        s_enq[1] = g.first_task;
+        s_enq[2] = atomicAdd(&p.ctrl[CTRL_TAIL], g.n_tasks);
+      }
+      if (trace) trace[ti] = TraceRec{t_claim, t_start, wall_clock64(), ti, (int32_t)blockIdx.x};
+    }
+    __syncthreads();
+    const int32_t n_enq = s_enq[0];
+    if (n_enq) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int32_t first = s_enq[1], base = s_enq[2];
+      for (int32_t i = tid; i < n_enq; i += kBlock)
+        __hip_atomic_store(&p.queue[base + i], first + i, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -408,25 +603,47 @@ int device_cus() {
   return cus;
 }
 
-kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
-                 kn_scalar* z, int32_t grid_override) {
-  uint8_t* state = ws + h.state_off;
-  const int32_t n_clear = h.n_tensors > 64 ? h.n_tensors : 64;
-  hipLaunchKernelGGL(clear_state, dim3((n_clear + 255) / 256), dim3(256), 0, st, state,
-                     h.n_tensors, h.o_tstate);
-  if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
-  int32_t grid = grid_override > 0 ? grid_override : device_cus() * 4;
+template <class T>
+int32_t resident_per_cu(size_t dyn_lds) {
+  int32_t nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, engine<T>, kBlock, dyn_lds) != hipSuccess ||
+      nb <= 0)
+    nb = 1;
+  return nb;
+}
+
+template <class T>
+kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
+                        kn_scalar* z, int32_t grid_override, TraceRec* trace) {
+  const size_t dyn = (size_t)kLdsArena + (size_t)h.lds_bytes;
+  static std::once_flag once;
+  static bool attr_ok = true;
+  std::call_once(once, [] {
+    attr_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(engine<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024 - 1024) == hipSuccess;
+  });
+  if (!attr_ok) return KN_E_DEVICE;
+  int32_t grid = grid_override;
+  if (grid <= 0) grid = device_cus() * resident_per_cu<T>(dyn);
   if (grid > h.n_tasks) grid = h.n_tasks;
   if (grid < 1) grid = 1;
-  if (h.precision == 1) {
-    hipLaunchKernelGGL(engine<float>, dim3(grid), dim3(kBlock), 0, st, ws, state,
-                       reinterpret_cast<Cx<float>*>(ws + h.arena_off), J, z);
-  } else {
-    hipLaunchKernelGGL(engine<double>, dim3(grid), dim3(kBlock), 0, st, ws, state,
-                       reinterpret_cast<Cx<double>*>(ws + h.arena_off), J, z);
-  }
+  hipLaunchKernelGGL(engine<T>, dim3(grid), dim3(kBlock), dyn, st, ws, ws + h.state_off,
+                     reinterpret_cast<Cx<T>*>(ws + h.arena_off), J, z, trace);
+  return hipGetLastError() == hipSuccess ? KN_OK : KN_E_DEVICE;
+}
+
+kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
+                 kn_scalar* z, int32_t grid_override, TraceRec* trace = nullptr) {
+  int64_t n_clear = CTRL_WORDS;
+  n_clear = std::max<int64_t>(n_clear, h.n_tasks);
+  n_clear = std::max<int64_t>(n_clear, h.n_groups);
+  n_clear = std::max<int64_t>(n_clear, h.n_tensors);
+  hipLaunchKernelGGL(clear_state, dim3((unsigned)((n_clear + 255) / 256)), dim3(256), 0, st, ws,
+                     ws + h.state_off);
   if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
-  return KN_OK;
+  if (h.precision == 1) return launch_engine<float>(h, ws, st, J, z, grid_override, trace);
+  return launch_engine<double>(h, ws, st, J, z, grid_override, trace);
 }
 
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
@@ -527,8 +744,9 @@ extern "C" kn_status kn_batch_contract(const kn_batch* b, const double* J, void*
   if (!aligned256(workspace)) return KN_E_INVALID;
   const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(b->image.data());
   if ((int64_t)workspace_bytes < h.workspace_bytes) return KN_E_BUDGET;
+  if (b->trace && b->trace_bytes < (size_t)h.n_tasks * sizeof(TraceRec)) return KN_E_BUDGET;
   return launch(h, reinterpret_cast<uint8_t*>(workspace), reinterpret_cast<hipStream_t>(stream), J,
-                z_dev, b->grid_override);
+                z_dev, b->grid_override, reinterpret_cast<TraceRec*>(b->trace));
 }
 
 extern "C" kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes) {
@@ -541,6 +759,13 @@ extern "C" kn_status kn_batch_image(const kn_batch* b, const void** data, size_t
 extern "C" kn_status kn_batch_set_grid(kn_batch* b, int32_t grid) {
   if (!b || grid < 0) return KN_E_INVALID;
   b->grid_override = grid;
+  return KN_OK;
+}
+
+extern "C" kn_status kn_batch_set_trace(kn_batch* b, void* trace_dev, size_t bytes) {
+  if (!b) return KN_E_INVALID;
+  b->trace = trace_dev;
+  b->trace_bytes = trace_dev ? bytes : 0;
   return KN_OK;
 }
 

@@ -1,15 +1,22 @@
 // image.cpp -- lay one or more knot plans out as a device program (see
-// program.h): descriptors, gather tables, task list with dependencies.
+// program.h): descriptors, gather tables, task groups, ready-queue roots and
+// LDS homes.
 //
-// Tasks of one knot form groups executed strictly one after another (a
-// serial run of small steps, or all tiles of one big step); every group waits
-// for the previous group's completion tensor, which also guarantees that
-// arena memory freed by a group is not reused while that group still reads
-// it.  Groups of different knots are independent; they are interleaved
-// round-robin, largest knots first, so that many knots are in flight at once.
+// The tasks of one knot form a chain of groups executed one after another (a
+// serial run of small steps on one workgroup, or all tiles of one big step);
+// the engine starts a group when every task of the previous group has
+// finished, which also guarantees that arena memory freed by a group is not
+// reused while that group still reads it.  Groups of different knots are
+// independent.  The first groups of all knots seed the device ready queue,
+// longest estimated chain first.
+//
+// A tensor produced and consumed inside the same serial task lives in that
+// workgroup's LDS arena when it fits (first fit over its live range);
+// everything else lives in the global arena.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
 
 #include "internal.h"
@@ -17,7 +24,6 @@
 namespace kn {
 
 namespace {
-
 template <class T>
 int64_t put(std::vector<uint8_t>& img, const std::vector<T>& v) {
   int64_t off = align256((int64_t)img.size());
@@ -44,20 +50,98 @@ void group_table(const std::vector<int32_t>& group, const std::vector<int32_t>& 
   for (size_t i = 0; i < group.size(); ++i) n *= q;
   size_t base = out.size();
   out.resize(base + n);
-  // enumerate the group's values, first spin most significant
+  // enumerate the group's values, first spin most significant (odometer)
+  const int r = (int)group.size();
+  int digit[64] = {0};
+  int64_t off = 0;
   for (int64_t idx = 0; idx < n; ++idx) {
-    int64_t rem = idx, off = 0;
-    for (int64_t i = (int64_t)group.size() - 1; i >= 0; --i) {
-      off += (rem % q) * gstride[i];
-      rem /= q;
-    }
     out[base + idx] = (int32_t)off;
+    for (int i = r - 1; i >= 0; --i) {
+      if (++digit[i] < q) {
+        off += gstride[i];
+        break;
+      }
+      digit[i] = 0;
+      off -= (int64_t)(q - 1) * gstride[i];
+    }
   }
 }
 
-struct Group {
-  int32_t knot;
-  std::vector<TaskDesc> tasks;
+}  // namespace
+
+void make_tables(PlanKnot& k) {
+  k.tables.clear();
+  k.tab_off.assign(k.steps.size(), 0);
+  for (size_t si = 0; si < k.steps.size(); ++si) {
+    const PStep& s = k.steps[si];
+    k.tab_off[si] = (int32_t)k.tables.size();
+    const auto& A = k.tensors[s.a].spins;
+    const auto& B = k.tensors[s.b].spins;
+    group_table(s.bs, A, k.q, k.tables);
+    group_table(s.ms, A, k.q, k.tables);
+    group_table(s.ks, A, k.q, k.tables);
+    group_table(s.bs, B, k.q, k.tables);
+    group_table(s.ks, B, k.q, k.tables);
+    group_table(s.ns, B, k.q, k.tables);
+  }
+}
+
+namespace {
+
+// First-fit allocator over [0, cap) entries; alloc returns -1 when full.
+struct FitAlloc {
+  int64_t cap;
+  int64_t top = 0;
+  std::map<int64_t, int64_t> free_blk;  // off -> len
+  explicit FitAlloc(int64_t c) : cap(c) {}
+  static int64_t round(int64_t len) { return (len + 7) / 8 * 8; }
+  int64_t alloc(int64_t len) {
+    len = round(len);
+    for (auto it = free_blk.begin(); it != free_blk.end(); ++it)
+      if (it->second >= len) {
+        int64_t off = it->first, rem = it->second - len;
+        free_blk.erase(it);
+        if (rem) free_blk.emplace(off + len, rem);
+        return off;
+      }
+    if (!free_blk.empty()) {
+      auto last = std::prev(free_blk.end());
+      if (last->first + last->second == top && last->first + len <= cap) {
+        int64_t off = last->first;
+        free_blk.erase(last);
+        top = off + len;
+        return off;
+      }
+    }
+    if (top + len > cap) return -1;
+    int64_t off = top;
+    top += len;
+    return off;
+  }
+  void release(int64_t off, int64_t len) {
+    len = round(len);
+    auto it = free_blk.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_blk.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_blk.erase(nx);
+    }
+    if (it != free_blk.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_blk.erase(it);
+      }
+    }
+  }
+};
+
+// A knot's groups before they are laid out.
+struct PGroup {
+  int32_t kind;         // TASK_SERIAL / TASK_TILE
+  int32_t first, count; // knot-local steps
+  int32_t flags;
+  int32_t n_tiles;
 };
 
 }  // namespace
@@ -67,7 +151,6 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   std::memset(&h, 0, sizeof(h));
   h.magic = kMagic;
   h.precision = knots.empty() ? 0 : knots[0]->precision;
-  h.tile = knots.empty() ? 256 : knots[0]->tile;
 
   std::vector<KnotDesc> kd;
   std::vector<TensorDesc> td;
@@ -80,8 +163,10 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   std::vector<int32_t> tables;
   std::vector<int8_t> eps;
   std::vector<int32_t> comps;
-  std::vector<int32_t> deps;
-  std::vector<std::vector<Group>> groups(knots.size());
+  std::vector<TaskDesc> tasks;
+  std::vector<GroupDesc> groups;
+  std::vector<std::pair<double, int32_t>> roots;  // (-estimated chain time, group)
+  int32_t lds_used = 0;
 
   int64_t arena = 0, n_edges = 0, n_medges = 0;
   for (size_t ki = 0; ki < knots.size(); ++ki) {
@@ -115,16 +200,17 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
     }
     for (auto& f : k.factors) fac.push_back(f);
     for (int32_t c : k.comps) comps.push_back(t0 + c);
-    // tensors
     const int64_t abase = arena;
-    for (auto& t : k.tensors) td.push_back({abase + t.off, (int32_t)t.size, 1});
+    for (auto& t : k.tensors) td.push_back({abase + t.off, (int32_t)t.size, -1});
     arena += (k.arena_elems + 15) / 16 * 16;
     for (auto& v : k.vtx) {
       vd.push_back({t0 + v.tensor, (int32_t)v.nbr.size(), (int32_t)vslot.size(),
                     v.keep_center ? 1 : 0});
       for (int32_t m : v.medge) vslot.push_back(m);
     }
-    // steps + tables
+    // steps + tables (precomputed per knot)
+    const int32_t tab0 = (int32_t)tables.size();
+    tables.insert(tables.end(), k.tables.begin(), k.tables.end());
     for (size_t si = 0; si < k.steps.size(); ++si) {
       const PStep& s = k.steps[si];
       StepDesc x;
@@ -140,133 +226,129 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
       x.nm = pw(s.ms.size());
       x.nn = pw(s.ns.size());
       x.nk = pw(s.ks.size());
-      x.tab = (int32_t)tables.size();
-      const auto& A = k.tensors[s.a].spins;
-      const auto& B = k.tensors[s.b].spins;
-      group_table(s.bs, A, q, tables);
-      group_table(s.ms, A, q, tables);
-      group_table(s.ks, A, q, tables);
-      group_table(s.bs, B, q, tables);
-      group_table(s.ks, B, q, tables);
-      group_table(s.ns, B, q, tables);
-      int64_t outs = (int64_t)x.nb * x.nm * x.nn;
-      x.n_tiles = k.big[si] ? (int32_t)((outs + k.tile - 1) / k.tile) : 0;
-      x.tile = k.tile;
-      if (k.big[si]) td[x.c].target = x.n_tiles;
+      x.tab = tab0 + k.tab_off[si];
+      const int64_t outs = (int64_t)x.nb * x.nm * x.nn;
+      const int32_t tile = k.step_tile[si];
+      x.n_tiles = k.big[si] ? (int32_t)((outs + tile - 1) / tile) : 0;
+      x.tile = tile;
       sd.push_back(x);
     }
-    // task groups
-    auto& G = groups[ki];
-    int32_t prev_done = -1;  // completion tensor of the previous group
-    TaskDesc cur;
-    bool open = true;
-    std::memset(&cur, 0, sizeof(cur));
-    cur.kind = TASK_SERIAL;
-    cur.knot = (int32_t)ki;
-    cur.first = s0;
-    cur.count = 0;
-    cur.flags = TF_SETUP;
-    std::vector<int32_t> produced;  // tensors produced by the open serial group
-    for (int32_t v = 0; v < (int32_t)k.vtx.size(); ++v) produced.push_back(t0 + k.vtx[v].tensor);
-    std::vector<int32_t> cur_deps;
-    auto add_dep = [&](std::vector<int32_t>& dl, int32_t t) {
-      if (std::find(dl.begin(), dl.end(), t) == dl.end()) dl.push_back(t);
-    };
-    auto flush = [&]() {
-      if (prev_done >= 0) add_dep(cur_deps, prev_done);
-      cur.dep_off = (int32_t)deps.size();
-      cur.n_deps = (int32_t)cur_deps.size();
-      for (int32_t t : cur_deps) deps.push_back(t);
-      // signal every produced tensor that someone outside may wait for
-      cur.sig_off = (int32_t)deps.size();
-      cur.n_sig = (int32_t)produced.size();
-      for (int32_t t : produced) deps.push_back(t);
-      Group g;
-      g.knot = (int32_t)ki;
-      g.tasks.push_back(cur);
-      G.push_back(std::move(g));
-      prev_done = produced.empty() ? prev_done : produced.back();
-      cur_deps.clear();
-      produced.clear();
-    };
-    for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
-      const StepDesc& x = sd[s0 + si];
-      if (!k.big[si]) {
-        if (!open) {
-          std::memset(&cur, 0, sizeof(cur));
-          cur.kind = TASK_SERIAL;
-          cur.knot = (int32_t)ki;
-          cur.first = s0 + si;
-          cur.count = 0;
-          cur.flags = 0;
-          open = true;
+
+    // ---- groups of this knot
+    std::vector<PGroup> pg;
+    {
+      PGroup cur{TASK_SERIAL, 0, 0, TF_SETUP, 0};
+      bool open = true;
+      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
+        if (!k.big[si]) {
+          if (!open) {
+            cur = PGroup{TASK_SERIAL, si, 0, 0, 0};
+            open = true;
+          }
+          cur.count++;
+          continue;
         }
-        for (int32_t op : {x.a, x.b})
-          if (std::find(produced.begin(), produced.end(), op) == produced.end())
-            add_dep(cur_deps, op);
-        cur.count++;
-        produced.push_back(x.c);
-        continue;
+        if (open) {
+          pg.push_back(cur);
+          open = false;
+        }
+        pg.push_back(PGroup{TASK_TILE, si, 1, 0, sd[s0 + si].n_tiles});
       }
-      if (open) {
-        flush();
-        open = false;
-      }
-      Group g;
-      g.knot = (int32_t)ki;
-      std::vector<int32_t> dl{x.a, x.b};
-      if (prev_done >= 0) add_dep(dl, prev_done);
-      int32_t doff = (int32_t)deps.size();
-      for (int32_t t : dl) deps.push_back(t);
-      int32_t soff = (int32_t)deps.size();
-      deps.push_back(x.c);
-      for (int32_t tile = 0; tile < x.n_tiles; ++tile) {
-        TaskDesc t;
-        std::memset(&t, 0, sizeof(t));
-        t.kind = TASK_TILE;
-        t.knot = (int32_t)ki;
-        t.first = s0 + si;
-        t.count = tile;
-        t.dep_off = doff;
-        t.n_deps = (int32_t)dl.size();
-        t.sig_off = soff;
-        t.n_sig = 1;
-        g.tasks.push_back(t);
-      }
-      G.push_back(std::move(g));
-      prev_done = x.c;
+      if (!open) cur = PGroup{TASK_SERIAL, (int32_t)k.steps.size(), 0, 0, 0};
+      cur.flags |= TF_FINAL;
+      pg.push_back(cur);
     }
-    if (!open) {
-      std::memset(&cur, 0, sizeof(cur));
-      cur.kind = TASK_SERIAL;
-      cur.knot = (int32_t)ki;
-      cur.first = s0 + (int32_t)k.steps.size();
-      cur.count = 0;
-      cur.flags = 0;
-      open = true;
+
+    // ---- LDS homes: tensors produced and consumed inside one serial group
+    {
+      const int32_t nt = (int32_t)k.tensors.size();
+      std::vector<int32_t> consumer(nt, -1);  // step index, or n_steps for the final
+      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
+        consumer[k.steps[si].a] = si;
+        consumer[k.steps[si].b] = si;
+      }
+      for (int32_t c : k.comps) consumer[c] = (int32_t)k.steps.size();
+      std::vector<int32_t> producer(nt, -1);  // -1: vertex tensor (setup)
+      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) producer[k.steps[si].c] = si;
+      const int64_t es = elem_bytes(k.precision);
+      const int64_t cap = k.lds_bytes / es;
+      for (const PGroup& g : pg) {
+        if (g.kind != TASK_SERIAL) continue;
+        const int32_t lo = g.first, hi = g.first + g.count;  // steps [lo, hi)
+        auto inside = [&](int32_t t) {
+          int32_t c = consumer[t];
+          if (c < 0) return false;
+          if (c == (int32_t)k.steps.size()) return (g.flags & TF_FINAL) != 0;
+          return c >= lo && c < hi;
+        };
+        FitAlloc la(cap);
+        std::vector<int64_t> loff(nt, -1);
+        int64_t peak = 0;
+        if (g.flags & TF_SETUP)
+          for (const auto& v : k.vtx)
+            if (inside(v.tensor)) {
+              int64_t o = la.alloc(k.tensors[v.tensor].size);
+              if (o >= 0) loff[v.tensor] = o;
+            }
+        peak = std::max(peak, la.top);
+        for (int32_t si = lo; si < hi; ++si) {
+          const PStep& s = k.steps[si];
+          if (inside(s.c)) {
+            int64_t o = la.alloc(k.tensors[s.c].size);
+            if (o >= 0) loff[s.c] = o;
+          }
+          peak = std::max(peak, la.top);
+          for (int32_t op : {s.a, s.b})
+            if (loff[op] >= 0) la.release(loff[op], k.tensors[op].size);
+        }
+        for (int32_t t = 0; t < nt; ++t)
+          if (loff[t] >= 0) td[t0 + t].lds_off = (int32_t)loff[t];
+        lds_used = std::max<int32_t>(lds_used, (int32_t)(peak * es));
+      }
     }
-    cur.flags |= TF_FINAL;
-    for (int32_t c : k.comps)
-      if (std::find(produced.begin(), produced.end(), t0 + c) == produced.end())
-        add_dep(cur_deps, t0 + c);
-    flush();
+
+    // ---- lay the groups out as tasks
+    double est = 0;
+    const int32_t g0 = (int32_t)groups.size();
+    for (size_t gi = 0; gi < pg.size(); ++gi) {
+      const PGroup& g = pg[gi];
+      GroupDesc G;
+      G.knot = (int32_t)ki;
+      G.first_task = (int32_t)tasks.size();
+      G.next = gi + 1 < pg.size() ? g0 + (int32_t)gi + 1 : -1;
+      G.n_pred = gi == 0 ? 0 : groups.back().n_tasks;
+      if (g.kind == TASK_SERIAL) {
+        // tensors made here: vertex tensors (ids t0..) and step outputs, consecutive
+        const int32_t n_vt = (int32_t)(k.tensors.size() - k.steps.size());
+        int32_t lo = (g.flags & TF_SETUP) ? t0 : t0 + n_vt + g.first;
+        int32_t len = ((g.flags & TF_SETUP) ? n_vt : 0) + g.count;
+        tasks.push_back({TASK_SERIAL, (int32_t)ki, g0 + (int32_t)gi, s0 + g.first, g.count, g.flags,
+                         lo, len});
+        G.n_tasks = 1;
+        for (int32_t si = g.first; si < g.first + g.count; ++si) {
+          const StepDesc& x = sd[s0 + si];
+          est += 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
+        }
+      } else {
+        for (int32_t tl = 0; tl < g.n_tiles; ++tl)
+          tasks.push_back({TASK_TILE, (int32_t)ki, g0 + (int32_t)gi, s0 + g.first, tl, 0, 0, 0});
+        G.n_tasks = g.n_tiles;
+        const StepDesc& x = sd[s0 + g.first];
+        est += 3.0 + double(x.tile) * x.nk / 512.0;
+      }
+      groups.push_back(G);
+    }
+    roots.emplace_back(-est, g0);
     kd.push_back(d);
     n_edges += k.n_edges;
     n_medges += (int64_t)k.medges.size();
   }
-
-  // interleave groups round-robin, knots with more groups first
-  std::vector<int32_t> order(knots.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return groups[a].size() > groups[b].size(); });
-  std::vector<TaskDesc> tasks;
-  size_t max_groups = 0;
-  for (auto& g : groups) max_groups = std::max(max_groups, g.size());
-  for (size_t r = 0; r < max_groups; ++r)
-    for (int32_t ki : order)
-      if (r < groups[ki].size())
-        for (auto& t : groups[ki][r].tasks) tasks.push_back(t);
+  std::stable_sort(roots.begin(), roots.end(),
+                   [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                     return a.first < b.first;
+                   });
+  std::vector<int32_t> root_tasks;
+  for (auto& r : roots) root_tasks.push_back(groups[r.second].first_task);
 
   h.n_tasks = (int32_t)tasks.size();
   h.n_knots = (int32_t)knots.size();
@@ -277,12 +359,25 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   h.n_members = (int32_t)members.size();
   h.n_factors = (int32_t)fac.size();
   h.n_tables = (int32_t)tables.size();
-  h.n_deps = (int32_t)deps.size();
+  h.n_groups = (int32_t)groups.size();
   h.n_edges = (int32_t)n_edges;
+  h.n_roots = (int32_t)root_tasks.size();
+  h.lds_bytes = (lds_used + 255) / 256 * 256;
 
   std::vector<uint8_t> img(sizeof(ImgHeader));
+  {
+    size_t total = 4096 + 256 * 18;
+    total += tasks.size() * sizeof(TaskDesc) + groups.size() * sizeof(GroupDesc) +
+             root_tasks.size() * 4 + kd.size() * sizeof(KnotDesc) +
+             td.size() * sizeof(TensorDesc) + sd.size() * sizeof(StepDesc) +
+             vd.size() * sizeof(VtxDesc) + vslot.size() * 4 + md.size() * sizeof(MEdge) +
+             members.size() * 4 + fac.size() * sizeof(Factor) + tables.size() * 4 + eps.size() +
+             comps.size() * 4;
+    img.reserve(total);
+  }
   h.o_tasks = put(img, tasks);
-  h.o_deps = put(img, deps);
+  h.o_groups = put(img, groups);
+  h.o_roots = put(img, root_tasks);
   h.o_knots = put(img, kd);
   h.o_tensors = put(img, td);
   h.o_steps = put(img, sd);
@@ -296,9 +391,14 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   h.o_comps = put(img, comps);
   h.image_bytes = align256((int64_t)img.size());
   img.resize(h.image_bytes);
-  // runtime state: ticket/error words, tensor states, weights
+  // runtime state: control words, ready queue, pending counters, tensor
+  // states, weights
   h.state_off = h.image_bytes;
-  int64_t st = 256;  // control words
+  int64_t st = CTRL_WORDS * 4;
+  h.o_queue = st;
+  st = align256(st + 4 * (int64_t)tasks.size());
+  h.o_pending = st;
+  st = align256(st + 4 * (int64_t)groups.size());
   h.o_tstate = st;
   st = align256(st + (int64_t)td.size() * (int64_t)sizeof(TensorState));
   h.o_weights = st;

@@ -57,8 +57,17 @@ struct PlanKnot {
   int64_t arena_elems = 0;
   int32_t tile = 256;
   int32_t big_log2 = 16;
+  int32_t lds_bytes = 32768;
   std::vector<uint8_t> big;                     // per step: split into tiles
+  std::vector<int32_t> step_tile;               // per step: outputs per tile
+  // gather tables of every step, concatenated (step i starts at tab_off[i]);
+  // filled by make_tables() and reused by every image built from this knot
+  std::vector<int32_t> tables;
+  std::vector<int32_t> tab_off;
 };
+
+// Fill k.tables / k.tab_off from the plan's steps.
+void make_tables(PlanKnot& k);
 
 // Build the device image for a list of knots (a batch of one or more).
 // out_slot of knot i is i.  Returns the image bytes; header filled in.
@@ -82,4 +91,6 @@ struct kn_batch {
   int32_t precision = 0;
   bool jones_only = false;
   int32_t grid_override = 0;
+  void* trace = nullptr;
+  size_t trace_bytes = 0;
 };

@@ -40,6 +40,11 @@ namespace kn {
 
 int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
 
+// Upper bound on the tiles of one step (a few per compute unit), and the
+// multiply-adds one tile aims at.
+constexpr double kMaxTiles = 1024;
+constexpr double kTileMacs = 32768;
+
 namespace {
 
 struct Simplified {
@@ -57,26 +62,24 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
   bool r1 = flags & 1, r2 = (flags & 2) && jones_only;
   // merge parallel classes; loops become factors (or stay as loops when R-I
   // is off: they are still constants, a loop never couples two spins)
-  std::map<std::pair<int32_t, int32_t>, int32_t> cls;
-  std::vector<std::pair<int32_t, int32_t>> ends;
+  std::vector<std::pair<int64_t, int32_t>> keyed;  // (u * nv + v, edge), u < v
+  keyed.reserve(ne);
   for (int32_t e = 0; e < ne; ++e) {
     int32_t u = g.uv[2 * e], v = g.uv[2 * e + 1];
     if (u == v) {
       k.factors.push_back({FAC_LOOP, e});
       continue;
     }
-    auto key = std::make_pair(std::min(u, v), std::max(u, v));
-    auto it = cls.find(key);
-    int32_t id;
-    if (it == cls.end()) {
-      id = (int32_t)k.medges.size();
-      cls.emplace(key, id);
+    keyed.emplace_back((int64_t)std::min(u, v) * nv + std::max(u, v), e);
+  }
+  std::sort(keyed.begin(), keyed.end());
+  std::vector<std::pair<int32_t, int32_t>> ends;
+  for (size_t i = 0; i < keyed.size(); ++i) {
+    if (i == 0 || keyed[i].first != keyed[i - 1].first) {
       k.medges.emplace_back();
-      ends.push_back(key);
-    } else {
-      id = it->second;
+      ends.emplace_back((int32_t)(keyed[i].first / nv), (int32_t)(keyed[i].first % nv));
     }
-    k.medges[id].push_back(e);
+    k.medges.back().push_back(keyed[i].second);
   }
   (void)r1;
   const int32_t nm = (int32_t)k.medges.size();
@@ -140,11 +143,16 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
 }
 
 // Max degree over the minors of the paper's greedy edge contraction on the
-// multigraph (each merged edge counted with its multiplicity).
+// multigraph (each merged edge counted with its multiplicity), Sec. III:
+// repeatedly contract the edge whose merged vertex has the smallest degree
+// deg(u) + deg(v) - 2 mult(u, v).  Merging u and v leaves every other
+// vertex's degree unchanged, so only candidates at the merged vertex change;
+// stale heap entries are skipped by a per-vertex version stamp.
 int32_t paper_delta_h(const Simplified& s) {
   const int32_t n = s.n_spins;
   std::vector<std::unordered_map<int32_t, int32_t>> adj(n);
-  std::vector<int32_t> deg(n, 0);
+  std::vector<int32_t> deg(n, 0), ver(n, 0), rep(n);
+  for (int32_t v = 0; v < n; ++v) rep[v] = v;
   for (size_t i = 0; i < s.e.size(); ++i) {
     auto [u, v] = s.e[i];
     int32_t w = std::max(1, s.e_mult[i]);
@@ -155,34 +163,46 @@ int32_t paper_delta_h(const Simplified& s) {
   }
   int32_t best = 0;
   for (int32_t v = 0; v < n; ++v) best = std::max(best, deg[v]);
-  std::vector<uint8_t> alive(n, 1);
-  while (true) {
-    // cheapest edge contraction: smallest resulting degree
-    int32_t bu = -1, bv = -1, bd = 0;
-    for (int32_t u = 0; u < n; ++u) {
-      if (!alive[u]) continue;
-      for (auto& [v, m] : adj[u]) {
-        if (v <= u) continue;
-        int32_t d = deg[u] + deg[v] - 2 * m;
-        if (bu < 0 || d < bd) { bu = u; bv = v; bd = d; }
-      }
+  struct E {
+    int32_t d, u, v, vu, vv;
+    bool operator<(const E& o) const {
+      if (d != o.d) return d > o.d;
+      if (u != o.u) return u > o.u;
+      return v > o.v;
     }
-    if (bu < 0) break;
-    // merge bv into bu
-    int32_t m_uv = adj[bu][bv];
-    adj[bu].erase(bv);
-    adj[bv].erase(bu);
-    deg[bu] -= m_uv;
-    deg[bv] -= m_uv;
-    for (auto& [w, m] : adj[bv]) {
-      adj[w].erase(bv);
-      adj[w][bu] += m;
-      adj[bu][w] += m;
+  };
+  std::priority_queue<E> pq;
+  auto push = [&](int32_t u, int32_t v, int32_t m) {
+    if (u > v) std::swap(u, v);
+    pq.push({deg[u] + deg[v] - 2 * m, u, v, ver[u], ver[v]});
+  };
+  for (int32_t u = 0; u < n; ++u)
+    for (auto& [v, m] : adj[u])
+      if (v > u) push(u, v, m);
+  while (!pq.empty()) {
+    E e = pq.top();
+    pq.pop();
+    if (e.vu != ver[e.u] || e.vv != ver[e.v]) continue;
+    auto it = adj[e.u].find(e.v);
+    if (it == adj[e.u].end()) continue;
+    // merge the smaller adjacency into the larger
+    int32_t a = e.u, b = e.v;
+    if (adj[a].size() < adj[b].size()) std::swap(a, b);
+    int32_t m_ab = adj[a][b];
+    adj[a].erase(b);
+    adj[b].erase(a);
+    for (auto& [w, m] : adj[b]) {
+      adj[w].erase(b);
+      adj[w][a] += m;
+      adj[a][w] += m;
     }
-    deg[bu] += deg[bv];
-    adj[bv].clear();
-    alive[bv] = 0;
-    best = std::max(best, deg[bu]);
+    adj[b].clear();
+    deg[a] = deg[a] + deg[b] - 2 * m_ab;
+    deg[b] = 0;
+    ver[a]++;
+    ver[b]++;
+    best = std::max(best, deg[a]);
+    for (auto& [w, m] : adj[a]) push(a, w, m);
   }
   return best;
 }
@@ -198,6 +218,254 @@ struct Cand {
   }
 };
 
+// Pairwise contraction of spin-indexed tensors.  A spin is summed when the two
+// operands are its last holders (cnt == 2); otherwise it stays as a batch
+// index of the result.
+struct Orderer {
+  int32_t n, q;
+  std::vector<PTensor> T;
+  std::vector<PStep> S;
+  std::vector<int32_t> cnt;
+  std::vector<std::vector<int32_t>> hold;  // live holders of each spin (lazily compacted)
+  std::vector<uint8_t> alive;
+  std::vector<uint32_t> mark;
+  uint32_t stamp = 0;
+  std::vector<double> qpow;
+
+  Orderer(int32_t n_, int32_t q_, const std::vector<PTensor>& init)
+      : n(n_), q(q_), T(init), cnt(n_, 0), hold(n_), alive(init.size(), 1), mark(n_, 0),
+        qpow(64) {
+    T.reserve(2 * init.size() + 1);
+    alive.reserve(2 * init.size() + 1);
+    for (int32_t t = 0; t < (int32_t)T.size(); ++t)
+      for (int32_t sp : T[t].spins) {
+        cnt[sp]++;
+        hold[sp].push_back(t);
+      }
+    qpow[0] = 1;
+    for (int i = 1; i < 64; ++i) qpow[i] = qpow[i - 1] * q;
+  }
+
+  // rank of the result and of the union
+  void ranks(int32_t a, int32_t b, int32_t& rc, int32_t& uni) {
+    const auto& A = T[a].spins;
+    const auto& B = T[b].spins;
+    ++stamp;
+    for (int32_t x : A) mark[x] = stamp;
+    int32_t kk = 0;
+    uni = (int32_t)A.size();
+    for (int32_t x : B) {
+      if (mark[x] != stamp) uni++;
+      else if (cnt[x] == 2) kk++;
+    }
+    rc = uni - kk;
+  }
+
+  int32_t contract(int32_t a, int32_t b) {
+    // the larger operand first (its private spins are the GEMM rows)
+    if (T[b].spins.size() > T[a].spins.size()) std::swap(a, b);
+    PStep stp;
+    stp.a = a;
+    stp.b = b;
+    {
+      const auto& A = T[a].spins;
+      const auto& B = T[b].spins;
+      ++stamp;
+      for (int32_t x : B) mark[x] = stamp;
+      for (int32_t x : A) {
+        if (mark[x] != stamp) stp.ms.push_back(x);
+        else if (cnt[x] == 2) stp.ks.push_back(x);
+        else stp.bs.push_back(x);
+      }
+      ++stamp;
+      for (int32_t x : A) mark[x] = stamp;
+      for (int32_t x : B)
+        if (mark[x] != stamp) stp.ns.push_back(x);
+    }
+    PTensor ct;
+    ct.spins.reserve(stp.bs.size() + stp.ms.size() + stp.ns.size());
+    for (int32_t x : stp.bs) ct.spins.push_back(x);
+    for (int32_t x : stp.ms) ct.spins.push_back(x);
+    for (int32_t x : stp.ns) ct.spins.push_back(x);
+    int32_t cid = (int32_t)T.size();
+    stp.c = cid;
+    for (int32_t x : stp.ks) cnt[x] = 0;
+    for (int32_t x : stp.bs) cnt[x]--;
+    alive[a] = alive[b] = 0;
+    alive.push_back(1);
+    for (int32_t x : ct.spins) hold[x].push_back(cid);
+    T.push_back(std::move(ct));
+    S.push_back(std::move(stp));
+    return cid;
+  }
+
+  // live holders of spin x (compacts the list)
+  std::vector<int32_t>& holders(int32_t x) {
+    auto& hl = hold[x];
+    size_t w = 0;
+    for (size_t i = 0; i < hl.size(); ++i)
+      if (alive[hl[i]]) hl[w++] = hl[i];
+    hl.resize(w);
+    return hl;
+  }
+
+  // Greedy: contract the pair (sharing a spin) with the smallest key.
+  // strategy 0: size(C) - size(A) - size(B); 1: rank(C).  Ties: flops, ids.
+  void greedy(int32_t strategy) {
+    std::vector<uint32_t> seen(2 * T.size() + 2, 0);
+    uint32_t tstamp = 0;
+    auto cost = [&](int32_t a, int32_t b, Cand& c) {
+      int32_t rc, uni;
+      ranks(a, b, rc, uni);
+      if (strategy == 1) c.k1 = rc;
+      else c.k1 = qpow[std::min(rc, 63)] - qpow[T[a].spins.size()] - qpow[T[b].spins.size()];
+      c.k2 = qpow[std::min(uni, 63)];
+      c.a = std::min(a, b);
+      c.b = std::max(a, b);
+    };
+    std::vector<Cand> store;
+    store.reserve(16 * T.size() + 16);
+    std::priority_queue<Cand> pq(std::less<Cand>(), std::move(store));
+    auto push_pairs = [&](int32_t a) {
+      if ((size_t)a >= seen.size()) seen.resize(2 * a + 2, 0);
+      ++tstamp;
+      seen[a] = tstamp;
+      for (int32_t sp : T[a].spins)
+        for (int32_t b : holders(sp)) {
+          if (seen[b] == tstamp) continue;
+          seen[b] = tstamp;
+          Cand c;
+          cost(a, b, c);
+          pq.push(c);
+        }
+    };
+    const int32_t n0 = (int32_t)T.size();
+    for (int32_t t = 0; t < n0; ++t) push_pairs(t);
+    while (!pq.empty()) {
+      Cand c = pq.top();
+      pq.pop();
+      if (!alive[c.a] || !alive[c.b]) continue;
+      Cand fresh;
+      cost(c.a, c.b, fresh);
+      if (fresh.k1 != c.k1 || fresh.k2 != c.k2) {  // counts changed since the push
+        pq.push(fresh);
+        continue;
+      }
+      push_pairs(contract(c.a, c.b));
+    }
+  }
+
+  // Variable elimination in min-fill order on the primal graph of the tensors
+  // (spins adjacent when some tensor holds both); eliminating a spin contracts
+  // its holders pairwise, smallest first, and the last pair sums it.
+  void minfill() {
+    const int32_t W = (n + 63) / 64;
+    std::vector<uint64_t> adj((size_t)n * W, 0);
+    auto has = [&](int32_t a, int32_t b) { return (adj[(size_t)a * W + (b >> 6)] >> (b & 63)) & 1; };
+    auto set = [&](int32_t a, int32_t b) {
+      adj[(size_t)a * W + (b >> 6)] |= uint64_t(1) << (b & 63);
+      adj[(size_t)b * W + (a >> 6)] |= uint64_t(1) << (a & 63);
+    };
+    for (const auto& t : T)
+      for (size_t i = 0; i < t.spins.size(); ++i)
+        for (size_t j = i + 1; j < t.spins.size(); ++j) set(t.spins[i], t.spins[j]);
+    std::vector<uint8_t> gone(n, 0);
+    std::vector<int32_t> fill(n, 0), deg(n, 0);
+    std::vector<int32_t> nb;
+    auto neigh = [&](int32_t v, std::vector<int32_t>& out) {
+      out.clear();
+      for (int32_t w = 0; w < W; ++w) {
+        uint64_t m = adj[(size_t)v * W + w];
+        while (m) {
+          int b = __builtin_ctzll(m);
+          m &= m - 1;
+          out.push_back(w * 64 + b);
+        }
+      }
+    };
+    auto eval = [&](int32_t v) {
+      neigh(v, nb);
+      deg[v] = (int32_t)nb.size();
+      int64_t missing = 0;
+      for (int32_t a : nb) {
+        // neighbours of v not adjacent to a (a itself included once)
+        int64_t c = 0;
+        for (int32_t w = 0; w < W; ++w)
+          c += __builtin_popcountll(adj[(size_t)v * W + w] & ~adj[(size_t)a * W + w]);
+        missing += c - 1;
+      }
+      fill[v] = (int32_t)(missing / 2);
+    };
+    for (int32_t v = 0; v < n; ++v) eval(v);
+    std::vector<int32_t> nv, touched;
+    std::vector<uint32_t> tmark(n, 0);
+    uint32_t ts = 0;
+    for (int32_t it = 0; it < n; ++it) {
+      int32_t best = -1;
+      for (int32_t v = 0; v < n; ++v) {
+        if (gone[v]) continue;
+        if (best < 0 || fill[v] < fill[best] || (fill[v] == fill[best] && deg[v] < deg[best]))
+          best = v;
+      }
+      const int32_t x = best;
+      // contract the holders of x pairwise, smallest first
+      if (cnt[x] > 0) {
+        for (;;) {
+          auto& hl = holders(x);
+          if (hl.size() < 2) break;
+          int32_t a = -1, b = -1;
+          for (int32_t t : hl) {
+            if (a < 0 || T[t].spins.size() < T[a].spins.size()) {
+              b = a;
+              a = t;
+            } else if (b < 0 || T[t].spins.size() < T[b].spins.size()) {
+              b = t;
+            }
+          }
+          contract(a, b);
+        }
+      }
+      // eliminate x from the graph: its neighbours become a clique
+      neigh(x, nv);
+      for (size_t i = 0; i < nv.size(); ++i)
+        for (size_t j = i + 1; j < nv.size(); ++j) set(nv[i], nv[j]);
+      for (int32_t a : nv) {
+        adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
+      }
+      for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
+      gone[x] = 1;
+      // fill values change within two hops of x
+      ++ts;
+      touched.clear();
+      for (int32_t a : nv) {
+        if (tmark[a] != ts) { tmark[a] = ts; touched.push_back(a); }
+        neigh(a, nb);
+        for (int32_t b2 : nb)
+          if (tmark[b2] != ts) { tmark[b2] = ts; touched.push_back(b2); }
+      }
+      for (int32_t a : touched)
+        if (!gone[a]) eval(a);
+    }
+  }
+
+  // Roofline-modelled time of the plan: per step max(flops/peak, bytes/bw)
+  // plus a fixed per-step latency.
+  double model_cost(int32_t precision) const {
+    const double peak = precision == 1 ? 157.3e12 : 78.6e12, bw = 8.0e12, lat = 0.3e-6;
+    const double es = precision == 1 ? 8 : 16;
+    double t = 0;
+    for (const auto& st : S) {
+      double macs = qpow[std::min<size_t>(st.bs.size() + st.ms.size() + st.ns.size() +
+                                              st.ks.size(), 63)];
+      double by = es * (qpow[std::min<size_t>(T[st.a].spins.size(), 63)] +
+                        qpow[std::min<size_t>(T[st.b].spins.size(), 63)] +
+                        qpow[std::min<size_t>(T[st.c].spins.size(), 63)]);
+      t += std::max(8.0 * macs / peak, by / bw) + lat;
+    }
+    return t;
+  }
+};
+
 }  // namespace
 
 // Build tensors, order and arena for one knot.  Returns KN_OK or an error.
@@ -210,6 +478,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.eps = g.eps;
   k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
   k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
+  k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
   {
     double qq = q;
     if (q < 4) {
@@ -224,7 +493,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   const int32_t n = s.n_spins;
   st.n_edges_simplified = (int32_t)s.e.size();
   st.n_vertices_simplified = n;
-  st.delta_h_paper = paper_delta_h(s);
+  st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
 
   // ---- absorption: orient edges by a minimum-degree elimination order
   std::vector<std::vector<std::pair<int32_t, int32_t>>> adj(n);  // (nbr, medge)
@@ -292,101 +561,47 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   const int32_t n_vt = (int32_t)k.tensors.size();
   st.n_vertex_tensors = n_vt;
 
-  // ---- greedy pairwise order over spin-indexed tensors
-  std::vector<int32_t> cnt(n, 0);
-  std::vector<std::vector<int32_t>> hold(n);
-  std::vector<uint8_t> alive(n_vt, 1);
-  for (int32_t t = 0; t < n_vt; ++t)
-    for (int32_t sp : k.tensors[t].spins) {
-      cnt[sp]++;
-      hold[sp].push_back(t);
-    }
-  for (int32_t sp = 0; sp < n; ++sp)
-    if (cnt[sp] == 1) return KN_E_INVALID;  // private spin left: planner bug guard
-  std::vector<double> qpow(64);
-  qpow[0] = 1;
-  for (int i = 1; i < 64; ++i) qpow[i] = qpow[i - 1] * q;
-  auto cost = [&](int32_t a, int32_t b, Cand& c) {
-    const auto& A = k.tensors[a].spins;
-    const auto& B = k.tensors[b].spins;
-    int32_t uni = (int32_t)A.size(), kk = 0;
-    for (int32_t x : B) {
-      bool inA = std::find(A.begin(), A.end(), x) != A.end();
-      if (!inA) uni++;
-      else if (cnt[x] == 2) kk++;
-    }
-    int32_t rc = uni - kk;
-    if (o.strategy == 1) c.k1 = rc;
-    else c.k1 = qpow[std::min(rc, 63)] - qpow[A.size()] - qpow[B.size()];
-    c.k2 = qpow[std::min(uni, 63)];
-    c.a = std::min(a, b);
-    c.b = std::max(a, b);
-  };
-  std::priority_queue<Cand> pq;
-  auto push_pairs = [&](int32_t a) {
-    std::vector<int32_t> seen;
-    for (int32_t sp : k.tensors[a].spins)
-      for (int32_t b : hold[sp]) {
-        if (b == a || !alive[b]) continue;
-        if (std::find(seen.begin(), seen.end(), b) != seen.end()) continue;
-        seen.push_back(b);
-        Cand c;
-        cost(a, b, c);
-        pq.push(c);
-      }
-  };
-  for (int32_t t = 0; t < n_vt; ++t) push_pairs(t);
-  while (!pq.empty()) {
-    Cand c = pq.top();
-    pq.pop();
-    if (!alive[c.a] || !alive[c.b]) continue;
-    // recompute: counts may have changed since the candidate was pushed
-    Cand fresh;
-    cost(c.a, c.b, fresh);
-    if (fresh.k1 != c.k1 || fresh.k2 != c.k2) {
-      pq.push(fresh);
-      continue;
-    }
-    int32_t a = c.a, b = c.b;
-    // put the larger operand first (rows come from A)
-    if (k.tensors[b].spins.size() > k.tensors[a].spins.size()) std::swap(a, b);
-    const auto A = k.tensors[a].spins;
-    const auto B = k.tensors[b].spins;
-    PStep stp;
-    stp.a = a;
-    stp.b = b;
-    for (int32_t x : A) {
-      bool inB = std::find(B.begin(), B.end(), x) != B.end();
-      if (!inB) stp.ms.push_back(x);
-      else if (cnt[x] == 2) stp.ks.push_back(x);
-      else stp.bs.push_back(x);
-    }
-    for (int32_t x : B)
-      if (std::find(A.begin(), A.end(), x) == A.end()) stp.ns.push_back(x);
-    PTensor ct;
-    for (int32_t x : stp.bs) ct.spins.push_back(x);
-    for (int32_t x : stp.ms) ct.spins.push_back(x);
-    for (int32_t x : stp.ns) ct.spins.push_back(x);
-    int32_t cid = (int32_t)k.tensors.size();
-    stp.c = cid;
-    for (int32_t x : stp.ks) cnt[x] = 0;
-    for (int32_t x : stp.bs) cnt[x]--;
-    alive[a] = alive[b] = 0;
-    alive.push_back(1);
-    for (int32_t x : ct.spins) hold[x].push_back(cid);
-    k.tensors.push_back(std::move(ct));
-    k.steps.push_back(std::move(stp));
-    push_pairs(cid);
+  // ---- pairwise contraction order
+  {
+    std::vector<int32_t> cnt0(n, 0);
+    for (int32_t t = 0; t < n_vt; ++t)
+      for (int32_t sp : k.tensors[t].spins) cnt0[sp]++;
+    for (int32_t sp = 0; sp < n; ++sp)
+      if (cnt0[sp] == 1) return KN_E_INVALID;  // private spin left: planner bug guard
   }
-  for (int32_t t = 0; t < (int32_t)k.tensors.size(); ++t)
-    if (alive[t]) {
-      if (!k.tensors[t].spins.empty()) return KN_E_INVALID;  // guard
-      k.comps.push_back(t);
+  {
+    const int32_t strat = o.strategy;
+    Orderer best(n, q, k.tensors);
+    bool have = false;
+    double best_cost = 0;
+    for (int32_t sgy : {0, 1, 2}) {
+      if (strat != 3 && sgy != strat) continue;
+      if (strat == 3 && sgy == 1) continue;  // auto: greedy-size vs min-fill
+      Orderer cand(n, q, k.tensors);
+      if (sgy == 2) cand.minfill();
+      else cand.greedy(sgy);
+      double c = cand.model_cost(o.precision);
+      if (!have || c < best_cost) {
+        best = std::move(cand);
+        best_cost = c;
+        have = true;
+      }
     }
+    k.tensors = std::move(best.T);
+    k.steps = std::move(best.S);
+    for (int32_t t = 0; t < (int32_t)k.tensors.size(); ++t)
+      if (best.alive[t]) {
+        if (!k.tensors[t].spins.empty()) return KN_E_INVALID;  // guard
+        k.comps.push_back(t);
+      }
+  }
   st.n_components = (int32_t)k.comps.size();
   st.n_steps = (int32_t)k.steps.size();
 
   // ---- sizes, statistics, tile decisions
+  std::vector<double> qpow(64);
+  qpow[0] = 1;
+  for (int i = 1; i < 64; ++i) qpow[i] = qpow[i - 1] * q;
   const int64_t es = elem_bytes(o.precision);
   double flops = 0, bytes = 0, maxlog = 0;
   int32_t maxrank = 0;
@@ -403,6 +618,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     maxlog = std::max(maxlog, std::log2(sz));
   }
   k.big.assign(k.steps.size(), 0);
+  k.step_tile.assign(k.steps.size(), k.tile);
   for (size_t i = 0; i < k.steps.size(); ++i) {
     auto& sp = k.steps[i];
     double nb = qpow[sp.bs.size()], nm = qpow[sp.ms.size()], nn = qpow[sp.ns.size()],
@@ -411,6 +627,14 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     bytes += es * double(k.tensors[sp.a].size + k.tensors[sp.b].size + k.tensors[sp.c].size);
     double macs = nb * nm * nn * nk;
     k.big[i] = macs >= std::ldexp(1.0, k.big_log2) ? 1 : 0;
+    // a serial step stages its gather tables in LDS; larger ones are tiled
+    if (2 * nb + nm + 2 * nk + nn > kTabBuf) k.big[i] = 1;
+    // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
+    const double outs = nb * nm * nn;
+    double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
+                                     : std::max(1.0, std::floor(kTileMacs / nk));
+    if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
+    k.step_tile[i] = (int32_t)std::min(tile, outs);
   }
   st.flops = flops;
   st.bytes = bytes;
@@ -477,13 +701,15 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
 static kn_plan_opts default_opts() {
   kn_plan_opts o;
   std::memset(&o, 0, sizeof(o));
-  o.strategy = 0;
+  o.strategy = 3;
   o.precision = 0;
   o.simplify = 3;
   o.jones_only = 1;
   o.mem_budget_bytes = 0;
   o.tile_outputs = 0;
   o.big_step_macs_log2 = 0;
+  o.paper_stats = 0;
+  o.lds_bytes = 0;
   return o;
 }
 
@@ -494,9 +720,9 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (!g) return KN_E_INVALID;
   if (q < 2 || q > 8) return KN_E_UNSUPPORTED;
   kn_plan_opts o = opts ? *opts : default_opts();
-  if (o.strategy < 0 || o.strategy > 1 || o.precision < 0 || o.precision > 1 ||
+  if (o.strategy < 0 || o.strategy > 3 || o.precision < 0 || o.precision > 1 ||
       o.simplify < 0 || o.simplify > 3 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
-      o.big_step_macs_log2 > 40)
+      o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304)
     return KN_E_INVALID;
   if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
   kn_plan* p = new (std::nothrow) kn_plan();
@@ -505,6 +731,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   try {
     rc = kn::make_plan(*g, q, o, p->k, p->stats);
     if (rc == KN_OK) {
+      kn::make_tables(p->k);
       std::vector<const kn::PlanKnot*> one{&p->k};
       p->image = kn::build_image(one);
       const auto* h = reinterpret_cast<const kn::ImgHeader*>(p->image.data());

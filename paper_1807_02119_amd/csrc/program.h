@@ -3,10 +3,13 @@
 //
 // An image describes the full contraction of one or more tensor networks G_T
 // (one per knot, Sec. III of arXiv:1807.02119): the vertex tensors built from
-// absorbed edge matrices, the pairwise contraction steps, and a list of tasks
-// that workgroups take in order from a global ticket.  Everything is plain
-// old data addressed by byte offsets from the start of the image, so the
-// image can be copied to the device verbatim.
+// absorbed edge matrices, the pairwise contraction steps, and the tasks that
+// perform them.  Tasks are organised in groups; the groups of one knot form a
+// chain (group g+1 starts when every task of group g has finished).  A group
+// is either one serial task (a run of small steps done by one workgroup, with
+// the knot's setup and/or final reduction) or the tiles of one large step.
+// Everything is plain old data addressed by byte offsets from the start of
+// the image, so the image is copied to the device verbatim.
 //
 // Workspace layout (device): [ image | runtime state | tensor arena ], each
 // part 256-byte aligned; offsets are recorded in the header.
@@ -15,13 +18,17 @@
 
 namespace kn {
 
-constexpr int32_t kMagic = 0x4b4e4731;  // "KNG1"
+constexpr int32_t kMagic = 0x4b4e4732;  // "KNG2"
 constexpr int32_t kBlock = 256;         // threads per workgroup of the engine
+// Fixed LDS areas of a workgroup (the tensor arena follows them):
+constexpr int32_t kTabBuf = 3072;   // gather-table entries staged per chunk of serial steps
+constexpr int32_t kDescBuf = 64;    // step descriptors staged per chunk
+constexpr int32_t kStateCap = 768;  // tensor states cached for the running serial task
 
 enum TaskKind : int32_t {
   // One workgroup runs, in order: the knot's setup (edge weights + vertex
-  // tensors) if flags&1, steps [first, first+count) entirely, and the knot's
-  // final reduction to Z if flags&2.
+  // tensors) if flags & TF_SETUP, steps [first, first+count) entirely, and
+  // the knot's final reduction to Z if flags & TF_FINAL.
   TASK_SERIAL = 0,
   // One tile (outputs [count*tile, (count+1)*tile)) of step `first`.
   TASK_TILE = 1,
@@ -39,15 +46,19 @@ struct ImgHeader {
   int32_t precision;  // 0 complex128, 1 complex64
   int32_t n_tasks, n_knots, n_tensors, n_steps;
   int32_t n_vtx, n_medges, n_members, n_factors;
-  int32_t n_tables, n_deps;
-  int32_t n_edges;   // original edges over all knots
-  int32_t tile;      // outputs per tile
-  int64_t o_tasks, o_deps, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
+  int32_t n_tables, n_groups;
+  int32_t n_edges;    // original edges over all knots
+  int32_t n_roots;    // first groups of the knots, in start-priority order
+  int32_t lds_bytes;  // per-workgroup LDS arena for serial tasks (bytes)
+  int32_t pad0;
+  int64_t o_tasks, o_groups, o_roots, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
   int64_t o_medges, o_members, o_factors, o_tables, o_eps, o_comps;
   int64_t image_bytes;
   // runtime state (relative to the workspace base)
   int64_t state_off, state_bytes;
-  int64_t o_tstate;   // TensorState[n_tensors] (relative to state)
+  int64_t o_queue;    // int32[n_tasks] ready queue (-1 = slot not yet written)
+  int64_t o_pending;  // int32[n_groups] unfinished predecessor tasks
+  int64_t o_tstate;   // TensorState[n_tensors]
   int64_t o_weights;  // complex128 x_e per original edge, then x_m per merged edge
   // tensor arena (relative to the workspace base), in complex entries
   int64_t arena_off, arena_elems;
@@ -55,11 +66,20 @@ struct ImgHeader {
 };
 
 struct TaskDesc {
-  int32_t kind, knot;
+  int32_t kind, knot, group;
   int32_t first, count;
   int32_t flags;
-  int32_t dep_off, n_deps;  // tensor ids whose producers must have finished
-  int32_t sig_off, n_sig;   // tensor ids whose `done` counter this task bumps
+  // serial tasks: tensor ids [state_lo, state_lo + state_len) are produced by
+  // this task (its vertex tensors and step outputs, consecutive ids); their
+  // states are kept in LDS while it runs
+  int32_t state_lo, state_len;
+};
+
+struct GroupDesc {
+  int32_t knot;
+  int32_t first_task, n_tasks;
+  int32_t next;    // next group of the same knot, -1 for the last
+  int32_t n_pred;  // tasks of the previous group (0 for a knot's first group)
 };
 
 struct KnotDesc {
@@ -76,9 +96,9 @@ struct KnotDesc {
 };
 
 struct TensorDesc {
-  int64_t off;     // complex entries from the arena base
-  int32_t size;    // entries
-  int32_t target;  // producer work units (1, or the producing step's tiles)
+  int64_t off;      // complex entries from the arena base (global home)
+  int32_t size;     // entries
+  int32_t lds_off;  // complex entries into the workgroup's LDS arena; -1 = global
 };
 
 struct StepDesc {
@@ -108,12 +128,31 @@ struct Factor {
 // Per-tensor runtime state.
 struct TensorState {
   int32_t shift;  // frexp exponent of max(|re|,|im|) over the raw entries
-                  // (INT32_MIN until written / for an all-zero tensor)
-  int32_t done;   // finished producer work units
+                  // (kShiftNone until written / for an all-zero tensor)
+  int32_t pad;
   int64_t exp2;   // true tensor = raw * 2^exp2
 };
 
+// Optional per-task trace record (device clock ticks, 100 MHz).
+struct TraceRec {
+  int64_t t_claim;  // slot claimed
+  int64_t t_start;  // task available, execution starts
+  int64_t t_end;    // execution finished
+  int32_t task;
+  int32_t wg;
+};
+
 constexpr int32_t kShiftNone = (-2147483647 - 1);
+
+// Byte offsets of the LDS areas; the tensor arena starts at kLdsArena.
+constexpr int32_t kLdsTab = 0;
+constexpr int32_t kLdsDesc = kLdsTab + kTabBuf * 4;
+constexpr int32_t kLdsShift = kLdsDesc + kDescBuf * (int32_t)sizeof(StepDesc);
+constexpr int32_t kLdsExp = (kLdsShift + kStateCap * 4 + 7) / 8 * 8;
+constexpr int32_t kLdsArena = (kLdsExp + kStateCap * 8 + 15) / 16 * 16;
+
+// control words at the start of the runtime state
+enum Ctrl : int32_t { CTRL_HEAD = 0, CTRL_TAIL = 1, CTRL_ERROR = 2, CTRL_WORDS = 64 };
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 

@@ -32,7 +32,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("simplify", ctypes.c_int32), ("jones_only", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
-                ("big_step_macs_log2", ctypes.c_int32)]
+                ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -93,7 +94,11 @@ _SIGS = {
     "kn_batch_contract": (I32, [P, P, P, ctypes.c_size_t, P, P]),
     "kn_batch_set_grid": (I32, [P, I32]),
     "kn_batch_image": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+    "kn_batch_set_trace": (I32, [P, P, ctypes.c_size_t]),
     "kn_batch_free": (None, [P]),
+    "kn_plan_many": (I32, [I32, PI32, PI32, PI8, PI32, ctypes.POINTER(PlanOpts), I32,
+                           ctypes.POINTER(P), ctypes.POINTER(P), PI32]),
+    "kn_jones_many": (I32, [I32, PI32, ctypes.POINTER(P), ctypes.POINTER(Scalar), PD, PD, PD]),
     "kn_status_string": (ctypes.c_char_p, [I32]),
     "kn_version": (ctypes.c_char_p, []),
 }
@@ -166,14 +171,14 @@ class Tait:
 class Plan:
     """Contraction plan for one knot at one q (kn_plan_create)."""
 
-    def __init__(self, tait: Tait, q: int, strategy=0, precision=0, simplify=None,
+    def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
-                 allow_budget=False):
+                 paper_stats=False, lds_bytes=0, allow_budget=False):
         L = lib()
         if simplify is None:
             simplify = 3 if jones_only else 1
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
-                     tile_outputs, big_step_macs_log2)
+                     tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -212,6 +217,77 @@ class Plan:
         if h and _lib is not None:
             _lib.kn_plan_free(h)
             self._h = None
+
+
+def _wrap_tait(h):
+    t = Tait.__new__(Tait)
+    t._h = h
+    nv, ne, w, tn = I32(), I32(), I32(), I32()
+    _check(lib().kn_tait_info(h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(w),
+                              ctypes.byref(tn)), "kn_tait_info")
+    t.n_vertices, t.n_edges, t.writhe, t.tait_number = nv.value, ne.value, w.value, tn.value
+    return t
+
+
+def _wrap_plan(h, tait, q, opts):
+    p = Plan.__new__(Plan)
+    p._h = h
+    p.status = 0
+    p.tait = tait
+    p.q = q
+    p.precision = opts.precision
+    p.jones_only = bool(opts.jones_only)
+    st = PlanStats()
+    _check(lib().kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
+    p.stats = st.as_dict()
+    return p
+
+
+def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
+              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0):
+    """Tait graphs and plans for many knots on the library's host thread pool
+    (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
+    L = lib()
+    n = len(pds)
+    ncr = np.array([np.asarray(p).reshape(-1, 4).shape[0] for p in pds], np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(p, np.int32).reshape(-1) for p in pds])
+                                if ncr.sum() else np.zeros(4, np.int32))
+    qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
+    if simplify is None:
+        simplify = 3 if jones_only else 1
+    o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
+                 big_step_macs_log2, 0, lds_bytes)
+    th = (P * n)()
+    ph = (P * n)()
+    stv = np.zeros(n, np.int32)
+    rc = L.kn_plan_many(n, ncr.ctypes.data_as(PI32), flat.ctypes.data_as(PI32), None,
+                        qa.ctypes.data_as(PI32), ctypes.byref(o), n_threads, th, ph,
+                        stv.ctypes.data_as(PI32))
+    taits = [_wrap_tait(P(h)) if h else None for h in th]
+    if rc != KN_OK:
+        for h in ph:
+            if h:
+                L.kn_plan_free(P(h))
+        raise KnError(rc, "kn_plan_many")
+    plans = [_wrap_plan(P(h), t, int(q), o) for h, t, q in zip(ph, taits, qa)]
+    return taits, plans
+
+
+def jones_many(qs, taits, z):
+    """kn_jones for many knots; z: (n, 3) float64 host array of kn_scalar.
+    Returns (v complex array, log2|v|, arg v)."""
+    n = len(taits)
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(n, 3)
+    qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
+    th = (P * n)(*[t._h for t in taits])
+    v = np.zeros(2 * n)
+    l2 = np.zeros(n)
+    ar = np.zeros(n)
+    _check(lib().kn_jones_many(n, qa.ctypes.data_as(PI32), th,
+                               z.ctypes.data_as(ctypes.POINTER(Scalar)),
+                               v.ctypes.data_as(PD), l2.ctypes.data_as(PD), ar.ctypes.data_as(PD)),
+           "kn_jones_many")
+    return v[0::2] + 1j * v[1::2], l2, ar
 
 
 def _torch():
@@ -331,6 +407,23 @@ class Batch:
         d, n = P(), ctypes.c_size_t()
         _check(lib().kn_batch_image(self._h, ctypes.byref(d), ctypes.byref(n)), "kn_batch_image")
         return ctypes.string_at(d, n.value)
+
+    def set_trace(self, trace=None):
+        """Record per-task timing into ``trace`` (a uint8 device tensor of at
+        least 32 * n_tasks bytes) on later launches; None switches it off."""
+        if trace is None:
+            _check(lib().kn_batch_set_trace(self._h, None, 0), "kn_batch_set_trace")
+        else:
+            _check(lib().kn_batch_set_trace(self._h, ctypes.c_void_p(trace.data_ptr()),
+                                            trace.numel() * trace.element_size()),
+                   "kn_batch_set_trace")
+        self._trace = trace
+
+    @staticmethod
+    def decode_trace(raw: bytes):
+        dt = np.dtype([("t_claim", "<i8"), ("t_start", "<i8"), ("t_end", "<i8"),
+                       ("task", "<i4"), ("wg", "<i4")])
+        return np.frombuffer(raw, dt)
 
     def set_grid(self, grid: int):
         _check(lib().kn_batch_set_grid(self._h, grid), "kn_batch_set_grid")

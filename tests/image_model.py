@@ -1,40 +1,47 @@
 """CPU model of the device program that libkn's planner writes.
 
-Test infrastructure: it reads a plan's image bytes (kn_plan_image) and
-executes the task list in order with numpy, following the semantics the HIP
-engine implements (setup -> gather-GEMM steps with power-of-two exponents ->
-final product).  It checks the host-side planner and image builder (tables,
-dependencies, arena layout) on the CPU; the device engine itself is checked
+Test infrastructure: it reads a program image (kn_plan_image /
+kn_batch_image) and executes it with numpy, following the semantics the HIP
+engine implements: a FIFO ready queue seeded with the knots' first groups,
+group chains, setup -> gather-GEMM steps with power-of-two exponents ->
+final product, and tensors homed in a per-task LDS arena or the global arena.
+It checks the host-side planner and image builder (tables, group order,
+arena and LDS layout, bounds) on the CPU; the device engine itself is checked
 against the oracle by the GPU parity tests.
 """
 
 from __future__ import annotations
 
 import math
+from collections import deque
 
 import numpy as np
 
 HDR = np.dtype([
     ("magic", "<i4"), ("precision", "<i4"), ("n_tasks", "<i4"), ("n_knots", "<i4"),
     ("n_tensors", "<i4"), ("n_steps", "<i4"), ("n_vtx", "<i4"), ("n_medges", "<i4"),
-    ("n_members", "<i4"), ("n_factors", "<i4"), ("n_tables", "<i4"), ("n_deps", "<i4"),
-    ("n_edges", "<i4"), ("tile", "<i4"),
-    ("o_tasks", "<i8"), ("o_deps", "<i8"), ("o_knots", "<i8"), ("o_tensors", "<i8"),
-    ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"), ("o_medges", "<i8"),
-    ("o_members", "<i8"), ("o_factors", "<i8"), ("o_tables", "<i8"), ("o_eps", "<i8"),
-    ("o_comps", "<i8"), ("image_bytes", "<i8"), ("state_off", "<i8"), ("state_bytes", "<i8"),
-    ("o_tstate", "<i8"), ("o_weights", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
+    ("n_members", "<i4"), ("n_factors", "<i4"), ("n_tables", "<i4"), ("n_groups", "<i4"),
+    ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("pad0", "<i4"),
+    ("o_tasks", "<i8"), ("o_groups", "<i8"), ("o_roots", "<i8"), ("o_knots", "<i8"),
+    ("o_tensors", "<i8"), ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"),
+    ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_tables", "<i8"),
+    ("o_eps", "<i8"), ("o_comps", "<i8"), ("image_bytes", "<i8"), ("state_off", "<i8"),
+    ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
+    ("o_weights", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
     ("workspace_bytes", "<i8")], align=True)
-TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "first", "count", "flags", "dep_off",
-                                      "n_deps", "sig_off", "n_sig")], align=True)
+TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "group", "first", "count", "flags",
+                                      "state_lo", "state_len")], align=True)
+GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", "n_pred")],
+                 align=True)
 KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
     "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps")], align=True)
-TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("target", "<i4")], align=True)
+TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "tab", "n_tiles",
                                       "tile")], align=True)
 VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
+TAB_CAP = 3072
 
 
 class Image:
@@ -42,13 +49,14 @@ class Image:
         self.raw = raw
         self.h = np.frombuffer(raw, HDR, 1)[0]
         h = self.h
-        assert h["magic"] == 0x4B4E4731
+        assert h["magic"] == 0x4B4E4732
 
         def arr(dt, off, n):
             return np.frombuffer(raw, dt, int(n), int(off))
 
         self.tasks = arr(TASK, h["o_tasks"], h["n_tasks"])
-        self.deps = arr("<i4", h["o_deps"], h["n_deps"])
+        self.groups = arr(GROUP, h["o_groups"], h["n_groups"])
+        self.roots = arr("<i4", h["o_roots"], h["n_roots"])
         self.knots = arr(KNOT, h["o_knots"], h["n_knots"])
         self.tensors = arr(TENSOR, h["o_tensors"], h["n_tensors"])
         self.steps = arr(STEP, h["o_steps"], h["n_steps"])
@@ -68,45 +76,76 @@ def run(raw: bytes, J=None):
     """Execute the image; returns a list of (mantissa, exp2) per knot."""
     im = Image(raw)
     h = im.h
+    es = 8 if h["precision"] else 16
+    lds_cap = int(h["lds_bytes"]) // es
     arena = np.zeros(int(h["arena_elems"]), np.complex128)
     nt = int(h["n_tensors"])
     shift = [None] * nt
     exp2 = [0] * nt
-    done = np.zeros(nt, np.int64)
+    finished = np.zeros(nt, bool)   # producer finished (visible to later groups)
     weights = np.zeros(int(h["n_edges"]) + int(h["n_medges"]), np.complex128)
     out = [None] * int(h["n_knots"])
-    # arena regions in use: check that no live tensor is overwritten
-    live = {}
 
-    for t in range(nt):
-        assert 0 <= int(im.tensors[t]["off"]) and \
-            int(im.tensors[t]["off"]) + int(im.tensors[t]["size"]) <= int(h["arena_elems"])
-    assert int(h["arena_off"]) + int(h["arena_elems"]) * (8 if h["precision"] else 16) \
-        <= int(h["workspace_bytes"])
-    assert int(h["state_off"]) + int(h["state_bytes"]) <= int(h["arena_off"])
+    # layout checks
     assert int(h["image_bytes"]) == len(raw)
-
-    def write_tensor(t, data):
+    assert int(h["state_off"]) + int(h["state_bytes"]) <= int(h["arena_off"])
+    assert int(h["arena_off"]) + int(h["arena_elems"]) * es <= int(h["workspace_bytes"])
+    for t in range(nt):
         off, size = int(im.tensors[t]["off"]), int(im.tensors[t]["size"])
-        for u, (o2, s2) in list(live.items()):
-            if u != t and o2 < off + size and off < o2 + s2:
-                raise AssertionError(f"tensor {t} overwrites live tensor {u}")
-        arena[off:off + size] = data
-        live[t] = (off, size)
+        lo = int(im.tensors[t]["lds_off"])
+        assert 0 <= off and off + size <= int(h["arena_elems"])
+        if lo >= 0:
+            assert lo + size <= lds_cap, "LDS tensor beyond the LDS arena"
+    for g in im.groups:
+        assert 0 <= g["first_task"] and g["first_task"] + g["n_tasks"] <= h["n_tasks"]
+        for t in range(int(g["first_task"]), int(g["first_task"] + g["n_tasks"])):
+            assert im.tasks[t]["knot"] == g["knot"]
 
-    def read(t):
-        off, size = int(im.tensors[t]["off"]), int(im.tensors[t]["size"])
+    # the LDS arena exists only while one serial task runs
+    live_g, live_l = {}, {}
+    state = {"lds": None}
+
+    def home(t):
+        return int(im.tensors[t]["lds_off"])
+
+    def write_tensor(t, data, task_local):
+        size = int(im.tensors[t]["size"])
+        assert data.size == size
+        lo = home(t)
+        if lo >= 0:
+            assert task_local, f"tensor {t} homed in LDS but written by a tile task"
+            for u, (o2, s2) in list(live_l.items()):
+                if u != t and o2 < lo + size and lo < o2 + s2:
+                    raise AssertionError(f"LDS tensor {t} overwrites live LDS tensor {u}")
+            state["lds"][lo:lo + size] = data
+            live_l[t] = (lo, size)
+        else:
+            off = int(im.tensors[t]["off"])
+            for u, (o2, s2) in list(live_g.items()):
+                if u != t and o2 < off + size and off < o2 + s2:
+                    raise AssertionError(f"tensor {t} overwrites live tensor {u}")
+            arena[off:off + size] = data
+            live_g[t] = (off, size)
+
+    def read(t, local):
+        size = int(im.tensors[t]["size"])
+        lo = home(t)
+        if lo >= 0:
+            assert t in local, f"LDS tensor {t} read outside the task that made it"
+            return state["lds"][lo:lo + size]
+        assert t in local or finished[t], f"tensor {t} read before its producer finished"
+        off = int(im.tensors[t]["off"])
         return arena[off:off + size]
 
     def sh(t):
         return 0 if shift[t] is None else shift[t]
 
-    local = set()  # tensors produced by the running task (visible to it at once)
-
-    def step(si):
+    def step(si, local):
         s = im.steps[si]
         nb, nm, nn, nk = (int(s[f]) for f in ("nb", "nm", "nn", "nk"))
         tab = int(s["tab"])
+        if not int(s["n_tiles"]):
+            assert 2 * nb + nm + 2 * nk + nn <= TAB_CAP, "serial step tables exceed LDS staging"
         tAb = im.tables[tab:tab + nb]
         tAm = im.tables[tab + nb:tab + nb + nm]
         tAk = im.tables[tab + nb + nm:tab + nb + nm + nk]
@@ -114,38 +153,53 @@ def run(raw: bytes, J=None):
         tBk = im.tables[tab + 2 * nb + nm + nk:tab + 2 * nb + nm + 2 * nk]
         tBn = im.tables[tab + 2 * nb + nm + 2 * nk:tab + 2 * nb + nm + 2 * nk + nn]
         a, b, c = int(s["a"]), int(s["b"]), int(s["c"])
-        for t in (a, b):
-            assert t in local or done[t] >= im.tensors[t]["target"], \
-                f"step {si} reads unfinished tensor {t}"
-        A = read(a)
-        B = read(b)
-        # every gather stays inside its operand
+        A = read(a, local)
+        B = read(b, local)
         assert int(tAb.max()) + int(tAm.max()) + int(tAk.max()) < A.size
         assert int(tBb.max()) + int(tBk.max()) + int(tBn.max()) < B.size
-        assert min(int(tAb.min()), int(tAm.min()), int(tAk.min()), int(tBb.min()),
-                   int(tBk.min()), int(tBn.min())) >= 0
+        assert min(int(x.min()) for x in (tAb, tAm, tAk, tBb, tBk, tBn)) >= 0
         assert nb * nm * nn == int(im.tensors[c]["size"])
         if int(s["n_tiles"]):
             assert int(s["n_tiles"]) * int(s["tile"]) >= nb * nm * nn
-            assert int(s["n_tiles"]) == int(im.tensors[c]["target"])
+            assert (int(s["n_tiles"]) - 1) * int(s["tile"]) < nb * nm * nn
         Am = A[tAb[:, None, None] + tAm[None, :, None] + tAk[None, None, :]]
         Bm = B[tBb[:, None, None] + tBk[None, :, None] + tBn[None, None, :]]
         C = np.matmul(Am, Bm).reshape(-1) * math.ldexp(1.0, -(sh(a) + sh(b)))
-        write_tensor(c, C)
+        write_tensor(c, C, task_local=not int(s["n_tiles"]))
         m = float(np.max(np.maximum(np.abs(C.real), np.abs(C.imag)))) if C.size else 0.0
         shift[c] = math.frexp(m)[1] if m > 0 else None
         exp2[c] = exp2[a] + exp2[b] + sh(a) + sh(b)
-        # operands are consumed exactly once
-        live.pop(a, None)
-        live.pop(b, None)
+        for op in (a, b):  # operands are consumed exactly once
+            live_g.pop(op, None)
+            live_l.pop(op, None)
+        local.add(c)
 
-    for ti, task in enumerate(im.tasks):
-        local.clear()
-        for d in im.deps[task["dep_off"]:task["dep_off"] + task["n_deps"]]:
-            assert done[d] >= im.tensors[d]["target"], f"task {ti} waits on unfinished tensor {d}"
+    def mul(z, e, f):
+        z = z * f
+        m = max(abs(z.real), abs(z.imag))
+        if m == 0 or not math.isfinite(m):
+            return z, e
+        s = math.frexp(m)[1]
+        return complex(math.ldexp(z.real, -s), math.ldexp(z.imag, -s)), e + s
+
+    queue = deque(int(r) for r in im.roots)
+    pending = {gi: int(g["n_pred"]) for gi, g in enumerate(im.groups)}
+    assert all(im.groups[im.tasks[r]["group"]]["n_pred"] == 0 for r in queue)
+    done_in_group = {}
+    executed = 0
+    while queue:
+        ti = queue.popleft()
+        task = im.tasks[ti]
+        executed += 1
         k = im.knots[task["knot"]]
         q = int(k["q"])
+        local = set()
         if task["kind"] == 0:
+            # the task's state range covers exactly the tensors it produces
+            lo, ln = int(task["state_lo"]), int(task["state_len"])
+            made = set(range(lo, lo + ln))
+            state["lds"] = np.zeros(max(lds_cap, 1), np.complex128)
+            live_l.clear()
             if task["flags"] & 1:
                 t = complex(k["t_re"], k["t_im"])
                 eo, mo = int(k["edge_off"]), int(k["medge_off"])
@@ -164,6 +218,7 @@ def run(raw: bytes, J=None):
                 for v in range(int(k["n_vtx"])):
                     vd = im.vtx[int(k["vtx_off"]) + v]
                     ns = int(vd["n_slots"])
+                    assert ns <= 8
                     xs = [weights[int(h["n_edges"]) + mo + int(im.vslot[int(vd["slot_off"]) + j])]
                           for j in range(ns)]
                     size = int(im.tensors[vd["tensor"]]["size"])
@@ -183,29 +238,20 @@ def run(raw: bytes, J=None):
                                     p *= xs[j]
                             acc += p
                         data[i] = acc
-                    write_tensor(int(vd["tensor"]), data)
+                    write_tensor(int(vd["tensor"]), data, task_local=True)
                     shift[int(vd["tensor"])] = 0
                     exp2[int(vd["tensor"])] = 0
                     local.add(int(vd["tensor"]))
             for si in range(int(task["first"]), int(task["first"]) + int(task["count"])):
-                step(si)
-                local.add(int(im.steps[si]["c"]))
+                step(si, local)
             if task["flags"] & 2:
                 z, e = 1 + 0j, 0
-
-                def mul(z, e, f):
-                    z = z * f
-                    m = max(abs(z.real), abs(z.imag))
-                    if m == 0 or not math.isfinite(m):
-                        return z, e
-                    s = math.frexp(m)[1]
-                    return complex(math.ldexp(z.real, -s), math.ldexp(z.imag, -s)), e + s
-
                 for i in range(int(k["n_comps"])):
                     t = int(im.comps[int(k["comp_off"]) + i])
-                    assert t in local or done[t] >= im.tensors[t]["target"]
                     e += exp2[t]
-                    z, e = mul(z, e, read(t)[0])
+                    z, e = mul(z, e, read(t, local)[0])
+                    live_l.pop(t, None)
+                    live_g.pop(t, None)
                 eo, mo = int(k["edge_off"]), int(k["medge_off"])
                 for i in range(int(k["n_factors"])):
                     f = im.factors[int(k["factor_off"]) + i]
@@ -217,14 +263,25 @@ def run(raw: bytes, J=None):
                 for i in range(int(k["n_iso"])):
                     z, e = mul(z, e, q)
                 out[int(k["out_slot"])] = (z, e)
-        else:
-            si = int(task["first"])
-            s = im.steps[si]
-            if task["count"] == 0:
-                step(si)
-        # publish: every signalled tensor's counter goes up by one
-        sig = im.deps[task["sig_off"]:task["sig_off"] + task["n_sig"]]
-        for t in sig:
-            done[t] += 1
-            assert done[t] <= im.tensors[t]["target"]
+            assert local == made, "state range differs from the tensors the task produced"
+            # LDS contents die with the task: nothing homed there may outlive it
+            assert not live_l, f"LDS tensors {list(live_l)} still live when their task ends"
+            for t in local:
+                if home(t) < 0:
+                    finished[t] = True
+        elif task["count"] == 0:
+            step(int(task["first"]), local)  # the model computes the whole step once
+        # group completion -> enqueue the next group
+        g = int(task["group"])
+        done_in_group[g] = done_in_group.get(g, 0) + 1
+        if done_in_group[g] == int(im.groups[g]["n_tasks"]):
+            if task["kind"] == 1:
+                finished[int(im.steps[int(task["first"])]["c"])] = True
+            nxt = int(im.groups[g]["next"])
+            if nxt >= 0:
+                pending[nxt] -= int(im.groups[g]["n_tasks"])
+                assert pending[nxt] == 0
+                G = im.groups[nxt]
+                queue.extend(range(int(G["first_task"]), int(G["first_task"] + G["n_tasks"])))
+    assert executed == int(h["n_tasks"]), "some tasks were never enqueued"
     return out

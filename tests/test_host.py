@@ -141,7 +141,8 @@ def test_plan_model_tiled_and_options():
                    dict(simplify=0, jones_only=True),
                    dict(simplify=1, jones_only=True),
                    dict(simplify=1, jones_only=False),
-                   dict(strategy=1)):
+                   dict(strategy=0), dict(strategy=1), dict(strategy=2),
+                   dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1)):
             _check_model(d, 3, **kw)
 
 
