@@ -61,7 +61,7 @@ struct DevProg {
   const MEdge* medges;
   const int32_t* members;
   const Factor* factors;
-  const int32_t* tables;
+  const int32_t* strides;
   const int8_t* eps;
   const int32_t* comps;
   int32_t* ctrl;
@@ -85,7 +85,7 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.medges = reinterpret_cast<const MEdge*>(img + h.o_medges);
   p.members = reinterpret_cast<const int32_t*>(img + h.o_members);
   p.factors = reinterpret_cast<const Factor*>(img + h.o_factors);
-  p.tables = reinterpret_cast<const int32_t*>(img + h.o_tables);
+  p.strides = reinterpret_cast<const int32_t*>(img + h.o_strides);
   p.eps = reinterpret_cast<const int8_t*>(img + h.o_eps);
   p.comps = reinterpret_cast<const int32_t*>(img + h.o_comps);
   p.ctrl = reinterpret_cast<int32_t*>(state);
@@ -113,6 +113,28 @@ __device__ inline void acc_mul(Cx<double>& z, int64_t& e, Cx<double> f) {
 }
 
 __device__ inline int32_t shift_of(int32_t s) { return s == kShiftNone ? 0 : s; }
+
+// Exact division by q (2 <= q <= 8) for 0 <= x < 2^31: with m = ceil(2^40 / q),
+// (x m) >> 40 = floor(x / q + e), 0 <= e < x / 2^40 < 2^-9, and the fractional
+// part of x / q is at most 7/8, so the floor is never pushed past an integer.
+struct QDiv {
+  uint64_t m;
+  int32_t q;
+  __device__ explicit QDiv(int32_t q_) : m(((uint64_t(1) << 40) + q_ - 1) / q_), q(q_) {}
+  __device__ inline int32_t div(int32_t x) const { return (int32_t)(((uint64_t)x * m) >> 40); }
+};
+
+// Offset of value `idx` of a spin group (r spins, strides str[], first spin
+// most significant) in its operand.
+__device__ inline int32_t group_off(int32_t idx, const int32_t* str, int32_t r, const QDiv& D) {
+  int32_t off = 0;
+  for (int32_t j = r - 1; j >= 0; --j) {
+    const int32_t qd = D.div(idx);
+    off += (idx - qd * D.q) * str[j];
+    idx = qd;
+  }
+  return off;
+}
 
 // Tensor data: the workgroup's LDS arena or the global arena (generic pointer).
 template <class T>
@@ -248,14 +270,36 @@ __device__ inline int32_t lanes_per_output(int64_t outs, int32_t nk) {
   return L;
 }
 
+// Operand offsets from generated tables (serial steps: tables in LDS).
+struct TabIx {
+  const int32_t *ab, *am, *ak, *bb, *bk, *bn;
+  __device__ inline int32_t a_row(int32_t b, int32_t m) const { return ab[b] + am[m]; }
+  __device__ inline int32_t b_col(int32_t b, int32_t n) const { return bb[b] + bn[n]; }
+  __device__ inline int32_t a_k(int32_t k) const { return ak[k]; }
+  __device__ inline int32_t b_k(int32_t k) const { return bk[k]; }
+};
+
+// Operand offsets for tiles: each spin group's offsets come from a table
+// generated in LDS when it fitted, else they are decoded from the strides.
+struct GenIx {
+  const int32_t *tab[6];  // A_b A_m A_k B_b B_k B_n (nullptr: decode)
+  const int32_t *str[6];
+  int32_t rank[6];
+  QDiv D;
+  __device__ inline int32_t off(int g, int32_t i) const {
+    return tab[g] ? tab[g][i] : group_off(i, str[g], rank[g], D);
+  }
+  __device__ inline int32_t a_row(int32_t b, int32_t m) const { return off(0, b) + off(1, m); }
+  __device__ inline int32_t b_col(int32_t b, int32_t n) const { return off(3, b) + off(5, n); }
+  __device__ inline int32_t a_k(int32_t k) const { return off(2, k); }
+  __device__ inline int32_t b_k(int32_t k) const { return off(4, k); }
+};
+
 // Outputs [o_begin, o_end) of C = A . B, each summed over k by L lanes of one
-// wavefront; returns this thread's max |.|.  Table pointers may point into
-// LDS or global memory.
-template <class T>
+// wavefront; returns this thread's max |.|.
+template <class T, class Ix>
 __device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict__ pb,
-                          Cx<T>* __restrict__ pc, const int32_t* tAb, const int32_t* tAm,
-                          const int32_t* tAk, const int32_t* tBb, const int32_t* tBk,
-                          const int32_t* tBn, int32_t nm, int32_t nn, int32_t nk,
+                          Cx<T>* __restrict__ pc, const Ix& ix, int32_t nm, int32_t nn, int32_t nk,
                           int64_t o_begin, int64_t o_end, T scale, int32_t L) {
   const int32_t mn = nm * nn;
   const int32_t lsub = threadIdx.x & (L - 1);
@@ -268,15 +312,15 @@ __device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict_
     const int32_t r = oi - b * mn;
     const int32_t m = r / nn;
     const int32_t n = r - m * nn;
-    const Cx<T>* ra = pa + tAb[b] + tAm[m];
-    const Cx<T>* rb = pb + tBb[b] + tBn[n];
+    const Cx<T>* ra = pa + ix.a_row(b, m);
+    const Cx<T>* rb = pb + ix.b_col(b, n);
     T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
     int32_t k = lsub;
     for (; k + 3 * L < nk; k += 4 * L) {
-      const Cx<T> x0 = ra[tAk[k]], x1 = ra[tAk[k + L]], x2 = ra[tAk[k + 2 * L]],
-                  x3 = ra[tAk[k + 3 * L]];
-      const Cx<T> y0 = rb[tBk[k]], y1 = rb[tBk[k + L]], y2 = rb[tBk[k + 2 * L]],
-                  y3 = rb[tBk[k + 3 * L]];
+      const Cx<T> x0 = ra[ix.a_k(k)], x1 = ra[ix.a_k(k + L)], x2 = ra[ix.a_k(k + 2 * L)],
+                  x3 = ra[ix.a_k(k + 3 * L)];
+      const Cx<T> y0 = rb[ix.b_k(k)], y1 = rb[ix.b_k(k + L)], y2 = rb[ix.b_k(k + 2 * L)],
+                  y3 = rb[ix.b_k(k + 3 * L)];
       cr0 = fma(x0.re, y0.re, cr0); cr0 = fma(-x0.im, y0.im, cr0);
       ci0 = fma(x0.re, y0.im, ci0); ci0 = fma(x0.im, y0.re, ci0);
       cr1 = fma(x1.re, y1.re, cr1); cr1 = fma(-x1.im, y1.im, cr1);
@@ -287,8 +331,8 @@ __device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict_
       ci1 = fma(x3.re, y3.im, ci1); ci1 = fma(x3.im, y3.re, ci1);
     }
     for (; k < nk; k += L) {
-      const Cx<T> x = ra[tAk[k]];
-      const Cx<T> y = rb[tBk[k]];
+      const Cx<T> x = ra[ix.a_k(k)];
+      const Cx<T> y = rb[ix.b_k(k)];
       cr0 = fma(x.re, y.re, cr0); cr0 = fma(-x.im, y.im, cr0);
       ci0 = fma(x.re, y.im, ci0); ci0 = fma(x.im, y.re, ci0);
     }
@@ -327,15 +371,25 @@ __device__ inline T step_scale(const States& st, int32_t a, int32_t b, int64_t& 
   return (T)ldexp(1.0, -sh);
 }
 
-// Serial steps [first, first + count): descriptors and gather tables are
-// staged in LDS one chunk at a time (tables of consecutive steps of a knot
-// are contiguous), then the chunk runs with no global round trip except the
-// operands that live in the global arena.
+__device__ inline int32_t step_tab_entries(const StepDesc& d) {
+  return 2 * d.nb + d.nm + 2 * d.nk + d.nn;
+}
+
+// Serial steps [first, first + count): descriptors are staged in LDS one
+// chunk at a time and the chunk's gather tables are generated there from the
+// strides; the chunk then runs with no global round trip except operands that
+// live in the global arena.
 template <class T>
-__device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, Cx<T>* arena,
-                             Cx<T>* lds, int32_t* s_tab, StepDesc* s_desc, const States& st,
-                             T* s_red) {
+__device__ inline Cx<T>* home_ptr(int32_t home, Cx<T>* arena, Cx<T>* lds) {
+  return home >= 0 ? arena + home : lds + (-1 - home);
+}
+
+template <class T>
+__device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int32_t q,
+                             Cx<T>* arena, Cx<T>* lds, int32_t* s_tab, StepDesc* s_desc,
+                             int32_t* s_tb, TensorState* s_ext, const States& st, T* s_red) {
   constexpr int32_t kDescWords = (int32_t)(sizeof(StepDesc) / 4);
+  const QDiv D(q);
   int32_t s = first;
   const int32_t end = first + count;
   while (s < end) {
@@ -346,32 +400,77 @@ __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, Cx<
       for (int32_t i = threadIdx.x; i < nd * kDescWords; i += kBlock) dst[i] = src[i];
     }
     __syncthreads();
-    const int32_t tab0 = s_desc[0].tab;
+    // steps of this chunk: as many as fit the table buffer (at least one)
     int32_t ce = 0, tab_end = 0;
     for (int32_t j = 0; j < nd; ++j) {
-      const StepDesc& d = s_desc[j];
-      const int32_t e = d.tab + 2 * d.nb + d.nm + 2 * d.nk + d.nn - tab0;
+      const int32_t e = tab_end + step_tab_entries(s_desc[j]);
       if (e > kTabBuf) break;
+      if (threadIdx.x == 0) s_tb[j] = tab_end;
       ce = j + 1;
       tab_end = e;
     }
-    for (int32_t i = threadIdx.x; i < tab_end; i += kBlock) s_tab[i] = p.tables[tab0 + i];
+    if (threadIdx.x == 0) s_tb[ce] = tab_end;
+    // states of operands made before this task (already final) are fetched now
+    if (threadIdx.x < 2 * ce) {
+      const int32_t j = threadIdx.x >> 1;
+      const int32_t t = (threadIdx.x & 1) ? s_desc[j].b : s_desc[j].a;
+      if (!st.local(t)) s_ext[threadIdx.x] = p.ts[t];
+    }
+    __syncthreads();
+    // generate the gather tables: entry i belongs to step j (binary search)
+    for (int32_t i = threadIdx.x; i < tab_end; i += kBlock) {
+      int32_t lo = 0, hi = ce - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_tb[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      const StepDesc& d = s_desc[lo];
+      int32_t r = i - s_tb[lo];
+      const int32_t rb = d.ranks & 255, rm = (d.ranks >> 8) & 255, rk = (d.ranks >> 16) & 255,
+                    rn = (d.ranks >> 24) & 255;
+      const int32_t* sp = p.strides + d.str;
+      int32_t off;
+      if (r < d.nb) {
+        off = group_off(r, sp, rb, D);
+      } else if ((r -= d.nb) < d.nm) {
+        off = group_off(r, sp + rb, rm, D);
+      } else if ((r -= d.nm) < d.nk) {
+        off = group_off(r, sp + rb + rm, rk, D);
+      } else if ((r -= d.nk) < d.nb) {
+        off = group_off(r, sp + rb + rm + rk, rb, D);
+      } else if ((r -= d.nb) < d.nk) {
+        off = group_off(r, sp + 2 * rb + rm + rk, rk, D);
+      } else {
+        r -= d.nk;
+        off = group_off(r, sp + 2 * rb + rm + 2 * rk, rn, D);
+      }
+      s_tab[i] = off;
+    }
     __syncthreads();
     for (int32_t j = 0; j < ce; ++j) {
       const StepDesc d = s_desc[j];
-      const int32_t* tAb = s_tab + (d.tab - tab0);
-      const int32_t* tAm = tAb + d.nb;
-      const int32_t* tAk = tAm + d.nm;
-      const int32_t* tBb = tAk + d.nk;
-      const int32_t* tBk = tBb + d.nb;
-      const int32_t* tBn = tBk + d.nk;
-      int64_t ec;
-      const T scale = step_scale<T>(st, d.a, d.b, ec);
+      TabIx ix;
+      ix.ab = s_tab + s_tb[j];
+      ix.am = ix.ab + d.nb;
+      ix.ak = ix.am + d.nm;
+      ix.bb = ix.ak + d.nk;
+      ix.bk = ix.bb + d.nb;
+      ix.bn = ix.bk + d.nk;
+      int32_t sa, sb;
+      int64_t ea, eb;
+      if (st.local(d.a)) st.get(d.a, sa, ea);
+      else { sa = s_ext[2 * j].shift; ea = s_ext[2 * j].exp2; }
+      if (st.local(d.b)) st.get(d.b, sb, eb);
+      else { sb = s_ext[2 * j + 1].shift; eb = s_ext[2 * j + 1].exp2; }
+      const int32_t sh = shift_of(sa) + shift_of(sb);
+      const int64_t ec = ea + eb + sh;
+      const T scale = (T)ldexp(1.0, -sh);
       const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
       const int32_t L = lanes_per_output(outs, d.nk);
-      T lm = step_outputs<T>(tptr<T>(p.tens[d.a], arena, lds), tptr<T>(p.tens[d.b], arena, lds),
-                             tptr<T>(p.tens[d.c], arena, lds), tAb, tAm, tAk, tBb, tBk, tBn,
-                             d.nm, d.nn, d.nk, 0, outs, scale, L);
+      T lm = step_outputs<T>(home_ptr<T>(d.home_a, arena, lds), home_ptr<T>(d.home_b, arena, lds),
+                             home_ptr<T>(d.home_c, arena, lds), ix, d.nm, d.nn, d.nk, 0, outs,
+                             scale, L);
       lm = block_max<T>(lm, s_red);
       if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
       __syncthreads();
@@ -380,37 +479,39 @@ __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, Cx<
   }
 }
 
-// One tile of a step split across workgroups.
+// One tile of a step split across workgroups.  Tile tasks use none of the
+// serial-task LDS areas, so the whole dynamic LDS (tab_cap entries) holds the
+// generated offset tables: contracted group first, then columns, rows, batch.
 template <class T>
-__device__ void tile_step(const DevProg& p, int32_t si, int32_t tile_id, Cx<T>* arena,
-                          int32_t* s_tab, const States& st, T* s_red) {
+__device__ void tile_step(const DevProg& p, int32_t si, int32_t tile_id, int32_t q, Cx<T>* arena,
+                          int32_t* s_tab, int32_t tab_cap, const States& st, T* s_red) {
   const StepDesc s = p.steps[si];
-  const int32_t* g = p.tables + s.tab;
-  const int32_t* tAb = g;
-  const int32_t* tAm = tAb + s.nb;
-  const int32_t* tAk = tAm + s.nm;
-  const int32_t* tBb = tAk + s.nk;
-  const int32_t* tBk = tBb + s.nb;
-  const int32_t* tBn = tBk + s.nk;
-  // the contracted-index tables are read by every output: stage them
-  if (2 * s.nk <= kTabBuf) {
-    for (int32_t i = threadIdx.x; i < s.nk; i += kBlock) {
-      s_tab[i] = tAk[i];
-      s_tab[s.nk + i] = tBk[i];
-    }
-    tAk = s_tab;
-    tBk = s_tab + s.nk;
+  const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
+                rn = (s.ranks >> 24) & 255;
+  const int32_t* sp = p.strides + s.str;
+  GenIx ix{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+           {sp, sp + rb, sp + rb + rm, sp + rb + rm + rk, sp + 2 * rb + rm + rk,
+            sp + 2 * rb + rm + 2 * rk},
+           {rb, rm, rk, rb, rk, rn},
+           QDiv(q)};
+  const int32_t n_of[6] = {s.nb, s.nm, s.nk, s.nb, s.nk, s.nn};
+  int32_t used = 0;
+  for (int g : {2, 4, 5, 1, 0, 3}) {
+    if (used + n_of[g] > tab_cap) continue;
+    int32_t* t = s_tab + used;
+    for (int32_t i = threadIdx.x; i < n_of[g]; i += kBlock) t[i] = group_off(i, ix.str[g], ix.rank[g], ix.D);
+    ix.tab[g] = t;
+    used += n_of[g];
   }
   int64_t ec;
   const T scale = step_scale<T>(st, s.a, s.b, ec);
-  const TensorDesc A = p.tens[s.a], B = p.tens[s.b], C = p.tens[s.c];
   __syncthreads();
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
   const int64_t o0 = (int64_t)tile_id * s.tile;
   const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
   const int32_t L = lanes_per_output(o1 - o0, s.nk);
-  T lm = step_outputs<T>(arena + A.off, arena + B.off, arena + C.off, tAb, tAm, tAk, tBb, tBk,
-                         tBn, s.nm, s.nn, s.nk, o0, o1, scale, L);
+  T lm = step_outputs<T>(arena + s.home_a, arena + s.home_b, arena + s.home_c, ix, s.nm, s.nn, s.nk,
+                         o0, o1, scale, L);
   lm = block_max<T>(lm, s_red);
   if (threadIdx.x == 0) {
     const int32_t sh = frexp_shift<T>(lm);
@@ -501,10 +602,12 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
   __shared__ int32_t s_task;
   __shared__ int32_t s_enq[3];
   __shared__ T s_red[kBlock / 64];
+  __shared__ int32_t s_tb[kDescBuf + 1];
   int32_t* s_tab = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsTab);
   StepDesc* s_desc = reinterpret_cast<StepDesc*>(kn_dyn_smem + kLdsDesc);
   int32_t* s_shift = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsShift);
   int64_t* s_exp = reinterpret_cast<int64_t*>(kn_dyn_smem + kLdsExp);
+  TensorState* s_ext = reinterpret_cast<TensorState*>(kn_dyn_smem + kLdsExt);
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(kn_dyn_smem + kLdsArena);
   const DevProg p = make_prog(img, state);
   const int32_t n_tasks = p.h->n_tasks;
@@ -547,7 +650,8 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
         knot_setup<T>(p, kd, arena, lds, J, st);
         __syncthreads();
       }
-      serial_steps<T>(p, td.first, td.count, arena, lds, s_tab, s_desc, st, s_red);
+      serial_steps<T>(p, td.first, td.count, kd.q, arena, lds, s_tab, s_desc, s_tb, s_ext, st,
+                      s_red);
       if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, lds, zout, st);
       // states of this task's tensors go back to global memory for later groups
       for (int32_t i = tid; i < st.len; i += kBlock) {
@@ -556,7 +660,8 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
       }
     } else {
       const States st{p.ts, s_shift, s_exp, 0, 0};
-      tile_step<T>(p, td.first, td.count, arena, s_tab, st, s_red);
+      tile_step<T>(p, td.first, td.count, p.knots[td.knot].q, arena, s_tab,
+                   (kLdsArena + p.h->lds_bytes) / 4, st, s_red);
     }
     // ---- publish; the last task of a group releases the knot's next group
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -684,6 +789,10 @@ extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_
   if (!b) return KN_E_NOMEM;
   try {
     b->image = build_image(ks);
+    if (b->image.empty()) {
+      delete b;
+      return KN_E_BUDGET;
+    }
     b->precision = plans[0]->k.precision;
     b->jones_only = jones_only;
     int64_t off = 0;

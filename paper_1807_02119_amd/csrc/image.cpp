@@ -1,6 +1,10 @@
-// image.cpp -- lay one or more knot plans out as a device program (see
-// program.h): descriptors, gather tables, task groups, ready-queue roots and
-// LDS homes.
+// image.cpp -- lay knot plans out as a device program (see program.h).
+//
+// Each plan is first turned into a relocatable section (make_section, run
+// once per plan, on the planning thread): descriptors, gather tables, task
+// groups and LDS homes with knot-local ids.  An image for one knot or a batch
+// is then the concatenation of sections with ids and offsets shifted
+// (build_image), which is a linear copy.
 //
 // The tasks of one knot form a chain of groups executed one after another (a
 // serial run of small steps on one workgroup, or all tiles of one big step);
@@ -14,9 +18,9 @@
 // workgroup's LDS arena when it fits (first fit over its live range);
 // everything else lives in the global arena.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
-#include <map>
 #include <numeric>
 
 #include "internal.h"
@@ -24,6 +28,7 @@
 namespace kn {
 
 namespace {
+
 template <class T>
 int64_t put(std::vector<uint8_t>& img, const std::vector<T>& v) {
   int64_t off = align256((int64_t)img.size());
@@ -32,86 +37,51 @@ int64_t put(std::vector<uint8_t>& img, const std::vector<T>& v) {
   return off;
 }
 
-// offset of each value of a spin group inside a tensor stored in `order`
-void group_table(const std::vector<int32_t>& group, const std::vector<int32_t>& order, int32_t q,
-                 std::vector<int32_t>& out) {
-  // stride of each spin in the storage order (row-major, last fastest)
-  std::vector<int64_t> gstride(group.size());
-  for (size_t i = 0; i < group.size(); ++i) {
+// Element stride of every spin of `group` in a tensor stored in `order`
+// (row-major, last spin fastest), appended to `out`.
+void group_strides(const std::vector<int32_t>& group, const std::vector<int32_t>& order,
+                   int32_t q, std::vector<int32_t>& out) {
+  for (int32_t sp : group) {
     int64_t s = 1;
     bool found = false;
     for (int64_t j = (int64_t)order.size() - 1; j >= 0; --j) {
-      if (order[j] == group[i]) { found = true; break; }
-      s *= q;
-    }
-    gstride[i] = found ? s : 0;
-  }
-  int64_t n = 1;
-  for (size_t i = 0; i < group.size(); ++i) n *= q;
-  size_t base = out.size();
-  out.resize(base + n);
-  // enumerate the group's values, first spin most significant (odometer)
-  const int r = (int)group.size();
-  int digit[64] = {0};
-  int64_t off = 0;
-  for (int64_t idx = 0; idx < n; ++idx) {
-    out[base + idx] = (int32_t)off;
-    for (int i = r - 1; i >= 0; --i) {
-      if (++digit[i] < q) {
-        off += gstride[i];
+      if (order[j] == sp) {
+        found = true;
         break;
       }
-      digit[i] = 0;
-      off -= (int64_t)(q - 1) * gstride[i];
+      s *= q;
     }
+    out.push_back(found ? (int32_t)s : 0);
   }
 }
 
-}  // namespace
-
-void make_tables(PlanKnot& k) {
-  k.tables.clear();
-  k.tab_off.assign(k.steps.size(), 0);
-  for (size_t si = 0; si < k.steps.size(); ++si) {
-    const PStep& s = k.steps[si];
-    k.tab_off[si] = (int32_t)k.tables.size();
-    const auto& A = k.tensors[s.a].spins;
-    const auto& B = k.tensors[s.b].spins;
-    group_table(s.bs, A, k.q, k.tables);
-    group_table(s.ms, A, k.q, k.tables);
-    group_table(s.ks, A, k.q, k.tables);
-    group_table(s.bs, B, k.q, k.tables);
-    group_table(s.ks, B, k.q, k.tables);
-    group_table(s.ns, B, k.q, k.tables);
-  }
-}
-
-namespace {
-
-// First-fit allocator over [0, cap) entries; alloc returns -1 when full.
+// First-fit allocator over [0, cap) entries, blocks kept in a sorted vector;
+// alloc returns -1 when the request does not fit.
 struct FitAlloc {
+  struct Blk {
+    int64_t off, len;
+  };
   int64_t cap;
   int64_t top = 0;
-  std::map<int64_t, int64_t> free_blk;  // off -> len
+  std::vector<Blk> free_blk;  // sorted by offset
   explicit FitAlloc(int64_t c) : cap(c) {}
   static int64_t round(int64_t len) { return (len + 7) / 8 * 8; }
   int64_t alloc(int64_t len) {
     len = round(len);
-    for (auto it = free_blk.begin(); it != free_blk.end(); ++it)
-      if (it->second >= len) {
-        int64_t off = it->first, rem = it->second - len;
-        free_blk.erase(it);
-        if (rem) free_blk.emplace(off + len, rem);
+    for (size_t i = 0; i < free_blk.size(); ++i)
+      if (free_blk[i].len >= len) {
+        int64_t off = free_blk[i].off;
+        free_blk[i].off += len;
+        free_blk[i].len -= len;
+        if (free_blk[i].len == 0) free_blk.erase(free_blk.begin() + i);
         return off;
       }
-    if (!free_blk.empty()) {
-      auto last = std::prev(free_blk.end());
-      if (last->first + last->second == top && last->first + len <= cap) {
-        int64_t off = last->first;
-        free_blk.erase(last);
-        top = off + len;
-        return off;
-      }
+    if (!free_blk.empty() && free_blk.back().off + free_blk.back().len == top &&
+        free_blk.back().off + len <= cap) {
+      int64_t off = free_blk.back().off;
+      free_blk.pop_back();
+      top = off + len;
+      return off;
     }
     if (top + len > cap) return -1;
     int64_t off = top;
@@ -120,31 +90,204 @@ struct FitAlloc {
   }
   void release(int64_t off, int64_t len) {
     len = round(len);
-    auto it = free_blk.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != free_blk.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_blk.erase(nx);
+    size_t i = 0;
+    while (i < free_blk.size() && free_blk[i].off < off) ++i;
+    free_blk.insert(free_blk.begin() + i, Blk{off, len});
+    if (i + 1 < free_blk.size() && free_blk[i].off + free_blk[i].len == free_blk[i + 1].off) {
+      free_blk[i].len += free_blk[i + 1].len;
+      free_blk.erase(free_blk.begin() + i + 1);
     }
-    if (it != free_blk.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_blk.erase(it);
-      }
+    if (i > 0 && free_blk[i - 1].off + free_blk[i - 1].len == free_blk[i].off) {
+      free_blk[i - 1].len += free_blk[i].len;
+      free_blk.erase(free_blk.begin() + i);
     }
   }
 };
 
 // A knot's groups before they are laid out.
 struct PGroup {
-  int32_t kind;         // TASK_SERIAL / TASK_TILE
-  int32_t first, count; // knot-local steps
+  int32_t kind;          // TASK_SERIAL / TASK_TILE
+  int32_t first, count;  // knot-local steps
   int32_t flags;
   int32_t n_tiles;
 };
 
 }  // namespace
+
+void make_section(PlanKnot& k) {
+  Section& S = k.sec;
+  S = Section();
+  const int32_t q = k.q;
+  KnotDesc& d = S.kd;
+  std::memset(&d, 0, sizeof(d));
+  d.t_re = k.t_re;
+  d.t_im = k.t_im;
+  d.q = q;
+  d.n_edges = k.n_edges;
+  d.n_medges = (int32_t)k.medges.size();
+  d.n_vtx = (int32_t)k.vtx.size();
+  d.n_factors = (int32_t)k.factors.size();
+  d.n_comps = (int32_t)k.comps.size();
+  d.n_iso = k.n_iso;
+  d.n_steps = (int32_t)k.steps.size();
+  for (auto& m : k.medges) {
+    S.md.push_back({(int32_t)S.members.size(), (int32_t)m.size()});
+    for (int32_t e : m) S.members.push_back(e);
+  }
+  S.fac = k.factors;
+  S.comps = k.comps;
+  S.td.reserve(k.tensors.size());
+  for (auto& t : k.tensors) S.td.push_back({t.off, (int32_t)t.size, -1});
+  S.arena_elems = (k.arena_elems + 15) / 16 * 16;
+  for (auto& v : k.vtx) {
+    S.vd.push_back({v.tensor, (int32_t)v.nbr.size(), (int32_t)S.vslot.size(),
+                    v.keep_center ? 1 : 0});
+    for (int32_t m : v.medge) S.vslot.push_back(m);
+  }
+  // steps + tables
+  S.sd.reserve(k.steps.size());
+  for (size_t si = 0; si < k.steps.size(); ++si) {
+    const PStep& s = k.steps[si];
+    StepDesc x;
+    x.a = s.a;
+    x.b = s.b;
+    x.c = s.c;
+    auto pw = [&](size_t r) {
+      int64_t v = 1;
+      for (size_t i = 0; i < r; ++i) v *= q;
+      return (int32_t)v;
+    };
+    x.nb = pw(s.bs.size());
+    x.nm = pw(s.ms.size());
+    x.nn = pw(s.ns.size());
+    x.nk = pw(s.ks.size());
+    x.str = (int32_t)S.strides.size();
+    x.ranks = (int32_t)(s.bs.size() | (s.ms.size() << 8) | (s.ks.size() << 16) |
+                        (s.ns.size() << 24));
+    const auto& A = k.tensors[s.a].spins;
+    const auto& B = k.tensors[s.b].spins;
+    group_strides(s.bs, A, q, S.strides);
+    group_strides(s.ms, A, q, S.strides);
+    group_strides(s.ks, A, q, S.strides);
+    group_strides(s.bs, B, q, S.strides);
+    group_strides(s.ks, B, q, S.strides);
+    group_strides(s.ns, B, q, S.strides);
+    const int64_t outs = (int64_t)x.nb * x.nm * x.nn;
+    const int32_t tile = k.step_tile[si];
+    x.n_tiles = k.big[si] ? (int32_t)((outs + tile - 1) / tile) : 0;
+    x.tile = tile;
+    S.sd.push_back(x);
+  }
+
+  // ---- groups
+  std::vector<PGroup> pg;
+  {
+    PGroup cur{TASK_SERIAL, 0, 0, TF_SETUP, 0};
+    bool open = true;
+    for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
+      if (!k.big[si]) {
+        if (!open) {
+          cur = PGroup{TASK_SERIAL, si, 0, 0, 0};
+          open = true;
+        }
+        cur.count++;
+        continue;
+      }
+      if (open) {
+        pg.push_back(cur);
+        open = false;
+      }
+      pg.push_back(PGroup{TASK_TILE, si, 1, 0, S.sd[si].n_tiles});
+    }
+    if (!open) cur = PGroup{TASK_SERIAL, (int32_t)k.steps.size(), 0, 0, 0};
+    cur.flags |= TF_FINAL;
+    pg.push_back(cur);
+  }
+
+  // ---- LDS homes: tensors produced and consumed inside one serial group
+  {
+    const int32_t nt = (int32_t)k.tensors.size();
+    const int32_t ns = (int32_t)k.steps.size();
+    std::vector<int32_t> consumer(nt, -1);  // step index, or ns for the final product
+    for (int32_t si = 0; si < ns; ++si) {
+      consumer[k.steps[si].a] = si;
+      consumer[k.steps[si].b] = si;
+    }
+    for (int32_t c : k.comps) consumer[c] = ns;
+    const int64_t es = elem_bytes(k.precision);
+    const int64_t cap = k.lds_bytes / es;
+    for (const PGroup& g : pg) {
+      if (g.kind != TASK_SERIAL) continue;
+      const int32_t lo = g.first, hi = g.first + g.count;  // steps [lo, hi)
+      auto inside = [&](int32_t t) {
+        int32_t c = consumer[t];
+        if (c < 0) return false;
+        if (c == ns) return (g.flags & TF_FINAL) != 0;
+        return c >= lo && c < hi;
+      };
+      FitAlloc la(cap);
+      int64_t peak = 0;
+      if (g.flags & TF_SETUP)
+        for (const auto& v : k.vtx)
+          if (inside(v.tensor)) {
+            int64_t o = la.alloc(k.tensors[v.tensor].size);
+            if (o >= 0) S.td[v.tensor].lds_off = (int32_t)o;
+          }
+      peak = std::max(peak, la.top);
+      for (int32_t si = lo; si < hi; ++si) {
+        const PStep& s = k.steps[si];
+        if (inside(s.c)) {
+          int64_t o = la.alloc(k.tensors[s.c].size);
+          if (o >= 0) S.td[s.c].lds_off = (int32_t)o;
+        }
+        peak = std::max(peak, la.top);
+        for (int32_t op : {s.a, s.b})
+          if (S.td[op].lds_off >= 0) la.release(S.td[op].lds_off, k.tensors[op].size);
+      }
+      S.lds_used = std::max<int32_t>(S.lds_used, (int32_t)(peak * es));
+    }
+  }
+
+  // ---- operand homes in the step descriptors (global offsets are knot-local)
+  for (auto& x : S.sd) {
+    auto home = [&](int32_t t) {
+      const TensorDesc& d = S.td[t];
+      return d.lds_off >= 0 ? -1 - d.lds_off : (int32_t)d.off;
+    };
+    x.home_a = home(x.a);
+    x.home_b = home(x.b);
+    x.home_c = home(x.c);
+  }
+
+  // ---- tasks
+  const int32_t n_vt = (int32_t)(k.tensors.size() - k.steps.size());
+  for (size_t gi = 0; gi < pg.size(); ++gi) {
+    const PGroup& g = pg[gi];
+    GroupDesc G;
+    G.knot = 0;
+    G.first_task = (int32_t)S.tasks.size();
+    G.next = gi + 1 < pg.size() ? (int32_t)gi + 1 : -1;
+    G.n_pred = gi == 0 ? 0 : S.groups.back().n_tasks;
+    if (g.kind == TASK_SERIAL) {
+      // tensors made here: vertex tensors (ids 0..) and step outputs, consecutive
+      int32_t lo = (g.flags & TF_SETUP) ? 0 : n_vt + g.first;
+      int32_t len = ((g.flags & TF_SETUP) ? n_vt : 0) + g.count;
+      S.tasks.push_back({TASK_SERIAL, 0, (int32_t)gi, g.first, g.count, g.flags, lo, len});
+      G.n_tasks = 1;
+      for (int32_t si = g.first; si < g.first + g.count; ++si) {
+        const StepDesc& x = S.sd[si];
+        S.est += 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
+      }
+    } else {
+      for (int32_t tl = 0; tl < g.n_tiles; ++tl)
+        S.tasks.push_back({TASK_TILE, 0, (int32_t)gi, g.first, tl, 0, 0, 0});
+      G.n_tasks = g.n_tiles;
+      const StepDesc& x = S.sd[g.first];
+      S.est += 3.0 + double(x.tile) * x.nk / 512.0;
+    }
+    S.groups.push_back(G);
+  }
+}
 
 std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   ImgHeader h;
@@ -152,229 +295,147 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   h.magic = kMagic;
   h.precision = knots.empty() ? 0 : knots[0]->precision;
 
-  std::vector<KnotDesc> kd;
-  std::vector<TensorDesc> td;
-  std::vector<StepDesc> sd;
-  std::vector<VtxDesc> vd;
-  std::vector<int32_t> vslot;
-  std::vector<MEdge> md;
-  std::vector<int32_t> members;
-  std::vector<Factor> fac;
-  std::vector<int32_t> tables;
-  std::vector<int8_t> eps;
-  std::vector<int32_t> comps;
-  std::vector<TaskDesc> tasks;
-  std::vector<GroupDesc> groups;
-  std::vector<std::pair<double, int32_t>> roots;  // (-estimated chain time, group)
+  // totals
+  size_t nK = knots.size(), nT = 0, nS = 0, nV = 0, nVS = 0, nM = 0, nMem = 0, nF = 0, nTab = 0,
+         nE = 0, nC = 0, nTask = 0, nG = 0;
+  int64_t arena = 0;
   int32_t lds_used = 0;
+  for (const PlanKnot* k : knots) {
+    const Section& S = k->sec;
+    nT += S.td.size();
+    nS += S.sd.size();
+    nV += S.vd.size();
+    nVS += S.vslot.size();
+    nM += S.md.size();
+    nMem += S.members.size();
+    nF += S.fac.size();
+    nTab += S.strides.size();
+    nE += k->eps.size();
+    nC += S.comps.size();
+    nTask += S.tasks.size();
+    nG += S.groups.size();
+    lds_used = std::max(lds_used, S.lds_used);
+  }
+  std::vector<KnotDesc> kd(nK);
+  std::vector<TensorDesc> td(nT);
+  std::vector<StepDesc> sd(nS);
+  std::vector<VtxDesc> vd(nV);
+  std::vector<int32_t> vslot(nVS);
+  std::vector<MEdge> md(nM);
+  std::vector<int32_t> members(nMem);
+  std::vector<Factor> fac(nF);
+  std::vector<int32_t> strides(nTab);
+  std::vector<int8_t> eps(nE);
+  std::vector<int32_t> comps(nC);
+  std::vector<TaskDesc> tasks(nTask);
+  std::vector<GroupDesc> groups(nG);
+  std::vector<std::pair<double, int32_t>> roots;  // (-estimated chain time, root task)
+  roots.reserve(nK);
 
-  int64_t arena = 0, n_edges = 0, n_medges = 0;
-  for (size_t ki = 0; ki < knots.size(); ++ki) {
+  size_t T0 = 0, S0 = 0, V0 = 0, VS0 = 0, M0 = 0, MEM0 = 0, F0 = 0, TAB0 = 0, E0 = 0, C0 = 0,
+         TK0 = 0, G0 = 0;
+  for (size_t ki = 0; ki < nK; ++ki) {
     const PlanKnot& k = *knots[ki];
-    const int32_t q = k.q;
-    const int32_t t0 = (int32_t)td.size();
-    const int32_t s0 = (int32_t)sd.size();
-    KnotDesc d;
-    std::memset(&d, 0, sizeof(d));
-    d.t_re = k.t_re;
-    d.t_im = k.t_im;
-    d.q = q;
-    d.edge_off = (int32_t)n_edges;
-    d.n_edges = k.n_edges;
-    d.medge_off = (int32_t)n_medges;
-    d.n_medges = (int32_t)k.medges.size();
-    d.vtx_off = (int32_t)vd.size();
-    d.n_vtx = (int32_t)k.vtx.size();
-    d.factor_off = (int32_t)fac.size();
-    d.n_factors = (int32_t)k.factors.size();
-    d.comp_off = (int32_t)comps.size();
-    d.n_comps = (int32_t)k.comps.size();
-    d.n_iso = k.n_iso;
-    d.out_slot = (int32_t)ki;
-    d.step_off = s0;
-    d.n_steps = (int32_t)k.steps.size();
-    for (int8_t e : k.eps) eps.push_back(e);
-    for (auto& m : k.medges) {
-      md.push_back({(int32_t)members.size(), (int32_t)m.size()});
-      for (int32_t e : m) members.push_back(e);
+    const Section& S = k.sec;
+    KnotDesc x = S.kd;
+    x.edge_off = (int32_t)E0;
+    x.medge_off = (int32_t)M0;
+    x.vtx_off = (int32_t)V0;
+    x.factor_off = (int32_t)F0;
+    x.comp_off = (int32_t)C0;
+    x.out_slot = (int32_t)ki;
+    x.step_off = (int32_t)S0;
+    kd[ki] = x;
+    const int32_t t0 = (int32_t)T0, s0 = (int32_t)S0, g0 = (int32_t)G0, tk0 = (int32_t)TK0;
+    for (size_t i = 0; i < S.td.size(); ++i) {
+      TensorDesc t = S.td[i];
+      t.off += arena;
+      td[T0 + i] = t;
     }
-    for (auto& f : k.factors) fac.push_back(f);
-    for (int32_t c : k.comps) comps.push_back(t0 + c);
-    const int64_t abase = arena;
-    for (auto& t : k.tensors) td.push_back({abase + t.off, (int32_t)t.size, -1});
-    arena += (k.arena_elems + 15) / 16 * 16;
-    for (auto& v : k.vtx) {
-      vd.push_back({t0 + v.tensor, (int32_t)v.nbr.size(), (int32_t)vslot.size(),
-                    v.keep_center ? 1 : 0});
-      for (int32_t m : v.medge) vslot.push_back(m);
+    for (size_t i = 0; i < S.sd.size(); ++i) {
+      StepDesc s = S.sd[i];
+      s.a += t0;
+      s.b += t0;
+      s.c += t0;
+      s.str += (int32_t)TAB0;
+      if (s.home_a >= 0) s.home_a += (int32_t)arena;
+      if (s.home_b >= 0) s.home_b += (int32_t)arena;
+      if (s.home_c >= 0) s.home_c += (int32_t)arena;
+      sd[S0 + i] = s;
     }
-    // steps + tables (precomputed per knot)
-    const int32_t tab0 = (int32_t)tables.size();
-    tables.insert(tables.end(), k.tables.begin(), k.tables.end());
-    for (size_t si = 0; si < k.steps.size(); ++si) {
-      const PStep& s = k.steps[si];
-      StepDesc x;
-      x.a = t0 + s.a;
-      x.b = t0 + s.b;
-      x.c = t0 + s.c;
-      auto pw = [&](size_t r) {
-        int64_t v = 1;
-        for (size_t i = 0; i < r; ++i) v *= q;
-        return (int32_t)v;
-      };
-      x.nb = pw(s.bs.size());
-      x.nm = pw(s.ms.size());
-      x.nn = pw(s.ns.size());
-      x.nk = pw(s.ks.size());
-      x.tab = tab0 + k.tab_off[si];
-      const int64_t outs = (int64_t)x.nb * x.nm * x.nn;
-      const int32_t tile = k.step_tile[si];
-      x.n_tiles = k.big[si] ? (int32_t)((outs + tile - 1) / tile) : 0;
-      x.tile = tile;
-      sd.push_back(x);
+    for (size_t i = 0; i < S.vd.size(); ++i) {
+      VtxDesc v = S.vd[i];
+      v.tensor += t0;
+      v.slot_off += (int32_t)VS0;
+      vd[V0 + i] = v;
     }
-
-    // ---- groups of this knot
-    std::vector<PGroup> pg;
-    {
-      PGroup cur{TASK_SERIAL, 0, 0, TF_SETUP, 0};
-      bool open = true;
-      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
-        if (!k.big[si]) {
-          if (!open) {
-            cur = PGroup{TASK_SERIAL, si, 0, 0, 0};
-            open = true;
-          }
-          cur.count++;
-          continue;
-        }
-        if (open) {
-          pg.push_back(cur);
-          open = false;
-        }
-        pg.push_back(PGroup{TASK_TILE, si, 1, 0, sd[s0 + si].n_tiles});
-      }
-      if (!open) cur = PGroup{TASK_SERIAL, (int32_t)k.steps.size(), 0, 0, 0};
-      cur.flags |= TF_FINAL;
-      pg.push_back(cur);
+    std::copy(S.vslot.begin(), S.vslot.end(), vslot.begin() + VS0);
+    for (size_t i = 0; i < S.md.size(); ++i) {
+      MEdge m = S.md[i];
+      m.member_off += (int32_t)MEM0;
+      md[M0 + i] = m;
     }
-
-    // ---- LDS homes: tensors produced and consumed inside one serial group
-    {
-      const int32_t nt = (int32_t)k.tensors.size();
-      std::vector<int32_t> consumer(nt, -1);  // step index, or n_steps for the final
-      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
-        consumer[k.steps[si].a] = si;
-        consumer[k.steps[si].b] = si;
-      }
-      for (int32_t c : k.comps) consumer[c] = (int32_t)k.steps.size();
-      std::vector<int32_t> producer(nt, -1);  // -1: vertex tensor (setup)
-      for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) producer[k.steps[si].c] = si;
-      const int64_t es = elem_bytes(k.precision);
-      const int64_t cap = k.lds_bytes / es;
-      for (const PGroup& g : pg) {
-        if (g.kind != TASK_SERIAL) continue;
-        const int32_t lo = g.first, hi = g.first + g.count;  // steps [lo, hi)
-        auto inside = [&](int32_t t) {
-          int32_t c = consumer[t];
-          if (c < 0) return false;
-          if (c == (int32_t)k.steps.size()) return (g.flags & TF_FINAL) != 0;
-          return c >= lo && c < hi;
-        };
-        FitAlloc la(cap);
-        std::vector<int64_t> loff(nt, -1);
-        int64_t peak = 0;
-        if (g.flags & TF_SETUP)
-          for (const auto& v : k.vtx)
-            if (inside(v.tensor)) {
-              int64_t o = la.alloc(k.tensors[v.tensor].size);
-              if (o >= 0) loff[v.tensor] = o;
-            }
-        peak = std::max(peak, la.top);
-        for (int32_t si = lo; si < hi; ++si) {
-          const PStep& s = k.steps[si];
-          if (inside(s.c)) {
-            int64_t o = la.alloc(k.tensors[s.c].size);
-            if (o >= 0) loff[s.c] = o;
-          }
-          peak = std::max(peak, la.top);
-          for (int32_t op : {s.a, s.b})
-            if (loff[op] >= 0) la.release(loff[op], k.tensors[op].size);
-        }
-        for (int32_t t = 0; t < nt; ++t)
-          if (loff[t] >= 0) td[t0 + t].lds_off = (int32_t)loff[t];
-        lds_used = std::max<int32_t>(lds_used, (int32_t)(peak * es));
-      }
+    std::copy(S.members.begin(), S.members.end(), members.begin() + MEM0);
+    std::copy(S.fac.begin(), S.fac.end(), fac.begin() + F0);
+    std::copy(S.strides.begin(), S.strides.end(), strides.begin() + TAB0);
+    std::copy(k.eps.begin(), k.eps.end(), eps.begin() + E0);
+    for (size_t i = 0; i < S.comps.size(); ++i) comps[C0 + i] = S.comps[i] + t0;
+    for (size_t i = 0; i < S.tasks.size(); ++i) {
+      TaskDesc t = S.tasks[i];
+      t.knot = (int32_t)ki;
+      t.group += g0;
+      t.first += s0;
+      t.state_lo += t0;
+      tasks[TK0 + i] = t;
     }
-
-    // ---- lay the groups out as tasks
-    double est = 0;
-    const int32_t g0 = (int32_t)groups.size();
-    for (size_t gi = 0; gi < pg.size(); ++gi) {
-      const PGroup& g = pg[gi];
-      GroupDesc G;
-      G.knot = (int32_t)ki;
-      G.first_task = (int32_t)tasks.size();
-      G.next = gi + 1 < pg.size() ? g0 + (int32_t)gi + 1 : -1;
-      G.n_pred = gi == 0 ? 0 : groups.back().n_tasks;
-      if (g.kind == TASK_SERIAL) {
-        // tensors made here: vertex tensors (ids t0..) and step outputs, consecutive
-        const int32_t n_vt = (int32_t)(k.tensors.size() - k.steps.size());
-        int32_t lo = (g.flags & TF_SETUP) ? t0 : t0 + n_vt + g.first;
-        int32_t len = ((g.flags & TF_SETUP) ? n_vt : 0) + g.count;
-        tasks.push_back({TASK_SERIAL, (int32_t)ki, g0 + (int32_t)gi, s0 + g.first, g.count, g.flags,
-                         lo, len});
-        G.n_tasks = 1;
-        for (int32_t si = g.first; si < g.first + g.count; ++si) {
-          const StepDesc& x = sd[s0 + si];
-          est += 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
-        }
-      } else {
-        for (int32_t tl = 0; tl < g.n_tiles; ++tl)
-          tasks.push_back({TASK_TILE, (int32_t)ki, g0 + (int32_t)gi, s0 + g.first, tl, 0, 0, 0});
-        G.n_tasks = g.n_tiles;
-        const StepDesc& x = sd[s0 + g.first];
-        est += 3.0 + double(x.tile) * x.nk / 512.0;
-      }
-      groups.push_back(G);
+    for (size_t i = 0; i < S.groups.size(); ++i) {
+      GroupDesc g = S.groups[i];
+      g.knot = (int32_t)ki;
+      g.first_task += tk0;
+      if (g.next >= 0) g.next += g0;
+      groups[G0 + i] = g;
     }
-    roots.emplace_back(-est, g0);
-    kd.push_back(d);
-    n_edges += k.n_edges;
-    n_medges += (int64_t)k.medges.size();
+    roots.emplace_back(-S.est, tk0 + S.groups[0].first_task);
+    arena += S.arena_elems;
+    T0 += S.td.size();
+    S0 += S.sd.size();
+    V0 += S.vd.size();
+    VS0 += S.vslot.size();
+    M0 += S.md.size();
+    MEM0 += S.members.size();
+    F0 += S.fac.size();
+    TAB0 += S.strides.size();
+    E0 += k.eps.size();
+    C0 += S.comps.size();
+    TK0 += S.tasks.size();
+    G0 += S.groups.size();
   }
   std::stable_sort(roots.begin(), roots.end(),
                    [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
                      return a.first < b.first;
                    });
-  std::vector<int32_t> root_tasks;
-  for (auto& r : roots) root_tasks.push_back(groups[r.second].first_task);
+  std::vector<int32_t> root_tasks(roots.size());
+  for (size_t i = 0; i < roots.size(); ++i) root_tasks[i] = roots[i].second;
 
-  h.n_tasks = (int32_t)tasks.size();
-  h.n_knots = (int32_t)knots.size();
-  h.n_tensors = (int32_t)td.size();
-  h.n_steps = (int32_t)sd.size();
-  h.n_vtx = (int32_t)vd.size();
-  h.n_medges = (int32_t)md.size();
-  h.n_members = (int32_t)members.size();
-  h.n_factors = (int32_t)fac.size();
-  h.n_tables = (int32_t)tables.size();
-  h.n_groups = (int32_t)groups.size();
-  h.n_edges = (int32_t)n_edges;
+  h.n_tasks = (int32_t)nTask;
+  h.n_knots = (int32_t)nK;
+  h.n_tensors = (int32_t)nT;
+  h.n_steps = (int32_t)nS;
+  h.n_vtx = (int32_t)nV;
+  h.n_medges = (int32_t)nM;
+  h.n_members = (int32_t)nMem;
+  h.n_factors = (int32_t)nF;
+  h.n_strides = (int32_t)nTab;
+  h.n_groups = (int32_t)nG;
+  h.n_edges = (int32_t)nE;
   h.n_roots = (int32_t)root_tasks.size();
   h.lds_bytes = (lds_used + 255) / 256 * 256;
 
   std::vector<uint8_t> img(sizeof(ImgHeader));
-  {
-    size_t total = 4096 + 256 * 18;
-    total += tasks.size() * sizeof(TaskDesc) + groups.size() * sizeof(GroupDesc) +
-             root_tasks.size() * 4 + kd.size() * sizeof(KnotDesc) +
-             td.size() * sizeof(TensorDesc) + sd.size() * sizeof(StepDesc) +
-             vd.size() * sizeof(VtxDesc) + vslot.size() * 4 + md.size() * sizeof(MEdge) +
-             members.size() * 4 + fac.size() * sizeof(Factor) + tables.size() * 4 + eps.size() +
-             comps.size() * 4;
-    img.reserve(total);
-  }
+  img.reserve(4096 + 256 * 18 + nTask * sizeof(TaskDesc) + nG * sizeof(GroupDesc) + nK * 4 +
+              nK * sizeof(KnotDesc) + nT * sizeof(TensorDesc) + nS * sizeof(StepDesc) +
+              nV * sizeof(VtxDesc) + nVS * 4 + nM * sizeof(MEdge) + nMem * 4 +
+              nF * sizeof(Factor) + nTab * 4 + nE + nC * 4);
   h.o_tasks = put(img, tasks);
   h.o_groups = put(img, groups);
   h.o_roots = put(img, root_tasks);
@@ -386,7 +447,7 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   h.o_medges = put(img, md);
   h.o_members = put(img, members);
   h.o_factors = put(img, fac);
-  h.o_tables = put(img, tables);
+  h.o_strides = put(img, strides);
   h.o_eps = put(img, eps);
   h.o_comps = put(img, comps);
   h.image_bytes = align256((int64_t)img.size());
@@ -396,16 +457,17 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   h.state_off = h.image_bytes;
   int64_t st = CTRL_WORDS * 4;
   h.o_queue = st;
-  st = align256(st + 4 * (int64_t)tasks.size());
+  st = align256(st + 4 * (int64_t)nTask);
   h.o_pending = st;
-  st = align256(st + 4 * (int64_t)groups.size());
+  st = align256(st + 4 * (int64_t)nG);
   h.o_tstate = st;
-  st = align256(st + (int64_t)td.size() * (int64_t)sizeof(TensorState));
+  st = align256(st + (int64_t)nT * (int64_t)sizeof(TensorState));
   h.o_weights = st;
-  st = align256(st + 16 * (n_edges + n_medges));
+  st = align256(st + 16 * (int64_t)(nE + nM));
   h.state_bytes = st;
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);
+  if (h.arena_elems > INT32_MAX) return {};  // step homes hold int32 offsets
   h.workspace_bytes = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
   std::memcpy(img.data(), &h, sizeof(h));
   return img;

@@ -19,6 +19,26 @@ struct kn_tait {
 
 namespace kn {
 
+// One knot's part of a device program with knot-local ids and offsets; an
+// image is the concatenation of sections with the ids shifted (build_image).
+struct Section {
+  KnotDesc kd;                      // offsets relative to the section
+  std::vector<TensorDesc> td;       // off relative to the knot's arena base
+  std::vector<StepDesc> sd;         // a, b, c knot-local; str relative to `strides`
+  std::vector<VtxDesc> vd;          // tensor knot-local; slot_off relative to `vslot`
+  std::vector<int32_t> vslot;       // merged-edge ids (knot-local, stay local)
+  std::vector<MEdge> md;            // member_off relative to `members`
+  std::vector<int32_t> members;     // original edge ids (knot-local, stay local)
+  std::vector<Factor> fac;          // ids knot-local (stay local)
+  std::vector<int32_t> strides;     // spin-group strides of every step
+  std::vector<int32_t> comps;       // knot-local tensor ids
+  std::vector<TaskDesc> tasks;      // group, first, state_lo knot-local
+  std::vector<GroupDesc> groups;    // first_task, next knot-local
+  double est = 0;                   // estimated chain time (start priority)
+  int32_t lds_used = 0;             // bytes of LDS arena the knot needs
+  int64_t arena_elems = 0;
+};
+
 // One pairwise contraction C = A . B over spin groups.
 struct PStep {
   int32_t a, b, c;
@@ -60,17 +80,14 @@ struct PlanKnot {
   int32_t lds_bytes = 32768;
   std::vector<uint8_t> big;                     // per step: split into tiles
   std::vector<int32_t> step_tile;               // per step: outputs per tile
-  // gather tables of every step, concatenated (step i starts at tab_off[i]);
-  // filled by make_tables() and reused by every image built from this knot
-  std::vector<int32_t> tables;
-  std::vector<int32_t> tab_off;
+  Section sec;  // device-program section (make_section)
 };
 
-// Fill k.tables / k.tab_off from the plan's steps.
-void make_tables(PlanKnot& k);
+// Lay the knot's plan out as a relocatable device-program section.
+void make_section(PlanKnot& k);
 
-// Build the device image for a list of knots (a batch of one or more).
-// out_slot of knot i is i.  Returns the image bytes; header filled in.
+// Build the device image for a list of knots (a batch of one or more) by
+// concatenating their sections.  out_slot of knot i is i.
 std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots);
 
 int64_t elem_bytes(int32_t precision);

@@ -44,6 +44,9 @@ int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
 // multiply-adds one tile aims at.
 constexpr double kMaxTiles = 1024;
 constexpr double kTileMacs = 32768;
+// Auto ordering also tries the greedy plan when the min-fill plan's modelled
+// compute (seconds, without per-step latency) exceeds this.
+constexpr double kAutoGreedyFrom = 1e-6;
 
 namespace {
 
@@ -400,14 +403,29 @@ struct Orderer {
     std::vector<int32_t> nv, touched;
     std::vector<uint32_t> tmark(n, 0);
     uint32_t ts = 0;
-    for (int32_t it = 0; it < n; ++it) {
-      int32_t best = -1;
-      for (int32_t v = 0; v < n; ++v) {
-        if (gone[v]) continue;
-        if (best < 0 || fill[v] < fill[best] || (fill[v] == fill[best] && deg[v] < deg[best]))
-          best = v;
+    // candidates (fill, degree, id) with lazy invalidation by a version stamp
+    struct F {
+      int32_t fill, deg, v, ver;
+      bool operator<(const F& o) const {
+        if (fill != o.fill) return fill > o.fill;
+        if (deg != o.deg) return deg > o.deg;
+        return v > o.v;
       }
-      const int32_t x = best;
+    };
+    std::vector<int32_t> ver(n, 0);
+    std::priority_queue<F> heap;
+    for (int32_t v = 0; v < n; ++v) heap.push({fill[v], deg[v], v, 0});
+    for (int32_t it = 0; it < n; ++it) {
+      int32_t x = -1;
+      while (!heap.empty()) {
+        F f = heap.top();
+        heap.pop();
+        if (!gone[f.v] && f.ver == ver[f.v]) {
+          x = f.v;
+          break;
+        }
+      }
+      if (x < 0) break;
       // contract the holders of x pairwise, smallest first
       if (cnt[x] > 0) {
         for (;;) {
@@ -444,13 +462,16 @@ struct Orderer {
           if (tmark[b2] != ts) { tmark[b2] = ts; touched.push_back(b2); }
       }
       for (int32_t a : touched)
-        if (!gone[a]) eval(a);
+        if (!gone[a]) {
+          eval(a);
+          heap.push({fill[a], deg[a], a, ++ver[a]});
+        }
     }
   }
 
-  // Roofline-modelled time of the plan: per step max(flops/peak, bytes/bw)
-  // plus a fixed per-step latency.
-  double model_cost(int32_t precision) const {
+  // Roofline-modelled time of the plan: per step max(flops/peak, bytes/bw),
+  // plus a fixed per-step latency when `latency`.
+  double model_cost(int32_t precision, bool latency) const {
     const double peak = precision == 1 ? 157.3e12 : 78.6e12, bw = 8.0e12, lat = 0.3e-6;
     const double es = precision == 1 ? 8 : 16;
     double t = 0;
@@ -460,7 +481,7 @@ struct Orderer {
       double by = es * (qpow[std::min<size_t>(T[st.a].spins.size(), 63)] +
                         qpow[std::min<size_t>(T[st.b].spins.size(), 63)] +
                         qpow[std::min<size_t>(T[st.c].spins.size(), 63)]);
-      t += std::max(8.0 * macs / peak, by / bw) + lat;
+      t += std::max(8.0 * macs / peak, by / bw) + (latency ? lat : 0.0);
     }
     return t;
   }
@@ -570,17 +591,21 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       if (cnt0[sp] == 1) return KN_E_INVALID;  // private spin left: planner bug guard
   }
   {
+    // auto (3): min-fill first; the greedy plan is also built, and the cheaper
+    // kept, only when the min-fill plan's modelled compute is material
     const int32_t strat = o.strategy;
     Orderer best(n, q, k.tensors);
     bool have = false;
     double best_cost = 0;
-    for (int32_t sgy : {0, 1, 2}) {
+    for (int32_t sgy : {2, 0, 1}) {
       if (strat != 3 && sgy != strat) continue;
-      if (strat == 3 && sgy == 1) continue;  // auto: greedy-size vs min-fill
+      if (strat == 3 && sgy == 1) continue;
+      if (strat == 3 && sgy == 0 && have && best.model_cost(o.precision, false) < kAutoGreedyFrom)
+        continue;
       Orderer cand(n, q, k.tensors);
       if (sgy == 2) cand.minfill();
       else cand.greedy(sgy);
-      double c = cand.model_cost(o.precision);
+      double c = cand.model_cost(o.precision, true);
       if (!have || c < best_cost) {
         best = std::move(cand);
         best_cost = c;
@@ -731,9 +756,10 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   try {
     rc = kn::make_plan(*g, q, o, p->k, p->stats);
     if (rc == KN_OK) {
-      kn::make_tables(p->k);
+      kn::make_section(p->k);
       std::vector<const kn::PlanKnot*> one{&p->k};
       p->image = kn::build_image(one);
+      if (p->image.empty()) rc = KN_E_BUDGET;
       const auto* h = reinterpret_cast<const kn::ImgHeader*>(p->image.data());
       p->stats.workspace_bytes = (uint64_t)h->workspace_bytes;
       p->stats.image_bytes = (uint64_t)h->image_bytes;

@@ -21,7 +21,7 @@ namespace kn {
 constexpr int32_t kMagic = 0x4b4e4732;  // "KNG2"
 constexpr int32_t kBlock = 256;         // threads per workgroup of the engine
 // Fixed LDS areas of a workgroup (the tensor arena follows them):
-constexpr int32_t kTabBuf = 3072;   // gather-table entries staged per chunk of serial steps
+constexpr int32_t kTabBuf = 3072;   // gather-table entries generated per chunk of serial steps
 constexpr int32_t kDescBuf = 64;    // step descriptors staged per chunk
 constexpr int32_t kStateCap = 768;  // tensor states cached for the running serial task
 
@@ -46,13 +46,13 @@ struct ImgHeader {
   int32_t precision;  // 0 complex128, 1 complex64
   int32_t n_tasks, n_knots, n_tensors, n_steps;
   int32_t n_vtx, n_medges, n_members, n_factors;
-  int32_t n_tables, n_groups;
+  int32_t n_strides, n_groups;
   int32_t n_edges;    // original edges over all knots
   int32_t n_roots;    // first groups of the knots, in start-priority order
   int32_t lds_bytes;  // per-workgroup LDS arena for serial tasks (bytes)
   int32_t pad0;
   int64_t o_tasks, o_groups, o_roots, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
-  int64_t o_medges, o_members, o_factors, o_tables, o_eps, o_comps;
+  int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps;
   int64_t image_bytes;
   // runtime state (relative to the workspace base)
   int64_t state_off, state_bytes;
@@ -101,12 +101,22 @@ struct TensorDesc {
   int32_t lds_off;  // complex entries into the workgroup's LDS arena; -1 = global
 };
 
+// A pairwise step C[b,m,n] = sum_k A[b,m,k] B[b,k,n].  Each of the four spin
+// groups (batch b, rows m, contracted k, columns n) is a list of spins, most
+// significant first; an operand entry's offset is the sum over the group's
+// spins of (digit of the group index) x (element stride of that spin in the
+// operand's storage order).  The strides are stored, the offset tables are
+// generated on the device.
 struct StepDesc {
   int32_t a, b, c;          // tensor ids: C = A . B
-  int32_t nb, nm, nn, nk;   // batch, rows, cols, contracted extents
-  int32_t tab;              // tables: tAb[nb] tAm[nm] tAk[nk] tBb[nb] tBk[nk] tBn[nn]
+  int32_t nb, nm, nn, nk;   // batch, rows, cols, contracted extents (powers of q)
+  int32_t str;              // strides: A_b[rb] A_m[rm] A_k[rk] B_b[rb] B_k[rk] B_n[rn]
+  int32_t ranks;            // rb | rm << 8 | rk << 16 | rn << 24
   int32_t n_tiles;          // 0 for steps run inside a serial task
   int32_t tile;             // outputs per tile (tiled steps)
+  // where A, B, C live: >= 0 global arena offset (complex entries),
+  // < 0 LDS arena offset -1 - value (serial steps only)
+  int32_t home_a, home_b, home_c;
 };
 
 struct VtxDesc {
@@ -149,7 +159,8 @@ constexpr int32_t kLdsTab = 0;
 constexpr int32_t kLdsDesc = kLdsTab + kTabBuf * 4;
 constexpr int32_t kLdsShift = kLdsDesc + kDescBuf * (int32_t)sizeof(StepDesc);
 constexpr int32_t kLdsExp = (kLdsShift + kStateCap * 4 + 7) / 8 * 8;
-constexpr int32_t kLdsArena = (kLdsExp + kStateCap * 8 + 15) / 16 * 16;
+constexpr int32_t kLdsExt = (kLdsExp + kStateCap * 8 + 15) / 16 * 16;  // operand states
+constexpr int32_t kLdsArena = kLdsExt + 2 * kDescBuf * (int32_t)sizeof(TensorState);
 
 // control words at the start of the runtime state
 enum Ctrl : int32_t { CTRL_HEAD = 0, CTRL_TAIL = 1, CTRL_ERROR = 2, CTRL_WORDS = 64 };

@@ -20,11 +20,11 @@ import numpy as np
 HDR = np.dtype([
     ("magic", "<i4"), ("precision", "<i4"), ("n_tasks", "<i4"), ("n_knots", "<i4"),
     ("n_tensors", "<i4"), ("n_steps", "<i4"), ("n_vtx", "<i4"), ("n_medges", "<i4"),
-    ("n_members", "<i4"), ("n_factors", "<i4"), ("n_tables", "<i4"), ("n_groups", "<i4"),
+    ("n_members", "<i4"), ("n_factors", "<i4"), ("n_strides", "<i4"), ("n_groups", "<i4"),
     ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("pad0", "<i4"),
     ("o_tasks", "<i8"), ("o_groups", "<i8"), ("o_roots", "<i8"), ("o_knots", "<i8"),
     ("o_tensors", "<i8"), ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"),
-    ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_tables", "<i8"),
+    ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_strides", "<i8"),
     ("o_eps", "<i8"), ("o_comps", "<i8"), ("image_bytes", "<i8"), ("state_off", "<i8"),
     ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
     ("o_weights", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
@@ -37,8 +37,9 @@ KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
     "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps")], align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
-STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "tab", "n_tiles",
-                                      "tile")], align=True)
+STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
+                                      "n_tiles", "tile", "home_a", "home_b", "home_c")],
+                align=True)
 VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
 TAB_CAP = 3072
@@ -66,7 +67,7 @@ class Image:
         self.medges = arr(PAIR, h["o_medges"], h["n_medges"])
         self.members = arr("<i4", h["o_members"], h["n_members"])
         self.factors = arr(PAIR, h["o_factors"], h["n_factors"])
-        self.tables = arr("<i4", h["o_tables"], h["n_tables"])
+        self.strides = arr("<i4", h["o_strides"], h["n_strides"])
         self.eps = arr("<i1", h["o_eps"], h["n_edges"])
         n_comps = int(sum(int(k["n_comps"]) for k in self.knots))
         self.comps = arr("<i4", h["o_comps"], n_comps)
@@ -140,19 +141,38 @@ def run(raw: bytes, J=None):
     def sh(t):
         return 0 if shift[t] is None else shift[t]
 
+    def table(strides, n, q):
+        """Offsets of the n = q^r values of a spin group (first spin most significant)."""
+        r = len(strides)
+        assert q ** r == n
+        idx = np.arange(n, dtype=np.int64)
+        off = np.zeros(n, np.int64)
+        for j in range(r - 1, -1, -1):
+            off += (idx % q) * int(strides[j])
+            idx //= q
+        return off
+
     def step(si, local):
         s = im.steps[si]
         nb, nm, nn, nk = (int(s[f]) for f in ("nb", "nm", "nn", "nk"))
-        tab = int(s["tab"])
+        q = int(im.knots[int(im.tasks[cur_task[0]]["knot"])]["q"])
         if not int(s["n_tiles"]):
             assert 2 * nb + nm + 2 * nk + nn <= TAB_CAP, "serial step tables exceed LDS staging"
-        tAb = im.tables[tab:tab + nb]
-        tAm = im.tables[tab + nb:tab + nb + nm]
-        tAk = im.tables[tab + nb + nm:tab + nb + nm + nk]
-        tBb = im.tables[tab + nb + nm + nk:tab + 2 * nb + nm + nk]
-        tBk = im.tables[tab + 2 * nb + nm + nk:tab + 2 * nb + nm + 2 * nk]
-        tBn = im.tables[tab + 2 * nb + nm + 2 * nk:tab + 2 * nb + nm + 2 * nk + nn]
+        rk = [(int(s["ranks"]) >> sh) & 255 for sh in (0, 8, 16, 24)]
+        rb, rm, rkk, rn = rk
+        st0 = int(s["str"])
+        sp = im.strides[st0:st0 + 2 * rb + rm + 2 * rkk + rn]
+        tAb = table(sp[:rb], nb, q)
+        tAm = table(sp[rb:rb + rm], nm, q)
+        tAk = table(sp[rb + rm:rb + rm + rkk], nk, q)
+        tBb = table(sp[rb + rm + rkk:2 * rb + rm + rkk], nb, q)
+        tBk = table(sp[2 * rb + rm + rkk:2 * rb + rm + 2 * rkk], nk, q)
+        tBn = table(sp[2 * rb + rm + 2 * rkk:], nn, q)
         a, b, c = int(s["a"]), int(s["b"]), int(s["c"])
+        for t, hm in ((a, "home_a"), (b, "home_b"), (c, "home_c")):
+            lo = home(t)
+            want = -1 - lo if lo >= 0 else int(im.tensors[t]["off"])
+            assert int(s[hm]) == want, "step descriptor home differs from the tensor's"
         A = read(a, local)
         B = read(b, local)
         assert int(tAb.max()) + int(tAm.max()) + int(tAk.max()) < A.size
@@ -187,8 +207,10 @@ def run(raw: bytes, J=None):
     assert all(im.groups[im.tasks[r]["group"]]["n_pred"] == 0 for r in queue)
     done_in_group = {}
     executed = 0
+    cur_task = [0]
     while queue:
         ti = queue.popleft()
+        cur_task[0] = ti
         task = im.tasks[ti]
         executed += 1
         k = im.knots[task["knot"]]
