@@ -273,9 +273,11 @@ kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes);
    calls; 0 restores the default (derived from the device's CU count). */
 kn_status kn_batch_set_grid(kn_batch* b, int32_t grid);
 /* Per-task timing of later kn_batch_contract calls: trace_dev (device, at
-   least 32 * n_tasks bytes; NULL switches tracing off) receives for task i the
-   record {int64 t_claim, t_start, t_end; int32 task, workgroup} in device
-   clock ticks (100 MHz): queue slot claimed, task available, task done. */
+   least 64 * n_tasks bytes; NULL switches tracing off) receives for task i the
+   record {int64 t_claim, t_start, t_end; int32 task, workgroup; int64 ph[4]}
+   in device clock ticks (100 MHz): queue slot claimed, task available, task
+   done; for serial tasks ph = time in setup, staging descriptors and
+   tables, step products, reductions and barriers. */
 kn_status kn_batch_set_trace(kn_batch* b, void* trace_dev, size_t bytes);
 void kn_batch_free(kn_batch* b);
 

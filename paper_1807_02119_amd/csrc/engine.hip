@@ -295,12 +295,12 @@ struct GenIx {
   __device__ inline int32_t b_k(int32_t k) const { return off(4, k); }
 };
 
-// Outputs [o_begin, o_end) of C = A . B, each summed over k by L lanes of one
-// wavefront; returns this thread's max |.|.
+// Outputs [o_begin, o_end) of C = A . B, each summed over k in [k0, nk) by L
+// lanes of one wavefront; returns this thread's max |.|.
 template <class T, class Ix>
 __device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict__ pb,
-                          Cx<T>* __restrict__ pc, const Ix& ix, int32_t nm, int32_t nn, int32_t nk,
-                          int64_t o_begin, int64_t o_end, T scale, int32_t L) {
+                          Cx<T>* __restrict__ pc, const Ix& ix, int32_t nm, int32_t nn, int32_t k0,
+                          int32_t nk, int64_t o_begin, int64_t o_end, T scale, int32_t L) {
   const int32_t mn = nm * nn;
   const int32_t lsub = threadIdx.x & (L - 1);
   const int32_t slot = threadIdx.x / L;
@@ -315,7 +315,7 @@ __device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict_
     const Cx<T>* ra = pa + ix.a_row(b, m);
     const Cx<T>* rb = pb + ix.b_col(b, n);
     T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
-    int32_t k = lsub;
+    int32_t k = k0 + lsub;
     for (; k + 3 * L < nk; k += 4 * L) {
       const Cx<T> x0 = ra[ix.a_k(k)], x1 = ra[ix.a_k(k + L)], x2 = ra[ix.a_k(k + 2 * L)],
                   x3 = ra[ix.a_k(k + 3 * L)];
@@ -387,7 +387,16 @@ __device__ inline Cx<T>* home_ptr(int32_t home, Cx<T>* arena, Cx<T>* lds) {
 template <class T>
 __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int32_t q,
                              Cx<T>* arena, Cx<T>* lds, int32_t* s_tab, StepDesc* s_desc,
-                             int32_t* s_tb, TensorState* s_ext, const States& st, T* s_red) {
+                             int32_t* s_tb, TensorState* s_ext, const States& st, T* s_red,
+                             int64_t* ph) {
+  int64_t tk = ph ? wall_clock64() : 0;
+  auto lap = [&](int i) {
+    if (ph) {
+      const int64_t t = wall_clock64();
+      ph[i] += t - tk;
+      tk = t;
+    }
+  };
   constexpr int32_t kDescWords = (int32_t)(sizeof(StepDesc) / 4);
   const QDiv D(q);
   int32_t s = first;
@@ -448,6 +457,7 @@ __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int
       s_tab[i] = off;
     }
     __syncthreads();
+    lap(1);
     for (int32_t j = 0; j < ce; ++j) {
       const StepDesc d = s_desc[j];
       TabIx ix;
@@ -469,31 +479,53 @@ __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int
       const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
       const int32_t L = lanes_per_output(outs, d.nk);
       T lm = step_outputs<T>(home_ptr<T>(d.home_a, arena, lds), home_ptr<T>(d.home_b, arena, lds),
-                             home_ptr<T>(d.home_c, arena, lds), ix, d.nm, d.nn, d.nk, 0, outs,
-                             scale, L);
+                             home_ptr<T>(d.home_c, arena, lds), ix, d.nm, d.nn, 0, d.nk, 0,
+                             outs, scale, L);
+      lap(2);
       lm = block_max<T>(lm, s_red);
       if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
       __syncthreads();
+      lap(3);
     }
     s += ce;
   }
 }
 
-// One tile of a step split across workgroups.  Tile tasks use none of the
-// serial-task LDS areas, so the whole dynamic LDS (tab_cap entries) holds the
-// generated offset tables: contracted group first, then columns, rows, batch.
+// Output shift of a tiled step: every tile of an unsplit step folds its max
+// into C's shift, and tile 0 writes C's exponent.
 template <class T>
-__device__ void tile_step(const DevProg& p, int32_t si, int32_t tile_id, int32_t q, Cx<T>* arena,
-                          int32_t* s_tab, int32_t tab_cap, const States& st, T* s_red) {
-  const StepDesc s = p.steps[si];
+__device__ inline void tile_publish(const DevProg& p, int32_t c, int32_t tile_id, T lm, int64_t ec,
+                                    T* s_red) {
+  lm = block_max<T>(lm, s_red);
+  if (threadIdx.x == 0) {
+    const int32_t sh = frexp_shift<T>(lm);
+    if (sh != kShiftNone)
+      __hip_atomic_fetch_max(&p.ts[c].shift, sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tile_id == 0) p.ts[c].exp2 = ec;
+  }
+}
+
+// Offset tables of the six spin groups of step s (A_b A_m A_k B_b B_k B_n).
+__device__ inline GenIx step_ix(const DevProg& p, const StepDesc& s, int32_t q) {
   const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
                 rn = (s.ranks >> 24) & 255;
   const int32_t* sp = p.strides + s.str;
-  GenIx ix{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
-           {sp, sp + rb, sp + rb + rm, sp + rb + rm + rk, sp + 2 * rb + rm + rk,
-            sp + 2 * rb + rm + 2 * rk},
-           {rb, rm, rk, rb, rk, rn},
-           QDiv(q)};
+  return GenIx{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+               {sp, sp + rb, sp + rb + rm, sp + rb + rm + rk, sp + 2 * rb + rm + rk,
+                sp + 2 * rb + rm + 2 * rk},
+               {rb, rm, rk, rb, rk, rn},
+               QDiv(q)};
+}
+
+// STEP_TILES: `tile` consecutive outputs of C (row-major over b, m, n), over
+// contracted range ks of the split.  Tile tasks use none of the serial-task
+// LDS areas, so the whole dynamic LDS (tab_cap entries) holds generated offset
+// tables: contracted group first, then columns, rows, batch.
+template <class T>
+__device__ void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
+                          Cx<T>* arena, int32_t* s_tab, int32_t tab_cap, const States& st,
+                          T* s_red) {
+  GenIx ix = step_ix(p, s, q);
   const int32_t n_of[6] = {s.nb, s.nm, s.nk, s.nb, s.nk, s.nn};
   int32_t used = 0;
   for (int g : {2, 4, 5, 1, 0, 3}) {
@@ -507,18 +539,166 @@ __device__ void tile_step(const DevProg& p, int32_t si, int32_t tile_id, int32_t
   const T scale = step_scale<T>(st, s.a, s.b, ec);
   __syncthreads();
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
-  const int64_t o0 = (int64_t)tile_id * s.tile;
+  const int32_t base = s.n_tiles / s.n_ks;
+  const int32_t ks = tile_id / base, t = tile_id - ks * base;
+  const int32_t k0 = ks * s.kseg, k1 = min(s.nk, k0 + s.kseg);
+  const int64_t o0 = (int64_t)t * s.tile;
   const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
-  const int32_t L = lanes_per_output(o1 - o0, s.nk);
-  T lm = step_outputs<T>(arena + s.home_a, arena + s.home_b, arena + s.home_c, ix, s.nm, s.nn, s.nk,
-                         o0, o1, scale, L);
-  lm = block_max<T>(lm, s_red);
-  if (threadIdx.x == 0) {
-    const int32_t sh = frexp_shift<T>(lm);
-    if (sh != kShiftNone)
-      __hip_atomic_fetch_max(&p.ts[s.c].shift, sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (tile_id == 0) p.ts[s.c].exp2 = ec;
+  const int32_t L = lanes_per_output(o1 - o0, k1 - k0);
+  Cx<T>* pc = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
+  T lm = step_outputs<T>(arena + s.home_a, arena + s.home_b, pc, ix, s.nm, s.nn, k0, k1, o0, o1,
+                         scale, L);
+  if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
+}
+
+// STEP_GEMM: a 32 x 32 block of C[b] over contracted range ks of the split.
+// Chunks of 16 contracted entries of A (32 rows) and B (32 columns) are
+// gathered into LDS (row pitch 33 entries, no bank conflicts on the
+// k-fastest stores) and every thread accumulates a 2 x 2 block of outputs.
+// The next chunk's operands are loaded into registers while the current one
+// is multiplied.  The contracted offsets come from tables generated in LDS
+// when the range fits, else they are decoded from the strides.
+template <class T>
+__device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
+                          Cx<T>* __restrict__ arena, uint8_t* smem, int32_t smem_bytes,
+                          const States& st, T* s_red) {
+  constexpr int32_t BM = kGemmBlock, BK = kGemmChunk, P = kGemmBlock + 1;
+  const QDiv D(q);
+  const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
+                rn = (s.ranks >> 24) & 255;
+  const int32_t* sab = p.strides + s.str;
+  const int32_t* sam = sab + rb;
+  const int32_t* sak = sam + rm;
+  const int32_t* sbb = sak + rk;
+  const int32_t* sbk = sbb + rb;
+  const int32_t* sbn = sbk + rk;
+  const int32_t tid = threadIdx.x;
+  const int32_t mb_nb = s.n_mb * s.n_nb;
+  const int32_t base = s.nb * mb_nb;
+  const int32_t ks = tile_id / base;
+  int32_t r = tile_id - ks * base;
+  const int32_t b = r / mb_nb;
+  r -= b * mb_nb;
+  const int32_t mblk = r / s.n_nb, nblk = r - mblk * s.n_nb;
+  const int32_t m0 = mblk * BM, n0 = nblk * BM;
+  const int32_t k0 = ks * s.kseg, k1 = min(s.nk, k0 + s.kseg), kl = k1 - k0;
+
+  Cx<T>* As = reinterpret_cast<Cx<T>*>(smem);
+  Cx<T>* Bs = As + BK * P;
+  int32_t* ktab = reinterpret_cast<int32_t*>(Bs + BK * P);
+  const int32_t kcap = (smem_bytes - 2 * BK * P * (int32_t)sizeof(Cx<T>)) / 8;
+  const bool use_tab = kl <= kcap;
+  if (use_tab) {
+    for (int32_t i = tid; i < kl; i += kBlock) {
+      ktab[2 * i] = group_off(k0 + i, sak, rk, D);
+      ktab[2 * i + 1] = group_off(k0 + i, sbk, rk, D);
+    }
   }
+  // this thread's loads: contracted entry kk of rows/columns lr and lr + 16
+  const int32_t kk = tid & (BK - 1), lr = tid >> 4;
+  const Cx<T>* __restrict__ A = arena + s.home_a;
+  const Cx<T>* __restrict__ B = arena + s.home_b;
+  const bool am0 = m0 + lr < s.nm, am1 = m0 + lr + 16 < s.nm;
+  const bool bn0 = n0 + lr < s.nn, bn1 = n0 + lr + 16 < s.nn;
+  const int32_t oab = group_off(b, sab, rb, D), obb = group_off(b, sbb, rb, D);
+  const int32_t ra0 = am0 ? oab + group_off(m0 + lr, sam, rm, D) : 0;
+  const int32_t ra1 = am1 ? oab + group_off(m0 + lr + 16, sam, rm, D) : 0;
+  const int32_t cb0 = bn0 ? obb + group_off(n0 + lr, sbn, rn, D) : 0;
+  const int32_t cb1 = bn1 ? obb + group_off(n0 + lr + 16, sbn, rn, D) : 0;
+  int64_t ec;
+  const T scale = step_scale<T>(st, s.a, s.b, ec);
+  __syncthreads();
+
+  struct Quad {
+    Cx<T> a0, a1, b0, b1;
+  };
+  auto load = [=](int32_t c0) -> Quad {
+    const int32_t k = c0 + kk;
+    Quad x{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (k < kl) {
+      int32_t oa, ob;
+      if (use_tab) {
+        oa = ktab[2 * k];
+        ob = ktab[2 * k + 1];
+      } else {
+        oa = group_off(k0 + k, sak, rk, D);
+        ob = group_off(k0 + k, sbk, rk, D);
+      }
+      if (am0) x.a0 = A[ra0 + oa];
+      if (am1) x.a1 = A[ra1 + oa];
+      if (bn0) x.b0 = B[cb0 + ob];
+      if (bn1) x.b1 = B[cb1 + ob];
+    }
+    return x;
+  };
+  const int32_t tx = tid & 15, ty = tid >> 4;
+  T c00r = 0, c00i = 0, c01r = 0, c01i = 0, c10r = 0, c10i = 0, c11r = 0, c11i = 0;
+  Quad x = load(0);
+  for (int32_t c0 = 0; c0 < kl; c0 += BK) {
+    As[kk * P + lr] = x.a0;
+    As[kk * P + lr + 16] = x.a1;
+    Bs[kk * P + lr] = x.b0;
+    Bs[kk * P + lr + 16] = x.b1;
+    __syncthreads();
+    if (c0 + BK < kl) x = load(c0 + BK);
+#pragma unroll 4
+    for (int32_t j = 0; j < BK; ++j) {
+      const Cx<T> a0 = As[j * P + ty], a1 = As[j * P + ty + 16];
+      const Cx<T> b0 = Bs[j * P + tx], b1 = Bs[j * P + tx + 16];
+      c00r = fma(a0.re, b0.re, c00r); c00r = fma(-a0.im, b0.im, c00r);
+      c00i = fma(a0.re, b0.im, c00i); c00i = fma(a0.im, b0.re, c00i);
+      c01r = fma(a0.re, b1.re, c01r); c01r = fma(-a0.im, b1.im, c01r);
+      c01i = fma(a0.re, b1.im, c01i); c01i = fma(a0.im, b1.re, c01i);
+      c10r = fma(a1.re, b0.re, c10r); c10r = fma(-a1.im, b0.im, c10r);
+      c10i = fma(a1.re, b0.im, c10i); c10i = fma(a1.im, b0.re, c10i);
+      c11r = fma(a1.re, b1.re, c11r); c11r = fma(-a1.im, b1.im, c11r);
+      c11i = fma(a1.re, b1.im, c11i); c11i = fma(a1.im, b1.re, c11i);
+    }
+    __syncthreads();
+  }
+  const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
+  Cx<T>* C = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
+  const int64_t crow = (int64_t)b * s.nm;
+  T lm = 0;
+  auto put = [&](int32_t m, int32_t n, T cr, T ci) {
+    if (m < s.nm && n < s.nn) {
+      cr *= scale;
+      ci *= scale;
+      C[(crow + m) * s.nn + n] = Cx<T>{cr, ci};
+      lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
+    }
+  };
+  put(m0 + ty, n0 + tx, c00r, c00i);
+  put(m0 + ty, n0 + tx + 16, c01r, c01i);
+  put(m0 + ty + 16, n0 + tx, c10r, c10i);
+  put(m0 + ty + 16, n0 + tx + 16, c11r, c11i);
+  if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
+}
+
+// Outputs [part * kReduceChunk, ...) of a split step: C = sum over the n_ks
+// partial results, in split order (the same bits on every run).
+template <class T>
+__device__ void reduce_step(const DevProg& p, const StepDesc& s, int32_t part, Cx<T>* arena,
+                            const States& st, T* s_red) {
+  const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
+  const int64_t o0 = (int64_t)part * kReduceChunk;
+  const int64_t o1 = o0 + kReduceChunk < outs ? o0 + kReduceChunk : outs;
+  const Cx<T>* P = arena + s.partial;
+  Cx<T>* C = arena + s.home_c;
+  T lm = 0;
+  for (int64_t o = o0 + threadIdx.x; o < o1; o += kBlock) {
+    T cr = 0, ci = 0;
+    for (int32_t j = 0; j < s.n_ks; ++j) {
+      const Cx<T> v = P[(int64_t)j * outs + o];
+      cr += v.re;
+      ci += v.im;
+    }
+    C[o] = Cx<T>{cr, ci};
+    lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
+  }
+  int64_t ec;
+  step_scale<T>(st, s.a, s.b, ec);
+  tile_publish<T>(p, s.c, part, lm, ec, s_red);
 }
 
 // ------------------------------------------------------------------ final
@@ -603,6 +783,7 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
   __shared__ int32_t s_enq[3];
   __shared__ T s_red[kBlock / 64];
   __shared__ int32_t s_tb[kDescBuf + 1];
+  __shared__ int64_t s_ph[4];
   int32_t* s_tab = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsTab);
   StepDesc* s_desc = reinterpret_cast<StepDesc*>(kn_dyn_smem + kLdsDesc);
   int32_t* s_shift = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsShift);
@@ -646,13 +827,18 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
     if (td.kind == TASK_SERIAL) {
       const KnotDesc kd = p.knots[td.knot];
       const States st{p.ts, s_shift, s_exp, td.state_lo, min(td.state_len, kStateCap)};
+      int64_t ph_buf[4] = {0, 0, 0, 0};
+      int64_t* ph = (trace && tid == 0) ? ph_buf : nullptr;
       if (td.flags & TF_SETUP) {
         knot_setup<T>(p, kd, arena, lds, J, st);
         __syncthreads();
       }
+      if (ph) ph[0] = wall_clock64() - t_start;
       serial_steps<T>(p, td.first, td.count, kd.q, arena, lds, s_tab, s_desc, s_tb, s_ext, st,
-                      s_red);
+                      s_red, ph);
       if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, lds, zout, st);
+      if (ph)
+        for (int i = 0; i < 4; ++i) s_ph[i] = ph[i];
       // states of this task's tensors go back to global memory for later groups
       for (int32_t i = tid; i < st.len; i += kBlock) {
         p.ts[st.lo + i].shift = s_shift[i];
@@ -660,8 +846,17 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
       }
     } else {
       const States st{p.ts, s_shift, s_exp, 0, 0};
-      tile_step<T>(p, td.first, td.count, p.knots[td.knot].q, arena, s_tab,
-                   (kLdsArena + p.h->lds_bytes) / 4, st, s_red);
+      if (tid == 0)
+        for (int i = 0; i < 4; ++i) s_ph[i] = 0;
+      const StepDesc sd = p.steps[td.first];
+      const int32_t q = p.knots[td.knot].q;
+      const int32_t dyn = kLdsArena + p.h->lds_bytes;
+      if (td.kind == TASK_REDUCE)
+        reduce_step<T>(p, sd, td.count, arena, st, s_red);
+      else if (sd.mode == STEP_GEMM)
+        gemm_tile<T>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
+      else
+        tile_step<T>(p, sd, td.count, q, arena, s_tab, dyn / 4, st, s_red);
     }
     // ---- publish; the last task of a group releases the knot's next group
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -676,7 +871,11 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
         s_enq[1] = g.first_task;
         s_enq[2] = atomicAdd(&p.ctrl[CTRL_TAIL], g.n_tasks);
       }
-      if (trace) trace[ti] = TraceRec{t_claim, t_start, wall_clock64(), ti, (int32_t)blockIdx.x};
+      if (trace) {
+        TraceRec r{t_claim, t_start, wall_clock64(), ti, (int32_t)blockIdx.x, {0, 0, 0, 0}};
+        for (int i = 0; i < 4; ++i) r.ph[i] = s_ph[i];
+        trace[ti] = r;
+      }
     }
     __syncthreads();
     const int32_t n_enq = s_enq[0];

@@ -106,10 +106,10 @@ struct FitAlloc {
 
 // A knot's groups before they are laid out.
 struct PGroup {
-  int32_t kind;          // TASK_SERIAL / TASK_TILE
+  int32_t kind;          // TASK_SERIAL / TASK_TILE / TASK_REDUCE
   int32_t first, count;  // knot-local steps
   int32_t flags;
-  int32_t n_tiles;
+  int32_t n_tiles;       // tile and reduce groups: tasks
 };
 
 }  // namespace
@@ -172,10 +172,15 @@ void make_section(PlanKnot& k) {
     group_strides(s.bs, B, q, S.strides);
     group_strides(s.ks, B, q, S.strides);
     group_strides(s.ns, B, q, S.strides);
-    const int64_t outs = (int64_t)x.nb * x.nm * x.nn;
-    const int32_t tile = k.step_tile[si];
-    x.n_tiles = k.big[si] ? (int32_t)((outs + tile - 1) / tile) : 0;
-    x.tile = tile;
+    const PTiling& t = k.tiling[si];
+    x.mode = t.mode;
+    x.n_tiles = t.mode == STEP_SERIAL ? 0 : t.n_tiles;
+    x.tile = t.tile;
+    x.n_mb = t.n_mb;
+    x.n_nb = t.n_nb;
+    x.n_ks = t.n_ks;
+    x.kseg = t.kseg;
+    x.partial = t.partial >= 0 ? (int32_t)t.partial : -1;
     S.sd.push_back(x);
   }
 
@@ -185,7 +190,7 @@ void make_section(PlanKnot& k) {
     PGroup cur{TASK_SERIAL, 0, 0, TF_SETUP, 0};
     bool open = true;
     for (int32_t si = 0; si < (int32_t)k.steps.size(); ++si) {
-      if (!k.big[si]) {
+      if (k.tiling[si].mode == STEP_SERIAL) {
         if (!open) {
           cur = PGroup{TASK_SERIAL, si, 0, 0, 0};
           open = true;
@@ -198,6 +203,10 @@ void make_section(PlanKnot& k) {
         open = false;
       }
       pg.push_back(PGroup{TASK_TILE, si, 1, 0, S.sd[si].n_tiles});
+      if (S.sd[si].n_ks > 1) {
+        const int64_t outs = (int64_t)S.sd[si].nb * S.sd[si].nm * S.sd[si].nn;
+        pg.push_back(PGroup{TASK_REDUCE, si, 1, 0, (int32_t)((outs + kReduceChunk - 1) / kReduceChunk)});
+      }
     }
     if (!open) cur = PGroup{TASK_SERIAL, (int32_t)k.steps.size(), 0, 0, 0};
     cur.flags |= TF_FINAL;
@@ -278,12 +287,17 @@ void make_section(PlanKnot& k) {
         const StepDesc& x = S.sd[si];
         S.est += 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
       }
-    } else {
+    } else if (g.kind == TASK_TILE) {
       for (int32_t tl = 0; tl < g.n_tiles; ++tl)
         S.tasks.push_back({TASK_TILE, 0, (int32_t)gi, g.first, tl, 0, 0, 0});
       G.n_tasks = g.n_tiles;
       const StepDesc& x = S.sd[g.first];
-      S.est += 3.0 + double(x.tile) * x.nk / 512.0;
+      S.est += 3.0 + double(x.nb) * x.nm * x.nn * x.nk / (512.0 * x.n_tiles);
+    } else {
+      for (int32_t tl = 0; tl < g.n_tiles; ++tl)
+        S.tasks.push_back({TASK_REDUCE, 0, (int32_t)gi, g.first, tl, 0, 0, 0});
+      G.n_tasks = g.n_tiles;
+      S.est += 2.0;
     }
     S.groups.push_back(G);
   }
@@ -361,6 +375,7 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
       if (s.home_a >= 0) s.home_a += (int32_t)arena;
       if (s.home_b >= 0) s.home_b += (int32_t)arena;
       if (s.home_c >= 0) s.home_c += (int32_t)arena;
+      if (s.partial >= 0) s.partial += (int32_t)arena;
       sd[S0 + i] = s;
     }
     for (size_t i = 0; i < S.vd.size(); ++i) {

@@ -39,6 +39,18 @@ struct Section {
   int64_t arena_elems = 0;
 };
 
+// How one step runs: inside a serial task, or as tiles over workgroups.
+struct PTiling {
+  int32_t mode = 0;     // STEP_SERIAL, STEP_TILES or STEP_GEMM (program.h)
+  int32_t tile = 0;     // STEP_TILES: outputs per tile
+  int32_t n_mb = 0;     // STEP_GEMM: row blocks and column blocks
+  int32_t n_nb = 0;
+  int32_t n_ks = 1;     // contracted-index splits (partial sums + reduce task)
+  int32_t kseg = 0;     // contracted entries per split
+  int32_t n_tiles = 0;  // tasks of the tile group
+  int64_t partial = -1; // arena offset of the n_ks x outputs partial sums
+};
+
 // One pairwise contraction C = A . B over spin groups.
 struct PStep {
   int32_t a, b, c;
@@ -78,8 +90,7 @@ struct PlanKnot {
   int32_t tile = 256;
   int32_t big_log2 = 16;
   int32_t lds_bytes = 32768;
-  std::vector<uint8_t> big;                     // per step: split into tiles
-  std::vector<int32_t> step_tile;               // per step: outputs per tile
+  std::vector<PTiling> tiling;                  // per step: how it is executed
   Section sec;  // device-program section (make_section)
 };
 

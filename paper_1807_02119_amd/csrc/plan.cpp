@@ -44,6 +44,8 @@ int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
 // multiply-adds one tile aims at.
 constexpr double kMaxTiles = 1024;
 constexpr double kTileMacs = 32768;
+// Steps with fewer tiles than this split a long contracted index.
+constexpr double kSplitBelow = 256;
 // Auto ordering also tries the greedy plan when the min-fill plan's modelled
 // compute (seconds, without per-step latency) exceeds this.
 constexpr double kAutoGreedyFrom = 1e-6;
@@ -402,6 +404,7 @@ struct Orderer {
     for (int32_t v = 0; v < n; ++v) eval(v);
     std::vector<int32_t> nv, touched;
     std::vector<uint32_t> tmark(n, 0);
+    std::vector<uint64_t> xm(W, 0);  // N(x) + x as a bit set
     uint32_t ts = 0;
     // candidates (fill, degree, id) with lazy invalidation by a version stamp
     struct F {
@@ -443,29 +446,42 @@ struct Orderer {
           contract(a, b);
         }
       }
-      // eliminate x from the graph: its neighbours become a clique
+      // eliminate x from the graph: its neighbours become a clique.  Fill
+      // values change only for x's neighbours (recomputed) and for common
+      // neighbours z of a new clique edge (u, w): that pair of N(z) is now
+      // adjacent, so fill(z) drops by one.
       neigh(x, nv);
+      std::fill(xm.begin(), xm.end(), 0);
+      for (int32_t a : nv) xm[a >> 6] |= uint64_t(1) << (a & 63);
+      xm[x >> 6] |= uint64_t(1) << (x & 63);
+      ++ts;
       for (size_t i = 0; i < nv.size(); ++i)
-        for (size_t j = i + 1; j < nv.size(); ++j) set(nv[i], nv[j]);
-      for (int32_t a : nv) {
-        adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
-      }
+        for (size_t j = i + 1; j < nv.size(); ++j) {
+          const int32_t u = nv[i], w = nv[j];
+          if (has(u, w)) continue;
+          set(u, w);
+          for (int32_t ww = 0; ww < W; ++ww) {
+            uint64_t m = adj[(size_t)u * W + ww] & adj[(size_t)w * W + ww] & ~xm[ww];
+            while (m) {
+              const int32_t z = ww * 64 + __builtin_ctzll(m);
+              m &= m - 1;
+              --fill[z];
+              if (tmark[z] != ts) {
+                tmark[z] = ts;
+                touched.push_back(z);
+              }
+            }
+          }
+        }
+      for (int32_t a : nv) adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
       for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
       gone[x] = 1;
-      // fill values change within two hops of x
-      ++ts;
-      touched.clear();
       for (int32_t a : nv) {
-        if (tmark[a] != ts) { tmark[a] = ts; touched.push_back(a); }
-        neigh(a, nb);
-        for (int32_t b2 : nb)
-          if (tmark[b2] != ts) { tmark[b2] = ts; touched.push_back(b2); }
+        eval(a);
+        heap.push({fill[a], deg[a], a, ++ver[a]});
       }
-      for (int32_t a : touched)
-        if (!gone[a]) {
-          eval(a);
-          heap.push({fill[a], deg[a], a, ++ver[a]});
-        }
+      for (int32_t z : touched) heap.push({fill[z], deg[z], z, ++ver[z]});
+      touched.clear();
     }
   }
 
@@ -642,8 +658,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     t.size = (int64_t)sz;
     maxlog = std::max(maxlog, std::log2(sz));
   }
-  k.big.assign(k.steps.size(), 0);
-  k.step_tile.assign(k.steps.size(), k.tile);
+  k.tiling.assign(k.steps.size(), PTiling());
   for (size_t i = 0; i < k.steps.size(); ++i) {
     auto& sp = k.steps[i];
     double nb = qpow[sp.bs.size()], nm = qpow[sp.ms.size()], nn = qpow[sp.ns.size()],
@@ -651,15 +666,43 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     flops += 8.0 * nb * nm * nn * nk;
     bytes += es * double(k.tensors[sp.a].size + k.tensors[sp.b].size + k.tensors[sp.c].size);
     double macs = nb * nm * nn * nk;
-    k.big[i] = macs >= std::ldexp(1.0, k.big_log2) ? 1 : 0;
-    // a serial step stages its gather tables in LDS; larger ones are tiled
-    if (2 * nb + nm + 2 * nk + nn > kTabBuf) k.big[i] = 1;
-    // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
+    bool big = macs >= std::ldexp(1.0, k.big_log2);
+    // a serial step generates its gather tables in LDS; larger ones are tiled
+    if (2 * nb + nm + 2 * nk + nn > kTabBuf) big = true;
+    if (!big) continue;
+    PTiling& t = k.tiling[i];
     const double outs = nb * nm * nn;
-    double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
-                                     : std::max(1.0, std::floor(kTileMacs / nk));
-    if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
-    k.step_tile[i] = (int32_t)std::min(tile, outs);
+    double base;
+    if (o.tile_outputs == 0 && nm >= 16 && nn >= 16) {
+      t.mode = STEP_GEMM;
+      t.n_mb = (int32_t)std::ceil(nm / kGemmBlock);
+      t.n_nb = (int32_t)std::ceil(nn / kGemmBlock);
+      base = nb * t.n_mb * t.n_nb;
+    } else {
+      // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
+      t.mode = STEP_TILES;
+      double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
+                                       : std::max(1.0, std::floor(kTileMacs / std::min(nk, 1024.0)));
+      if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
+      tile = std::min(tile, outs);
+      t.tile = (int32_t)tile;
+      base = std::ceil(outs / tile);
+    }
+    // few tiles over a long contracted index: split it (partial sums, then a
+    // reduce task) so that the step spreads over the device
+    t.n_ks = 1;
+    t.kseg = (int32_t)nk;
+    if (nk >= 256 && base < kSplitBelow) {
+      double want = std::ceil(kSplitBelow / base), most = std::ceil(nk / 128.0);
+      double ks = std::min(std::min(want, most), 256.0);
+      if (ks > 1) {
+        int64_t kseg = (int64_t)std::ceil(nk / ks);
+        kseg = (kseg + 15) / 16 * 16;
+        t.kseg = (int32_t)kseg;
+        t.n_ks = (int32_t)((int64_t(nk) + kseg - 1) / kseg);
+      }
+    }
+    t.n_tiles = (int32_t)(base * t.n_ks);
   }
   st.flops = flops;
   st.bytes = bytes;
@@ -711,8 +754,15 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       }
     };
     for (int32_t t = 0; t < n_vt; ++t) k.tensors[t].off = alloc(k.tensors[t].size);
-    for (auto& sp : k.steps) {
+    for (size_t i = 0; i < k.steps.size(); ++i) {
+      const auto& sp = k.steps[i];
       k.tensors[sp.c].off = alloc(k.tensors[sp.c].size);
+      PTiling& t = k.tiling[i];
+      if (t.n_ks > 1) {
+        const int64_t len = (int64_t)t.n_ks * k.tensors[sp.c].size;
+        t.partial = alloc(len);
+        release(t.partial, len);
+      }
       release(k.tensors[sp.a].off, k.tensors[sp.a].size);
       release(k.tensors[sp.b].off, k.tensors[sp.b].size);
     }

@@ -30,9 +30,21 @@ enum TaskKind : int32_t {
   // tensors) if flags & TF_SETUP, steps [first, first+count) entirely, and
   // the knot's final reduction to Z if flags & TF_FINAL.
   TASK_SERIAL = 0,
-  // One tile (outputs [count*tile, (count+1)*tile)) of step `first`.
+  // Tile `count` of step `first` (see StepDesc.mode).
   TASK_TILE = 1,
+  // Sum the n_ks partial results of split step `first` into outputs
+  // [count * kReduceChunk, (count + 1) * kReduceChunk) of its output.
+  TASK_REDUCE = 2,
 };
+
+enum StepMode : int32_t {
+  STEP_SERIAL = 0,  // done inside a serial task
+  STEP_TILES = 1,   // tiles of `tile` consecutive outputs (all L lanes per output)
+  STEP_GEMM = 2,    // 32 x 32 output blocks per batch index, LDS-staged, 2x2 per thread
+};
+constexpr int32_t kGemmBlock = 32;  // rows and columns of a STEP_GEMM tile
+constexpr int32_t kGemmChunk = 16;  // contracted entries staged per LDS round
+constexpr int32_t kReduceChunk = 8192;  // outputs per task of a split step's reduction
 
 enum TaskFlags : int32_t { TF_SETUP = 1, TF_FINAL = 2 };
 
@@ -113,10 +125,14 @@ struct StepDesc {
   int32_t str;              // strides: A_b[rb] A_m[rm] A_k[rk] B_b[rb] B_k[rk] B_n[rn]
   int32_t ranks;            // rb | rm << 8 | rk << 16 | rn << 24
   int32_t n_tiles;          // 0 for steps run inside a serial task
-  int32_t tile;             // outputs per tile (tiled steps)
+  int32_t tile;             // STEP_TILES: outputs per tile
   // where A, B, C live: >= 0 global arena offset (complex entries),
   // < 0 LDS arena offset -1 - value (serial steps only)
   int32_t home_a, home_b, home_c;
+  int32_t mode;             // StepMode
+  int32_t n_mb, n_nb;       // STEP_GEMM: row and column blocks
+  int32_t n_ks, kseg;       // contracted-index splits and entries per split
+  int32_t partial;          // n_ks > 1: arena offset of the partial sums [ks][output]
 };
 
 struct VtxDesc {
@@ -150,6 +166,9 @@ struct TraceRec {
   int64_t t_end;    // execution finished
   int32_t task;
   int32_t wg;
+  // serial tasks: time in setup, in staging descriptors and generating
+  // tables, in the step products, in reductions and barriers
+  int64_t ph[4];
 };
 
 constexpr int32_t kShiftNone = (-2147483647 - 1);

@@ -410,7 +410,7 @@ class Batch:
 
     def set_trace(self, trace=None):
         """Record per-task timing into ``trace`` (a uint8 device tensor of at
-        least 32 * n_tasks bytes) on later launches; None switches it off."""
+        least 64 * n_tasks bytes) on later launches; None switches it off."""
         if trace is None:
             _check(lib().kn_batch_set_trace(self._h, None, 0), "kn_batch_set_trace")
         else:
@@ -422,7 +422,7 @@ class Batch:
     @staticmethod
     def decode_trace(raw: bytes):
         dt = np.dtype([("t_claim", "<i8"), ("t_start", "<i8"), ("t_end", "<i8"),
-                       ("task", "<i4"), ("wg", "<i4")])
+                       ("task", "<i4"), ("wg", "<i4"), ("ph", "<i8", (4,))])
         return np.frombuffer(raw, dt)
 
     def set_grid(self, grid: int):

@@ -38,11 +38,16 @@ KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps")], align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
-                                      "n_tiles", "tile", "home_a", "home_b", "home_c")],
+                                      "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
+                                      "n_mb", "n_nb", "n_ks", "kseg", "partial")],
                 align=True)
 VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
 TAB_CAP = 3072
+STEP_SERIAL, STEP_TILES, STEP_GEMM = 0, 1, 2
+GEMM_BLOCK = 32
+REDUCE_CHUNK = 8192
+TASK_SERIAL, TASK_TILE, TASK_REDUCE = 0, 1, 2
 
 
 class Image:
@@ -104,6 +109,7 @@ def run(raw: bytes, J=None):
 
     # the LDS arena exists only while one serial task runs
     live_g, live_l = {}, {}
+    split_pending = {}
     state = {"lds": None}
 
     def home(t):
@@ -178,14 +184,49 @@ def run(raw: bytes, J=None):
         assert int(tAb.max()) + int(tAm.max()) + int(tAk.max()) < A.size
         assert int(tBb.max()) + int(tBk.max()) + int(tBn.max()) < B.size
         assert min(int(x.min()) for x in (tAb, tAm, tAk, tBb, tBk, tBn)) >= 0
-        assert nb * nm * nn == int(im.tensors[c]["size"])
-        if int(s["n_tiles"]):
-            assert int(s["n_tiles"]) * int(s["tile"]) >= nb * nm * nn
-            assert (int(s["n_tiles"]) - 1) * int(s["tile"]) < nb * nm * nn
+        outs = nb * nm * nn
+        assert outs == int(im.tensors[c]["size"])
+        mode, n_tiles, n_ks, kseg = (int(s[f]) for f in ("mode", "n_tiles", "n_ks", "kseg"))
+        assert (mode == STEP_SERIAL) == (n_tiles == 0)
+        if mode != STEP_SERIAL:
+            assert n_ks >= 1 and kseg >= 1
+            assert n_ks * kseg >= nk and (n_ks - 1) * kseg < nk, "split does not cover k"
+            assert n_tiles % n_ks == 0
+            base = n_tiles // n_ks
+            if mode == STEP_TILES:
+                tile = int(s["tile"])
+                assert base * tile >= outs and (base - 1) * tile < outs
+            else:
+                n_mb, n_nb = int(s["n_mb"]), int(s["n_nb"])
+                assert base == nb * n_mb * n_nb
+                assert n_mb * GEMM_BLOCK >= nm and (n_mb - 1) * GEMM_BLOCK < nm
+                assert n_nb * GEMM_BLOCK >= nn and (n_nb - 1) * GEMM_BLOCK < nn
         Am = A[tAb[:, None, None] + tAm[None, :, None] + tAk[None, None, :]]
         Bm = B[tBb[:, None, None] + tBk[None, :, None] + tBn[None, None, :]]
-        C = np.matmul(Am, Bm).reshape(-1) * math.ldexp(1.0, -(sh(a) + sh(b)))
-        write_tensor(c, C, task_local=not int(s["n_tiles"]))
+        scale = math.ldexp(1.0, -(sh(a) + sh(b)))
+        if mode != STEP_SERIAL and n_ks > 1:
+            # partial sums of each contracted range go to the partial buffer,
+            # which must not touch a live tensor (operands, C or any other)
+            off = int(s["partial"])
+            assert off >= 0 and off + n_ks * outs <= int(h["arena_elems"])
+            reserved = dict(live_g)
+            reserved[c] = (int(im.tensors[c]["off"]), outs)
+            for u, (o2, s2) in reserved.items():
+                assert not (o2 < off + n_ks * outs and off < o2 + s2), \
+                    f"partial buffer of step {si} overlaps live tensor {u}"
+            parts = [np.matmul(Am[:, :, j * kseg:(j + 1) * kseg],
+                               Bm[:, j * kseg:(j + 1) * kseg, :]).reshape(-1) * scale
+                     for j in range(n_ks)]
+            arena[off:off + n_ks * outs] = np.concatenate(parts)
+            split_pending[si] = (off, n_ks, outs)
+            return
+        C = np.matmul(Am, Bm).reshape(-1) * scale
+        finish_step(si, C, local, task_local=mode == STEP_SERIAL)
+
+    def finish_step(si, C, local, task_local):
+        s = im.steps[si]
+        a, b, c = int(s["a"]), int(s["b"]), int(s["c"])
+        write_tensor(c, C, task_local=task_local)
         m = float(np.max(np.maximum(np.abs(C.real), np.abs(C.imag)))) if C.size else 0.0
         shift[c] = math.frexp(m)[1] if m > 0 else None
         exp2[c] = exp2[a] + exp2[b] + sh(a) + sh(b)
@@ -193,6 +234,14 @@ def run(raw: bytes, J=None):
             live_g.pop(op, None)
             live_l.pop(op, None)
         local.add(c)
+
+    def reduce(si, local):
+        off, n_ks, outs = split_pending.pop(si)
+        P = arena[off:off + n_ks * outs].reshape(n_ks, outs).copy()
+        C = P[0].copy()
+        for j in range(1, n_ks):
+            C = C + P[j]
+        finish_step(si, C, local, task_local=False)
 
     def mul(z, e, f):
         z = z * f
@@ -291,14 +340,33 @@ def run(raw: bytes, J=None):
             for t in local:
                 if home(t) < 0:
                     finished[t] = True
-        elif task["count"] == 0:
-            step(int(task["first"]), local)  # the model computes the whole step once
+        elif task["kind"] == TASK_TILE:
+            sd = im.steps[int(task["first"])]
+            assert int(sd["mode"]) in (STEP_TILES, STEP_GEMM)
+            assert 0 <= int(task["count"]) < int(sd["n_tiles"])
+            if task["count"] == 0:
+                step(int(task["first"]), local)  # the model computes the whole step once
+        else:
+            assert task["kind"] == TASK_REDUCE
+            si = int(task["first"])
+            sd = im.steps[si]
+            outs = int(sd["nb"]) * int(sd["nm"]) * int(sd["nn"])
+            assert int(sd["n_ks"]) > 1
+            assert int(im.groups[int(task["group"])]["n_tasks"]) == -(-outs // REDUCE_CHUNK)
+            if task["count"] == 0:
+                assert si in split_pending, "reduce before the step's tiles"
+                reduce(si, local)
         # group completion -> enqueue the next group
         g = int(task["group"])
         done_in_group[g] = done_in_group.get(g, 0) + 1
         if done_in_group[g] == int(im.groups[g]["n_tasks"]):
-            if task["kind"] == 1:
-                finished[int(im.steps[int(task["first"])]["c"])] = True
+            if task["kind"] != TASK_SERIAL:
+                sd = im.steps[int(task["first"])]
+                if task["kind"] == TASK_REDUCE or int(sd["n_ks"]) == 1:
+                    finished[int(sd["c"])] = True
+                else:
+                    nxt_g = im.groups[int(im.groups[g]["next"])]
+                    assert im.tasks[int(nxt_g["first_task"])]["kind"] == TASK_REDUCE
             nxt = int(im.groups[g]["next"])
             if nxt >= 0:
                 pending[nxt] -= int(im.groups[g]["n_tasks"])

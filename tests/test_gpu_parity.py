@@ -143,6 +143,23 @@ def test_tiled_steps_parity():
             assert z_close(m, e, mo, eo), (k, kw)
 
 
+def test_gemm_and_split_parity():
+    """32 x 32 GEMM tiles (ragged row and column blocks), GEMM tiles over a
+    split contracted range with their reduction, and split output tiles."""
+    work = gen.config_knots("q3_200_600", 0, count=72)
+    cases = [(71, work[71][0], {}), (11, work[11][0], {})]
+    for k in range(3):
+        cases.append((f"lattice{k}", gen.lattice_knot((63, k), 100, 400),
+                      dict(big_step_macs_log2=4)))
+    for name, d, kw in cases:
+        _log(f"gemm/split case {name} {kw}")
+        tg, mo, eo = oracle_z(d, 3)
+        for prec in (0, 1):
+            t, p, m, e = gpu_z(d, 3, precision=prec, **kw)
+            tol = TOL if prec == 0 else 1e-3
+            assert z_close(m, e, mo, eo, tol), (name, kw, prec)
+
+
 def test_exact_ring_parity():
     """Bit-for-bit-exact reference (Z in Z[t]) on mid-size knots."""
     for k in range(4):

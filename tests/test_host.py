@@ -146,6 +146,27 @@ def test_plan_model_tiled_and_options():
             _check_model(d, 3, **kw)
 
 
+def _split_gemm_cases():
+    """Knots whose plans hold every kind of large step: 32 x 32 GEMM tiles,
+    GEMM tiles over a split contracted range, and split output tiles."""
+    work = gen.config_knots("q3_200_600", 0, count=72)
+    cases = [(work[71][0], {}), (work[11][0], {})]
+    for k in range(2):
+        cases.append((gen.lattice_knot((63, k), 100, 400), dict(big_step_macs_log2=4)))
+    return cases
+
+
+def test_plan_model_gemm_and_split_steps():
+    seen = set()
+    for d, kw in _split_gemm_cases():
+        p = kn.Plan(kn.Tait(d.pd), 3, **kw)
+        for s in image_model.Image(p.image()).steps:
+            seen.add((int(s["mode"]), int(s["n_ks"]) > 1))
+        _check_model(d, 3, **kw)
+    assert {(image_model.STEP_GEMM, False), (image_model.STEP_GEMM, True),
+            (image_model.STEP_TILES, True), (image_model.STEP_TILES, False)} <= seen
+
+
 def test_plan_model_general_couplings():
     rng = np.random.default_rng(7)
     for k in range(5):
