@@ -226,7 +226,7 @@ kn_status kn_jones_variable(int32_t q, double* t_re, double* t_im);
 
 /* ------------------------------------------------------------------ host runtime
  * kn_plan_many: kn_build_tait + kn_plan_create for many knots on a pool of
- * host threads (n_threads <= 0: one per hardware thread).  Knot i has
+ * host threads (n_threads <= 0: one per CPU in the process affinity mask).  Knot i has
  * n_crossings[i] crossings; its PD code starts at pd + 4*s_i and its signs
  * (optional, NULL for all knots) at signs + s_i, s_i = sum of n_crossings[j]
  * for j < i.  q[i] in [2, 8].  taits[i] / plans[i] receive handles owned by

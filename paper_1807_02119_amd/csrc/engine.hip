@@ -262,11 +262,11 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
 
 // ------------------------------------------------------------------ step
 
-// Lanes per output: enough to give every thread work, at most 64 (one
-// wavefront, reduced with shuffles) and at most the contracted extent.
-__device__ inline int32_t lanes_per_output(int64_t outs, int32_t nk) {
+// Lanes per output: enough to give each of the nthr threads work, at most 64
+// (one wavefront, reduced with shuffles) and at most the contracted extent.
+__device__ inline int32_t lanes_per_output(int64_t outs, int32_t nk, int32_t nthr = kBlock) {
   int32_t L = 1;
-  while (L < 64 && 2 * L <= nk && outs * L < kBlock) L *= 2;
+  while (L < 64 && 2 * L <= nk && outs * L < nthr) L *= 2;
   return L;
 }
 
@@ -295,60 +295,148 @@ struct GenIx {
   __device__ inline int32_t b_k(int32_t k) const { return off(4, k); }
 };
 
+// Operand pointers with their address space fixed at compile time: LDS
+// operands are read with LDS instructions and global ones with global
+// instructions.  A generic (flat) load shares the vector-memory counter with
+// stores, so a flat operand load would wait for every earlier output store.
+template <class T>
+using LdsCx = __attribute__((address_space(3))) Cx<T>;
+template <class T>
+using GlbCx = __attribute__((address_space(1))) Cx<T>;
+
+// Loads and stores of complex entries through address-space-qualified
+// pointers (member-wise, merged into one wide access by the compiler).
+template <class P>
+__device__ inline auto ldc(P p) {
+  using T = decltype(+p->re);
+  return Cx<T>{p->re, p->im};
+}
+template <class P, class T>
+__device__ inline void stc(P p, Cx<T> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+
+// This lane's part of sum_k A[row, k] B[k, col] over k = k_first, k_first + L,
+// ... < nk: four entries per round, the loads of a round issued before its
+// products (entries past nk read as zero) so that a short contracted range
+// does not serialise on memory latency.
+template <class T, class Ix, class PA, class PB>
+__device__ inline void lane_dot(PA ra, PB rb, const Ix& ix, int32_t k, int32_t nk, int32_t L,
+                                T& cr, T& ci) {
+  T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
+  const Cx<T> zero{0, 0};
+  for (; k < nk; k += 4 * L) {
+    const bool v1 = k + L < nk, v2 = k + 2 * L < nk, v3 = k + 3 * L < nk;
+    const Cx<T> x0 = ldc(ra + ix.a_k(k));
+    const Cx<T> y0 = ldc(rb + ix.b_k(k));
+    Cx<T> x1 = zero, y1 = zero, x2 = zero, y2 = zero, x3 = zero, y3 = zero;
+    if (v1) {
+      x1 = ldc(ra + ix.a_k(k + L));
+      y1 = ldc(rb + ix.b_k(k + L));
+    }
+    if (v2) {
+      x2 = ldc(ra + ix.a_k(k + 2 * L));
+      y2 = ldc(rb + ix.b_k(k + 2 * L));
+    }
+    if (v3) {
+      x3 = ldc(ra + ix.a_k(k + 3 * L));
+      y3 = ldc(rb + ix.b_k(k + 3 * L));
+    }
+    cr0 = fma(x0.re, y0.re, cr0); cr0 = fma(-x0.im, y0.im, cr0);
+    ci0 = fma(x0.re, y0.im, ci0); ci0 = fma(x0.im, y0.re, ci0);
+    cr1 = fma(x1.re, y1.re, cr1); cr1 = fma(-x1.im, y1.im, cr1);
+    ci1 = fma(x1.re, y1.im, ci1); ci1 = fma(x1.im, y1.re, ci1);
+    cr0 = fma(x2.re, y2.re, cr0); cr0 = fma(-x2.im, y2.im, cr0);
+    ci0 = fma(x2.re, y2.im, ci0); ci0 = fma(x2.im, y2.re, ci0);
+    cr1 = fma(x3.re, y3.re, cr1); cr1 = fma(-x3.im, y3.im, cr1);
+    ci1 = fma(x3.re, y3.im, ci1); ci1 = fma(x3.im, y3.re, ci1);
+  }
+  cr = cr0 + cr1;
+  ci = ci0 + ci1;
+}
+
 // Outputs [o_begin, o_end) of C = A . B, each summed over k in [k0, nk) by L
-// lanes of one wavefront; returns this thread's max |.|.
-template <class T, class Ix>
-__device__ T step_outputs(const Cx<T>* __restrict__ pa, const Cx<T>* __restrict__ pb,
-                          Cx<T>* __restrict__ pc, const Ix& ix, int32_t nm, int32_t nn, int32_t k0,
-                          int32_t nk, int64_t o_begin, int64_t o_end, T scale, int32_t L) {
+// lanes of one wavefront; threads tid = 0..nthr-1 (a whole workgroup or one
+// wavefront) share the outputs.  A thread computes two outputs before it
+// stores either, so its stores overlap the next pair's loads.  Returns this
+// thread's max |.|.
+template <class T, class Ix, class PA, class PB, class PC>
+__device__ T step_outputs(PA pa, PB pb, PC pc, const Ix& ix, int32_t nm, int32_t nn, int32_t k0,
+                          int32_t nk, int64_t o_begin, int64_t o_end, T scale, int32_t L,
+                          int32_t tid, int32_t nthr) {
   const int32_t mn = nm * nn;
-  const int32_t lsub = threadIdx.x & (L - 1);
-  const int32_t slot = threadIdx.x / L;
-  const int32_t nslot = kBlock / L;
+  const int32_t lsub = tid & (L - 1);
+  const int32_t slot = tid / L;
+  const int32_t nslot = nthr / L;
   T lmax = 0;
-  for (int64_t o = o_begin + slot; o < o_end; o += nslot) {
+  for (int64_t o = o_begin + slot; o < o_end; o += 2 * nslot) {
     const int32_t oi = (int32_t)o;
-    const int32_t b = oi / mn;
-    const int32_t r = oi - b * mn;
-    const int32_t m = r / nn;
-    const int32_t n = r - m * nn;
-    const Cx<T>* ra = pa + ix.a_row(b, m);
-    const Cx<T>* rb = pb + ix.b_col(b, n);
-    T cr0 = 0, ci0 = 0, cr1 = 0, ci1 = 0;
-    int32_t k = k0 + lsub;
-    for (; k + 3 * L < nk; k += 4 * L) {
-      const Cx<T> x0 = ra[ix.a_k(k)], x1 = ra[ix.a_k(k + L)], x2 = ra[ix.a_k(k + 2 * L)],
-                  x3 = ra[ix.a_k(k + 3 * L)];
-      const Cx<T> y0 = rb[ix.b_k(k)], y1 = rb[ix.b_k(k + L)], y2 = rb[ix.b_k(k + 2 * L)],
-                  y3 = rb[ix.b_k(k + 3 * L)];
-      cr0 = fma(x0.re, y0.re, cr0); cr0 = fma(-x0.im, y0.im, cr0);
-      ci0 = fma(x0.re, y0.im, ci0); ci0 = fma(x0.im, y0.re, ci0);
-      cr1 = fma(x1.re, y1.re, cr1); cr1 = fma(-x1.im, y1.im, cr1);
-      ci1 = fma(x1.re, y1.im, ci1); ci1 = fma(x1.im, y1.re, ci1);
-      cr0 = fma(x2.re, y2.re, cr0); cr0 = fma(-x2.im, y2.im, cr0);
-      ci0 = fma(x2.re, y2.im, ci0); ci0 = fma(x2.im, y2.re, ci0);
-      cr1 = fma(x3.re, y3.re, cr1); cr1 = fma(-x3.im, y3.im, cr1);
-      ci1 = fma(x3.re, y3.im, ci1); ci1 = fma(x3.im, y3.re, ci1);
+    const int32_t oi2 = oi + nslot;
+    const bool two = oi2 < o_end;  // the same for the L lanes of an output
+    T cr, ci, cr2 = 0, ci2 = 0;
+    {
+      const int32_t b = oi / mn;
+      const int32_t r = oi - b * mn;
+      const int32_t m = r / nn;
+      const int32_t n = r - m * nn;
+      lane_dot<T>(pa + ix.a_row(b, m), pb + ix.b_col(b, n), ix, k0 + lsub, nk, L, cr, ci);
     }
-    for (; k < nk; k += L) {
-      const Cx<T> x = ra[ix.a_k(k)];
-      const Cx<T> y = rb[ix.b_k(k)];
-      cr0 = fma(x.re, y.re, cr0); cr0 = fma(-x.im, y.im, cr0);
-      ci0 = fma(x.re, y.im, ci0); ci0 = fma(x.im, y.re, ci0);
+    if (two) {
+      const int32_t b = oi2 / mn;
+      const int32_t r = oi2 - b * mn;
+      const int32_t m = r / nn;
+      const int32_t n = r - m * nn;
+      lane_dot<T>(pa + ix.a_row(b, m), pb + ix.b_col(b, n), ix, k0 + lsub, nk, L, cr2, ci2);
     }
-    T cr = cr0 + cr1, ci = ci0 + ci1;
     for (int32_t off = L >> 1; off >= 1; off >>= 1) {
       cr += __shfl_xor(cr, off, 64);
       ci += __shfl_xor(ci, off, 64);
+      cr2 += __shfl_xor(cr2, off, 64);
+      ci2 += __shfl_xor(ci2, off, 64);
     }
     if (lsub == 0) {
       cr *= scale;
       ci *= scale;
-      pc[oi] = Cx<T>{cr, ci};
+      stc(pc + oi, Cx<T>{cr, ci});
       lmax = fmax(lmax, fmax(fabs(cr), fabs(ci)));
+      if (two) {
+        cr2 *= scale;
+        ci2 *= scale;
+        stc(pc + oi2, Cx<T>{cr2, ci2});
+        lmax = fmax(lmax, fmax(fabs(cr2), fabs(ci2)));
+      }
     }
   }
   return lmax;
+}
+
+// step_outputs with each operand's home (>= 0 global arena offset, < 0 LDS
+// arena offset -1 - home) resolved to a pointer of its address space.
+template <class T, class Ix>
+__device__ T step_outputs_homes(int32_t ha, int32_t hb, int32_t hc, Cx<T>* arena, Cx<T>* lds,
+                                const Ix& ix, int32_t nm, int32_t nn, int32_t k0, int32_t nk,
+                                int64_t o_begin, int64_t o_end, T scale, int32_t L, int32_t tid,
+                                int32_t nthr) {
+  auto gl = [&](int32_t h) { return (GlbCx<T>*)(arena + h); };
+  auto ld = [&](int32_t h) { return (LdsCx<T>*)(lds + (-1 - h)); };
+#define KN_RUN(A, B, C) \
+  return step_outputs<T>(A(ha), B(hb), C(hc), ix, nm, nn, k0, nk, o_begin, o_end, scale, L, tid, nthr)
+  if (ha < 0) {
+    if (hb < 0) {
+      if (hc < 0) KN_RUN(ld, ld, ld);
+      KN_RUN(ld, ld, gl);
+    }
+    if (hc < 0) KN_RUN(ld, gl, ld);
+    KN_RUN(ld, gl, gl);
+  }
+  if (hb < 0) {
+    if (hc < 0) KN_RUN(gl, ld, ld);
+    KN_RUN(gl, ld, gl);
+  }
+  if (hc < 0) KN_RUN(gl, gl, ld);
+  KN_RUN(gl, gl, gl);
+#undef KN_RUN
 }
 
 template <class T>
@@ -375,14 +463,47 @@ __device__ inline int32_t step_tab_entries(const StepDesc& d) {
   return 2 * d.nb + d.nm + 2 * d.nk + d.nn;
 }
 
-// Serial steps [first, first + count): descriptors are staged in LDS one
-// chunk at a time and the chunk's gather tables are generated there from the
-// strides; the chunk then runs with no global round trip except operands that
-// live in the global arena.
 template <class T>
 __device__ inline Cx<T>* home_ptr(int32_t home, Cx<T>* arena, Cx<T>* lds) {
   return home >= 0 ? arena + home : lds + (-1 - home);
 }
+
+// One serial step C = A . B on threads tid = 0..nthr-1, with the gather
+// tables `tab` (A_b A_m A_k B_b B_k B_n, generated in LDS) and the states of
+// operands made before the task in ext[0..1].  Returns this thread's max |.|
+// and C's exponent.
+template <class T>
+__device__ inline T serial_step(const StepDesc& d, const int32_t* tab, Cx<T>* arena, Cx<T>* lds,
+                                const States& st, const TensorState* ext, int32_t tid,
+                                int32_t nthr, int64_t& ec) {
+  TabIx ix;
+  ix.ab = tab;
+  ix.am = ix.ab + d.nb;
+  ix.ak = ix.am + d.nm;
+  ix.bb = ix.ak + d.nk;
+  ix.bk = ix.bb + d.nb;
+  ix.bn = ix.bk + d.nk;
+  int32_t sa, sb;
+  int64_t ea, eb;
+  if (st.local(d.a)) st.get(d.a, sa, ea);
+  else { sa = ext[0].shift; ea = ext[0].exp2; }
+  if (st.local(d.b)) st.get(d.b, sb, eb);
+  else { sb = ext[1].shift; eb = ext[1].exp2; }
+  const int32_t sh = shift_of(sa) + shift_of(sb);
+  ec = ea + eb + sh;
+  const T scale = (T)ldexp(1.0, -sh);
+  const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
+  const int32_t L = lanes_per_output(outs, d.nk, nthr);
+  return step_outputs_homes<T>(d.home_a, d.home_b, d.home_c, arena, lds, ix, d.nm, d.nn, 0, d.nk,
+                               0, outs, scale, L, tid, nthr);
+}
+
+// Serial steps [first, first + count): descriptors are staged in LDS one
+// chunk at a time and the chunk's gather tables are generated there from the
+// strides; the chunk then runs with no global round trip except operands that
+// live in the global arena.
+// Serial steps of a level with fewer products than this run on one wavefront.
+constexpr int64_t kWaveMacs = 2048;
 
 template <class T>
 __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int32_t q,
@@ -458,34 +579,43 @@ __device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int
     }
     __syncthreads();
     lap(1);
-    for (int32_t j = 0; j < ce; ++j) {
-      const StepDesc d = s_desc[j];
-      TabIx ix;
-      ix.ab = s_tab + s_tb[j];
-      ix.am = ix.ab + d.nb;
-      ix.ak = ix.am + d.nm;
-      ix.bb = ix.ak + d.nk;
-      ix.bk = ix.bb + d.nb;
-      ix.bn = ix.bk + d.nk;
-      int32_t sa, sb;
-      int64_t ea, eb;
-      if (st.local(d.a)) st.get(d.a, sa, ea);
-      else { sa = s_ext[2 * j].shift; ea = s_ext[2 * j].exp2; }
-      if (st.local(d.b)) st.get(d.b, sb, eb);
-      else { sb = s_ext[2 * j + 1].shift; eb = s_ext[2 * j + 1].exp2; }
-      const int32_t sh = shift_of(sa) + shift_of(sb);
-      const int64_t ec = ea + eb + sh;
-      const T scale = (T)ldexp(1.0, -sh);
-      const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
-      const int32_t L = lanes_per_output(outs, d.nk);
-      T lm = step_outputs<T>(home_ptr<T>(d.home_a, arena, lds), home_ptr<T>(d.home_b, arena, lds),
-                             home_ptr<T>(d.home_c, arena, lds), ix, d.nm, d.nn, 0, d.nk, 0,
-                             outs, scale, L);
+    // levels: a run of adjacent steps of equal level is independent; a lone
+    // step uses the whole workgroup, otherwise each wavefront takes steps of
+    // the level in turn, and one barrier ends the level
+    for (int32_t j = 0; j < ce;) {
+      int32_t je = j + 1;
+      while (je < ce && s_desc[je].lvl == s_desc[j].lvl) ++je;
+      // steps with many products use the whole workgroup, one after another;
+      // the rest are shared out to the wavefronts
+      for (int32_t u = j; u < je; ++u) {
+        const StepDesc& d = s_desc[u];
+        if (je - j > 1 && (int64_t)d.nb * d.nm * d.nn * d.nk < kWaveMacs) continue;
+        int64_t ec;
+        T lm = serial_step<T>(d, s_tab + s_tb[u], arena, lds, st, s_ext + 2 * u,
+                              (int32_t)threadIdx.x, kBlock, ec);
+        lm = block_max<T>(lm, s_red);
+        if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
+      }
+      if (je - j > 1) {
+        // the wavefront index is uniform within a wavefront: readfirstlane
+        // lets the step's descriptor live in scalar registers
+        const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+        const int32_t lane = threadIdx.x & 63;
+        int32_t r = 0;  // rank among the level's small steps
+        for (int32_t u = j; u < je; ++u) {
+          const StepDesc& d = s_desc[u];
+          if ((int64_t)d.nb * d.nm * d.nn * d.nk >= kWaveMacs) continue;
+          if ((r++ & (kBlock / 64 - 1)) != wv) continue;
+          int64_t ec;
+          T lm = serial_step<T>(d, s_tab + s_tb[u], arena, lds, st, s_ext + 2 * u, lane, 64, ec);
+          lm = wave_max(lm);
+          if (lane == 0) st.set(d.c, frexp_shift<T>(lm), ec);
+        }
+      }
       lap(2);
-      lm = block_max<T>(lm, s_red);
-      if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
       __syncthreads();
       lap(3);
+      j = je;
     }
     s += ce;
   }
@@ -546,8 +676,9 @@ __device__ void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
   const int32_t L = lanes_per_output(o1 - o0, k1 - k0);
   Cx<T>* pc = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
-  T lm = step_outputs<T>(arena + s.home_a, arena + s.home_b, pc, ix, s.nm, s.nn, k0, k1, o0, o1,
-                         scale, L);
+  T lm = step_outputs<T>((const GlbCx<T>*)(arena + s.home_a), (const GlbCx<T>*)(arena + s.home_b),
+                         (GlbCx<T>*)pc, ix, s.nm, s.nn, k0, k1, o0, o1, scale, L,
+                         (int32_t)threadIdx.x, kBlock);
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
 
@@ -596,8 +727,8 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   }
   // this thread's loads: contracted entry kk of rows/columns lr and lr + 16
   const int32_t kk = tid & (BK - 1), lr = tid >> 4;
-  const Cx<T>* __restrict__ A = arena + s.home_a;
-  const Cx<T>* __restrict__ B = arena + s.home_b;
+  const GlbCx<T>* A = (const GlbCx<T>*)(arena + s.home_a);
+  const GlbCx<T>* B = (const GlbCx<T>*)(arena + s.home_b);
   const bool am0 = m0 + lr < s.nm, am1 = m0 + lr + 16 < s.nm;
   const bool bn0 = n0 + lr < s.nn, bn1 = n0 + lr + 16 < s.nn;
   const int32_t oab = group_off(b, sab, rb, D), obb = group_off(b, sbb, rb, D);
@@ -624,10 +755,10 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
         oa = group_off(k0 + k, sak, rk, D);
         ob = group_off(k0 + k, sbk, rk, D);
       }
-      if (am0) x.a0 = A[ra0 + oa];
-      if (am1) x.a1 = A[ra1 + oa];
-      if (bn0) x.b0 = B[cb0 + ob];
-      if (bn1) x.b1 = B[cb1 + ob];
+      if (am0) x.a0 = ldc(A + ra0 + oa);
+      if (am1) x.a1 = ldc(A + ra1 + oa);
+      if (bn0) x.b0 = ldc(B + cb0 + ob);
+      if (bn1) x.b1 = ldc(B + cb1 + ob);
     }
     return x;
   };
@@ -657,14 +788,14 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
     __syncthreads();
   }
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
-  Cx<T>* C = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
+  GlbCx<T>* C = (GlbCx<T>*)(s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c);
   const int64_t crow = (int64_t)b * s.nm;
   T lm = 0;
   auto put = [&](int32_t m, int32_t n, T cr, T ci) {
     if (m < s.nm && n < s.nn) {
       cr *= scale;
       ci *= scale;
-      C[(crow + m) * s.nn + n] = Cx<T>{cr, ci};
+      stc(C + (crow + m) * s.nn + n, Cx<T>{cr, ci});
       lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
     }
   };
@@ -683,17 +814,17 @@ __device__ void reduce_step(const DevProg& p, const StepDesc& s, int32_t part, C
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
   const int64_t o0 = (int64_t)part * kReduceChunk;
   const int64_t o1 = o0 + kReduceChunk < outs ? o0 + kReduceChunk : outs;
-  const Cx<T>* P = arena + s.partial;
-  Cx<T>* C = arena + s.home_c;
+  const GlbCx<T>* P = (const GlbCx<T>*)(arena + s.partial);
+  GlbCx<T>* C = (GlbCx<T>*)(arena + s.home_c);
   T lm = 0;
   for (int64_t o = o0 + threadIdx.x; o < o1; o += kBlock) {
     T cr = 0, ci = 0;
     for (int32_t j = 0; j < s.n_ks; ++j) {
-      const Cx<T> v = P[(int64_t)j * outs + o];
+      const Cx<T> v = ldc(P + (int64_t)j * outs + o);
       cr += v.re;
       ci += v.im;
     }
-    C[o] = Cx<T>{cr, ci};
+    stc(C + o, Cx<T>{cr, ci});
     lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
   }
   int64_t ec;

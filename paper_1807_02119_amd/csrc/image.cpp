@@ -39,12 +39,12 @@ int64_t put(std::vector<uint8_t>& img, const std::vector<T>& v) {
 
 // Element stride of every spin of `group` in a tensor stored in `order`
 // (row-major, last spin fastest), appended to `out`.
-void group_strides(const std::vector<int32_t>& group, const std::vector<int32_t>& order,
-                   int32_t q, std::vector<int32_t>& out) {
+void group_strides(const SpinList& group, const SpinList& order, int32_t q,
+                   std::vector<int32_t>& out) {
   for (int32_t sp : group) {
     int64_t s = 1;
     bool found = false;
-    for (int64_t j = (int64_t)order.size() - 1; j >= 0; --j) {
+    for (int32_t j = order.size() - 1; j >= 0; --j) {
       if (order[j] == sp) {
         found = true;
         break;
@@ -54,55 +54,6 @@ void group_strides(const std::vector<int32_t>& group, const std::vector<int32_t>
     out.push_back(found ? (int32_t)s : 0);
   }
 }
-
-// First-fit allocator over [0, cap) entries, blocks kept in a sorted vector;
-// alloc returns -1 when the request does not fit.
-struct FitAlloc {
-  struct Blk {
-    int64_t off, len;
-  };
-  int64_t cap;
-  int64_t top = 0;
-  std::vector<Blk> free_blk;  // sorted by offset
-  explicit FitAlloc(int64_t c) : cap(c) {}
-  static int64_t round(int64_t len) { return (len + 7) / 8 * 8; }
-  int64_t alloc(int64_t len) {
-    len = round(len);
-    for (size_t i = 0; i < free_blk.size(); ++i)
-      if (free_blk[i].len >= len) {
-        int64_t off = free_blk[i].off;
-        free_blk[i].off += len;
-        free_blk[i].len -= len;
-        if (free_blk[i].len == 0) free_blk.erase(free_blk.begin() + i);
-        return off;
-      }
-    if (!free_blk.empty() && free_blk.back().off + free_blk.back().len == top &&
-        free_blk.back().off + len <= cap) {
-      int64_t off = free_blk.back().off;
-      free_blk.pop_back();
-      top = off + len;
-      return off;
-    }
-    if (top + len > cap) return -1;
-    int64_t off = top;
-    top += len;
-    return off;
-  }
-  void release(int64_t off, int64_t len) {
-    len = round(len);
-    size_t i = 0;
-    while (i < free_blk.size() && free_blk[i].off < off) ++i;
-    free_blk.insert(free_blk.begin() + i, Blk{off, len});
-    if (i + 1 < free_blk.size() && free_blk[i].off + free_blk[i].len == free_blk[i + 1].off) {
-      free_blk[i].len += free_blk[i + 1].len;
-      free_blk.erase(free_blk.begin() + i + 1);
-    }
-    if (i > 0 && free_blk[i - 1].off + free_blk[i - 1].len == free_blk[i].off) {
-      free_blk[i - 1].len += free_blk[i].len;
-      free_blk.erase(free_blk.begin() + i);
-    }
-  }
-};
 
 // A knot's groups before they are laid out.
 struct PGroup {
@@ -124,15 +75,15 @@ void make_section(PlanKnot& k) {
   d.t_im = k.t_im;
   d.q = q;
   d.n_edges = k.n_edges;
-  d.n_medges = (int32_t)k.medges.size();
+  d.n_medges = (int32_t)k.medge_off.size() - 1;
   d.n_vtx = (int32_t)k.vtx.size();
   d.n_factors = (int32_t)k.factors.size();
   d.n_comps = (int32_t)k.comps.size();
   d.n_iso = k.n_iso;
   d.n_steps = (int32_t)k.steps.size();
-  for (auto& m : k.medges) {
-    S.md.push_back({(int32_t)S.members.size(), (int32_t)m.size()});
-    for (int32_t e : m) S.members.push_back(e);
+  for (size_t m = 0; m + 1 < k.medge_off.size(); ++m) {
+    S.md.push_back({(int32_t)S.members.size(), k.medge_off[m + 1] - k.medge_off[m]});
+    for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) S.members.push_back(k.medge_mem[j]);
   }
   S.fac = k.factors;
   S.comps = k.comps;
@@ -148,7 +99,7 @@ void make_section(PlanKnot& k) {
   S.sd.reserve(k.steps.size());
   for (size_t si = 0; si < k.steps.size(); ++si) {
     const PStep& s = k.steps[si];
-    StepDesc x;
+    StepDesc x{};
     x.a = s.a;
     x.b = s.b;
     x.c = s.c;
@@ -181,6 +132,7 @@ void make_section(PlanKnot& k) {
     x.n_ks = t.n_ks;
     x.kseg = t.kseg;
     x.partial = t.partial >= 0 ? (int32_t)t.partial : -1;
+    x.lvl = t.level;
     S.sd.push_back(x);
   }
 
@@ -234,7 +186,7 @@ void make_section(PlanKnot& k) {
         if (c == ns) return (g.flags & TF_FINAL) != 0;
         return c >= lo && c < hi;
       };
-      FitAlloc la(cap);
+      FitAlloc la(cap, 8);
       int64_t peak = 0;
       if (g.flags & TF_SETUP)
         for (const auto& v : k.vtx)
@@ -243,15 +195,24 @@ void make_section(PlanKnot& k) {
             if (o >= 0) S.td[v.tensor].lds_off = (int32_t)o;
           }
       peak = std::max(peak, la.top);
-      for (int32_t si = lo; si < hi; ++si) {
-        const PStep& s = k.steps[si];
-        if (inside(s.c)) {
-          int64_t o = la.alloc(k.tensors[s.c].size);
-          if (o >= 0) S.td[s.c].lds_off = (int32_t)o;
+      // a level's outputs are placed before any of its operands is released
+      for (int32_t si = lo; si < hi;) {
+        int32_t sj = si + 1;
+        while (sj < hi && same_level(k, sj - 1)) ++sj;
+        for (int32_t u = si; u < sj; ++u) {
+          const PStep& s = k.steps[u];
+          if (inside(s.c)) {
+            int64_t o = la.alloc(k.tensors[s.c].size);
+            if (o >= 0) S.td[s.c].lds_off = (int32_t)o;
+          }
         }
         peak = std::max(peak, la.top);
-        for (int32_t op : {s.a, s.b})
-          if (S.td[op].lds_off >= 0) la.release(S.td[op].lds_off, k.tensors[op].size);
+        for (int32_t u = si; u < sj; ++u) {
+          const PStep& s = k.steps[u];
+          for (int32_t op : {s.a, s.b})
+            if (S.td[op].lds_off >= 0) la.release(S.td[op].lds_off, k.tensors[op].size);
+        }
+        si = sj;
       }
       S.lds_used = std::max<int32_t>(S.lds_used, (int32_t)(peak * es));
     }

@@ -19,6 +19,80 @@ struct kn_tait {
 
 namespace kn {
 
+// A short list of spin ids.  Tensors of a plan have low rank, so up to kIn ids
+// are stored inline and only longer lists go to the heap; this keeps the
+// planner's thousands of small lists out of the allocator.
+class SpinList {
+ public:
+  static constexpr int32_t kIn = 10;
+  SpinList() = default;
+  SpinList(const SpinList& o) { copy_from(o); }
+  SpinList(SpinList&& o) noexcept { move_from(o); }
+  SpinList& operator=(const SpinList& o) {
+    if (this != &o) {
+      n_ = 0;
+      copy_from(o);
+    }
+    return *this;
+  }
+  SpinList& operator=(SpinList&& o) noexcept {
+    if (this != &o) {
+      release();
+      move_from(o);
+    }
+    return *this;
+  }
+  ~SpinList() { release(); }
+  int32_t size() const { return n_; }
+  bool empty() const { return n_ == 0; }
+  const int32_t* begin() const { return data(); }
+  const int32_t* end() const { return data() + n_; }
+  int32_t operator[](int32_t i) const { return data()[i]; }
+  void reserve(int32_t c) {
+    if (c > cap_) grow(c);
+  }
+  void push_back(int32_t x) {
+    if (n_ == cap_) grow(2 * cap_);
+    data()[n_++] = x;
+  }
+
+ private:
+  int32_t* data() { return heap_ ? heap_ : in_; }
+  const int32_t* data() const { return heap_ ? heap_ : in_; }
+  void grow(int32_t c) {
+    int32_t* p = new int32_t[c];
+    for (int32_t i = 0; i < n_; ++i) p[i] = data()[i];
+    delete[] heap_;
+    heap_ = p;
+    cap_ = c;
+  }
+  void release() {
+    delete[] heap_;
+    heap_ = nullptr;
+    cap_ = kIn;
+    n_ = 0;
+  }
+  void copy_from(const SpinList& o) {
+    reserve(o.n_);
+    for (int32_t i = 0; i < o.n_; ++i) data()[i] = o.data()[i];
+    n_ = o.n_;
+  }
+  void move_from(SpinList& o) {
+    n_ = o.n_;
+    cap_ = o.cap_;
+    heap_ = o.heap_;
+    if (!heap_)
+      for (int32_t i = 0; i < n_; ++i) in_[i] = o.in_[i];
+    o.heap_ = nullptr;
+    o.cap_ = kIn;
+    o.n_ = 0;
+  }
+  int32_t n_ = 0;
+  int32_t cap_ = kIn;
+  int32_t* heap_ = nullptr;
+  int32_t in_[kIn];
+};
+
 // One knot's part of a device program with knot-local ids and offsets; an
 // image is the concatenation of sections with the ids shifted (build_image).
 struct Section {
@@ -49,16 +123,17 @@ struct PTiling {
   int32_t kseg = 0;     // contracted entries per split
   int32_t n_tiles = 0;  // tasks of the tile group
   int64_t partial = -1; // arena offset of the n_ks x outputs partial sums
+  int32_t level = 0;    // serial steps: dependency level inside its run (from 1)
 };
 
 // One pairwise contraction C = A . B over spin groups.
 struct PStep {
   int32_t a, b, c;
-  std::vector<int32_t> bs, ms, ns, ks;  // batch, rows (A only), cols (B only), contracted
+  SpinList bs, ms, ns, ks;  // batch, rows (A only), cols (B only), contracted
 };
 
 struct PTensor {
-  std::vector<int32_t> spins;  // storage order, first = most significant
+  SpinList spins;  // storage order, first = most significant
   int64_t off = 0;             // arena offset (entries), knot-local
   int64_t size = 1;            // q^rank
 };
@@ -67,8 +142,8 @@ struct PVertex {
   int32_t tensor;
   int32_t center;               // spin of the vertex itself
   bool keep_center;
-  std::vector<int32_t> nbr;     // neighbour spins, slot order
-  std::vector<int32_t> medge;   // merged edge per slot (knot-local)
+  SpinList nbr;                 // neighbour spins, slot order
+  SpinList medge;               // merged edge per slot (knot-local)
 };
 
 // Everything about one knot's contraction, in knot-local ids.
@@ -79,7 +154,8 @@ struct PlanKnot {
   bool jones_only = true;
   int32_t n_edges = 0;                          // original Tait edges
   std::vector<int8_t> eps;                      // original Tait signs
-  std::vector<std::vector<int32_t>> medges;     // members of each merged edge
+  // merged edge m: original edges medge_mem[medge_off[m] .. medge_off[m + 1])
+  std::vector<int32_t> medge_off{0}, medge_mem;
   std::vector<Factor> factors;                  // simplification factors
   int32_t n_iso = 0;                            // isolated spins
   std::vector<PTensor> tensors;                 // vertex tensors, then step outputs
@@ -92,6 +168,65 @@ struct PlanKnot {
   int32_t lds_bytes = 32768;
   std::vector<PTiling> tiling;                  // per step: how it is executed
   Section sec;  // device-program section (make_section)
+};
+
+// Adjacent steps i and i + 1 run concurrently: both serial and of the same
+// level (runs of serial steps are separated by tiled steps, and levels
+// ascend inside a run).
+inline bool same_level(const PlanKnot& k, size_t i) {
+  const PTiling& a = k.tiling[i];
+  const PTiling& b = k.tiling[i + 1];
+  return a.mode == STEP_SERIAL && b.mode == STEP_SERIAL && a.level == b.level;
+}
+
+// First-fit allocator over [0, cap) entries, sizes rounded up to `align`
+// entries, free blocks kept in a sorted vector; alloc returns -1 when the
+// request does not fit.
+struct FitAlloc {
+  struct Blk {
+    int64_t off, len;
+  };
+  int64_t cap, align;
+  int64_t top = 0;
+  std::vector<Blk> free_blk;  // sorted by offset
+  FitAlloc(int64_t c, int64_t a) : cap(c), align(a) {}
+  int64_t round(int64_t len) const { return (len + align - 1) / align * align; }
+  int64_t alloc(int64_t len) {
+    len = round(len);
+    for (size_t i = 0; i < free_blk.size(); ++i)
+      if (free_blk[i].len >= len) {
+        int64_t off = free_blk[i].off;
+        free_blk[i].off += len;
+        free_blk[i].len -= len;
+        if (free_blk[i].len == 0) free_blk.erase(free_blk.begin() + i);
+        return off;
+      }
+    if (!free_blk.empty() && free_blk.back().off + free_blk.back().len == top &&
+        free_blk.back().off + len <= cap) {
+      int64_t off = free_blk.back().off;
+      free_blk.pop_back();
+      top = off + len;
+      return off;
+    }
+    if (top + len > cap) return -1;
+    int64_t off = top;
+    top += len;
+    return off;
+  }
+  void release(int64_t off, int64_t len) {
+    len = round(len);
+    size_t i = 0;
+    while (i < free_blk.size() && free_blk[i].off < off) ++i;
+    free_blk.insert(free_blk.begin() + i, Blk{off, len});
+    if (i + 1 < free_blk.size() && free_blk[i].off + free_blk[i].len == free_blk[i + 1].off) {
+      free_blk[i].len += free_blk[i + 1].len;
+      free_blk.erase(free_blk.begin() + i + 1);
+    }
+    if (i > 0 && free_blk[i - 1].off + free_blk[i - 1].len == free_blk[i].off) {
+      free_blk[i - 1].len += free_blk[i].len;
+      free_blk.erase(free_blk.begin() + i);
+    }
+  }
 };
 
 // Lay the knot's plan out as a relocatable device-program section.

@@ -30,6 +30,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <memory>
 #include <queue>
 #include <set>
 #include <unordered_map>
@@ -46,9 +47,10 @@ constexpr double kMaxTiles = 1024;
 constexpr double kTileMacs = 32768;
 // Steps with fewer tiles than this split a long contracted index.
 constexpr double kSplitBelow = 256;
-// Auto ordering also tries the greedy plan when the min-fill plan's modelled
-// compute (seconds, without per-step latency) exceeds this.
-constexpr double kAutoGreedyFrom = 1e-6;
+// Auto ordering also tries the greedy plan when the min-fill plan has at least
+// this many flops (below it the greedy plan rarely wins and planning time
+// matters more).
+constexpr double kAutoGreedyFrom = 1e8;
 
 namespace {
 
@@ -79,32 +81,46 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
   }
   std::sort(keyed.begin(), keyed.end());
   std::vector<std::pair<int32_t, int32_t>> ends;
+  k.medge_off.assign(1, 0);
+  k.medge_mem.clear();
+  k.medge_mem.reserve(keyed.size());
   for (size_t i = 0; i < keyed.size(); ++i) {
-    if (i == 0 || keyed[i].first != keyed[i - 1].first) {
-      k.medges.emplace_back();
+    if (i > 0 && keyed[i].first != keyed[i - 1].first)
+      k.medge_off.push_back((int32_t)k.medge_mem.size());
+    if (i == 0 || keyed[i].first != keyed[i - 1].first)
       ends.emplace_back((int32_t)(keyed[i].first / nv), (int32_t)(keyed[i].first % nv));
-    }
-    k.medges.back().push_back(keyed[i].second);
+    k.medge_mem.push_back(keyed[i].second);
   }
+  if (!keyed.empty()) k.medge_off.push_back((int32_t)k.medge_mem.size());
   (void)r1;
-  const int32_t nm = (int32_t)k.medges.size();
+  const int32_t nm = (int32_t)k.medge_off.size() - 1;
   std::vector<uint8_t> alive_e(nm, 1);
   std::vector<int32_t> mult(nm);
   for (int32_t m = 0; m < nm; ++m) {
     int32_t s = 0;
-    for (int32_t e : k.medges[m]) s += g.eps[e];
-    mult[m] = r2 ? std::abs(s) : (int32_t)k.medges[m].size();
+    for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) s += g.eps[k.medge_mem[j]];
+    mult[m] = r2 ? std::abs(s) : k.medge_off[m + 1] - k.medge_off[m];
     if (r2 && s == 0) alive_e[m] = 0;  // Reidemeister II: x_m = 1
   }
-  // adjacency over live merged edges
-  std::vector<std::vector<int32_t>> inc(nv);
+  // incidence over live merged edges, in compressed rows
+  std::vector<int32_t> ioff(nv + 1, 0), inc;
   for (int32_t m = 0; m < nm; ++m)
     if (alive_e[m]) {
-      inc[ends[m].first].push_back(m);
-      inc[ends[m].second].push_back(m);
+      ioff[ends[m].first + 1]++;
+      ioff[ends[m].second + 1]++;
     }
+  for (int32_t v = 0; v < nv; ++v) ioff[v + 1] += ioff[v];
+  inc.resize(ioff[nv]);
+  {
+    std::vector<int32_t> fp(ioff.begin(), ioff.end() - 1);
+    for (int32_t m = 0; m < nm; ++m)
+      if (alive_e[m]) {
+        inc[fp[ends[m].first]++] = m;
+        inc[fp[ends[m].second]++] = m;
+      }
+  }
   std::vector<int32_t> deg(nv);
-  for (int32_t v = 0; v < nv; ++v) deg[v] = (int32_t)inc[v].size();
+  for (int32_t v = 0; v < nv; ++v) deg[v] = ioff[v + 1] - ioff[v];
   std::vector<uint8_t> alive_v(nv, 1);
   if (flags & 1) {
     // Reidemeister I on spikes: peel degree-1 vertices repeatedly
@@ -116,8 +132,8 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
       stack.pop_back();
       if (!alive_v[v] || deg[v] != 1) continue;
       int32_t m = -1;
-      for (int32_t x : inc[v])
-        if (alive_e[x]) { m = x; break; }
+      for (int32_t j = ioff[v]; j < ioff[v + 1]; ++j)
+        if (alive_e[inc[j]]) { m = inc[j]; break; }
       if (m < 0) continue;
       alive_e[m] = 0;
       k.factors.push_back({FAC_LEAF, m});
@@ -241,6 +257,7 @@ struct Orderer {
       : n(n_), q(q_), T(init), cnt(n_, 0), hold(n_), alive(init.size(), 1), mark(n_, 0),
         qpow(64) {
     T.reserve(2 * init.size() + 1);
+    S.reserve(init.size() + 1);
     alive.reserve(2 * init.size() + 1);
     for (int32_t t = 0; t < (int32_t)T.size(); ++t)
       for (int32_t sp : T[t].spins) {
@@ -485,6 +502,15 @@ struct Orderer {
     }
   }
 
+  // 8 flops per complex multiply-add over all steps.
+  double flops() const {
+    double f = 0;
+    for (const auto& st : S)
+      f += 8.0 * qpow[std::min<size_t>(st.bs.size() + st.ms.size() + st.ns.size() + st.ks.size(),
+                                       63)];
+    return f;
+  }
+
   // Roofline-modelled time of the plan: per step max(flops/peak, bytes/bw),
   // plus a fixed per-step latency when `latency`.
   double model_cost(int32_t precision, bool latency) const {
@@ -504,6 +530,66 @@ struct Orderer {
 };
 
 }  // namespace
+
+// Serial steps that depend on each other only through earlier levels run
+// concurrently on the waves of one workgroup.  Every maximal run of serial
+// steps is reordered by dependency level (1 + the highest level among the
+// producers of its operands inside the run; stable within a level), and the
+// tensors are renumbered so that step i still produces tensor n_vt + i.
+void level_schedule(PlanKnot& k, int32_t n_vt) {
+  const int32_t ns = (int32_t)k.steps.size();
+  std::vector<int32_t> order;
+  order.reserve(ns);
+  std::vector<int32_t> lvl(ns, 0);  // by old step index
+  for (int32_t i = 0; i < ns;) {
+    if (k.tiling[i].mode != STEP_SERIAL) {
+      order.push_back(i++);
+      continue;
+    }
+    int32_t j = i;
+    while (j < ns && k.tiling[j].mode == STEP_SERIAL) ++j;
+    int32_t top = 0;
+    for (int32_t u = i; u < j; ++u) {
+      int32_t l = 0;
+      for (int32_t op : {k.steps[u].a, k.steps[u].b}) {
+        const int32_t ps = op - n_vt;  // producing step
+        if (ps >= i && ps < u) l = std::max(l, lvl[ps]);
+      }
+      lvl[u] = l + 1;
+      top = std::max(top, l + 1);
+    }
+    // counting sort by level keeps the original order within a level
+    std::vector<int32_t> cnt(top + 2, 0);
+    for (int32_t u = i; u < j; ++u) cnt[lvl[u] + 1]++;
+    for (int32_t l = 1; l <= top + 1; ++l) cnt[l] += cnt[l - 1];
+    const size_t base = order.size();
+    order.resize(base + (j - i));
+    for (int32_t u = i; u < j; ++u) order[base + cnt[lvl[u]]++] = u;
+    i = j;
+  }
+  std::vector<int32_t> pos(ns);
+  for (int32_t r = 0; r < ns; ++r) pos[order[r]] = r;
+  auto remap = [&](int32_t t) { return t < n_vt ? t : n_vt + pos[t - n_vt]; };
+  std::vector<PStep> steps(ns);
+  std::vector<PTiling> tiling(ns);
+  std::vector<PTensor> tensors(k.tensors.size());
+  for (int32_t t = 0; t < n_vt; ++t) tensors[t] = std::move(k.tensors[t]);
+  for (int32_t r = 0; r < ns; ++r) {
+    const int32_t u = order[r];
+    PStep st = std::move(k.steps[u]);
+    st.a = remap(st.a);
+    st.b = remap(st.b);
+    st.c = n_vt + r;
+    tensors[n_vt + r] = std::move(k.tensors[n_vt + u]);
+    steps[r] = std::move(st);
+    tiling[r] = k.tiling[u];
+    tiling[r].level = tiling[r].mode == STEP_SERIAL ? lvl[u] : 0;
+  }
+  for (auto& c : k.comps) c = remap(c);
+  k.steps = std::move(steps);
+  k.tiling = std::move(tiling);
+  k.tensors = std::move(tensors);
+}
 
 // Build tensors, order and arena for one knot.  Returns KN_OK or an error.
 kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
@@ -533,16 +619,28 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
 
   // ---- absorption: orient edges by a minimum-degree elimination order
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> adj(n);  // (nbr, medge)
-  for (size_t i = 0; i < s.e.size(); ++i) {
-    auto [u, v] = s.e[i];
-    adj[u].emplace_back(v, s.e_medge[i]);
-    adj[v].emplace_back(u, s.e_medge[i]);
+  // adjacency (neighbour, merged edge) in compressed rows
+  const int32_t ne2 = 2 * (int32_t)s.e.size();
+  std::vector<int32_t> aoff(n + 1, 0), anb(ne2), amd(ne2);
+  for (auto [u, v] : s.e) {
+    aoff[u + 1]++;
+    aoff[v + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) aoff[v + 1] += aoff[v];
+  {
+    std::vector<int32_t> fp(aoff.begin(), aoff.end() - 1);
+    for (size_t i = 0; i < s.e.size(); ++i) {
+      auto [u, v] = s.e[i];
+      anb[fp[u]] = v;
+      amd[fp[u]++] = s.e_medge[i];
+      anb[fp[v]] = u;
+      amd[fp[v]++] = s.e_medge[i];
+    }
   }
   std::vector<int32_t> deg(n), pos(n, -1);
   int32_t maxd = 0;
   for (int32_t v = 0; v < n; ++v) {
-    deg[v] = (int32_t)adj[v].size();
+    deg[v] = aoff[v + 1] - aoff[v];
     maxd = std::max(maxd, deg[v]);
   }
   {
@@ -556,43 +654,49 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       bucket[d].pop_back();
       if (pos[v] >= 0 || deg[v] != d) continue;
       pos[v] = placed++;
-      for (auto& [w, m] : adj[v])
+      for (int32_t j = aoff[v]; j < aoff[v + 1]; ++j) {
+        const int32_t w = anb[j];
         if (pos[w] < 0) {
           --deg[w];
           bucket[deg[w]].push_back(w);
         }
+      }
     }
   }
-  // out-edges of v: to neighbours placed later
-  std::vector<int32_t> holders(n, 0);
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> outs(n);
-  for (int32_t v = 0; v < n; ++v)
-    for (auto& [w, m] : adj[v])
-      if (pos[w] > pos[v]) outs[v].emplace_back(w, m);
+  // out-edges of v: to neighbours placed later, sorted by (neighbour, edge)
+  std::vector<int32_t> holders(n, 0), ooff(n + 1, 0);
+  std::vector<std::pair<int32_t, int32_t>> outs;
+  outs.reserve(ne2 / 2);
   for (int32_t v = 0; v < n; ++v) {
-    std::sort(outs[v].begin(), outs[v].end());
-    if (!outs[v].empty()) holders[v]++;
-    for (auto& [w, m] : outs[v]) holders[w]++;
+    for (int32_t j = aoff[v]; j < aoff[v + 1]; ++j)
+      if (pos[anb[j]] > pos[v]) outs.emplace_back(anb[j], amd[j]);
+    ooff[v + 1] = (int32_t)outs.size();
+    std::sort(outs.begin() + ooff[v], outs.end());
+    if (ooff[v + 1] > ooff[v]) holders[v]++;
+    for (int32_t j = ooff[v]; j < ooff[v + 1]; ++j) holders[outs[j].first]++;
   }
   // vertex tensors
+  k.vtx.reserve(n);
+  k.tensors.reserve(2 * n + 1);
   for (int32_t v = 0; v < n; ++v) {
-    bool has = !outs[v].empty();
+    const bool none = ooff[v + 1] == ooff[v];
+    bool has = !none;
     if (!has && holders[v] == 1) has = true;  // lone holder elsewhere: add [v] of ones
     if (!has) continue;
+    if (ooff[v + 1] - ooff[v] > 7) return KN_E_UNSUPPORTED;  // planar graphs give <= 5
     PVertex pv;
     pv.tensor = (int32_t)k.tensors.size();
     pv.center = v;
-    int32_t cnt = holders[v] + (outs[v].empty() ? 1 : 0);
+    int32_t cnt = holders[v] + (none ? 1 : 0);
     pv.keep_center = cnt >= 2;
     PTensor t;
     if (pv.keep_center) t.spins.push_back(v);
-    for (auto& [w, m] : outs[v]) {
-      pv.nbr.push_back(w);
-      pv.medge.push_back(m);
-      t.spins.push_back(w);
+    for (int32_t j = ooff[v]; j < ooff[v + 1]; ++j) {
+      pv.nbr.push_back(outs[j].first);
+      pv.medge.push_back(outs[j].second);
+      t.spins.push_back(outs[j].first);
     }
-    if (pv.nbr.size() > 7) return KN_E_UNSUPPORTED;  // planar graphs give <= 5
-    k.vtx.push_back(pv);
+    k.vtx.push_back(std::move(pv));
     k.tensors.push_back(std::move(t));
   }
   const int32_t n_vt = (int32_t)k.tensors.size();
@@ -610,28 +714,25 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     // auto (3): min-fill first; the greedy plan is also built, and the cheaper
     // kept, only when the min-fill plan's modelled compute is material
     const int32_t strat = o.strategy;
-    Orderer best(n, q, k.tensors);
-    bool have = false;
+    std::unique_ptr<Orderer> best;
     double best_cost = 0;
     for (int32_t sgy : {2, 0, 1}) {
       if (strat != 3 && sgy != strat) continue;
       if (strat == 3 && sgy == 1) continue;
-      if (strat == 3 && sgy == 0 && have && best.model_cost(o.precision, false) < kAutoGreedyFrom)
-        continue;
-      Orderer cand(n, q, k.tensors);
-      if (sgy == 2) cand.minfill();
-      else cand.greedy(sgy);
-      double c = cand.model_cost(o.precision, true);
-      if (!have || c < best_cost) {
+      if (strat == 3 && sgy == 0 && best && best->flops() < kAutoGreedyFrom) continue;
+      auto cand = std::make_unique<Orderer>(n, q, k.tensors);
+      if (sgy == 2) cand->minfill();
+      else cand->greedy(sgy);
+      double c = cand->model_cost(o.precision, true);
+      if (!best || c < best_cost) {
         best = std::move(cand);
         best_cost = c;
-        have = true;
       }
     }
-    k.tensors = std::move(best.T);
-    k.steps = std::move(best.S);
+    k.tensors = std::move(best->T);
+    k.steps = std::move(best->S);
     for (int32_t t = 0; t < (int32_t)k.tensors.size(); ++t)
-      if (best.alive[t]) {
+      if (best->alive[t]) {
         if (!k.tensors[t].spins.empty()) return KN_E_INVALID;  // guard
         k.comps.push_back(t);
       }
@@ -708,65 +809,38 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   st.bytes = bytes;
   st.log2_max_entries = maxlog;
   st.max_rank = maxrank;
+  level_schedule(k, n_vt);
 
   // ---- arena: first fit over live ranges, in execution order
   {
-    const int64_t align = 16;  // entries
-    std::map<int64_t, int64_t> free_blk;  // off -> len
-    int64_t top = 0;
-    auto alloc = [&](int64_t len) {
-      len = (len + align - 1) / align * align;
-      for (auto it = free_blk.begin(); it != free_blk.end(); ++it)
-        if (it->second >= len) {
-          int64_t off = it->first, rem = it->second - len;
-          free_blk.erase(it);
-          if (rem) free_blk.emplace(off + len, rem);
-          return off;
-        }
-      // extend: merge with a free block touching the top
-      if (!free_blk.empty()) {
-        auto last = std::prev(free_blk.end());
-        if (last->first + last->second == top) {
-          int64_t off = last->first;
-          free_blk.erase(last);
-          top = off + len;
-          return off;
-        }
-      }
-      int64_t off = top;
-      top += len;
-      return off;
-    };
-    auto release = [&](int64_t off, int64_t len) {
-      len = (len + align - 1) / align * align;
-      auto it = free_blk.emplace(off, len).first;
-      auto nx = std::next(it);
-      if (nx != free_blk.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        free_blk.erase(nx);
-      }
-      if (it != free_blk.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-          pv->second += it->second;
-          free_blk.erase(it);
-        }
-      }
-    };
+    FitAlloc fa(INT64_MAX, 16);
+    auto alloc = [&](int64_t len) { return fa.alloc(len); };
+    auto release = [&](int64_t off, int64_t len) { fa.release(off, len); };
     for (int32_t t = 0; t < n_vt; ++t) k.tensors[t].off = alloc(k.tensors[t].size);
-    for (size_t i = 0; i < k.steps.size(); ++i) {
-      const auto& sp = k.steps[i];
-      k.tensors[sp.c].off = alloc(k.tensors[sp.c].size);
-      PTiling& t = k.tiling[i];
-      if (t.n_ks > 1) {
-        const int64_t len = (int64_t)t.n_ks * k.tensors[sp.c].size;
-        t.partial = alloc(len);
-        release(t.partial, len);
+    // steps of one level run concurrently: their outputs are placed before
+    // any of their operands is released
+    const size_t ns = k.steps.size();
+    for (size_t i = 0; i < ns;) {
+      size_t j = i + 1;
+      while (j < ns && same_level(k, j - 1)) ++j;
+      for (size_t u = i; u < j; ++u) {
+        const auto& sp = k.steps[u];
+        k.tensors[sp.c].off = alloc(k.tensors[sp.c].size);
+        PTiling& t = k.tiling[u];
+        if (t.n_ks > 1) {
+          const int64_t len = (int64_t)t.n_ks * k.tensors[sp.c].size;
+          t.partial = alloc(len);
+          release(t.partial, len);
+        }
       }
-      release(k.tensors[sp.a].off, k.tensors[sp.a].size);
-      release(k.tensors[sp.b].off, k.tensors[sp.b].size);
+      for (size_t u = i; u < j; ++u) {
+        const auto& sp = k.steps[u];
+        release(k.tensors[sp.a].off, k.tensors[sp.a].size);
+        release(k.tensors[sp.b].off, k.tensors[sp.b].size);
+      }
+      i = j;
     }
-    k.arena_elems = std::max<int64_t>(top, 16);
+    k.arena_elems = std::max<int64_t>(fa.top, 16);
   }
   return KN_OK;
 }

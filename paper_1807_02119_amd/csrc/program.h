@@ -133,6 +133,9 @@ struct StepDesc {
   int32_t n_mb, n_nb;       // STEP_GEMM: row and column blocks
   int32_t n_ks, kseg;       // contracted-index splits and entries per split
   int32_t partial;          // n_ks > 1: arena offset of the partial sums [ks][output]
+  // serial steps: dependency level inside the task's run of steps; adjacent
+  // steps of equal level are independent and run concurrently
+  int32_t lvl;
 };
 
 struct VtxDesc {

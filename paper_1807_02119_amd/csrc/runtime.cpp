@@ -5,7 +5,24 @@
 #include <thread>
 #include <vector>
 
+#include <sched.h>
+
 #include "internal.h"
+
+namespace {
+
+// CPUs this process may run on (its affinity mask), at least 1.
+int32_t usable_cpus() {
+  cpu_set_t set;
+  CPU_ZERO(&set);
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+    const int c = CPU_COUNT(&set);
+    if (c > 0) return c;
+  }
+  return (int32_t)std::max(1u, std::thread::hardware_concurrency());
+}
+
+}  // namespace
 
 extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_t* pd,
                                   const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
@@ -22,7 +39,7 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
     taits[i] = nullptr;
     plans[i] = nullptr;
   }
-  int32_t nt = n_threads > 0 ? n_threads : (int32_t)std::max(1u, std::thread::hardware_concurrency());
+  int32_t nt = n_threads > 0 ? n_threads : usable_cpus();
   nt = std::min(nt, std::max(1, n_knots));
   std::atomic<int32_t> next{0};
   std::vector<kn_status> st(n_knots, KN_OK);

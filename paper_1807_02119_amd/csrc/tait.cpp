@@ -99,12 +99,15 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
     }
     if (nreg != n + 2) { delete g; return KN_E_INVALID; }  // not a plane diagram
 
-    // two-colouring by breadth-first search across arcs
-    std::vector<std::vector<int32_t>> adj(nreg);
-    for (int32_t c = 0; c < nc; ++c) {
-      int32_t other = (c & ~3) | ((c + 3) & 3);  // across slot c
-      adj[region[c]].push_back(region[other]);
-      adj[region[other]].push_back(region[c]);
+    // two-colouring by breadth-first search across arcs: the corners of each
+    // region (counting sort by region); corner c and corner (c & ~3) |
+    // ((c + 3) & 3) lie on the two sides of slot c
+    std::vector<int32_t> rc_off(nreg + 1, 0), rc(nc);
+    for (int32_t c = 0; c < nc; ++c) rc_off[region[c] + 1]++;
+    for (int32_t r = 0; r < nreg; ++r) rc_off[r + 1] += rc_off[r];
+    {
+      std::vector<int32_t> fillp(rc_off.begin(), rc_off.end() - 1);
+      for (int32_t c = 0; c < nc; ++c) rc[fillp[region[c]]++] = c;
     }
     int32_t arc = outer_arc < 0 ? 0 : outer_arc;
     if (arc >= m) { delete g; return KN_E_INVALID; }
@@ -123,13 +126,16 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
     queue.push_back(region[outer_corner]);
     for (size_t h = 0; h < queue.size(); ++h) {
       int32_t r = queue[h];
-      for (int32_t s : adj[r]) {
-        if (colour[s] < 0) {
-          colour[s] = (int8_t)(1 - colour[r]);
-          queue.push_back(s);
-        } else if (colour[s] == colour[r]) {
-          delete g;
-          return KN_E_INVALID;
+      for (int32_t j = rc_off[r]; j < rc_off[r + 1]; ++j) {
+        const int32_t c = rc[j];
+        for (int32_t s : {region[(c & ~3) | ((c + 3) & 3)], region[(c & ~3) | ((c + 1) & 3)]}) {
+          if (colour[s] < 0) {
+            colour[s] = (int8_t)(1 - colour[r]);
+            queue.push_back(s);
+          } else if (colour[s] == colour[r]) {
+            delete g;
+            return KN_E_INVALID;
+          }
         }
       }
     }

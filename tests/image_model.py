@@ -39,7 +39,7 @@ KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
                                       "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
-                                      "n_mb", "n_nb", "n_ks", "kseg", "partial")],
+                                      "n_mb", "n_nb", "n_ks", "kseg", "partial", "lvl")],
                 align=True)
 VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
@@ -221,19 +221,25 @@ def run(raw: bytes, J=None):
             split_pending[si] = (off, n_ks, outs)
             return
         C = np.matmul(Am, Bm).reshape(-1) * scale
-        finish_step(si, C, local, task_local=mode == STEP_SERIAL)
+        if mode == STEP_SERIAL:
+            return C  # the caller commits the level's results together
+        finish_step(si, C, local, task_local=False)
 
-    def finish_step(si, C, local, task_local):
+    def commit_step(si, C, local, task_local=True):
         s = im.steps[si]
         a, b, c = int(s["a"]), int(s["b"]), int(s["c"])
         write_tensor(c, C, task_local=task_local)
         m = float(np.max(np.maximum(np.abs(C.real), np.abs(C.imag)))) if C.size else 0.0
         shift[c] = math.frexp(m)[1] if m > 0 else None
         exp2[c] = exp2[a] + exp2[b] + sh(a) + sh(b)
-        for op in (a, b):  # operands are consumed exactly once
+        local.add(c)
+
+    def finish_step(si, C, local, task_local):
+        commit_step(si, C, local, task_local)
+        s = im.steps[si]
+        for op in (int(s["a"]), int(s["b"])):  # operands are consumed exactly once
             live_g.pop(op, None)
             live_l.pop(op, None)
-        local.add(c)
 
     def reduce(si, local):
         off, n_ks, outs = split_pending.pop(si)
@@ -313,8 +319,28 @@ def run(raw: bytes, J=None):
                     shift[int(vd["tensor"])] = 0
                     exp2[int(vd["tensor"])] = 0
                     local.add(int(vd["tensor"]))
-            for si in range(int(task["first"]), int(task["first"]) + int(task["count"])):
-                step(si, local)
+            # adjacent steps of equal level run concurrently on the device:
+            # every output is computed from operands that are all still live,
+            # outputs must not overlap them, and operands die after the level
+            first, count = int(task["first"]), int(task["count"])
+            i = first
+            while i < first + count:
+                j = i + 1
+                while j < first + count and int(im.steps[j]["lvl"]) == int(im.steps[i]["lvl"]):
+                    j += 1
+                assert all(int(im.steps[u]["lvl"]) >= 1 for u in range(i, j))
+                made_here = {int(im.steps[u]["c"]) for u in range(i, j)}
+                for u in range(i, j):
+                    assert int(im.steps[u]["a"]) not in made_here, "step reads its own level"
+                    assert int(im.steps[u]["b"]) not in made_here, "step reads its own level"
+                results = [step(u, local) for u in range(i, j)]
+                for u, C in zip(range(i, j), results):
+                    commit_step(u, C, local)
+                for u in range(i, j):
+                    for op in (int(im.steps[u]["a"]), int(im.steps[u]["b"])):
+                        live_g.pop(op, None)
+                        live_l.pop(op, None)
+                i = j
             if task["flags"] & 2:
                 z, e = 1 + 0j, 0
                 for i in range(int(k["n_comps"])):
