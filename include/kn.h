@@ -105,9 +105,10 @@ void kn_tait_free(kn_tait* g);
  *               contraction in terms of the resulting degree");
  *            2: variable elimination in min-fill order, each spin's holders
  *               contracted pairwise, smallest first;
- *            3: auto (default) -- plans 0 and 2 are both built and the one
- *               with the smaller modelled time (per step max(flops/peak,
- *               bytes/HBM bandwidth) plus a fixed per-step latency) is kept;
+ *            3: auto (default) -- plan 2; when it has at least 1e8 flops
+ *               plan 0 is built too and the one with the smaller modelled
+ *               time (per step max(flops/peak, bytes/HBM bandwidth) plus a
+ *               fixed per-step latency) is kept;
  * precision  0: complex128 (FP64) tensors; 1: complex64 (FP32) tensors with
  *               FP32 accumulation, exponents and normalisation kept in
  *               int64 / FP64.
@@ -128,8 +129,16 @@ void kn_tait_free(kn_tait* g);
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
- *               (0 = default 32 KiB, at most 96 KiB).  All plans of a batch
+ *               (0 = default 24 KiB, at most 96 KiB).  All plans of a batch
  *               are launched with the largest value any of them uses.
+ * gradient      1: the plan also carries the reverse pass of the contraction
+ *               (for kn_contract_backward): after the forward steps, the
+ *               adjoint of every intermediate is contracted back to the vertex
+ *               tensors (for C = A.B: dS/dA = dS/dC . B, dS/dB = A . dS/dC),
+ *               and every intermediate is kept until its reverse step.
+ *               Requires simplify without bit 1 (Reidemeister II drops edges
+ *               whose derivative is not zero).  kn_contract on such a plan
+ *               computes Z and runs the reverse steps without writing them out.
  */
 typedef struct {
   int32_t strategy;
@@ -141,6 +150,7 @@ typedef struct {
   int32_t big_step_macs_log2;
   int32_t paper_stats;
   int32_t lds_bytes;
+  int32_t gradient;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).
@@ -201,13 +211,16 @@ kn_status kn_plan_steps(const kn_plan* p, int32_t* ab);
 kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
                       size_t workspace_bytes, void* stream, kn_scalar* z_dev);
 
-/* d log Z / d J_e (holomorphic derivative) for every ORIGINAL edge, written to
- * grad_dev (device, 2*n_edges doubles).  Runs its own forward sweep (the
- * intermediates are recomputed, nothing from a previous kn_contract is
- * needed); z_dev receives Z as in kn_contract.  The plan must not be
- * jones_only if J is non-NULL.  workspace must hold kn_plan_info's
- * workspace_bytes of a plan created with the same options; the backward sweep
- * needs the extra room reported by kn_backward_workspace. */
+/* d log Z / d J_e (holomorphic derivative, dT_e/dJ_e = e^{J_e} delta) for
+ * every ORIGINAL edge, written to grad_dev (device, 2*n_edges doubles, re/im
+ * interleaved, edge order of kn_tait_edges).  One launch runs the forward
+ * sweep and the reverse sweep (nothing from a previous kn_contract is
+ * needed); z_dev receives Z as in kn_contract.  Edges removed by
+ * simplification get their closed forms: a loop 1, an edge of a merged spike
+ * m: x_m / (x_m + q - 1) with x_m the product of its members' e^{J}.
+ * Requires a plan created with opts.gradient = 1 (else KN_E_UNSUPPORTED);
+ * J as in kn_contract.  kn_backward_workspace gives the workspace size (the
+ * plan's workspace_bytes). */
 kn_status kn_backward_workspace(const kn_plan* p, uint64_t* bytes);
 kn_status kn_contract_backward(const kn_plan* p, const double* J, void* workspace,
                                size_t workspace_bytes, void* stream,
@@ -267,6 +280,12 @@ kn_status kn_batch_edge_offset(const kn_batch* b, int32_t i, int64_t* off);
 kn_status kn_batch_upload(const kn_batch* b, void* workspace, size_t workspace_bytes, void* stream);
 kn_status kn_batch_contract(const kn_batch* b, const double* J, void* workspace,
                             size_t workspace_bytes, void* stream, kn_scalar* z_dev);
+/* kn_contract_backward for a batch of gradient plans: grad_dev receives, for
+   knot i, 2*n_edges(i) doubles at offset 2*edge_offset(i).  KN_E_UNSUPPORTED
+   unless every plan was created with opts.gradient = 1. */
+kn_status kn_batch_contract_backward(const kn_batch* b, const double* J, void* workspace,
+                                     size_t workspace_bytes, void* stream, kn_scalar* z_dev,
+                                     double* grad_dev);
 /* Read-only view of the batch's device image (see kn_plan_image). */
 kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes);
 /* Override the persistent grid size (workgroups) of later kn_batch_contract

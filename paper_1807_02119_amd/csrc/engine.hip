@@ -69,6 +69,7 @@ struct DevProg {
   int32_t* pending;
   TensorState* ts;
   Cx<double>* weights;  // x_e (n_edges) then x_m (n_medges)
+  Cx<double>* mgrad;    // d log Z / d J per merged edge (gradient plans)
 };
 
 __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
@@ -93,6 +94,7 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.pending = reinterpret_cast<int32_t*>(state + h.o_pending);
   p.ts = reinterpret_cast<TensorState*>(state + h.o_tstate);
   p.weights = reinterpret_cast<Cx<double>*>(state + h.o_weights);
+  p.mgrad = reinterpret_cast<Cx<double>*>(state + h.o_mgrad);
   return p;
 }
 
@@ -238,7 +240,9 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
     for (int j = 0; j < vd.n_slots; ++j) qn *= q;
     for (int i = lane; i < td.size; i += 64) {
       // digits of i: last neighbour slot fastest; a kept centre is the leading
-      // index (i / q^n_slots), a private centre is summed over
+      // index (i / q^n_slots), a private centre is summed over.  A reverse-pass
+      // seed (keep_center < 0, no slots, one entry) takes the kept branch with
+      // an empty product: the scalar 1.
       const int a_lo = vd.keep_center ? i / qn : 0;
       const int a_hi = vd.keep_center ? a_lo + 1 : q;
       Cx<double> acc{0.0, 0.0};
@@ -871,6 +875,132 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
   zout[kd.out_slot] = out;
 }
 
+__device__ inline Cx<double> cdiv(Cx<double> a, Cx<double> b) {
+  const double s = fmax(fabs(b.re), fabs(b.im));
+  const Cx<double> bs{b.re / s, b.im / s};
+  const double d = bs.re * bs.re + bs.im * bs.im;
+  return {(a.re * bs.re + a.im * bs.im) / (d * s), (a.im * bs.re - a.re * bs.im) / (d * s)};
+}
+
+// d log Z / d J_e for every original edge of a gradient plan (after the
+// reverse steps).  For the merged edge m in slot j of vertex tensor
+// F_v(s_v, s_w1..) = prod_l T_ml(s_v, s_wl) (Eq. 5; a private s_v summed),
+//   dF_v/dx_m = delta(s_v, s_wj) prod_{l != j} T_ml(s_v, s_wl),
+// so d log S / d J_m = x_m sum_i dS/dF_v[i] dF_v/dx_m[i] / S, S the scalar of
+// the vertex's component.  A spike factor x_m + q - 1 gives
+// x_m / (x_m + q - 1), a loop factor x_e gives 1, and each original edge takes
+// the value of its merged edge (x_m is the product of its members' e^{J}).
+// One wavefront per vertex tensor; the whole workgroup calls this, after the
+// persistent kernel (tensor states and data are then all in global memory).
+template <class T>
+__device__ void knot_gradient(const DevProg& p, const KnotDesc& kd, const Cx<T>* arena,
+                              double* grad) {
+  const ImgHeader& h = *p.h;
+  const Cx<double>* xm = p.weights + h.n_edges + kd.medge_off;
+  Cx<double>* mg = p.mgrad + kd.medge_off;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = kd.q;
+  constexpr int kMaxSlots = 7;
+  for (int v = wv; v < kd.n_vtx; v += kBlock / 64) {
+    const VtxDesc vd = p.vtx[kd.vtx_off + v];
+    if (vd.keep_center < 0 || vd.adjoint < 0 || vd.n_slots == 0) continue;
+    const int ns = vd.n_slots;
+    const int32_t* slot_me = p.vslot + vd.slot_off;
+    Cx<double> x[kMaxSlots];
+#pragma unroll
+    for (int j = 0; j < kMaxSlots; ++j) x[j] = j < ns ? xm[slot_me[j]] : Cx<double>{1.0, 0.0};
+    int32_t qn = 1;
+    for (int j = 0; j < ns; ++j) qn *= q;
+    // gradient plans keep every tensor and state in global memory
+    const TensorDesc td = p.tens[vd.adjoint];
+    const Cx<T>* fb = arena + td.off;
+    double ar[kMaxSlots], ai[kMaxSlots];
+#pragma unroll
+    for (int j = 0; j < kMaxSlots; ++j) ar[j] = ai[j] = 0.0;
+    // entry i in F_v's order (kept centre leading, last slot fastest) sits at
+    // sum of digit x stride in the adjoint's storage order
+    const int32_t* astr = p.strides + vd.adj_str;
+    const int32_t* sstr = astr + (vd.keep_center ? 1 : 0);
+    for (int i = lane; i < td.size; i += 64) {
+      int dig[kMaxSlots];
+      int rem = i;
+      int32_t off = 0;
+#pragma unroll
+      for (int j = kMaxSlots - 1; j >= 0; --j) {
+        if (j < ns) {
+          dig[j] = rem % q;
+          rem /= q;
+          off += dig[j] * sstr[j];
+        } else {
+          dig[j] = -1;
+        }
+      }
+      const int centre = rem;  // kept centre (leading index); unused when private
+      if (vd.keep_center) off += centre * astr[0];
+      const Cx<T> f = fb[off];
+#pragma unroll
+      for (int j = 0; j < kMaxSlots; ++j) {
+        if (j >= ns) continue;
+        const int a = vd.keep_center ? centre : dig[j];
+        if (dig[j] != a) continue;
+        Cx<double> prod{(double)f.re, (double)f.im};
+#pragma unroll
+        for (int l = 0; l < kMaxSlots; ++l)
+          if (l != j && l < ns && dig[l] == a) prod = cmul(prod, x[l]);
+        ar[j] += prod.re;
+        ai[j] += prod.im;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxSlots; ++j) {
+      for (int o = 32; o >= 1; o >>= 1) {
+        ar[j] += __shfl_xor(ar[j], o, 64);
+        ai[j] += __shfl_xor(ai[j], o, 64);
+      }
+    }
+    if (lane == 0) {
+      const int64_t ef = p.ts[vd.adjoint].exp2;
+      const int32_t root = p.comps[kd.comp_off + vd.comp];
+      const Cx<T> r = arena[p.tens[root].off];
+      const int64_t er = p.ts[root].exp2;
+      const Cx<double> rs{(double)r.re, (double)r.im};
+#pragma unroll
+      for (int j = 0; j < kMaxSlots; ++j) {
+        if (j >= ns) continue;
+        Cx<double> g = cdiv(cmul(Cx<double>{ar[j], ai[j]}, x[j]), rs);
+        g.re = ldexp(g.re, (int)(ef - er));
+        g.im = ldexp(g.im, (int)(ef - er));
+        mg[slot_me[j]] = g;
+      }
+    }
+  }
+  for (int i = tid; i < kd.n_factors; i += kBlock) {
+    const Factor f = p.factors[kd.factor_off + i];
+    if (f.kind == FAC_LEAF) {
+      const Cx<double> x = xm[f.id];
+      mg[f.id] = cdiv(x, Cx<double>{x.re + (double)(q - 1), x.im});
+    }
+  }
+  __syncthreads();
+  double* g = grad + 2 * (int64_t)kd.edge_off;
+  for (int m = tid; m < kd.n_medges; m += kBlock) {
+    const MEdge me = p.medges[kd.medge_off + m];
+    const Cx<double> v = mg[m];
+    for (int i = 0; i < me.n_members; ++i) {
+      const int32_t e = p.members[me.member_off + i];
+      g[2 * e] = v.re;
+      g[2 * e + 1] = v.im;
+    }
+  }
+  for (int i = tid; i < kd.n_factors; i += kBlock) {
+    const Factor f = p.factors[kd.factor_off + i];
+    if (f.kind == FAC_LOOP) {
+      g[2 * f.id] = 1.0;
+      g[2 * f.id + 1] = 0.0;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ kernels
 
 // Reset the runtime state of an image: control words, ready queue seeded
@@ -894,6 +1024,19 @@ __global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict
     ts[i].pad = 0;
     ts[i].exp2 = 0;
   }
+}
+
+// d log Z / d J of every knot of a gradient image: one workgroup per knot,
+// launched after the persistent kernel on the same stream.
+template <class T>
+__global__ __launch_bounds__(kBlock) void gradient_kernel(const uint8_t* __restrict__ img,
+                                                          uint8_t* __restrict__ state,
+                                                          Cx<T>* __restrict__ arena,
+                                                          double* __restrict__ grad) {
+  const DevProg p = make_prog(img, state);
+  const KnotDesc kd = p.knots[blockIdx.x];
+  if (!kd.grad) return;
+  knot_gradient<T>(p, kd, arena, grad);
 }
 
 // Bound on the wait for a queue slot (sleep iterations): a slot that is never
@@ -1049,7 +1192,7 @@ int32_t resident_per_cu(size_t dyn_lds) {
 
 template <class T>
 kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
-                        kn_scalar* z, int32_t grid_override, TraceRec* trace) {
+                        kn_scalar* z, double* grad, int32_t grid_override, TraceRec* trace) {
   const size_t dyn = (size_t)kLdsArena + (size_t)h.lds_bytes;
   static std::once_flag once;
   static bool attr_ok = true;
@@ -1065,11 +1208,17 @@ kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const d
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(engine<T>, dim3(grid), dim3(kBlock), dyn, st, ws, ws + h.state_off,
                      reinterpret_cast<Cx<T>*>(ws + h.arena_off), J, z, trace);
-  return hipGetLastError() == hipSuccess ? KN_OK : KN_E_DEVICE;
+  if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
+  if (grad) {
+    hipLaunchKernelGGL(gradient_kernel<T>, dim3(h.n_knots), dim3(kBlock), 0, st, ws,
+                       ws + h.state_off, reinterpret_cast<Cx<T>*>(ws + h.arena_off), grad);
+    if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
+  }
+  return KN_OK;
 }
 
 kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
-                 kn_scalar* z, int32_t grid_override, TraceRec* trace = nullptr) {
+                 kn_scalar* z, double* grad, int32_t grid_override, TraceRec* trace = nullptr) {
   int64_t n_clear = CTRL_WORDS;
   n_clear = std::max<int64_t>(n_clear, h.n_tasks);
   n_clear = std::max<int64_t>(n_clear, h.n_groups);
@@ -1077,8 +1226,8 @@ kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* 
   hipLaunchKernelGGL(clear_state, dim3((unsigned)((n_clear + 255) / 256)), dim3(256), 0, st, ws,
                      ws + h.state_off);
   if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
-  if (h.precision == 1) return launch_engine<float>(h, ws, st, J, z, grid_override, trace);
-  return launch_engine<double>(h, ws, st, J, z, grid_override, trace);
+  if (h.precision == 1) return launch_engine<float>(h, ws, st, J, z, grad, grid_override, trace);
+  return launch_engine<double>(h, ws, st, J, z, grad, grid_override, trace);
 }
 
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
@@ -1088,8 +1237,10 @@ bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) =
 
 using namespace kn;
 
-extern "C" kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
-                                 size_t workspace_bytes, void* stream, kn_scalar* z_dev) {
+namespace {
+
+kn_status contract_plan(const kn_plan* p, const double* J, void* workspace,
+                        size_t workspace_bytes, void* stream, kn_scalar* z_dev, double* grad) {
   if (!p || !workspace || !z_dev) return KN_E_INVALID;
   if (p->image.empty()) return KN_E_BUDGET;
   if (J && p->k.jones_only) return KN_E_UNSUPPORTED;
@@ -1100,7 +1251,14 @@ extern "C" kn_status kn_contract(const kn_plan* p, const double* J, void* worksp
   if (hipMemcpyAsync(workspace, p->image.data(), (size_t)h.image_bytes, hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return KN_E_DEVICE;
-  return launch(h, reinterpret_cast<uint8_t*>(workspace), st, J, z_dev, 0);
+  return launch(h, reinterpret_cast<uint8_t*>(workspace), st, J, z_dev, grad, 0);
+}
+
+}  // namespace
+
+extern "C" kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
+                                 size_t workspace_bytes, void* stream, kn_scalar* z_dev) {
+  return contract_plan(p, J, workspace, workspace_bytes, stream, z_dev, nullptr);
 }
 
 extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_batch** out) {
@@ -1108,11 +1266,12 @@ extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_
   *out = nullptr;
   if (!plans || n <= 0) return KN_E_INVALID;
   std::vector<const PlanKnot*> ks;
-  bool jones_only = false;
+  bool jones_only = false, gradient = true;
   for (int32_t i = 0; i < n; ++i) {
     if (!plans[i] || plans[i]->image.empty()) return KN_E_INVALID;
     if (plans[i]->k.precision != plans[0]->k.precision) return KN_E_INVALID;
     jones_only |= plans[i]->k.jones_only;
+    gradient &= plans[i]->k.gradient;
     ks.push_back(&plans[i]->k);
   }
   kn_batch* b = new (std::nothrow) kn_batch();
@@ -1125,6 +1284,7 @@ extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_
     }
     b->precision = plans[0]->k.precision;
     b->jones_only = jones_only;
+    b->gradient = gradient;
     int64_t off = 0;
     double flops = 0, bytes = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -1176,8 +1336,10 @@ extern "C" kn_status kn_batch_upload(const kn_batch* b, void* workspace, size_t 
   return KN_OK;
 }
 
-extern "C" kn_status kn_batch_contract(const kn_batch* b, const double* J, void* workspace,
-                                       size_t workspace_bytes, void* stream, kn_scalar* z_dev) {
+namespace {
+
+kn_status contract_batch(const kn_batch* b, const double* J, void* workspace,
+                         size_t workspace_bytes, void* stream, kn_scalar* z_dev, double* grad) {
   if (!b || !workspace || !z_dev) return KN_E_INVALID;
   if (J && b->jones_only) return KN_E_UNSUPPORTED;
   if (!aligned256(workspace)) return KN_E_INVALID;
@@ -1185,7 +1347,22 @@ extern "C" kn_status kn_batch_contract(const kn_batch* b, const double* J, void*
   if ((int64_t)workspace_bytes < h.workspace_bytes) return KN_E_BUDGET;
   if (b->trace && b->trace_bytes < (size_t)h.n_tasks * sizeof(TraceRec)) return KN_E_BUDGET;
   return launch(h, reinterpret_cast<uint8_t*>(workspace), reinterpret_cast<hipStream_t>(stream), J,
-                z_dev, b->grid_override, reinterpret_cast<TraceRec*>(b->trace));
+                z_dev, grad, b->grid_override, reinterpret_cast<TraceRec*>(b->trace));
+}
+
+}  // namespace
+
+extern "C" kn_status kn_batch_contract(const kn_batch* b, const double* J, void* workspace,
+                                       size_t workspace_bytes, void* stream, kn_scalar* z_dev) {
+  return contract_batch(b, J, workspace, workspace_bytes, stream, z_dev, nullptr);
+}
+
+extern "C" kn_status kn_batch_contract_backward(const kn_batch* b, const double* J,
+                                                void* workspace, size_t workspace_bytes,
+                                                void* stream, kn_scalar* z_dev, double* grad_dev) {
+  if (!b || !grad_dev) return KN_E_INVALID;
+  if (!b->gradient) return KN_E_UNSUPPORTED;
+  return contract_batch(b, J, workspace, workspace_bytes, stream, z_dev, grad_dev);
 }
 
 extern "C" kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes) {
@@ -1212,13 +1389,15 @@ extern "C" void kn_batch_free(kn_batch* b) { delete b; }
 
 extern "C" kn_status kn_backward_workspace(const kn_plan* p, uint64_t* bytes) {
   if (!p || !bytes) return KN_E_INVALID;
-  return KN_E_UNSUPPORTED;
+  if (!p->k.gradient) return KN_E_UNSUPPORTED;
+  *bytes = p->stats.workspace_bytes;
+  return KN_OK;
 }
 
 extern "C" kn_status kn_contract_backward(const kn_plan* p, const double* J, void* workspace,
                                           size_t workspace_bytes, void* stream, kn_scalar* z_dev,
                                           double* grad_dev) {
-  (void)J; (void)workspace; (void)workspace_bytes; (void)stream; (void)z_dev; (void)grad_dev;
-  if (!p) return KN_E_INVALID;
-  return KN_E_UNSUPPORTED;
+  if (!p || !grad_dev) return KN_E_INVALID;
+  if (!p->k.gradient) return KN_E_UNSUPPORTED;
+  return contract_plan(p, J, workspace, workspace_bytes, stream, z_dev, grad_dev);
 }

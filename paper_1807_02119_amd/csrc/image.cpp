@@ -81,6 +81,7 @@ void make_section(PlanKnot& k) {
   d.n_comps = (int32_t)k.comps.size();
   d.n_iso = k.n_iso;
   d.n_steps = (int32_t)k.steps.size();
+  d.grad = k.gradient ? 1 : 0;
   for (size_t m = 0; m + 1 < k.medge_off.size(); ++m) {
     S.md.push_back({(int32_t)S.members.size(), k.medge_off[m + 1] - k.medge_off[m]});
     for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) S.members.push_back(k.medge_mem[j]);
@@ -91,8 +92,16 @@ void make_section(PlanKnot& k) {
   for (auto& t : k.tensors) S.td.push_back({t.off, (int32_t)t.size, -1});
   S.arena_elems = (k.arena_elems + 15) / 16 * 16;
   for (auto& v : k.vtx) {
+    int32_t adj_str = -1;
+    if (v.adjoint >= 0) {  // the adjoint's own spin order differs from F_v's
+      adj_str = (int32_t)S.strides.size();
+      SpinList vs;
+      if (v.keep_center) vs.push_back(v.center);
+      for (int32_t w : v.nbr) vs.push_back(w);
+      group_strides(vs, k.tensors[v.adjoint].spins, q, S.strides);
+    }
     S.vd.push_back({v.tensor, (int32_t)v.nbr.size(), (int32_t)S.vslot.size(),
-                    v.keep_center ? 1 : 0});
+                    v.seed ? -1 : (v.keep_center ? 1 : 0), v.adjoint, v.comp, adj_str});
     for (int32_t m : v.medge) S.vslot.push_back(m);
   }
   // steps + tables
@@ -166,7 +175,8 @@ void make_section(PlanKnot& k) {
   }
 
   // ---- LDS homes: tensors produced and consumed inside one serial group
-  {
+  // (gradient plans read every tensor again in the reverse pass: all global)
+  if (!k.gradient) {
     const int32_t nt = (int32_t)k.tensors.size();
     const int32_t ns = (int32_t)k.steps.size();
     std::vector<int32_t> consumer(nt, -1);  // step index, or ns for the final product
@@ -342,6 +352,10 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
     for (size_t i = 0; i < S.vd.size(); ++i) {
       VtxDesc v = S.vd[i];
       v.tensor += t0;
+      if (v.adjoint >= 0) {
+        v.adjoint += t0;
+        v.adj_str += (int32_t)TAB0;
+      }
       v.slot_off += (int32_t)VS0;
       vd[V0 + i] = v;
     }
@@ -440,6 +454,8 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
   st = align256(st + (int64_t)nT * (int64_t)sizeof(TensorState));
   h.o_weights = st;
   st = align256(st + 16 * (int64_t)(nE + nM));
+  h.o_mgrad = st;
+  st = align256(st + 16 * (int64_t)nM);
   h.state_bytes = st;
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);

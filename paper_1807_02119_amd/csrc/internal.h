@@ -142,6 +142,9 @@ struct PVertex {
   int32_t tensor;
   int32_t center;               // spin of the vertex itself
   bool keep_center;
+  bool seed = false;            // reverse-pass seed: the scalar 1, no spins
+  int32_t adjoint = -1;         // gradient plans: tensor id of dS/dF_v
+  int32_t comp = 0;             // gradient plans: component index
   SpinList nbr;                 // neighbour spins, slot order
   SpinList medge;               // merged edge per slot (knot-local)
 };
@@ -152,6 +155,7 @@ struct PlanKnot {
   double t_re = 0, t_im = 0;
   int32_t precision = 0;
   bool jones_only = true;
+  bool gradient = false;                        // reverse pass appended
   int32_t n_edges = 0;                          // original Tait edges
   std::vector<int8_t> eps;                      // original Tait signs
   // merged edge m: original edges medge_mem[medge_off[m] .. medge_off[m + 1])
@@ -253,6 +257,7 @@ struct kn_batch {
   std::vector<int64_t> edge_offset;
   int32_t precision = 0;
   bool jones_only = false;
+  bool gradient = false;  // every plan carries the reverse pass
   int32_t grid_override = 0;
   void* trace = nullptr;
   size_t trace_bytes = 0;

@@ -531,6 +531,86 @@ struct Orderer {
 
 }  // namespace
 
+// Reverse pass of the contraction for d log Z / d J.  For every component a
+// seed tensor (the scalar 1) becomes dS/dS of its final scalar S; the forward
+// steps are then walked backwards and each C = A . B (batch b, rows m, cols
+// n, contracted k) adds two steps of the same kind:
+//   dS/dA[b,m,k] = sum_n dS/dC[b,m,n] B[b,k,n]   (rows m, cols k, contracted n)
+//   dS/dB[b,k,n] = sum_m A[b,m,k] dS/dC[b,m,n]   (rows k, cols n, contracted m)
+// Seeds are numbered after the vertex tensors (n_vt grows by the number of
+// components) so that step i still produces tensor n_vt + i.  Each vertex
+// learns the id of its adjoint and its component.
+void add_reverse(PlanKnot& k, int32_t& n_vt) {
+  const int32_t nc = (int32_t)k.comps.size();
+  const int32_t ns = (int32_t)k.steps.size();
+  auto shifted = [&](int32_t t) { return t < n_vt ? t : t + nc; };
+  std::vector<PTensor> tensors;
+  tensors.reserve(k.tensors.size() + nc + 2 * ns);
+  for (int32_t t = 0; t < n_vt; ++t) tensors.push_back(std::move(k.tensors[t]));
+  for (int32_t c = 0; c < nc; ++c) tensors.emplace_back();  // seed: no spins, one entry
+  for (size_t t = n_vt; t < k.tensors.size(); ++t) tensors.push_back(std::move(k.tensors[t]));
+  for (auto& st : k.steps) {
+    st.a = shifted(st.a);
+    st.b = shifted(st.b);
+    st.c = shifted(st.c);
+  }
+  for (auto& c : k.comps) c = shifted(c);
+  for (int32_t c = 0; c < nc; ++c) {
+    PVertex pv;
+    pv.tensor = n_vt + c;
+    pv.center = -1;
+    pv.keep_center = false;
+    pv.seed = true;
+    pv.comp = c;
+    k.vtx.push_back(std::move(pv));
+  }
+  n_vt += nc;
+  const size_t total = tensors.size() + 2 * (size_t)ns;
+  std::vector<int32_t> adj(total, -1), comp(total, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    adj[k.comps[c]] = n_vt - nc + c;
+    comp[k.comps[c]] = c;
+  }
+  k.steps.reserve(3 * (size_t)ns);
+  for (int32_t s = ns - 1; s >= 0; --s) {
+    const PStep fw = k.steps[s];
+    const int32_t cbar = adj[fw.c];
+    PStep ra;  // dS/dA
+    ra.a = cbar;
+    ra.b = fw.b;
+    ra.bs = fw.bs;
+    ra.ms = fw.ms;
+    ra.ns = fw.ks;
+    ra.ks = fw.ns;
+    PStep rb;  // dS/dB
+    rb.a = fw.a;
+    rb.b = cbar;
+    rb.bs = fw.bs;
+    rb.ms = fw.ks;
+    rb.ns = fw.ns;
+    rb.ks = fw.ms;
+    for (PStep* r : {&ra, &rb}) {
+      r->c = (int32_t)tensors.size();
+      PTensor t;
+      for (int32_t x : r->bs) t.spins.push_back(x);
+      for (int32_t x : r->ms) t.spins.push_back(x);
+      for (int32_t x : r->ns) t.spins.push_back(x);
+      tensors.push_back(std::move(t));
+    }
+    adj[fw.a] = ra.c;
+    adj[fw.b] = rb.c;
+    comp[fw.a] = comp[fw.b] = comp[fw.c];
+    k.steps.push_back(std::move(ra));
+    k.steps.push_back(std::move(rb));
+  }
+  for (auto& v : k.vtx)
+    if (!v.seed) {
+      v.adjoint = adj[v.tensor];
+      v.comp = comp[v.tensor];
+    }
+  k.tensors = std::move(tensors);
+}
+
 // Serial steps that depend on each other only through earlier levels run
 // concurrently on the waves of one workgroup.  Every maximal run of serial
 // steps is reordered by dependency level (1 + the highest level among the
@@ -586,6 +666,8 @@ void level_schedule(PlanKnot& k, int32_t n_vt) {
     tiling[r].level = tiling[r].mode == STEP_SERIAL ? lvl[u] : 0;
   }
   for (auto& c : k.comps) c = remap(c);
+  for (auto& v : k.vtx)
+    if (v.adjoint >= 0) v.adjoint = remap(v.adjoint);
   k.steps = std::move(steps);
   k.tiling = std::move(tiling);
   k.tensors = std::move(tensors);
@@ -597,6 +679,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.q = q;
   k.precision = o.precision;
   k.jones_only = o.jones_only != 0;
+  k.gradient = o.gradient != 0;
   k.n_edges = (int32_t)g.eps.size();
   k.eps = g.eps;
   k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
@@ -699,8 +782,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     k.vtx.push_back(std::move(pv));
     k.tensors.push_back(std::move(t));
   }
-  const int32_t n_vt = (int32_t)k.tensors.size();
-  st.n_vertex_tensors = n_vt;
+  int32_t n_vt = (int32_t)k.tensors.size();
 
   // ---- pairwise contraction order
   {
@@ -738,6 +820,8 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       }
   }
   st.n_components = (int32_t)k.comps.size();
+  if (k.gradient) add_reverse(k, n_vt);
+  st.n_vertex_tensors = n_vt;
   st.n_steps = (int32_t)k.steps.size();
 
   // ---- sizes, statistics, tile decisions
@@ -833,7 +917,9 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
           release(t.partial, len);
         }
       }
-      for (size_t u = i; u < j; ++u) {
+      // gradient plans keep every tensor: forward ones are operands of the
+      // reverse steps, adjoints of the final gradient evaluation
+      for (size_t u = i; u < j && !k.gradient; ++u) {
         const auto& sp = k.steps[u];
         release(k.tensors[sp.a].off, k.tensors[sp.a].size);
         release(k.tensors[sp.b].off, k.tensors[sp.b].size);
@@ -859,6 +945,7 @@ static kn_plan_opts default_opts() {
   o.big_step_macs_log2 = 0;
   o.paper_stats = 0;
   o.lds_bytes = 0;
+  o.gradient = 0;
   return o;
 }
 
@@ -874,6 +961,8 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
       o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304)
     return KN_E_INVALID;
   if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
+  if (o.gradient != 0 && o.gradient != 1) return KN_E_INVALID;
+  if (o.gradient && (o.simplify & 2)) return KN_E_INVALID;
   kn_plan* p = new (std::nothrow) kn_plan();
   if (!p) return KN_E_NOMEM;
   kn_status rc;

@@ -72,6 +72,7 @@ struct ImgHeader {
   int64_t o_pending;  // int32[n_groups] unfinished predecessor tasks
   int64_t o_tstate;   // TensorState[n_tensors]
   int64_t o_weights;  // complex128 x_e per original edge, then x_m per merged edge
+  int64_t o_mgrad;    // complex128 d log Z / d J per merged edge (gradient plans)
   // tensor arena (relative to the workspace base), in complex entries
   int64_t arena_off, arena_elems;
   int64_t workspace_bytes;
@@ -105,6 +106,8 @@ struct KnotDesc {
   int32_t n_iso;                  // isolated vertices: factor q each
   int32_t out_slot;               // index into the kn_scalar output array
   int32_t step_off, n_steps;
+  int32_t grad;  // 1: the steps include the reverse pass; the final task
+                 // writes d log Z / d J_e for every original edge
 };
 
 struct TensorDesc {
@@ -143,7 +146,13 @@ struct VtxDesc {
   int32_t n_slots;     // neighbour spins (absorbed edges)
   int32_t slot_off;    // merged-edge id (knot-local) per neighbour slot
   int32_t keep_center; // 1: the vertex's own spin is the leading index;
-                       // 0: it is private to this tensor and summed at build
+                       // 0: it is private to this tensor and summed at build;
+                       // -1: not a vertex but a reverse-pass seed, the scalar 1
+  int32_t adjoint;     // gradient plans: tensor id of dS/dF_v (-1: none)
+  int32_t comp;        // gradient plans: index of the vertex's component
+  int32_t adj_str;     // gradient plans: offset into the stride table of the
+                       // element strides, in the adjoint's storage, of the
+                       // kept centre (if any) and then of each slot's spin
 };
 
 struct MEdge {

@@ -7,6 +7,7 @@ The names mirror the C ABI in ``include/kn.h``.
 
 from __future__ import annotations
 
+import cmath
 import ctypes
 import math
 import os
@@ -33,7 +34,7 @@ class PlanOpts(ctypes.Structure):
                 ("simplify", ctypes.c_int32), ("jones_only", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
                 ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -92,6 +93,7 @@ _SIGS = {
     "kn_batch_edge_offset": (I32, [P, I32, ctypes.POINTER(ctypes.c_int64)]),
     "kn_batch_upload": (I32, [P, P, ctypes.c_size_t, P]),
     "kn_batch_contract": (I32, [P, P, P, ctypes.c_size_t, P, P]),
+    "kn_batch_contract_backward": (I32, [P, P, P, ctypes.c_size_t, P, P, P]),
     "kn_batch_set_grid": (I32, [P, I32]),
     "kn_batch_image": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
     "kn_batch_set_trace": (I32, [P, P, ctypes.c_size_t]),
@@ -173,12 +175,13 @@ class Plan:
 
     def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
-                 paper_stats=False, lds_bytes=0, allow_budget=False):
+                 paper_stats=False, lds_bytes=0, gradient=False, allow_budget=False):
         L = lib()
         if simplify is None:
-            simplify = 3 if jones_only else 1
+            simplify = 1 if (gradient or not jones_only) else 3
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
-                     tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes)
+                     tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
+                     1 if gradient else 0)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -192,6 +195,7 @@ class Plan:
         self.q = q
         self.precision = precision
         self.jones_only = jones_only
+        self.gradient = bool(gradient)
         st = PlanStats()
         _check(L.kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
         self.stats = st.as_dict()
@@ -237,6 +241,7 @@ def _wrap_plan(h, tait, q, opts):
     p.q = q
     p.precision = opts.precision
     p.jones_only = bool(opts.jones_only)
+    p.gradient = bool(opts.gradient)
     st = PlanStats()
     _check(lib().kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
     p.stats = st.as_dict()
@@ -244,7 +249,7 @@ def _wrap_plan(h, tait, q, opts):
 
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
-              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0):
+              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False):
     """Tait graphs and plans for many knots on the library's host thread pool
     (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
     L = lib()
@@ -254,9 +259,9 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
                                 if ncr.sum() else np.zeros(4, np.int32))
     qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
     if simplify is None:
-        simplify = 3 if jones_only else 1
+        simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
-                 big_step_macs_log2, 0, lds_bytes)
+                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)
@@ -449,6 +454,25 @@ class Batch:
                "kn_batch_contract")
         return z
 
+    def contract_backward(self, J=None, stream=None, z=None, grad=None):
+        """Z and d log Z / d J of every knot (kn_batch_contract_backward);
+        grad: (total_edges, 2) float64, knot i's edges from edge_offset(i)."""
+        torch = _torch()
+        if self.workspace is None:
+            self.upload(stream=stream)
+        if z is None:
+            z = alloc_scalars(len(self.plans))
+        if grad is None:
+            grad = torch.empty((max(1, int(self.stats["total_edges"])), 2), dtype=torch.float64,
+                               device="cuda")
+        ptr, nbytes = _aligned_ptr(self.workspace)
+        jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+        _check(lib().kn_batch_contract_backward(self._h, jp, ctypes.c_void_p(ptr), nbytes,
+                                                _stream_ptr(stream), ctypes.c_void_p(z.data_ptr()),
+                                                ctypes.c_void_p(grad.data_ptr())),
+               "kn_batch_contract_backward")
+        return z, grad
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
@@ -469,3 +493,41 @@ def z_to_log(z_mant: complex, z_exp2: int):
     if z_mant == 0:
         return -math.inf, 0.0
     return math.log2(abs(z_mant)) + z_exp2, math.atan2(z_mant.imag, z_mant.real)
+
+
+def _make_logz():
+    torch = _torch()
+
+    class LogZ(torch.autograd.Function):
+        """log Z of one knot as a differentiable function of its complex edge
+        couplings J (complex128, n_edges, on the GPU).  The forward launch runs
+        the forward and reverse sweeps together (kn_contract_backward) and
+        keeps d log Z / d J for the backward call."""
+
+        @staticmethod
+        def forward(ctx, J, plan):
+            Jr = torch.view_as_real(J.detach().contiguous()).reshape(-1)
+            z, g = contract_backward(plan, Jr)
+            (m, e), = scalars_from_device(z)
+            ctx.save_for_backward(torch.view_as_complex(g))
+            logz = cmath.log(m) + e * math.log(2.0)
+            return torch.tensor(logz, dtype=torch.complex128, device=J.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            dlogz, = ctx.saved_tensors
+            # holomorphic function: vector-Jacobian product with conj(f')
+            return gout * dlogz.conj(), None
+
+    return LogZ
+
+
+_LOGZ = None
+
+
+def log_z(J, plan: Plan):
+    """Differentiable log Z(J) for a gradient plan (torch.autograd)."""
+    global _LOGZ
+    if _LOGZ is None:
+        _LOGZ = _make_logz()
+    return _LOGZ.apply(J, plan)

@@ -27,7 +27,7 @@ HDR = np.dtype([
     ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_strides", "<i8"),
     ("o_eps", "<i8"), ("o_comps", "<i8"), ("image_bytes", "<i8"), ("state_off", "<i8"),
     ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
-    ("o_weights", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
+    ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
     ("workspace_bytes", "<i8")], align=True)
 TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "group", "first", "count", "flags",
                                       "state_lo", "state_len")], align=True)
@@ -35,13 +35,15 @@ GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", 
                  align=True)
 KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
-    "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps")], align=True)
+    "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps", "grad")],
+    align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
                                       "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
                                       "n_mb", "n_nb", "n_ks", "kseg", "partial", "lvl")],
                 align=True)
-VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center")], align=True)
+VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center", "adjoint",
+                                    "comp", "adj_str")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
 TAB_CAP = 3072
 STEP_SERIAL, STEP_TILES, STEP_GEMM = 0, 1, 2
@@ -78,8 +80,10 @@ class Image:
         self.comps = arr("<i4", h["o_comps"], n_comps)
 
 
-def run(raw: bytes, J=None):
-    """Execute the image; returns a list of (mantissa, exp2) per knot."""
+def run(raw: bytes, J=None, want_grad=False):
+    """Execute the image; returns a list of (mantissa, exp2) per knot, and with
+    want_grad also d log Z / d J per original edge (knot-global edge order)
+    for the knots of gradient plans."""
     im = Image(raw)
     h = im.h
     es = 8 if h["precision"] else 16
@@ -91,6 +95,9 @@ def run(raw: bytes, J=None):
     finished = np.zeros(nt, bool)   # producer finished (visible to later groups)
     weights = np.zeros(int(h["n_edges"]) + int(h["n_medges"]), np.complex128)
     out = [None] * int(h["n_knots"])
+    grads = np.full(int(h["n_edges"]), np.nan, np.complex128)
+    # gradient plans read every tensor again in the reverse pass: nothing dies
+    keep_all = any(int(k["grad"]) for k in im.knots)
 
     # layout checks
     assert int(h["image_bytes"]) == len(raw)
@@ -238,7 +245,8 @@ def run(raw: bytes, J=None):
         commit_step(si, C, local, task_local)
         s = im.steps[si]
         for op in (int(s["a"]), int(s["b"])):  # operands are consumed exactly once
-            live_g.pop(op, None)
+            if not keep_all:
+                live_g.pop(op, None)
             live_l.pop(op, None)
 
     def reduce(si, local):
@@ -256,6 +264,64 @@ def run(raw: bytes, J=None):
             return z, e
         s = math.frexp(m)[1]
         return complex(math.ldexp(z.real, -s), math.ldexp(z.imag, -s)), e + s
+
+    def knot_gradient(k, local):
+        """d log Z / d J per original edge, as the device computes it: for the
+        merged edge in slot j of vertex tensor F_v, x_m * sum_i dS/dF_v[i]
+        dF_v/dx_m[i] / S with S the component's scalar; spikes x/(x+q-1),
+        loops 1."""
+        q = int(k["q"])
+        eo, mo = int(k["edge_off"]), int(k["medge_off"])
+        ne, nm = int(h["n_edges"]), int(k["n_medges"])
+        mg = np.full(nm, np.nan, np.complex128)
+        for v in range(int(k["n_vtx"])):
+            vd = im.vtx[int(k["vtx_off"]) + v]
+            ns = int(vd["n_slots"])
+            if int(vd["keep_center"]) < 0 or int(vd["adjoint"]) < 0 or ns == 0:
+                continue
+            adj_t = int(vd["adjoint"])
+            fb = read(adj_t, local)
+            root = int(im.comps[int(k["comp_off"]) + int(vd["comp"])])
+            r = complex(read(root, local)[0])
+            slots = [int(im.vslot[int(vd["slot_off"]) + j]) for j in range(ns)]
+            xs = [weights[ne + mo + m] for m in slots]
+            qn = q ** ns
+            kc = 1 if int(vd["keep_center"]) else 0
+            astr = [int(x) for x in im.strides[int(vd["adj_str"]):int(vd["adj_str"]) + kc + ns]]
+            assert sorted(astr) == [q ** r for r in range(kc + ns)], "adjoint strides"
+            for j in range(ns):
+                acc = 0j
+                for i in range(fb.size):
+                    rem = i
+                    dig = [0] * ns
+                    for l in range(ns - 1, -1, -1):
+                        dig[l] = rem % q
+                        rem //= q
+                    off = sum(dig[l] * astr[kc + l] for l in range(ns)) + (rem * astr[0] if kc else 0)
+                    a = rem if kc else dig[j]
+                    if dig[j] != a:
+                        continue
+                    p = complex(fb[off])
+                    for l in range(ns):
+                        if l != j and dig[l] == a:
+                            p *= xs[l]
+                    acc += p
+                assert math.isnan(mg[slots[j]].real), "merged edge absorbed twice"
+                mg[slots[j]] = xs[j] * acc / r * 2.0 ** (exp2[adj_t] - exp2[root])
+            assert fb.size == qn * (q if int(vd["keep_center"]) else 1)
+        for i in range(int(k["n_factors"])):
+            f = im.factors[int(k["factor_off"]) + i]
+            if f["x"] == 1:
+                x = weights[ne + mo + int(f["y"])]
+                mg[int(f["y"])] = x / (x + q - 1)
+        for m in range(nm):
+            me = im.medges[mo + m]
+            for i in range(int(me["y"])):
+                grads[eo + int(im.members[int(me["x"]) + i])] = mg[m]
+        for i in range(int(k["n_factors"])):
+            f = im.factors[int(k["factor_off"]) + i]
+            if f["x"] == 0:
+                grads[eo + int(f["y"])] = 1.0
 
     queue = deque(int(r) for r in im.roots)
     pending = {gi: int(g["n_pred"]) for gi, g in enumerate(im.groups)}
@@ -338,7 +404,8 @@ def run(raw: bytes, J=None):
                     commit_step(u, C, local)
                 for u in range(i, j):
                     for op in (int(im.steps[u]["a"]), int(im.steps[u]["b"])):
-                        live_g.pop(op, None)
+                        if not keep_all:
+                            live_g.pop(op, None)
                         live_l.pop(op, None)
                 i = j
             if task["flags"] & 2:
@@ -348,7 +415,8 @@ def run(raw: bytes, J=None):
                     e += exp2[t]
                     z, e = mul(z, e, read(t, local)[0])
                     live_l.pop(t, None)
-                    live_g.pop(t, None)
+                    if not keep_all:
+                        live_g.pop(t, None)
                 eo, mo = int(k["edge_off"]), int(k["medge_off"])
                 for i in range(int(k["n_factors"])):
                     f = im.factors[int(k["factor_off"]) + i]
@@ -360,6 +428,8 @@ def run(raw: bytes, J=None):
                 for i in range(int(k["n_iso"])):
                     z, e = mul(z, e, q)
                 out[int(k["out_slot"])] = (z, e)
+                if int(k["grad"]):
+                    knot_gradient(k, local)
             assert local == made, "state range differs from the tensors the task produced"
             # LDS contents die with the task: nothing homed there may outlive it
             assert not live_l, f"LDS tensors {list(live_l)} still live when their task ends"
@@ -400,4 +470,6 @@ def run(raw: bytes, J=None):
                 G = im.groups[nxt]
                 queue.extend(range(int(G["first_task"]), int(G["first_task"] + G["n_tasks"])))
     assert executed == int(h["n_tasks"]), "some tasks were never enqueued"
+    if want_grad:
+        return out, grads
     return out

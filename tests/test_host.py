@@ -274,3 +274,65 @@ def test_jones_large_knot_phase_exact():
 def test_status_strings():
     for c in range(-6, 1):
         assert kn.status_string(c)
+
+
+def _gradient_cases():
+    cases = [gen.trefoil(), gen.figure_eight(), gen.add_kink(gen.figure_eight(), 0, True, 1)]
+    cases += [gen.lattice_knot((70, k), 8, 16) for k in range(6)]
+    cases += [gen.lattice_knot((71, k), 20, 40) for k in range(3)]
+    return cases
+
+
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_gradient_plan_model_matches_oracle(q):
+    """Reverse pass of the device program (CPU model) against the oracle's
+    d log Z / d J (one elimination per edge), random complex couplings."""
+    rng = np.random.default_rng(100 + q)
+    for d in _gradient_cases():
+        t = kn.Tait(d.pd, d.signs if d.n == 1 else None)
+        p = kn.Plan(t, q, jones_only=False, gradient=True)
+        J = rng.normal(scale=0.4, size=2 * t.n_edges)
+        ((zm, ze),), g = image_model.run(p.image(), J, want_grad=True)
+        uv, eps = t.edges()
+        x = np.exp(J[0::2] + 1j * J[1::2])
+        edges = [tuple(a) for a in uv]
+        m, e = potts.partition_function(t.n_vertices, edges, x, q)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+        go = potts.dlogz_dj(t.n_vertices, edges, x, q)
+        assert np.max(np.abs(g - go) / np.abs(go)) < 1e-12, (d.label, q)
+
+
+def test_gradient_plan_model_jones_point_and_batch():
+    """J = NULL (the Jones couplings) on gradient plans, in one batch image."""
+    knots = [gen.lattice_knot((72, k), 10, 30) for k in range(4)]
+    taits = [kn.Tait(d.pd) for d in knots]
+    plans = [kn.Plan(t, 3, gradient=True) for t in taits]
+    b = kn.Batch(plans)
+    out, g = image_model.run(b.image(), None, want_grad=True)
+    tq = ojones.t_of_q(3)
+    for i, (t, (zm, ze)) in enumerate(zip(taits, out)):
+        uv, eps = t.edges()
+        x = potts.jones_weights(eps, tq)
+        edges = [tuple(a) for a in uv]
+        m, e = potts.partition_function(t.n_vertices, edges, x, 3)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+        off = b.edge_offset(i)
+        go = potts.dlogz_dj(t.n_vertices, edges, x, 3)
+        gi = g[off:off + t.n_edges]
+        assert np.max(np.abs(gi - go) / np.abs(go)) < 1e-12
+
+
+def test_gradient_plan_options():
+    t = kn.Tait(gen.figure_eight().pd)
+    with pytest.raises(kn.KnError):
+        kn.Plan(t, 3, gradient=True, simplify=3)  # Reidemeister II drops edges
+    p = kn.Plan(t, 3)
+    with pytest.raises(kn.KnError) as ei:
+        kn.backward_workspace_bytes(p)
+    assert ei.value.code == -6
+    pg = kn.Plan(t, 3, gradient=True, jones_only=False)
+    assert kn.backward_workspace_bytes(pg) == pg.workspace_bytes
+    # the reverse pass doubles the steps and adds one seed per component
+    pf = kn.Plan(t, 3, jones_only=False, simplify=1)
+    assert pg.stats["n_steps"] == 3 * pf.stats["n_steps"]
+    assert pg.stats["n_vertex_tensors"] == pf.stats["n_vertex_tensors"] + pf.stats["n_components"]
