@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the one-knot-per-call comparison")
+    ap.add_argument("--untuned", action="store_true",
+                    help="ignore the autotuner's recorded setting (library defaults)")
     return ap.parse_args()
 
 
@@ -90,7 +92,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1807_02119_amd import gen, kn
+    from paper_1807_02119_amd import gen, kn, tune
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -111,9 +113,17 @@ def main():
     state = {}
     pool = ThreadPoolExecutor(max_workers=1)
 
+    # knob settings recorded by the autotuner for this workload (plan options
+    # and the persistent grid), per precision; defaults when none was recorded
+    tuned = {p: tune.load("q3_200_600", p) for p in (0, 1)} if not args.untuned else {0: {}, 1: {}}
+
     def prepare(precision=0):
-        taits, plans = kn.plan_many(pds, q, n_threads=args.threads, precision=precision)
-        return taits, plans, kn.Batch(plans)
+        opts = {k: v for k, v in tuned[precision].items() if k != "grid"}
+        taits, plans = kn.plan_many(pds, q, n_threads=args.threads, precision=precision, **opts)
+        batch = kn.Batch(plans)
+        if tuned[precision].get("grid"):
+            batch.set_grid(int(tuned[precision]["grid"]))
+        return taits, plans, batch
 
     def device(prepared, precision=0):
         taits, plans, batch = prepared
@@ -174,7 +184,8 @@ def main():
 
     # host-only breakdown of one step: plans, then plans + device program
     t0 = time.perf_counter()
-    kn.plan_many(pds, q, n_threads=args.threads)
+    kn.plan_many(pds, q, n_threads=args.threads,
+                 **{k: v for k, v in tuned[0].items() if k != "grid"})
     ms_plan = 1e3 * (time.perf_counter() - t0)
     t0 = time.perf_counter()
     prepare()
@@ -229,6 +240,7 @@ def main():
         "host_prepare_ms": ms_prepare,
         "host_threads": args.threads if args.threads > 0 else len(os.sched_getaffinity(0)),
         "pipelined": "host preparation of batch i+1 overlaps the GPU work of batch i",
+        "tuned": tuned[0] or None,
         "gpu_contract": {
             "ms_per_batch": ms_gpu,
             "knots_per_s": B / (ms_gpu * 1e-3),

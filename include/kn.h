@@ -125,7 +125,9 @@ void kn_tait_free(kn_tait* g);
  * tile_outputs      outputs per tile for steps split across workgroups
  *               (0 = default); big_step_macs_log2: log2 of the complex
  *               multiply-adds above which a step is split into tiles
- *               (0 = default).
+ *               (0 = default 16); tile_macs_log2: log2 of the multiply-adds a
+ *               tile of outputs aims at when tile_outputs is 0 (0 = default
+ *               15).  These are the knobs the autotuner searches.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -151,6 +153,7 @@ typedef struct {
   int32_t paper_stats;
   int32_t lds_bytes;
   int32_t gradient;
+  int32_t tile_macs_log2;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

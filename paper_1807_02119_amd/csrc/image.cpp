@@ -18,24 +18,18 @@
 // workgroup's LDS arena when it fits (first fit over its live range);
 // everything else lives in the global arena.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
 namespace kn {
 
 namespace {
-
-template <class T>
-int64_t put(std::vector<uint8_t>& img, const std::vector<T>& v) {
-  int64_t off = align256((int64_t)img.size());
-  img.resize(off + v.size() * sizeof(T));
-  if (!v.empty()) std::memcpy(img.data() + off, v.data(), v.size() * sizeof(T));
-  return off;
-}
 
 // Element stride of every spin of `group` in a tensor stored in `order`
 // (row-major, last spin fastest), appended to `out`.
@@ -274,54 +268,120 @@ void make_section(PlanKnot& k) {
   }
 }
 
-std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
+Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   ImgHeader h;
   std::memset(&h, 0, sizeof(h));
   h.magic = kMagic;
   h.precision = knots.empty() ? 0 : knots[0]->precision;
 
-  // totals
-  size_t nK = knots.size(), nT = 0, nS = 0, nV = 0, nVS = 0, nM = 0, nMem = 0, nF = 0, nTab = 0,
-         nE = 0, nC = 0, nTask = 0, nG = 0;
-  int64_t arena = 0;
+  // offsets of every knot's section in the concatenated arrays (prefix
+  // sums), then the sections are copied and relocated in parallel
+  struct Off {
+    size_t T, S, V, VS, M, MEM, F, TAB, E, C, TK, G;
+    int64_t arena;
+  };
+  const size_t nK = knots.size();
+  std::vector<Off> off(nK + 1);
   int32_t lds_used = 0;
-  for (const PlanKnot* k : knots) {
-    const Section& S = k->sec;
-    nT += S.td.size();
-    nS += S.sd.size();
-    nV += S.vd.size();
-    nVS += S.vslot.size();
-    nM += S.md.size();
-    nMem += S.members.size();
-    nF += S.fac.size();
-    nTab += S.strides.size();
-    nE += k->eps.size();
-    nC += S.comps.size();
-    nTask += S.tasks.size();
-    nG += S.groups.size();
-    lds_used = std::max(lds_used, S.lds_used);
+  {
+    Off o{};
+    for (size_t ki = 0; ki < nK; ++ki) {
+      off[ki] = o;
+      const PlanKnot& k = *knots[ki];
+      const Section& S = k.sec;
+      o.T += S.td.size();
+      o.S += S.sd.size();
+      o.V += S.vd.size();
+      o.VS += S.vslot.size();
+      o.M += S.md.size();
+      o.MEM += S.members.size();
+      o.F += S.fac.size();
+      o.TAB += S.strides.size();
+      o.E += k.eps.size();
+      o.C += S.comps.size();
+      o.TK += S.tasks.size();
+      o.G += S.groups.size();
+      o.arena += S.arena_elems;
+      lds_used = std::max(lds_used, S.lds_used);
+    }
+    off[nK] = o;
   }
-  std::vector<KnotDesc> kd(nK);
-  std::vector<TensorDesc> td(nT);
-  std::vector<StepDesc> sd(nS);
-  std::vector<VtxDesc> vd(nV);
-  std::vector<int32_t> vslot(nVS);
-  std::vector<MEdge> md(nM);
-  std::vector<int32_t> members(nMem);
-  std::vector<Factor> fac(nF);
-  std::vector<int32_t> strides(nTab);
-  std::vector<int8_t> eps(nE);
-  std::vector<int32_t> comps(nC);
-  std::vector<TaskDesc> tasks(nTask);
-  std::vector<GroupDesc> groups(nG);
-  std::vector<std::pair<double, int32_t>> roots;  // (-estimated chain time, root task)
-  roots.reserve(nK);
+  const Off& tot = off[nK];
+  const size_t nT = tot.T, nS = tot.S, nV = tot.V, nVS = tot.VS, nM = tot.M, nMem = tot.MEM,
+               nF = tot.F, nTab = tot.TAB, nE = tot.E, nC = tot.C, nTask = tot.TK, nG = tot.G;
+  const int64_t arena = tot.arena;
+  // image layout: header, then each array 256-byte aligned; the buffer is
+  // not zero-filled (every array is written in full below, the padding is
+  // cleared), and the knots' sections are written straight into it
+  h.n_tasks = (int32_t)nTask;
+  h.n_knots = (int32_t)nK;
+  h.n_tensors = (int32_t)nT;
+  h.n_steps = (int32_t)nS;
+  h.n_vtx = (int32_t)nV;
+  h.n_medges = (int32_t)nM;
+  h.n_members = (int32_t)nMem;
+  h.n_factors = (int32_t)nF;
+  h.n_strides = (int32_t)nTab;
+  h.n_groups = (int32_t)nG;
+  h.n_edges = (int32_t)nE;
+  h.n_roots = (int32_t)nK;
+  h.lds_bytes = (lds_used + 255) / 256 * 256;
+  std::vector<std::pair<int64_t, int64_t>> used;  // (offset, bytes) of each array
+  int64_t top = sizeof(ImgHeader);
+  auto reserve = [&](size_t n, size_t elem) {
+    const int64_t o = align256(top);
+    used.emplace_back(o, (int64_t)(n * elem));
+    top = o + (int64_t)(n * elem);
+    return o;
+  };
+  h.o_tasks = reserve(nTask, sizeof(TaskDesc));
+  h.o_groups = reserve(nG, sizeof(GroupDesc));
+  h.o_roots = reserve(nK, sizeof(int32_t));
+  h.o_knots = reserve(nK, sizeof(KnotDesc));
+  h.o_tensors = reserve(nT, sizeof(TensorDesc));
+  h.o_steps = reserve(nS, sizeof(StepDesc));
+  h.o_vtx = reserve(nV, sizeof(VtxDesc));
+  h.o_vslot = reserve(nVS, sizeof(int32_t));
+  h.o_medges = reserve(nM, sizeof(MEdge));
+  h.o_members = reserve(nMem, sizeof(int32_t));
+  h.o_factors = reserve(nF, sizeof(Factor));
+  h.o_strides = reserve(nTab, sizeof(int32_t));
+  h.o_eps = reserve(nE, sizeof(int8_t));
+  h.o_comps = reserve(nC, sizeof(int32_t));
+  h.image_bytes = align256(top);
+  Bytes img((size_t)h.image_bytes);
+  uint8_t* base = img.data();
+  {
+    int64_t end = sizeof(ImgHeader);
+    for (auto [o, n] : used) {
+      std::memset(base + end, 0, (size_t)(o - end));
+      end = o + n;
+    }
+    std::memset(base + end, 0, (size_t)(h.image_bytes - end));
+  }
+  auto arr = [&](int64_t o, auto* type) { return reinterpret_cast<decltype(type)>(base + o); };
+  KnotDesc* kd = arr(h.o_knots, (KnotDesc*)nullptr);
+  TensorDesc* td = arr(h.o_tensors, (TensorDesc*)nullptr);
+  StepDesc* sd = arr(h.o_steps, (StepDesc*)nullptr);
+  VtxDesc* vd = arr(h.o_vtx, (VtxDesc*)nullptr);
+  int32_t* vslot = arr(h.o_vslot, (int32_t*)nullptr);
+  MEdge* md = arr(h.o_medges, (MEdge*)nullptr);
+  int32_t* members = arr(h.o_members, (int32_t*)nullptr);
+  Factor* fac = arr(h.o_factors, (Factor*)nullptr);
+  int32_t* strides = arr(h.o_strides, (int32_t*)nullptr);
+  int8_t* eps = arr(h.o_eps, (int8_t*)nullptr);
+  int32_t* comps = arr(h.o_comps, (int32_t*)nullptr);
+  TaskDesc* tasks = arr(h.o_tasks, (TaskDesc*)nullptr);
+  GroupDesc* groups = arr(h.o_groups, (GroupDesc*)nullptr);
+  std::vector<std::pair<double, int32_t>> roots(nK);  // (-estimated chain time, root task)
 
-  size_t T0 = 0, S0 = 0, V0 = 0, VS0 = 0, M0 = 0, MEM0 = 0, F0 = 0, TAB0 = 0, E0 = 0, C0 = 0,
-         TK0 = 0, G0 = 0;
-  for (size_t ki = 0; ki < nK; ++ki) {
+  auto place = [&](size_t ki) {
     const PlanKnot& k = *knots[ki];
     const Section& S = k.sec;
+    const Off& o = off[ki];
+    const size_t T0 = o.T, S0 = o.S, V0 = o.V, VS0 = o.VS, M0 = o.M, MEM0 = o.MEM, F0 = o.F,
+                 TAB0 = o.TAB, E0 = o.E, C0 = o.C, TK0 = o.TK, G0 = o.G;
+    const int64_t arena0 = o.arena;
     KnotDesc x = S.kd;
     x.edge_off = (int32_t)E0;
     x.medge_off = (int32_t)M0;
@@ -334,7 +394,7 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
     const int32_t t0 = (int32_t)T0, s0 = (int32_t)S0, g0 = (int32_t)G0, tk0 = (int32_t)TK0;
     for (size_t i = 0; i < S.td.size(); ++i) {
       TensorDesc t = S.td[i];
-      t.off += arena;
+      t.off += arena0;
       td[T0 + i] = t;
     }
     for (size_t i = 0; i < S.sd.size(); ++i) {
@@ -343,10 +403,10 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
       s.b += t0;
       s.c += t0;
       s.str += (int32_t)TAB0;
-      if (s.home_a >= 0) s.home_a += (int32_t)arena;
-      if (s.home_b >= 0) s.home_b += (int32_t)arena;
-      if (s.home_c >= 0) s.home_c += (int32_t)arena;
-      if (s.partial >= 0) s.partial += (int32_t)arena;
+      if (s.home_a >= 0) s.home_a += (int32_t)arena0;
+      if (s.home_b >= 0) s.home_b += (int32_t)arena0;
+      if (s.home_c >= 0) s.home_c += (int32_t)arena0;
+      if (s.partial >= 0) s.partial += (int32_t)arena0;
       sd[S0 + i] = s;
     }
     for (size_t i = 0; i < S.vd.size(); ++i) {
@@ -359,16 +419,16 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
       v.slot_off += (int32_t)VS0;
       vd[V0 + i] = v;
     }
-    std::copy(S.vslot.begin(), S.vslot.end(), vslot.begin() + VS0);
+    std::copy(S.vslot.begin(), S.vslot.end(), vslot + VS0);
     for (size_t i = 0; i < S.md.size(); ++i) {
       MEdge m = S.md[i];
       m.member_off += (int32_t)MEM0;
       md[M0 + i] = m;
     }
-    std::copy(S.members.begin(), S.members.end(), members.begin() + MEM0);
-    std::copy(S.fac.begin(), S.fac.end(), fac.begin() + F0);
-    std::copy(S.strides.begin(), S.strides.end(), strides.begin() + TAB0);
-    std::copy(k.eps.begin(), k.eps.end(), eps.begin() + E0);
+    std::copy(S.members.begin(), S.members.end(), members + MEM0);
+    std::copy(S.fac.begin(), S.fac.end(), fac + F0);
+    std::copy(S.strides.begin(), S.strides.end(), strides + TAB0);
+    std::copy(k.eps.begin(), k.eps.end(), eps + E0);
     for (size_t i = 0; i < S.comps.size(); ++i) comps[C0 + i] = S.comps[i] + t0;
     for (size_t i = 0; i < S.tasks.size(); ++i) {
       TaskDesc t = S.tasks[i];
@@ -385,63 +445,29 @@ std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots) {
       if (g.next >= 0) g.next += g0;
       groups[G0 + i] = g;
     }
-    roots.emplace_back(-S.est, tk0 + S.groups[0].first_task);
-    arena += S.arena_elems;
-    T0 += S.td.size();
-    S0 += S.sd.size();
-    V0 += S.vd.size();
-    VS0 += S.vslot.size();
-    M0 += S.md.size();
-    MEM0 += S.members.size();
-    F0 += S.fac.size();
-    TAB0 += S.strides.size();
-    E0 += k.eps.size();
-    C0 += S.comps.size();
-    TK0 += S.tasks.size();
-    G0 += S.groups.size();
+    roots[ki] = {-S.est, tk0 + S.groups[0].first_task};
+  };
+  // a few knots per thread; small batches are laid out on the calling thread
+  const size_t nth = std::min<size_t>(std::max<size_t>(1, nK / 16),
+                                      std::max(1u, std::thread::hardware_concurrency()));
+  if (nth <= 1) {
+    for (size_t ki = 0; ki < nK; ++ki) place(ki);
+  } else {
+    std::atomic<size_t> next{0};
+    auto worker = [&] {
+      for (size_t ki; (ki = next.fetch_add(1)) < nK;) place(ki);
+    };
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < std::min<size_t>(nth, 16); ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
   }
   std::stable_sort(roots.begin(), roots.end(),
                    [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
                      return a.first < b.first;
                    });
-  std::vector<int32_t> root_tasks(roots.size());
+  int32_t* root_tasks = arr(h.o_roots, (int32_t*)nullptr);
   for (size_t i = 0; i < roots.size(); ++i) root_tasks[i] = roots[i].second;
-
-  h.n_tasks = (int32_t)nTask;
-  h.n_knots = (int32_t)nK;
-  h.n_tensors = (int32_t)nT;
-  h.n_steps = (int32_t)nS;
-  h.n_vtx = (int32_t)nV;
-  h.n_medges = (int32_t)nM;
-  h.n_members = (int32_t)nMem;
-  h.n_factors = (int32_t)nF;
-  h.n_strides = (int32_t)nTab;
-  h.n_groups = (int32_t)nG;
-  h.n_edges = (int32_t)nE;
-  h.n_roots = (int32_t)root_tasks.size();
-  h.lds_bytes = (lds_used + 255) / 256 * 256;
-
-  std::vector<uint8_t> img(sizeof(ImgHeader));
-  img.reserve(4096 + 256 * 18 + nTask * sizeof(TaskDesc) + nG * sizeof(GroupDesc) + nK * 4 +
-              nK * sizeof(KnotDesc) + nT * sizeof(TensorDesc) + nS * sizeof(StepDesc) +
-              nV * sizeof(VtxDesc) + nVS * 4 + nM * sizeof(MEdge) + nMem * 4 +
-              nF * sizeof(Factor) + nTab * 4 + nE + nC * 4);
-  h.o_tasks = put(img, tasks);
-  h.o_groups = put(img, groups);
-  h.o_roots = put(img, root_tasks);
-  h.o_knots = put(img, kd);
-  h.o_tensors = put(img, td);
-  h.o_steps = put(img, sd);
-  h.o_vtx = put(img, vd);
-  h.o_vslot = put(img, vslot);
-  h.o_medges = put(img, md);
-  h.o_members = put(img, members);
-  h.o_factors = put(img, fac);
-  h.o_strides = put(img, strides);
-  h.o_eps = put(img, eps);
-  h.o_comps = put(img, comps);
-  h.image_bytes = align256((int64_t)img.size());
-  img.resize(h.image_bytes);
   // runtime state: control words, ready queue, pending counters, tensor
   // states, weights
   h.state_off = h.image_bytes;

@@ -2,7 +2,10 @@
 #pragma once
 #include <stdint.h>
 
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/kn.h"
@@ -18,6 +21,28 @@ struct kn_tait {
 };
 
 namespace kn {
+
+// Allocator whose value-less construct leaves elements uninitialised, so that
+// a buffer about to be overwritten in full is not zero-filled first.
+template <class T>
+struct DefaultInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = DefaultInit<U>;
+  };
+  DefaultInit() = default;
+  template <class U>
+  DefaultInit(const DefaultInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+using Bytes = std::vector<uint8_t, DefaultInit<uint8_t>>;
 
 // A short list of spin ids.  Tensors of a plan have low rank, so up to kIn ids
 // are stored inline and only longer lists go to the heap; this keeps the
@@ -238,7 +263,7 @@ void make_section(PlanKnot& k);
 
 // Build the device image for a list of knots (a batch of one or more) by
 // concatenating their sections.  out_slot of knot i is i.
-std::vector<uint8_t> build_image(const std::vector<const PlanKnot*>& knots);
+Bytes build_image(const std::vector<const PlanKnot*>& knots);
 
 int64_t elem_bytes(int32_t precision);
 
@@ -247,12 +272,12 @@ int64_t elem_bytes(int32_t precision);
 struct kn_plan {
   kn::PlanKnot k;
   kn_plan_stats stats{};
-  std::vector<uint8_t> image;  // single-knot device image
+  kn::Bytes image;  // single-knot device image
   uint64_t bwd_workspace = 0;
 };
 
 struct kn_batch {
-  std::vector<uint8_t> image;
+  kn::Bytes image;
   kn_batch_stats stats{};
   std::vector<int64_t> edge_offset;
   int32_t precision = 0;

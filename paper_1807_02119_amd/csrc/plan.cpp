@@ -866,8 +866,9 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     } else {
       // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
       t.mode = STEP_TILES;
+      const double tile_macs = o.tile_macs_log2 > 0 ? std::ldexp(1.0, o.tile_macs_log2) : kTileMacs;
       double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
-                                       : std::max(1.0, std::floor(kTileMacs / std::min(nk, 1024.0)));
+                                       : std::max(1.0, std::floor(tile_macs / std::min(nk, 1024.0)));
       if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
       tile = std::min(tile, outs);
       t.tile = (int32_t)tile;
@@ -946,6 +947,7 @@ static kn_plan_opts default_opts() {
   o.paper_stats = 0;
   o.lds_bytes = 0;
   o.gradient = 0;
+  o.tile_macs_log2 = 0;
   return o;
 }
 
@@ -958,7 +960,8 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   kn_plan_opts o = opts ? *opts : default_opts();
   if (o.strategy < 0 || o.strategy > 3 || o.precision < 0 || o.precision > 1 ||
       o.simplify < 0 || o.simplify > 3 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
-      o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304)
+      o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304 ||
+      o.tile_macs_log2 < 0 || o.tile_macs_log2 > 30)
     return KN_E_INVALID;
   if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
   if (o.gradient != 0 && o.gradient != 1) return KN_E_INVALID;

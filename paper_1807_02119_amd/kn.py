@@ -34,7 +34,8 @@ class PlanOpts(ctypes.Structure):
                 ("simplify", ctypes.c_int32), ("jones_only", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
                 ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32),
+                ("tile_macs_log2", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -151,10 +152,21 @@ class Tait:
                              outer_arc, outer_side, ctypes.byref(h))
         _check(rc, "kn_build_tait")
         self._h = h
-        nv, ne, w, t = I32(), I32(), I32(), I32()
-        _check(L.kn_tait_info(h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(w),
-                              ctypes.byref(t)), "kn_tait_info")
-        self.n_vertices, self.n_edges, self.writhe, self.tait_number = nv.value, ne.value, w.value, t.value
+        self._info = None
+
+    def _get_info(self):
+        if self._info is None:
+            nv, ne, w, t = I32(), I32(), I32(), I32()
+            _check(lib().kn_tait_info(self._h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(w),
+                                      ctypes.byref(t)), "kn_tait_info")
+            self._info = (nv.value, ne.value, w.value, t.value)
+        return self._info
+
+    # graph facts are read from the library on first use (kn_tait_info)
+    n_vertices = property(lambda self: self._get_info()[0])
+    n_edges = property(lambda self: self._get_info()[1])
+    writhe = property(lambda self: self._get_info()[2])
+    tait_number = property(lambda self: self._get_info()[3])
 
     def edges(self):
         uv = np.zeros(2 * self.n_edges, np.int32)
@@ -175,13 +187,14 @@ class Plan:
 
     def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
-                 paper_stats=False, lds_bytes=0, gradient=False, allow_budget=False):
+                 paper_stats=False, lds_bytes=0, gradient=False, tile_macs_log2=0,
+                 allow_budget=False):
         L = lib()
         if simplify is None:
             simplify = 1 if (gradient or not jones_only) else 3
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
                      tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
-                     1 if gradient else 0)
+                     1 if gradient else 0, tile_macs_log2)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -196,9 +209,16 @@ class Plan:
         self.precision = precision
         self.jones_only = jones_only
         self.gradient = bool(gradient)
-        st = PlanStats()
-        _check(L.kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
-        self.stats = st.as_dict()
+        self._stats = None
+
+    @property
+    def stats(self):
+        """kn_plan_info as a dict (read on first use)."""
+        if self._stats is None:
+            st = PlanStats()
+            _check(lib().kn_plan_info(self._h, ctypes.byref(st)), "kn_plan_info")
+            self._stats = st.as_dict()
+        return self._stats
 
     @property
     def workspace_bytes(self):
@@ -226,10 +246,7 @@ class Plan:
 def _wrap_tait(h):
     t = Tait.__new__(Tait)
     t._h = h
-    nv, ne, w, tn = I32(), I32(), I32(), I32()
-    _check(lib().kn_tait_info(h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(w),
-                              ctypes.byref(tn)), "kn_tait_info")
-    t.n_vertices, t.n_edges, t.writhe, t.tait_number = nv.value, ne.value, w.value, tn.value
+    t._info = None
     return t
 
 
@@ -242,14 +259,13 @@ def _wrap_plan(h, tait, q, opts):
     p.precision = opts.precision
     p.jones_only = bool(opts.jones_only)
     p.gradient = bool(opts.gradient)
-    st = PlanStats()
-    _check(lib().kn_plan_info(h, ctypes.byref(st)), "kn_plan_info")
-    p.stats = st.as_dict()
+    p._stats = None
     return p
 
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
-              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False):
+              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
+              tile_macs_log2=0):
     """Tait graphs and plans for many knots on the library's host thread pool
     (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
     L = lib()
@@ -261,7 +277,7 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
     if simplify is None:
         simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
-                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0)
+                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)
@@ -453,6 +469,24 @@ class Batch:
                                        _stream_ptr(stream), ctypes.c_void_p(z.data_ptr())),
                "kn_batch_contract")
         return z
+
+    def graph(self, z, J=None, grad=None):
+        """Capture one launch of the batch (its clear kernel and persistent
+        kernel; with ``grad`` also the gradient kernel) in a hipGraph through
+        torch.cuda.CUDAGraph; ``g.replay()`` then re-runs the contraction into
+        the same ``z`` (and ``grad``).  The batch must have been uploaded and
+        launched once eagerly (kernel attributes are set on the first launch)."""
+        torch = _torch()
+        if self.workspace is None:
+            raise RuntimeError("upload and run the batch once before capturing it")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s = torch.cuda.current_stream()
+            if grad is None:
+                self.contract(J, stream=s, z=z)
+            else:
+                self.contract_backward(J, stream=s, z=z, grad=grad)
+        return g
 
     def contract_backward(self, J=None, stream=None, z=None, grad=None):
         """Z and d log Z / d J of every knot (kn_batch_contract_backward);

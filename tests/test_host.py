@@ -336,3 +336,33 @@ def test_gradient_plan_options():
     pf = kn.Plan(t, 3, jones_only=False, simplify=1)
     assert pg.stats["n_steps"] == 3 * pf.stats["n_steps"]
     assert pg.stats["n_vertex_tensors"] == pf.stats["n_vertex_tensors"] + pf.stats["n_components"]
+
+
+def test_autotuner_coordinate_descent():
+    """The tuner's search on a known cost surface: it reaches the minimum of
+    a separable function and measures each setting once."""
+    from paper_1807_02119_amd import tune
+
+    calls = []
+
+    def cost(s):
+        calls.append(dict(s))
+        return (s["a"] - 3) ** 2 + abs(s["b"] - 20) + 0.5 * (s["c"] != "y")
+
+    space = {"a": [1, 2, 3, 4], "b": [10, 20, 30], "c": ["x", "y"]}
+    best, v, seen = tune.coordinate_descent(cost, space, {"a": 1, "b": 10, "c": "x"})
+    assert best == {"a": 3, "b": 20, "c": "y"} and v == 0
+    keys = [tuple(sorted(c.items())) for c in calls]
+    assert len(keys) == len(set(keys)) == len(seen)
+
+
+def test_tile_macs_option():
+    d = gen.lattice_knot((44, 0), 60, 160)
+    t = kn.Tait(d.pd)
+    a = image_model.Image(kn.Plan(t, 3, big_step_macs_log2=4, tile_macs_log2=3).image())
+    b = image_model.Image(kn.Plan(t, 3, big_step_macs_log2=4, tile_macs_log2=16).image())
+    tiles = lambda im: sum(int(s["n_tiles"]) for s in im.steps if int(s["mode"]) == 1)
+    assert tiles(a) > tiles(b) > 0
+    with pytest.raises(kn.KnError):
+        kn.Plan(t, 3, tile_macs_log2=31)
+    _check_model(d, 3, big_step_macs_log2=4, tile_macs_log2=3)
