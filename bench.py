@@ -55,6 +55,9 @@ def parse():
                     help="skip the one-knot-per-call comparison")
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's recorded setting (library defaults)")
+    ap.add_argument("--pmc-calibrate", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers (a plain copy of known "
+                         "size, to scale the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -98,6 +101,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.pmc_calibrate:
+        n = args.pmc_calibrate // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": 4 * n, "launches": 3}), flush=True)
+        return
     kn.lib()
     q = 3
     B = args.batch
