@@ -128,6 +128,18 @@ void kn_tait_free(kn_tait* g);
  *               (0 = default 16); tile_macs_log2: log2 of the multiply-adds a
  *               tile of outputs aims at when tile_outputs is 0 (0 = default
  *               15).  These are the knobs the autotuner searches.
+ * slice_log2_budget  0: no slicing.  Otherwise spins are fixed one at a time
+ *               (each time the spin held by most of the plan's largest
+ *               tensors) until the largest tensor has at most 2^budget
+ *               entries, 12 spins are fixed or one more would exceed 4096
+ *               slices.  The plan then covers q^k
+ *               slices, each the same network with those spins at fixed
+ *               values: an edge to a fixed spin becomes a diagonal factor on
+ *               its other end, an edge between two fixed spins a constant, and
+ *               Z is the sum of the slices' values (formed on the device).
+ *               Slices run as chains sharing one arena each, as many chains
+ *               as mem_budget_bytes (default 16 GiB of arena) allows.  Not
+ *               combinable with gradient.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -154,6 +166,7 @@ typedef struct {
   int32_t lds_bytes;
   int32_t gradient;
   int32_t tile_macs_log2;
+  int32_t slice_log2_budget;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).
@@ -181,6 +194,8 @@ typedef struct {
   int32_t n_tasks;
   int32_t n_components;
   int32_t max_rank;
+  int32_t n_slices;       /* q^(fixed spins); flops and bytes cover all slices */
+  int32_t slice_chains;   /* slices run as this many concurrent chains */
 } kn_plan_stats;
 
 /* Build a plan for q.  opts == NULL selects the defaults above (Jones-only,

@@ -64,12 +64,14 @@ struct DevProg {
   const int32_t* strides;
   const int8_t* eps;
   const int32_t* comps;
+  const int32_t* pins;
   int32_t* ctrl;
   int32_t* queue;
   int32_t* pending;
   TensorState* ts;
   Cx<double>* weights;  // x_e (n_edges) then x_m (n_medges)
   Cx<double>* mgrad;    // d log Z / d J per merged edge (gradient plans)
+  kn_scalar* zslice;    // result of every slice (sliced plans)
 };
 
 __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
@@ -89,12 +91,14 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.strides = reinterpret_cast<const int32_t*>(img + h.o_strides);
   p.eps = reinterpret_cast<const int8_t*>(img + h.o_eps);
   p.comps = reinterpret_cast<const int32_t*>(img + h.o_comps);
+  p.pins = reinterpret_cast<const int32_t*>(img + h.o_pins);
   p.ctrl = reinterpret_cast<int32_t*>(state);
   p.queue = reinterpret_cast<int32_t*>(state + h.o_queue);
   p.pending = reinterpret_cast<int32_t*>(state + h.o_pending);
   p.ts = reinterpret_cast<TensorState*>(state + h.o_tstate);
   p.weights = reinterpret_cast<Cx<double>*>(state + h.o_weights);
   p.mgrad = reinterpret_cast<Cx<double>*>(state + h.o_mgrad);
+  p.zslice = reinterpret_cast<kn_scalar*>(state + h.o_zslice);
   return p;
 }
 
@@ -200,8 +204,8 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
                            const double* J, const States& st) {
   const int tid = threadIdx.x;
   const ImgHeader& h = *p.h;
-  Cx<double>* xe = p.weights + kd.edge_off;
-  Cx<double>* xm = p.weights + h.n_edges + kd.medge_off;
+  Cx<double>* xe = p.weights + kd.w_off;
+  Cx<double>* xm = xe + kd.n_edges;
   // x_e = e^{J_e}, or the Jones coupling -t^{-eps_e} (Sec. II)
   const Cx<double> t{kd.t_re, kd.t_im};
   const double tn = t.re * t.re + t.im * t.im;
@@ -253,6 +257,14 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
           const int d = rem % q;
           rem /= q;
           if (d == a) prod = cmul(prod, xm[slot_me[j]]);
+        }
+        // slices: an edge to a fixed spin contributes x_m where this spin
+        // takes the fixed value (digit j of the slice number, base q)
+        for (int j = 0; j < vd.n_pins; ++j) {
+          const int32_t* pn = p.pins + 2 * (vd.pin_off + j);
+          int sv = kd.slice;
+          for (int r = 0; r < pn[1]; ++r) sv /= q;
+          if (sv % q == a) prod = cmul(prod, xm[pn[0]]);
         }
         acc.re += prod.re;
         acc.im += prod.im;
@@ -843,8 +855,8 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
                            kn_scalar* zout, const States& st) {
   if (threadIdx.x != 0) return;
   const ImgHeader& h = *p.h;
-  const Cx<double>* xe = p.weights + kd.edge_off;
-  const Cx<double>* xm = p.weights + h.n_edges + kd.medge_off;
+  const Cx<double>* xe = p.weights + kd.w_off;
+  const Cx<double>* xm = xe + kd.n_edges;
   Cx<double> z{1.0, 0.0};
   int64_t e = 0;
   for (int i = 0; i < kd.n_comps; ++i) {
@@ -860,6 +872,12 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
     const Factor f = p.factors[kd.factor_off + i];
     Cx<double> x = f.kind == FAC_LOOP ? xe[f.id] : xm[f.id];
     if (f.kind == FAC_LEAF) x.re += (double)(kd.q - 1);
+    if (f.kind == FAC_PAIR) {  // equal fixed values: x_m, else 1
+      int sa = kd.slice, sb = kd.slice;
+      for (int r = 0; r < f.a; ++r) sa /= kd.q;
+      for (int r = 0; r < f.b; ++r) sb /= kd.q;
+      if (sa % kd.q != sb % kd.q) x = Cx<double>{1.0, 0.0};
+    }
     acc_mul(z, e, x);
   }
   for (int i = 0; i < kd.n_iso; ++i) acc_mul(z, e, Cx<double>{(double)kd.q, 0.0});
@@ -872,7 +890,9 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
     out.im = z.im;
     out.exp2 = (z.re == 0.0 && z.im == 0.0) ? 0 : e;
   }
-  zout[kd.out_slot] = out;
+  // a slice's value goes to the slice array; sum_slices adds them up
+  if (kd.n_slices > 1) p.zslice[kd.out_slot] = out;
+  else zout[kd.out_slot] = out;
 }
 
 __device__ inline Cx<double> cdiv(Cx<double> a, Cx<double> b) {
@@ -896,7 +916,7 @@ template <class T>
 __device__ void knot_gradient(const DevProg& p, const KnotDesc& kd, const Cx<T>* arena,
                               double* grad) {
   const ImgHeader& h = *p.h;
-  const Cx<double>* xm = p.weights + h.n_edges + kd.medge_off;
+  const Cx<double>* xm = p.weights + kd.w_off + kd.n_edges;
   Cx<double>* mg = p.mgrad + kd.medge_off;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int q = kd.q;
@@ -1024,6 +1044,49 @@ __global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict
     ts[i].pad = 0;
     ts[i].exp2 = 0;
   }
+}
+
+// Z of a sliced plan = the sum of its slices' values: one thread per knot
+// descriptor, the first slice of each plan adds up the plan's slices (they
+// are consecutive), aligned to the largest exponent.
+__global__ void sum_slices(const uint8_t* __restrict__ img, uint8_t* __restrict__ state,
+                           kn_scalar* __restrict__ zout) {
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(img);
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= h.n_knots) return;
+  const KnotDesc* kds = reinterpret_cast<const KnotDesc*>(img + h.o_knots);
+  const KnotDesc kd = kds[i];
+  if (kd.n_slices <= 1 || kd.slice != 0) return;
+  const kn_scalar* zs = reinterpret_cast<const kn_scalar*>(state + h.o_zslice) + kd.out_slot;
+  int64_t emax = INT64_MIN;
+  bool bad = false;
+  for (int32_t j = 0; j < kd.n_slices; ++j) {
+    const kn_scalar z = zs[j];
+    if (!isfinite(z.re) || !isfinite(z.im)) bad = true;
+    if (z.re != 0.0 || z.im != 0.0) emax = max(emax, z.exp2);
+  }
+  kn_scalar out{0.0, 0.0, 0};
+  if (bad) {
+    out.re = out.im = __builtin_nan("");
+  } else if (emax != INT64_MIN) {
+    double re = 0.0, im = 0.0;
+    for (int32_t j = 0; j < kd.n_slices; ++j) {
+      const kn_scalar z = zs[j];
+      const int64_t d = z.exp2 - emax;  // <= 0
+      if (d < -1100) continue;
+      re += ldexp(z.re, (int)d);
+      im += ldexp(z.im, (int)d);
+    }
+    const double m = fmax(fabs(re), fabs(im));
+    if (m > 0.0) {
+      int s;
+      frexp(m, &s);
+      out.re = ldexp(re, -s);
+      out.im = ldexp(im, -s);
+      out.exp2 = emax + s;
+    }
+  }
+  zout[kd.plan_slot] = out;
 }
 
 // d log Z / d J of every knot of a gradient image: one workgroup per knot,
@@ -1212,6 +1275,11 @@ kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const d
   if (grad) {
     hipLaunchKernelGGL(gradient_kernel<T>, dim3(h.n_knots), dim3(kBlock), 0, st, ws,
                        ws + h.state_off, reinterpret_cast<Cx<T>*>(ws + h.arena_off), grad);
+    if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
+  }
+  if (h.sliced) {
+    hipLaunchKernelGGL(sum_slices, dim3((h.n_knots + 255) / 256), dim3(256), 0, st, ws,
+                       ws + h.state_off, z);
     if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
   }
   return KN_OK;

@@ -76,6 +76,8 @@ void make_section(PlanKnot& k) {
   d.n_iso = k.n_iso;
   d.n_steps = (int32_t)k.steps.size();
   d.grad = k.gradient ? 1 : 0;
+  d.n_slices = k.n_slices;
+  d.n_slice_spins = k.n_slice_spins;
   for (size_t m = 0; m + 1 < k.medge_off.size(); ++m) {
     S.md.push_back({(int32_t)S.members.size(), k.medge_off[m + 1] - k.medge_off[m]});
     for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) S.members.push_back(k.medge_mem[j]);
@@ -95,8 +97,13 @@ void make_section(PlanKnot& k) {
       group_strides(vs, k.tensors[v.adjoint].spins, q, S.strides);
     }
     S.vd.push_back({v.tensor, (int32_t)v.nbr.size(), (int32_t)S.vslot.size(),
-                    v.seed ? -1 : (v.keep_center ? 1 : 0), v.adjoint, v.comp, adj_str});
+                    v.seed ? -1 : (v.keep_center ? 1 : 0), v.adjoint, v.comp, adj_str,
+                    (int32_t)S.pins.size() / 2, v.pin_medge.size()});
     for (int32_t m : v.medge) S.vslot.push_back(m);
+    for (int32_t j = 0; j < v.pin_medge.size(); ++j) {
+      S.pins.push_back(v.pin_medge[j]);
+      S.pins.push_back(v.pin_slice[j]);
+    }
   }
   // steps + tables
   S.sd.reserve(k.steps.size());
@@ -274,47 +281,72 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   h.magic = kMagic;
   h.precision = knots.empty() ? 0 : knots[0]->precision;
 
-  // offsets of every knot's section in the concatenated arrays (prefix
-  // sums), then the sections are copied and relocated in parallel
-  struct Off {
-    size_t T, S, V, VS, M, MEM, F, TAB, E, C, TK, G;
+  // Every plan contributes n_slices units (knot descriptors), one per slice
+  // (one for an unsliced plan).  Arrays that do not depend on the slice
+  // (merged edges, members, factors, slot lists, pins, strides, Tait signs)
+  // are stored once per plan; tensors, steps, vertices, components, tasks,
+  // groups and weight slots once per unit.  The units of a plan run as
+  // slice_chains chains: unit c follows unit c - slice_chains, and the units
+  // of a chain share one arena region.  Offsets are prefix sums; the units are
+  // then written in parallel straight into the image.
+  struct PlanOff {
+    size_t VS, M, MEM, F, TAB, E, PIN, unit;
     int64_t arena;
   };
-  const size_t nK = knots.size();
-  std::vector<Off> off(nK + 1);
+  struct UnitOff {
+    size_t T, S, V, C, TK, G, W;
+  };
+  const size_t nP = knots.size();
+  std::vector<PlanOff> poff(nP + 1);
+  std::vector<UnitOff> uoff;
+  std::vector<std::pair<int32_t, int32_t>> unit_of;  // (plan, slice)
   int32_t lds_used = 0;
+  bool sliced = false;
   {
-    Off o{};
-    for (size_t ki = 0; ki < nK; ++ki) {
-      off[ki] = o;
+    PlanOff po{};
+    UnitOff uo{};
+    for (size_t ki = 0; ki < nP; ++ki) {
+      poff[ki] = po;
       const PlanKnot& k = *knots[ki];
       const Section& S = k.sec;
-      o.T += S.td.size();
-      o.S += S.sd.size();
-      o.V += S.vd.size();
-      o.VS += S.vslot.size();
-      o.M += S.md.size();
-      o.MEM += S.members.size();
-      o.F += S.fac.size();
-      o.TAB += S.strides.size();
-      o.E += k.eps.size();
-      o.C += S.comps.size();
-      o.TK += S.tasks.size();
-      o.G += S.groups.size();
-      o.arena += S.arena_elems;
+      po.VS += S.vslot.size();
+      po.M += S.md.size();
+      po.MEM += S.members.size();
+      po.F += S.fac.size();
+      po.TAB += S.strides.size();
+      po.E += k.eps.size();
+      po.PIN += S.pins.size() / 2;
+      po.unit += k.n_slices;
+      po.arena += S.arena_elems * std::max(1, k.slice_chains);
       lds_used = std::max(lds_used, S.lds_used);
+      sliced |= k.n_slices > 1;
+      for (int32_t c = 0; c < k.n_slices; ++c) {
+        uoff.push_back(uo);
+        unit_of.emplace_back((int32_t)ki, c);
+        uo.T += S.td.size();
+        uo.S += S.sd.size();
+        uo.V += S.vd.size();
+        uo.C += S.comps.size();
+        uo.TK += S.tasks.size();
+        uo.G += S.groups.size();
+        uo.W += k.eps.size() + S.md.size();
+      }
     }
-    off[nK] = o;
+    poff[nP] = po;
+    uoff.push_back(uo);
   }
-  const Off& tot = off[nK];
-  const size_t nT = tot.T, nS = tot.S, nV = tot.V, nVS = tot.VS, nM = tot.M, nMem = tot.MEM,
-               nF = tot.F, nTab = tot.TAB, nE = tot.E, nC = tot.C, nTask = tot.TK, nG = tot.G;
-  const int64_t arena = tot.arena;
+  const size_t nU = unit_of.size();
+  const UnitOff& ut = uoff[nU];
+  const PlanOff& pt = poff[nP];
+  const size_t nT = ut.T, nS = ut.S, nV = ut.V, nC = ut.C, nTask = ut.TK, nG = ut.G;
+  const size_t nVS = pt.VS, nM = pt.M, nMem = pt.MEM, nF = pt.F, nTab = pt.TAB, nE = pt.E,
+               nPin = pt.PIN;
+  const int64_t arena = pt.arena;
   // image layout: header, then each array 256-byte aligned; the buffer is
   // not zero-filled (every array is written in full below, the padding is
-  // cleared), and the knots' sections are written straight into it
+  // cleared)
   h.n_tasks = (int32_t)nTask;
-  h.n_knots = (int32_t)nK;
+  h.n_knots = (int32_t)nU;
   h.n_tensors = (int32_t)nT;
   h.n_steps = (int32_t)nS;
   h.n_vtx = (int32_t)nV;
@@ -324,7 +356,10 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   h.n_strides = (int32_t)nTab;
   h.n_groups = (int32_t)nG;
   h.n_edges = (int32_t)nE;
-  h.n_roots = (int32_t)nK;
+  h.n_pins = (int32_t)nPin;
+  h.n_wslots = (int32_t)ut.W;
+  h.n_outputs = (int32_t)nP;
+  h.sliced = sliced ? 1 : 0;
   h.lds_bytes = (lds_used + 255) / 256 * 256;
   std::vector<std::pair<int64_t, int64_t>> used;  // (offset, bytes) of each array
   int64_t top = sizeof(ImgHeader);
@@ -336,8 +371,7 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   };
   h.o_tasks = reserve(nTask, sizeof(TaskDesc));
   h.o_groups = reserve(nG, sizeof(GroupDesc));
-  h.o_roots = reserve(nK, sizeof(int32_t));
-  h.o_knots = reserve(nK, sizeof(KnotDesc));
+  h.o_knots = reserve(nU, sizeof(KnotDesc));
   h.o_tensors = reserve(nT, sizeof(TensorDesc));
   h.o_steps = reserve(nS, sizeof(StepDesc));
   h.o_vtx = reserve(nV, sizeof(VtxDesc));
@@ -348,6 +382,13 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   h.o_strides = reserve(nTab, sizeof(int32_t));
   h.o_eps = reserve(nE, sizeof(int8_t));
   h.o_comps = reserve(nC, sizeof(int32_t));
+  h.o_pins = reserve(2 * nPin, sizeof(int32_t));
+  // roots last: their count is known once the chains are laid out
+  size_t n_roots = 0;
+  for (size_t ki = 0; ki < nP; ++ki)
+    n_roots += (size_t)std::min(knots[ki]->n_slices, std::max(1, knots[ki]->slice_chains));
+  h.n_roots = (int32_t)n_roots;
+  h.o_roots = reserve(n_roots, sizeof(int32_t));
   h.image_bytes = align256(top);
   Bytes img((size_t)h.image_bytes);
   uint8_t* base = img.data();
@@ -371,43 +412,63 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   int32_t* strides = arr(h.o_strides, (int32_t*)nullptr);
   int8_t* eps = arr(h.o_eps, (int8_t*)nullptr);
   int32_t* comps = arr(h.o_comps, (int32_t*)nullptr);
+  int32_t* pins = arr(h.o_pins, (int32_t*)nullptr);
   TaskDesc* tasks = arr(h.o_tasks, (TaskDesc*)nullptr);
   GroupDesc* groups = arr(h.o_groups, (GroupDesc*)nullptr);
-  std::vector<std::pair<double, int32_t>> roots(nK);  // (-estimated chain time, root task)
+  // (-estimated chain time, root task) of the first unit of every chain
+  std::vector<std::pair<double, int32_t>> roots(nU, {0.0, -1});
 
-  auto place = [&](size_t ki) {
-    const PlanKnot& k = *knots[ki];
+  auto place = [&](size_t ui) {
+    const auto [pk, slice] = unit_of[ui];
+    const PlanKnot& k = *knots[pk];
     const Section& S = k.sec;
-    const Off& o = off[ki];
-    const size_t T0 = o.T, S0 = o.S, V0 = o.V, VS0 = o.VS, M0 = o.M, MEM0 = o.MEM, F0 = o.F,
-                 TAB0 = o.TAB, E0 = o.E, C0 = o.C, TK0 = o.TK, G0 = o.G;
-    const int64_t arena0 = o.arena;
+    const PlanOff& o = poff[pk];
+    const UnitOff& u = uoff[ui];
+    const int32_t chains = std::max(1, k.slice_chains);
+    const int64_t arena0 = o.arena + S.arena_elems * (slice % chains);
+    const size_t TAB0 = o.TAB, VS0 = o.VS, MEM0 = o.MEM, PIN0 = o.PIN;
+    if (slice == 0) {  // per-plan arrays
+      std::copy(S.vslot.begin(), S.vslot.end(), vslot + VS0);
+      for (size_t i = 0; i < S.md.size(); ++i) {
+        MEdge m = S.md[i];
+        m.member_off += (int32_t)MEM0;
+        md[o.M + i] = m;
+      }
+      std::copy(S.members.begin(), S.members.end(), members + MEM0);
+      std::copy(S.fac.begin(), S.fac.end(), fac + o.F);
+      std::copy(S.strides.begin(), S.strides.end(), strides + TAB0);
+      std::copy(k.eps.begin(), k.eps.end(), eps + o.E);
+      std::copy(S.pins.begin(), S.pins.end(), pins + 2 * PIN0);
+    }
     KnotDesc x = S.kd;
-    x.edge_off = (int32_t)E0;
-    x.medge_off = (int32_t)M0;
-    x.vtx_off = (int32_t)V0;
-    x.factor_off = (int32_t)F0;
-    x.comp_off = (int32_t)C0;
-    x.out_slot = (int32_t)ki;
-    x.step_off = (int32_t)S0;
-    kd[ki] = x;
-    const int32_t t0 = (int32_t)T0, s0 = (int32_t)S0, g0 = (int32_t)G0, tk0 = (int32_t)TK0;
+    x.edge_off = (int32_t)o.E;
+    x.medge_off = (int32_t)o.M;
+    x.vtx_off = (int32_t)u.V;
+    x.factor_off = (int32_t)o.F;
+    x.comp_off = (int32_t)u.C;
+    x.step_off = (int32_t)u.S;
+    x.slice = slice;
+    x.plan_slot = (int32_t)pk;
+    x.out_slot = k.n_slices > 1 ? (int32_t)ui : (int32_t)pk;
+    x.w_off = (int32_t)u.W;
+    kd[ui] = x;
+    const int32_t t0 = (int32_t)u.T, s0 = (int32_t)u.S, g0 = (int32_t)u.G, tk0 = (int32_t)u.TK;
     for (size_t i = 0; i < S.td.size(); ++i) {
       TensorDesc t = S.td[i];
       t.off += arena0;
-      td[T0 + i] = t;
+      td[t0 + i] = t;
     }
     for (size_t i = 0; i < S.sd.size(); ++i) {
-      StepDesc s = S.sd[i];
-      s.a += t0;
-      s.b += t0;
-      s.c += t0;
-      s.str += (int32_t)TAB0;
-      if (s.home_a >= 0) s.home_a += (int32_t)arena0;
-      if (s.home_b >= 0) s.home_b += (int32_t)arena0;
-      if (s.home_c >= 0) s.home_c += (int32_t)arena0;
-      if (s.partial >= 0) s.partial += (int32_t)arena0;
-      sd[S0 + i] = s;
+      StepDesc st = S.sd[i];
+      st.a += t0;
+      st.b += t0;
+      st.c += t0;
+      st.str += (int32_t)TAB0;
+      if (st.home_a >= 0) st.home_a += (int32_t)arena0;
+      if (st.home_b >= 0) st.home_b += (int32_t)arena0;
+      if (st.home_c >= 0) st.home_c += (int32_t)arena0;
+      if (st.partial >= 0) st.partial += (int32_t)arena0;
+      sd[s0 + i] = st;
     }
     for (size_t i = 0; i < S.vd.size(); ++i) {
       VtxDesc v = S.vd[i];
@@ -417,59 +478,67 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
         v.adj_str += (int32_t)TAB0;
       }
       v.slot_off += (int32_t)VS0;
-      vd[V0 + i] = v;
+      v.pin_off += (int32_t)PIN0;
+      vd[u.V + i] = v;
     }
-    std::copy(S.vslot.begin(), S.vslot.end(), vslot + VS0);
-    for (size_t i = 0; i < S.md.size(); ++i) {
-      MEdge m = S.md[i];
-      m.member_off += (int32_t)MEM0;
-      md[M0 + i] = m;
-    }
-    std::copy(S.members.begin(), S.members.end(), members + MEM0);
-    std::copy(S.fac.begin(), S.fac.end(), fac + F0);
-    std::copy(S.strides.begin(), S.strides.end(), strides + TAB0);
-    std::copy(k.eps.begin(), k.eps.end(), eps + E0);
-    for (size_t i = 0; i < S.comps.size(); ++i) comps[C0 + i] = S.comps[i] + t0;
+    for (size_t i = 0; i < S.comps.size(); ++i) comps[u.C + i] = S.comps[i] + t0;
     for (size_t i = 0; i < S.tasks.size(); ++i) {
       TaskDesc t = S.tasks[i];
-      t.knot = (int32_t)ki;
+      t.knot = (int32_t)ui;
       t.group += g0;
       t.first += s0;
       t.state_lo += t0;
-      tasks[TK0 + i] = t;
+      tasks[tk0 + i] = t;
     }
-    for (size_t i = 0; i < S.groups.size(); ++i) {
+    const size_t ng = S.groups.size();
+    for (size_t i = 0; i < ng; ++i) {
       GroupDesc g = S.groups[i];
-      g.knot = (int32_t)ki;
+      g.knot = (int32_t)ui;
       g.first_task += tk0;
       if (g.next >= 0) g.next += g0;
-      groups[G0 + i] = g;
+      groups[g0 + i] = g;
     }
-    roots[ki] = {-S.est, tk0 + S.groups[0].first_task};
+    // chains: the last group of this unit releases the first group of the
+    // unit `chains` slices later, which waits for it
+    if (slice + chains < k.n_slices) {
+      const UnitOff& nxt = uoff[ui + chains];
+      groups[g0 + ng - 1].next = (int32_t)nxt.G;
+    }
+    if (slice >= chains) groups[g0].n_pred = S.groups.back().n_tasks;
+    if (slice < chains) {
+      const double per_chain = (double)((k.n_slices - slice + chains - 1) / chains);
+      roots[ui] = {-S.est * per_chain, tk0 + S.groups[0].first_task};
+    }
   };
-  // a few knots per thread; small batches are laid out on the calling thread
-  const size_t nth = std::min<size_t>(std::max<size_t>(1, nK / 16),
+  // a few units per thread; small images are laid out on the calling thread
+  const size_t nth = std::min<size_t>(std::max<size_t>(1, nU / 16),
                                       std::max(1u, std::thread::hardware_concurrency()));
   if (nth <= 1) {
-    for (size_t ki = 0; ki < nK; ++ki) place(ki);
+    for (size_t ui = 0; ui < nU; ++ui) place(ui);
   } else {
     std::atomic<size_t> next{0};
     auto worker = [&] {
-      for (size_t ki; (ki = next.fetch_add(1)) < nK;) place(ki);
+      for (size_t ui; (ui = next.fetch_add(1)) < nU;) place(ui);
     };
     std::vector<std::thread> pool;
     for (size_t t = 1; t < std::min<size_t>(nth, 16); ++t) pool.emplace_back(worker);
     worker();
     for (auto& th : pool) th.join();
   }
-  std::stable_sort(roots.begin(), roots.end(),
-                   [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
-                     return a.first < b.first;
-                   });
-  int32_t* root_tasks = arr(h.o_roots, (int32_t*)nullptr);
-  for (size_t i = 0; i < roots.size(); ++i) root_tasks[i] = roots[i].second;
+  {
+    std::vector<std::pair<double, int32_t>> rs;
+    rs.reserve(n_roots);
+    for (auto& r : roots)
+      if (r.second >= 0) rs.push_back(r);
+    std::stable_sort(rs.begin(), rs.end(),
+                     [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                       return a.first < b.first;
+                     });
+    int32_t* root_tasks = arr(h.o_roots, (int32_t*)nullptr);
+    for (size_t i = 0; i < rs.size(); ++i) root_tasks[i] = rs[i].second;
+  }
   // runtime state: control words, ready queue, pending counters, tensor
-  // states, weights
+  // states, weights, gradients, slice results
   h.state_off = h.image_bytes;
   int64_t st = CTRL_WORDS * 4;
   h.o_queue = st;
@@ -479,9 +548,11 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   h.o_tstate = st;
   st = align256(st + (int64_t)nT * (int64_t)sizeof(TensorState));
   h.o_weights = st;
-  st = align256(st + 16 * (int64_t)(nE + nM));
+  st = align256(st + 16 * (int64_t)ut.W);
   h.o_mgrad = st;
   st = align256(st + 16 * (int64_t)nM);
+  h.o_zslice = st;
+  st = align256(st + (int64_t)sizeof(kn_scalar) * (int64_t)nU);
   h.state_bytes = st;
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);

@@ -131,6 +131,7 @@ struct Section {
   std::vector<Factor> fac;          // ids knot-local (stay local)
   std::vector<int32_t> strides;     // spin-group strides of every step
   std::vector<int32_t> comps;       // knot-local tensor ids
+  std::vector<int32_t> pins;        // (merged edge, sliced spin) pairs of the vertices
   std::vector<TaskDesc> tasks;      // group, first, state_lo knot-local
   std::vector<GroupDesc> groups;    // first_task, next knot-local
   double est = 0;                   // estimated chain time (start priority)
@@ -172,6 +173,7 @@ struct PVertex {
   int32_t comp = 0;             // gradient plans: component index
   SpinList nbr;                 // neighbour spins, slot order
   SpinList medge;               // merged edge per slot (knot-local)
+  SpinList pin_medge, pin_slice;  // slices: edges to sliced spins (merged edge, sliced spin)
 };
 
 // Everything about one knot's contraction, in knot-local ids.
@@ -181,6 +183,9 @@ struct PlanKnot {
   int32_t precision = 0;
   bool jones_only = true;
   bool gradient = false;                        // reverse pass appended
+  int32_t n_slice_spins = 0;                    // spins fixed by slicing
+  int32_t n_slices = 1;                         // q^n_slice_spins slices
+  int32_t slice_chains = 1;                     // slices run as this many chains
   int32_t n_edges = 0;                          // original Tait edges
   std::vector<int8_t> eps;                      // original Tait signs
   // merged edge m: original edges medge_mem[medge_off[m] .. medge_off[m + 1])

@@ -51,6 +51,9 @@ constexpr double kSplitBelow = 256;
 // this many flops (below it the greedy plan rarely wins and planning time
 // matters more).
 constexpr double kAutoGreedyFrom = 1e8;
+// Slicing fixes at most this many spins, and makes at most kMaxSlices slices.
+constexpr int32_t kMaxSliceSpins = 12;
+constexpr double kMaxSlices = 4096;  // each slice is a copy of the knot's descriptors
 
 namespace {
 
@@ -673,51 +676,43 @@ void level_schedule(PlanKnot& k, int32_t n_vt) {
   k.tensors = std::move(tensors);
 }
 
-// Build tensors, order and arena for one knot.  Returns KN_OK or an error.
-kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
-                    kn_plan_stats& st) {
-  k.q = q;
-  k.precision = o.precision;
-  k.jones_only = o.jones_only != 0;
-  k.gradient = o.gradient != 0;
-  k.n_edges = (int32_t)g.eps.size();
-  k.eps = g.eps;
-  k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
-  k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
-  k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
-  {
-    double qq = q;
-    if (q < 4) {
-      k.t_re = (qq - 2.0) / 2.0;
-      k.t_im = std::sqrt(qq * (4.0 - qq)) / 2.0;
-    } else {
-      k.t_re = (qq - 2.0 + std::sqrt(qq * (qq - 4.0))) / 2.0;
-      k.t_im = 0.0;
-    }
-  }
-  Simplified s = simplify(g, o.simplify, k.jones_only, k);
-  const int32_t n = s.n_spins;
-  st.n_edges_simplified = (int32_t)s.e.size();
-  st.n_vertices_simplified = n;
-  st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
+// The graph whose tensor network is contracted: spins 0..n-1, edges (u, v)
+// carrying merged edges, and per spin its pins (merged edge to a sliced spin,
+// index of that sliced spin), in compressed rows.
+struct NetGraph {
+  int32_t n = 0;
+  std::vector<std::pair<int32_t, int32_t>> e;
+  std::vector<int32_t> e_medge;
+  std::vector<int32_t> pin_off{0};
+  std::vector<std::pair<int32_t, int32_t>> pins;
+};
 
+// Absorption of the edge matrices into vertex tensors and the pairwise order
+// (Sec. III): fills k.vtx, k.tensors, k.steps, k.comps; n_vt = vertex tensors.
+kn_status build_network(const NetGraph& G, int32_t q, const kn_plan_opts& o, PlanKnot& k,
+                        int32_t& n_vt) {
+  const int32_t n = G.n;
+  k.vtx.clear();
+  k.tensors.clear();
+  k.steps.clear();
+  k.comps.clear();
   // ---- absorption: orient edges by a minimum-degree elimination order
   // adjacency (neighbour, merged edge) in compressed rows
-  const int32_t ne2 = 2 * (int32_t)s.e.size();
+  const int32_t ne2 = 2 * (int32_t)G.e.size();
   std::vector<int32_t> aoff(n + 1, 0), anb(ne2), amd(ne2);
-  for (auto [u, v] : s.e) {
+  for (auto [u, v] : G.e) {
     aoff[u + 1]++;
     aoff[v + 1]++;
   }
   for (int32_t v = 0; v < n; ++v) aoff[v + 1] += aoff[v];
   {
     std::vector<int32_t> fp(aoff.begin(), aoff.end() - 1);
-    for (size_t i = 0; i < s.e.size(); ++i) {
-      auto [u, v] = s.e[i];
+    for (size_t i = 0; i < G.e.size(); ++i) {
+      auto [u, v] = G.e[i];
       anb[fp[u]] = v;
-      amd[fp[u]++] = s.e_medge[i];
+      amd[fp[u]++] = G.e_medge[i];
       anb[fp[v]] = u;
-      amd[fp[v]++] = s.e_medge[i];
+      amd[fp[v]++] = G.e_medge[i];
     }
   }
   std::vector<int32_t> deg(n), pos(n, -1);
@@ -763,7 +758,8 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.tensors.reserve(2 * n + 1);
   for (int32_t v = 0; v < n; ++v) {
     const bool none = ooff[v + 1] == ooff[v];
-    bool has = !none;
+    const bool pinned = G.pin_off[v + 1] > G.pin_off[v];
+    bool has = !none || pinned;  // pins multiply the vertex's own tensor
     if (!has && holders[v] == 1) has = true;  // lone holder elsewhere: add [v] of ones
     if (!has) continue;
     if (ooff[v + 1] - ooff[v] > 7) return KN_E_UNSUPPORTED;  // planar graphs give <= 5
@@ -779,10 +775,14 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       pv.medge.push_back(outs[j].second);
       t.spins.push_back(outs[j].first);
     }
+    for (int32_t j = G.pin_off[v]; j < G.pin_off[v + 1]; ++j) {
+      pv.pin_medge.push_back(G.pins[j].first);
+      pv.pin_slice.push_back(G.pins[j].second);
+    }
     k.vtx.push_back(std::move(pv));
     k.tensors.push_back(std::move(t));
   }
-  int32_t n_vt = (int32_t)k.tensors.size();
+  n_vt = (int32_t)k.tensors.size();
 
   // ---- pairwise contraction order
   {
@@ -818,6 +818,107 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
         if (!k.tensors[t].spins.empty()) return KN_E_INVALID;  // guard
         k.comps.push_back(t);
       }
+  }
+  return KN_OK;
+}
+
+// The simplified graph with the spins of `sliced` (simplified ids) fixed:
+// they leave the network, each edge to one of them becomes a pin of its other
+// end, and edges between two of them become pair factors (in `pairs`).
+// new_id maps simplified ids to the sliced graph's spins (-1 for sliced).
+NetGraph sliced_graph(const Simplified& s, const std::vector<int32_t>& sliced,
+                      std::vector<int32_t>& new_id, std::vector<Factor>& pairs) {
+  NetGraph G;
+  std::vector<int32_t> slice_of(s.n_spins, -1);
+  for (size_t j = 0; j < sliced.size(); ++j) slice_of[sliced[j]] = (int32_t)j;
+  new_id.assign(s.n_spins, -1);
+  for (int32_t v = 0; v < s.n_spins; ++v)
+    if (slice_of[v] < 0) new_id[v] = G.n++;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> pin(G.n);
+  pairs.clear();
+  for (size_t i = 0; i < s.e.size(); ++i) {
+    const auto [u, v] = s.e[i];
+    const int32_t m = s.e_medge[i];
+    const int32_t su = slice_of[u], sv = slice_of[v];
+    if (su < 0 && sv < 0) {
+      G.e.emplace_back(new_id[u], new_id[v]);
+      G.e_medge.push_back(m);
+    } else if (su >= 0 && sv >= 0) {
+      pairs.push_back(Factor{FAC_PAIR, m, su, sv});
+    } else if (su >= 0) {
+      pin[new_id[v]].emplace_back(m, su);
+    } else {
+      pin[new_id[u]].emplace_back(m, sv);
+    }
+  }
+  for (int32_t v = 0; v < G.n; ++v) {
+    for (auto& pp : pin[v]) G.pins.push_back(pp);
+    G.pin_off.push_back((int32_t)G.pins.size());
+  }
+  return G;
+}
+
+// Build tensors, order and arena for one knot.  Returns KN_OK or an error.
+kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
+                    kn_plan_stats& st) {
+  k.q = q;
+  k.precision = o.precision;
+  k.jones_only = o.jones_only != 0;
+  k.gradient = o.gradient != 0;
+  k.n_edges = (int32_t)g.eps.size();
+  k.eps = g.eps;
+  k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
+  k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
+  k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
+  {
+    double qq = q;
+    if (q < 4) {
+      k.t_re = (qq - 2.0) / 2.0;
+      k.t_im = std::sqrt(qq * (4.0 - qq)) / 2.0;
+    } else {
+      k.t_re = (qq - 2.0 + std::sqrt(qq * (qq - 4.0))) / 2.0;
+      k.t_im = 0.0;
+    }
+  }
+  Simplified s = simplify(g, o.simplify, k.jones_only, k);
+  const int32_t n = s.n_spins;
+  st.n_edges_simplified = (int32_t)s.e.size();
+  st.n_vertices_simplified = n;
+  st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
+
+  // ---- slicing (optional), then absorption and order of the network
+  int32_t n_vt = 0;
+  {
+    std::vector<int32_t> sliced, new_id;
+    std::vector<Factor> pairs;
+    const double lq = std::log2((double)q);
+    for (;;) {
+      NetGraph G = sliced_graph(s, sliced, new_id, pairs);
+      kn_status rc = build_network(G, q, o, k, n_vt);
+      if (rc != KN_OK) return rc;
+      if (o.slice_log2_budget <= 0) break;
+      int32_t maxr = 0;
+      for (const auto& t : k.tensors) maxr = std::max(maxr, (int32_t)t.spins.size());
+      double slices = 1;
+      for (size_t j = 0; j <= sliced.size(); ++j) slices *= q;  // after one more spin
+      if (maxr * lq <= o.slice_log2_budget || (int32_t)sliced.size() >= kMaxSliceSpins ||
+          slices > kMaxSlices || G.n == 0)
+        break;
+      // fix the spin held by most of the largest tensors (ties: lowest id)
+      std::vector<int32_t> hits(G.n, 0);
+      for (const auto& t : k.tensors)
+        if ((int32_t)t.spins.size() >= maxr - 1)
+          for (int32_t x : t.spins) hits[x]++;
+      int32_t best = 0;
+      for (int32_t v = 1; v < G.n; ++v)
+        if (hits[v] > hits[best]) best = v;
+      for (int32_t v = 0; v < s.n_spins; ++v)
+        if (new_id[v] == best) sliced.push_back(v);
+    }
+    k.n_slice_spins = (int32_t)sliced.size();
+    k.n_slices = 1;
+    for (size_t j = 0; j < sliced.size(); ++j) k.n_slices *= q;
+    for (const Factor& f : pairs) k.factors.push_back(f);
   }
   st.n_components = (int32_t)k.comps.size();
   if (k.gradient) add_reverse(k, n_vt);
@@ -929,6 +1030,18 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     }
     k.arena_elems = std::max<int64_t>(fa.top, 16);
   }
+  // slices: work and traffic of all slices; chains share arenas within the
+  // memory budget (16 GiB of arena by default)
+  st.n_slices = k.n_slices;
+  st.flops *= k.n_slices;
+  st.bytes *= k.n_slices;
+  {
+    const double budget = o.mem_budget_bytes ? (double)o.mem_budget_bytes : 16.0 * (1 << 30);
+    const double per = (double)k.arena_elems * (double)es;
+    const double fit = std::floor(budget / std::max(per, 1.0));
+    k.slice_chains = (int32_t)std::max(1.0, std::min({(double)k.n_slices, fit, 64.0}));
+    st.slice_chains = k.slice_chains;
+  }
   return KN_OK;
 }
 
@@ -948,6 +1061,7 @@ static kn_plan_opts default_opts() {
   o.lds_bytes = 0;
   o.gradient = 0;
   o.tile_macs_log2 = 0;
+  o.slice_log2_budget = 0;
   return o;
 }
 
@@ -966,6 +1080,8 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
   if (o.gradient != 0 && o.gradient != 1) return KN_E_INVALID;
   if (o.gradient && (o.simplify & 2)) return KN_E_INVALID;
+  if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
+  if (o.gradient && o.slice_log2_budget) return KN_E_UNSUPPORTED;
   kn_plan* p = new (std::nothrow) kn_plan();
   if (!p) return KN_E_NOMEM;
   kn_status rc;

@@ -51,6 +51,8 @@ enum TaskFlags : int32_t { TF_SETUP = 1, TF_FINAL = 2 };
 enum FactorKind : int32_t {
   FAC_LOOP = 0,  // loop edge e: factor x_e (original edge id)
   FAC_LEAF = 1,  // degree-1 vertex on merged edge m: factor x_m + q - 1
+  FAC_PAIR = 2,  // merged edge m between sliced spins a and b: x_m if their
+                 // fixed values are equal, else 1
 };
 
 struct ImgHeader {
@@ -59,12 +61,15 @@ struct ImgHeader {
   int32_t n_tasks, n_knots, n_tensors, n_steps;
   int32_t n_vtx, n_medges, n_members, n_factors;
   int32_t n_strides, n_groups;
-  int32_t n_edges;    // original edges over all knots
+  int32_t n_edges;    // original edges over all knots (couplings J, gradients)
   int32_t n_roots;    // first groups of the knots, in start-priority order
   int32_t lds_bytes;  // per-workgroup LDS arena for serial tasks (bytes)
-  int32_t pad0;
+  int32_t n_pins;
+  int32_t n_wslots;   // complex weight slots over all knots (x_e then x_m per knot)
+  int32_t n_outputs;  // entries of the output scalar array
+  int32_t sliced;     // 1: some knots are slices; their sums are formed after the launch
   int64_t o_tasks, o_groups, o_roots, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
-  int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps;
+  int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps, o_pins;
   int64_t image_bytes;
   // runtime state (relative to the workspace base)
   int64_t state_off, state_bytes;
@@ -73,6 +78,7 @@ struct ImgHeader {
   int64_t o_tstate;   // TensorState[n_tensors]
   int64_t o_weights;  // complex128 x_e per original edge, then x_m per merged edge
   int64_t o_mgrad;    // complex128 d log Z / d J per merged edge (gradient plans)
+  int64_t o_zslice;   // kn_scalar per knot: the result of each slice
   // tensor arena (relative to the workspace base), in complex entries
   int64_t arena_off, arena_elems;
   int64_t workspace_bytes;
@@ -108,6 +114,13 @@ struct KnotDesc {
   int32_t step_off, n_steps;
   int32_t grad;  // 1: the steps include the reverse pass; the final task
                  // writes d log Z / d J_e for every original edge
+  // Slicing: the network of one plan with n_slice_spins spins fixed; this knot
+  // is slice number `slice` (digit j in base q = the value of sliced spin j)
+  // of n_slices.  Its Z goes to the slice array (out_slot indexes it) and the
+  // sum over slices to output plan_slot.  n_slices == 1: not sliced.
+  int32_t slice, n_slices, n_slice_spins, plan_slot;
+  int32_t w_off;  // this knot's weight slots: x_e at w_off, x_m at w_off + n_edges
+  int32_t pad;
 };
 
 struct TensorDesc {
@@ -153,6 +166,9 @@ struct VtxDesc {
   int32_t adj_str;     // gradient plans: offset into the stride table of the
                        // element strides, in the adjoint's storage, of the
                        // kept centre (if any) and then of each slot's spin
+  int32_t pin_off, n_pins;  // slices: pins (merged edge, sliced spin) of the
+                            // vertex's own spin, a factor x_m where it equals
+                            // the sliced spin's value
 };
 
 struct MEdge {
@@ -161,6 +177,7 @@ struct MEdge {
 
 struct Factor {
   int32_t kind, id;
+  int32_t a, b;  // FAC_PAIR: the two sliced spins (indices into the slice digits)
 };
 
 // Per-tensor runtime state.

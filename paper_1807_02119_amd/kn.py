@@ -35,7 +35,7 @@ class PlanOpts(ctypes.Structure):
                 ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
                 ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32),
-                ("tile_macs_log2", ctypes.c_int32)]
+                ("tile_macs_log2", ctypes.c_int32), ("slice_log2_budget", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -45,7 +45,8 @@ class PlanStats(ctypes.Structure):
                 ("image_bytes", ctypes.c_uint64), ("delta_h_paper", ctypes.c_int32),
                 ("n_edges_simplified", ctypes.c_int32), ("n_vertices_simplified", ctypes.c_int32),
                 ("n_tasks", ctypes.c_int32), ("n_components", ctypes.c_int32),
-                ("max_rank", ctypes.c_int32)]
+                ("max_rank", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+                ("slice_chains", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -188,13 +189,13 @@ class Plan:
     def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
                  paper_stats=False, lds_bytes=0, gradient=False, tile_macs_log2=0,
-                 allow_budget=False):
+                 slice_log2_budget=0, allow_budget=False):
         L = lib()
         if simplify is None:
             simplify = 1 if (gradient or not jones_only) else 3
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
                      tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
-                     1 if gradient else 0, tile_macs_log2)
+                     1 if gradient else 0, tile_macs_log2, slice_log2_budget)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -265,7 +266,7 @@ def _wrap_plan(h, tait, q, opts):
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
               tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-              tile_macs_log2=0):
+              tile_macs_log2=0, slice_log2_budget=0):
     """Tait graphs and plans for many knots on the library's host thread pool
     (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
     L = lib()
@@ -277,7 +278,8 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
     if simplify is None:
         simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
-                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2)
+                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
+                 slice_log2_budget)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)

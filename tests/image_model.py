@@ -21,13 +21,16 @@ HDR = np.dtype([
     ("magic", "<i4"), ("precision", "<i4"), ("n_tasks", "<i4"), ("n_knots", "<i4"),
     ("n_tensors", "<i4"), ("n_steps", "<i4"), ("n_vtx", "<i4"), ("n_medges", "<i4"),
     ("n_members", "<i4"), ("n_factors", "<i4"), ("n_strides", "<i4"), ("n_groups", "<i4"),
-    ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("pad0", "<i4"),
+    ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("n_pins", "<i4"),
+    ("n_wslots", "<i4"), ("n_outputs", "<i4"), ("sliced", "<i4"),
     ("o_tasks", "<i8"), ("o_groups", "<i8"), ("o_roots", "<i8"), ("o_knots", "<i8"),
     ("o_tensors", "<i8"), ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"),
     ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_strides", "<i8"),
-    ("o_eps", "<i8"), ("o_comps", "<i8"), ("image_bytes", "<i8"), ("state_off", "<i8"),
+    ("o_eps", "<i8"), ("o_comps", "<i8"), ("o_pins", "<i8"), ("image_bytes", "<i8"),
+    ("state_off", "<i8"),
     ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
-    ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("arena_off", "<i8"), ("arena_elems", "<i8"),
+    ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("o_zslice", "<i8"), ("arena_off", "<i8"),
+    ("arena_elems", "<i8"),
     ("workspace_bytes", "<i8")], align=True)
 TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "group", "first", "count", "flags",
                                       "state_lo", "state_len")], align=True)
@@ -35,16 +38,17 @@ GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", 
                  align=True)
 KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
-    "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps", "grad")],
-    align=True)
+    "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps", "grad",
+    "slice", "n_slices", "n_slice_spins", "plan_slot", "w_off", "pad")], align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
                                       "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
                                       "n_mb", "n_nb", "n_ks", "kseg", "partial", "lvl")],
                 align=True)
 VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_center", "adjoint",
-                                    "comp", "adj_str")], align=True)
+                                    "comp", "adj_str", "pin_off", "n_pins")], align=True)
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
+FACTOR = np.dtype([("x", "<i4"), ("y", "<i4"), ("a", "<i4"), ("b", "<i4")], align=True)
 TAB_CAP = 3072
 STEP_SERIAL, STEP_TILES, STEP_GEMM = 0, 1, 2
 GEMM_BLOCK = 32
@@ -60,6 +64,9 @@ class Image:
         assert h["magic"] == 0x4B4E4732
 
         def arr(dt, off, n):
+            if int(n) == 0:
+                return np.zeros(0, dt)
+            assert int(off) + int(n) * np.dtype(dt).itemsize <= len(raw), "array past the image"
             return np.frombuffer(raw, dt, int(n), int(off))
 
         self.tasks = arr(TASK, h["o_tasks"], h["n_tasks"])
@@ -69,11 +76,13 @@ class Image:
         self.tensors = arr(TENSOR, h["o_tensors"], h["n_tensors"])
         self.steps = arr(STEP, h["o_steps"], h["n_steps"])
         self.vtx = arr(VTX, h["o_vtx"], h["n_vtx"])
-        n_vslot = int(sum(int(v["n_slots"]) for v in self.vtx))
+        # slot lists are shared by the slices of a plan: the furthest slot used
+        n_vslot = max([int(v["slot_off"]) + int(v["n_slots"]) for v in self.vtx] + [0])
         self.vslot = arr("<i4", h["o_vslot"], n_vslot)
         self.medges = arr(PAIR, h["o_medges"], h["n_medges"])
         self.members = arr("<i4", h["o_members"], h["n_members"])
-        self.factors = arr(PAIR, h["o_factors"], h["n_factors"])
+        self.factors = arr(FACTOR, h["o_factors"], h["n_factors"])
+        self.pins = arr(PAIR, h["o_pins"], h["n_pins"])
         self.strides = arr("<i4", h["o_strides"], h["n_strides"])
         self.eps = arr("<i1", h["o_eps"], h["n_edges"])
         n_comps = int(sum(int(k["n_comps"]) for k in self.knots))
@@ -93,8 +102,9 @@ def run(raw: bytes, J=None, want_grad=False):
     shift = [None] * nt
     exp2 = [0] * nt
     finished = np.zeros(nt, bool)   # producer finished (visible to later groups)
-    weights = np.zeros(int(h["n_edges"]) + int(h["n_medges"]), np.complex128)
-    out = [None] * int(h["n_knots"])
+    weights = np.zeros(int(h["n_wslots"]), np.complex128)
+    out = [None] * int(h["n_outputs"])
+    zslice = {}
     grads = np.full(int(h["n_edges"]), np.nan, np.complex128)
     # gradient plans read every tensor again in the reverse pass: nothing dies
     keep_all = any(int(k["grad"]) for k in im.knots)
@@ -284,7 +294,7 @@ def run(raw: bytes, J=None, want_grad=False):
             root = int(im.comps[int(k["comp_off"]) + int(vd["comp"])])
             r = complex(read(root, local)[0])
             slots = [int(im.vslot[int(vd["slot_off"]) + j]) for j in range(ns)]
-            xs = [weights[ne + mo + m] for m in slots]
+            xs = [weights[int(k["w_off"]) + int(k["n_edges"]) + m] for m in slots]
             qn = q ** ns
             kc = 1 if int(vd["keep_center"]) else 0
             astr = [int(x) for x in im.strides[int(vd["adj_str"]):int(vd["adj_str"]) + kc + ns]]
@@ -312,7 +322,7 @@ def run(raw: bytes, J=None, want_grad=False):
         for i in range(int(k["n_factors"])):
             f = im.factors[int(k["factor_off"]) + i]
             if f["x"] == 1:
-                x = weights[ne + mo + int(f["y"])]
+                x = weights[int(k["w_off"]) + int(k["n_edges"]) + int(f["y"])]
                 mg[int(f["y"])] = x / (x + q - 1)
         for m in range(nm):
             me = im.medges[mo + m]
@@ -346,24 +356,27 @@ def run(raw: bytes, J=None, want_grad=False):
             if task["flags"] & 1:
                 t = complex(k["t_re"], k["t_im"])
                 eo, mo = int(k["edge_off"]), int(k["medge_off"])
+                wo, wm = int(k["w_off"]), int(k["w_off"]) + int(k["n_edges"])
                 for e in range(int(k["n_edges"])):
                     if J is not None:
                         x = np.exp(complex(J[2 * (eo + e)], J[2 * (eo + e) + 1]))
                     else:
                         x = -(t ** (-int(im.eps[eo + e])))
-                    weights[eo + e] = x
+                    weights[wo + e] = x
                 for m in range(int(k["n_medges"])):
                     me = im.medges[mo + m]
                     x = 1.0 + 0j
                     for i in range(int(me["y"])):
-                        x *= weights[eo + int(im.members[int(me["x"]) + i])]
-                    weights[int(h["n_edges"]) + mo + m] = x
+                        x *= weights[wo + int(im.members[int(me["x"]) + i])]
+                    weights[wm + m] = x
+                sigma = [(int(k["slice"]) // q ** j) % q for j in range(int(k["n_slice_spins"]))]
                 for v in range(int(k["n_vtx"])):
                     vd = im.vtx[int(k["vtx_off"]) + v]
                     ns = int(vd["n_slots"])
                     assert ns <= 8
-                    xs = [weights[int(h["n_edges"]) + mo + int(im.vslot[int(vd["slot_off"]) + j])]
-                          for j in range(ns)]
+                    xs = [weights[wm + int(im.vslot[int(vd["slot_off"]) + j])] for j in range(ns)]
+                    pins = [(int(im.pins[int(vd["pin_off"]) + j]["x"]),
+                             int(im.pins[int(vd["pin_off"]) + j]["y"])) for j in range(int(vd["n_pins"]))]
                     size = int(im.tensors[vd["tensor"]]["size"])
                     data = np.zeros(size, np.complex128)
                     for i in range(size):
@@ -379,6 +392,9 @@ def run(raw: bytes, J=None, want_grad=False):
                             for j in range(ns):
                                 if dig[j] == aa:
                                     p *= xs[j]
+                            for m, sj in pins:  # edges to fixed spins
+                                if sigma[sj] == aa:
+                                    p *= weights[wm + m]
                             acc += p
                         data[i] = acc
                     write_tensor(int(vd["tensor"]), data, task_local=True)
@@ -417,17 +433,23 @@ def run(raw: bytes, J=None, want_grad=False):
                     live_l.pop(t, None)
                     if not keep_all:
                         live_g.pop(t, None)
-                eo, mo = int(k["edge_off"]), int(k["medge_off"])
+                wo, wm = int(k["w_off"]), int(k["w_off"]) + int(k["n_edges"])
+                sigma = [(int(k["slice"]) // q ** j) % q for j in range(int(k["n_slice_spins"]))]
                 for i in range(int(k["n_factors"])):
                     f = im.factors[int(k["factor_off"]) + i]
                     if f["x"] == 0:
-                        x = weights[eo + int(f["y"])]
-                    else:
-                        x = weights[int(h["n_edges"]) + mo + int(f["y"])] + (q - 1)
+                        x = weights[wo + int(f["y"])]
+                    elif f["x"] == 1:
+                        x = weights[wm + int(f["y"])] + (q - 1)
+                    else:  # edge between two fixed spins
+                        x = weights[wm + int(f["y"])] if sigma[int(f["a"])] == sigma[int(f["b"])] else 1.0
                     z, e = mul(z, e, x)
                 for i in range(int(k["n_iso"])):
                     z, e = mul(z, e, q)
-                out[int(k["out_slot"])] = (z, e)
+                if int(k["n_slices"]) > 1:
+                    zslice[int(k["out_slot"])] = (z, e, int(k["plan_slot"]))
+                else:
+                    out[int(k["out_slot"])] = (z, e)
                 if int(k["grad"]):
                     knot_gradient(k, local)
             assert local == made, "state range differs from the tensors the task produced"
@@ -470,6 +492,16 @@ def run(raw: bytes, J=None, want_grad=False):
                 G = im.groups[nxt]
                 queue.extend(range(int(G["first_task"]), int(G["first_task"] + G["n_tasks"])))
     assert executed == int(h["n_tasks"]), "some tasks were never enqueued"
+    # sliced plans: Z is the sum over slices (exact complex sum, aligned exponents)
+    acc = {}
+    for z, e, slot in zslice.values():
+        acc.setdefault(slot, []).append((z, e))
+    for slot, terms in acc.items():
+        emax = max(e for z, e in terms if z != 0) if any(z != 0 for z, e in terms) else 0
+        tot = sum(z * 2.0 ** (e - emax) for z, e in terms)
+        m = max(abs(tot.real), abs(tot.imag))
+        sh = math.frexp(m)[1] if m > 0 else 0
+        out[slot] = (complex(math.ldexp(tot.real, -sh), math.ldexp(tot.imag, -sh)), emax + sh)
     if want_grad:
         return out, grads
     return out

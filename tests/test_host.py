@@ -366,3 +366,60 @@ def test_tile_macs_option():
     with pytest.raises(kn.KnError):
         kn.Plan(t, 3, tile_macs_log2=31)
     _check_model(d, 3, big_step_macs_log2=4, tile_macs_log2=3)
+
+
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_sliced_plan_model_matches_oracle(q):
+    """Slicing (spins fixed, q^k slices, chains of slices sharing an arena)
+    through the CPU model of the device program, against the oracle."""
+    rng = np.random.default_rng(300 + q)
+    cases = [gen.trefoil(), gen.lattice_knot((80, 0), 20, 60), gen.lattice_knot((80, 1), 20, 60),
+             gen.random_grid_diagram(rng, 14)]
+    seen_chained = False
+    for d in cases:
+        t = kn.Tait(d.pd, d.signs if d.n == 1 else None)
+        tg, m, e = oracle_z(d, q)
+        for rank in (1, 2):  # budgets of one and two spins
+            budget = math.ceil(rank * math.log2(q))
+            p = kn.Plan(t, q, slice_log2_budget=budget)
+            assert p.stats["log2_max_entries"] <= budget + 1e-9
+            seen_chained |= p.stats["n_slices"] > p.stats["slice_chains"]
+            (zm, ze), = image_model.run(p.image())
+            assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, budget)
+    assert seen_chained or q < 3  # q = 2 slices fit one chain each
+
+
+def test_sliced_batch_and_couplings():
+    """Sliced and unsliced plans in one batch, general couplings."""
+    rng = np.random.default_rng(17)
+    knots = [gen.lattice_knot((81, k), 15, 50) for k in range(4)]
+    taits = [kn.Tait(d.pd) for d in knots]
+    plans = [kn.Plan(t, 3, jones_only=False, slice_log2_budget=(3 if i % 2 else 0))
+             for i, t in enumerate(taits)]
+    assert any(p.stats["n_slices"] > 1 for p in plans)
+    b = kn.Batch(plans)
+    J = rng.normal(scale=0.3, size=2 * b.stats["total_edges"])
+    out = image_model.run(b.image(), J)
+    for i, (t, (zm, ze)) in enumerate(zip(taits, out)):
+        off = b.edge_offset(i)
+        uv, _ = t.edges()
+        x = np.exp(J[2 * off:2 * (off + t.n_edges):2] + 1j * J[2 * off + 1:2 * (off + t.n_edges):2])
+        m, e = potts.partition_function(t.n_vertices, [tuple(a) for a in uv], x, 3)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+
+
+def test_slicing_makes_wide_knots_fit():
+    """A paper-model grid-walk knot wider than the int32 tensor limit plans
+    only when sliced; the sliced plan keeps every tensor within the budget."""
+    rng = np.random.default_rng(70)
+    d = gen.random_grid_diagram(rng, 70)
+    t = kn.Tait(d.pd)
+    with pytest.raises(kn.KnError) as ei:
+        kn.Plan(t, 3)
+    assert ei.value.code == -3
+    p = kn.Plan(t, 3, slice_log2_budget=24)
+    assert p.stats["log2_max_entries"] <= 24 + 1e-9
+    assert p.stats["n_slices"] == 3 ** round(math.log(p.stats["n_slices"], 3))
+    assert 1 <= p.stats["slice_chains"] <= min(64, p.stats["n_slices"])
+    with pytest.raises(kn.KnError):
+        kn.Plan(t, 3, slice_log2_budget=24, gradient=True)
