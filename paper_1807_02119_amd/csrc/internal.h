@@ -2,6 +2,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <cstring>
 #include <memory>
 #include <new>
 #include <string>
@@ -70,51 +71,59 @@ class SpinList {
   ~SpinList() { release(); }
   int32_t size() const { return n_; }
   bool empty() const { return n_ == 0; }
-  const int32_t* begin() const { return data(); }
-  const int32_t* end() const { return data() + n_; }
-  int32_t operator[](int32_t i) const { return data()[i]; }
+  const int32_t* begin() const { return p_; }
+  const int32_t* end() const { return p_ + n_; }
+  int32_t operator[](int32_t i) const { return p_[i]; }
   void reserve(int32_t c) {
     if (c > cap_) grow(c);
   }
   void push_back(int32_t x) {
     if (n_ == cap_) grow(2 * cap_);
-    data()[n_++] = x;
+    p_[n_++] = x;
+  }
+  // in-place edits: entries [0, size) writable, shrink to the first k
+  int32_t* mut() { return p_; }
+  void truncate(int32_t k) {
+    if (k < n_) n_ = k;
   }
 
  private:
-  int32_t* data() { return heap_ ? heap_ : in_; }
-  const int32_t* data() const { return heap_ ? heap_ : in_; }
+  bool inline_() const { return p_ == in_; }
   void grow(int32_t c) {
-    int32_t* p = new int32_t[c];
-    for (int32_t i = 0; i < n_; ++i) p[i] = data()[i];
-    delete[] heap_;
-    heap_ = p;
+    int32_t* np = new int32_t[c];
+    std::memcpy(np, p_, sizeof(int32_t) * (size_t)n_);
+    if (!inline_()) delete[] p_;
+    p_ = np;
     cap_ = c;
   }
   void release() {
-    delete[] heap_;
-    heap_ = nullptr;
+    if (!inline_()) delete[] p_;
+    p_ = in_;
     cap_ = kIn;
     n_ = 0;
   }
   void copy_from(const SpinList& o) {
     reserve(o.n_);
-    for (int32_t i = 0; i < o.n_; ++i) data()[i] = o.data()[i];
+    std::memcpy(p_, o.p_, sizeof(int32_t) * (size_t)o.n_);
     n_ = o.n_;
   }
   void move_from(SpinList& o) {
     n_ = o.n_;
-    cap_ = o.cap_;
-    heap_ = o.heap_;
-    if (!heap_)
-      for (int32_t i = 0; i < n_; ++i) in_[i] = o.in_[i];
-    o.heap_ = nullptr;
+    if (o.inline_()) {
+      std::memcpy(in_, o.in_, sizeof(in_));
+      p_ = in_;
+      cap_ = kIn;
+    } else {
+      p_ = o.p_;
+      cap_ = o.cap_;
+    }
+    o.p_ = o.in_;
     o.cap_ = kIn;
     o.n_ = 0;
   }
+  int32_t* p_ = in_;
   int32_t n_ = 0;
   int32_t cap_ = kIn;
-  int32_t* heap_ = nullptr;
   int32_t in_[kIn];
 };
 

@@ -72,17 +72,33 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
   bool r1 = flags & 1, r2 = (flags & 2) && jones_only;
   // merge parallel classes; loops become factors (or stay as loops when R-I
   // is off: they are still constants, a loop never couples two spins)
-  std::vector<std::pair<int64_t, int32_t>> keyed;  // (u * nv + v, edge), u < v
-  keyed.reserve(ne);
-  for (int32_t e = 0; e < ne; ++e) {
-    int32_t u = g.uv[2 * e], v = g.uv[2 * e + 1];
-    if (u == v) {
-      k.factors.push_back({FAC_LOOP, e});
-      continue;
+  // (u * nv + v, edge) with u < v, sorted by key then edge: two stable
+  // counting sorts, by v and then by u
+  std::vector<std::pair<int64_t, int32_t>> keyed;
+  {
+    std::vector<int32_t> by_v, cnt(nv + 1, 0);
+    by_v.reserve(ne);
+    for (int32_t e = 0; e < ne; ++e) {
+      const int32_t u = g.uv[2 * e], v = g.uv[2 * e + 1];
+      if (u == v) {
+        k.factors.push_back({FAC_LOOP, e});
+        continue;
+      }
+      cnt[std::max(u, v) + 1]++;
+      by_v.push_back(e);
     }
-    keyed.emplace_back((int64_t)std::min(u, v) * nv + std::max(u, v), e);
+    for (int32_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    std::vector<int32_t> tmp(by_v.size());
+    for (int32_t e : by_v) tmp[cnt[std::max(g.uv[2 * e], g.uv[2 * e + 1])]++] = e;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int32_t e : tmp) cnt[std::min(g.uv[2 * e], g.uv[2 * e + 1]) + 1]++;
+    for (int32_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    keyed.resize(tmp.size());
+    for (int32_t e : tmp) {
+      const int32_t u = g.uv[2 * e], v = g.uv[2 * e + 1];
+      keyed[cnt[std::min(u, v)]++] = {(int64_t)std::min(u, v) * nv + std::max(u, v), e};
+    }
   }
-  std::sort(keyed.begin(), keyed.end());
   std::vector<std::pair<int32_t, int32_t>> ends;
   k.medge_off.assign(1, 0);
   k.medge_mem.clear();
@@ -250,7 +266,7 @@ struct Orderer {
   std::vector<PTensor> T;
   std::vector<PStep> S;
   std::vector<int32_t> cnt;
-  std::vector<std::vector<int32_t>> hold;  // live holders of each spin (lazily compacted)
+  std::vector<SpinList> hold;  // live holders of each spin (lazily compacted)
   std::vector<uint8_t> alive;
   std::vector<uint32_t> mark;
   uint32_t stamp = 0;
@@ -325,12 +341,13 @@ struct Orderer {
   }
 
   // live holders of spin x (compacts the list)
-  std::vector<int32_t>& holders(int32_t x) {
-    auto& hl = hold[x];
-    size_t w = 0;
-    for (size_t i = 0; i < hl.size(); ++i)
-      if (alive[hl[i]]) hl[w++] = hl[i];
-    hl.resize(w);
+  const SpinList& holders(int32_t x) {
+    SpinList& hl = hold[x];
+    int32_t* h = hl.mut();
+    int32_t w = 0;
+    for (int32_t i = 0; i < hl.size(); ++i)
+      if (alive[h[i]]) h[w++] = h[i];
+    hl.truncate(w);
     return hl;
   }
 
@@ -394,7 +411,6 @@ struct Orderer {
     for (const auto& t : T)
       for (size_t i = 0; i < t.spins.size(); ++i)
         for (size_t j = i + 1; j < t.spins.size(); ++j) set(t.spins[i], t.spins[j]);
-    std::vector<uint8_t> gone(n, 0);
     std::vector<int32_t> fill(n, 0), deg(n, 0);
     std::vector<int32_t> nb;
     auto neigh = [&](int32_t v, std::vector<int32_t>& out) {
@@ -426,33 +442,22 @@ struct Orderer {
     std::vector<uint32_t> tmark(n, 0);
     std::vector<uint64_t> xm(W, 0);  // N(x) + x as a bit set
     uint32_t ts = 0;
-    // candidates (fill, degree, id) with lazy invalidation by a version stamp
-    struct F {
-      int32_t fill, deg, v, ver;
-      bool operator<(const F& o) const {
-        if (fill != o.fill) return fill > o.fill;
-        if (deg != o.deg) return deg > o.deg;
-        return v > o.v;
-      }
+    // next spin: least fill, then least degree, then lowest id (a linear scan
+    // over packed keys; the graphs have a few hundred spins)
+    std::vector<uint64_t> key(n);
+    auto pack = [&](int32_t v) {
+      key[v] = (uint64_t)fill[v] << 42 | (uint64_t)deg[v] << 21 | (uint64_t)v;
     };
-    std::vector<int32_t> ver(n, 0);
-    std::priority_queue<F> heap;
-    for (int32_t v = 0; v < n; ++v) heap.push({fill[v], deg[v], v, 0});
+    for (int32_t v = 0; v < n; ++v) pack(v);
     for (int32_t it = 0; it < n; ++it) {
-      int32_t x = -1;
-      while (!heap.empty()) {
-        F f = heap.top();
-        heap.pop();
-        if (!gone[f.v] && f.ver == ver[f.v]) {
-          x = f.v;
-          break;
-        }
-      }
+      uint64_t best = UINT64_MAX;
+      for (int32_t v = 0; v < n; ++v) best = std::min(best, key[v]);
+      const int32_t x = best == UINT64_MAX ? -1 : (int32_t)(best & ((1u << 21) - 1));
       if (x < 0) break;
       // contract the holders of x pairwise, smallest first
       if (cnt[x] > 0) {
         for (;;) {
-          auto& hl = holders(x);
+          const SpinList& hl = holders(x);
           if (hl.size() < 2) break;
           int32_t a = -1, b = -1;
           for (int32_t t : hl) {
@@ -466,10 +471,12 @@ struct Orderer {
           contract(a, b);
         }
       }
-      // eliminate x from the graph: its neighbours become a clique.  Fill
-      // values change only for x's neighbours (recomputed) and for common
-      // neighbours z of a new clique edge (u, w): that pair of N(z) is now
-      // adjacent, so fill(z) drops by one.
+      // eliminate x from the graph: its neighbours become a clique, then x
+      // leaves.  Fill counts are kept exact incrementally.  Adding an edge
+      // (u, w): each common neighbour z has that pair of N(z) joined
+      // (fill - 1); u gains the pairs {w, y}, y in N(u) \ N(w) (and the same
+      // for w).  Removing x: a neighbour a loses the pairs {x, y}, y in
+      // N(a) not adjacent to x, i.e. outside N(x) + x once N(x) is a clique.
       neigh(x, nv);
       std::fill(xm.begin(), xm.end(), 0);
       for (int32_t a : nv) xm[a >> 6] |= uint64_t(1) << (a & 63);
@@ -479,9 +486,13 @@ struct Orderer {
         for (size_t j = i + 1; j < nv.size(); ++j) {
           const int32_t u = nv[i], w = nv[j];
           if (has(u, w)) continue;
-          set(u, w);
+          const uint64_t* au = &adj[(size_t)u * W];
+          const uint64_t* aw = &adj[(size_t)w * W];
+          int32_t du = 0, dw = 0;
           for (int32_t ww = 0; ww < W; ++ww) {
-            uint64_t m = adj[(size_t)u * W + ww] & adj[(size_t)w * W + ww] & ~xm[ww];
+            du += __builtin_popcountll(au[ww] & ~aw[ww]);
+            dw += __builtin_popcountll(aw[ww] & ~au[ww]);
+            uint64_t m = au[ww] & aw[ww];
             while (m) {
               const int32_t z = ww * 64 + __builtin_ctzll(m);
               m &= m - 1;
@@ -492,15 +503,25 @@ struct Orderer {
               }
             }
           }
+          fill[u] += du;
+          fill[w] += dw;
+          ++deg[u];
+          ++deg[w];
+          set(u, w);
         }
-      for (int32_t a : nv) adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
-      for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
-      gone[x] = 1;
       for (int32_t a : nv) {
-        eval(a);
-        heap.push({fill[a], deg[a], a, ++ver[a]});
+        const uint64_t* aa = &adj[(size_t)a * W];
+        int32_t c = 0;
+        for (int32_t ww = 0; ww < W; ++ww) c += __builtin_popcountll(aa[ww] & ~xm[ww]);
+        fill[a] -= c;
+        --deg[a];
+        adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
       }
-      for (int32_t z : touched) heap.push({fill[z], deg[z], z, ++ver[z]});
+      for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
+      key[x] = UINT64_MAX;
+      for (int32_t z : touched)
+        if (z != x) pack(z);
+      for (int32_t a : nv) pack(a);
       touched.clear();
     }
   }

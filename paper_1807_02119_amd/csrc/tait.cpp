@@ -19,6 +19,12 @@ namespace {
 // Slot of the outgoing over-arc: b for a positive crossing, d for a negative.
 inline int out_over_slot(int sign) { return sign > 0 ? 1 : 3; }
 
+// Labels a, b in [0, m): is b the label after a (b = a + 1 mod m)?
+inline bool follows(int32_t a, int32_t b, int32_t m) {
+  const int32_t d = b - a - 1;
+  return d == 0 || d == -m;
+}
+
 }  // namespace
 
 extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* signs,
@@ -64,14 +70,14 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
         sg = signs[i] > 0 ? 1 : (signs[i] < 0 ? -1 : 0);
         if (!sg) { delete g; return KN_E_INVALID; }
       } else {
-        bool pos = (x[1] - x[3] - 1) % m == 0;
-        bool neg = (x[3] - x[1] - 1) % m == 0;
+        bool pos = follows(x[3], x[1], m);
+        bool neg = follows(x[1], x[3], m);
         if (pos == neg) { delete g; return KN_E_INVALID; }
         sg = pos ? 1 : -1;
       }
-      if (((x[2] - x[0] - 1) % m + m) % m != 0) { delete g; return KN_E_INVALID; }
+      if (!follows(x[0], x[2], m)) { delete g; return KN_E_INVALID; }
       int oo = out_over_slot(sg), oi = oo ^ 2;
-      if ((((x[oo] - x[oi] - 1) % m) + m) % m != 0 && n > 1) { delete g; return KN_E_INVALID; }
+      if (!follows(x[oi], x[oo], m) && n > 1) { delete g; return KN_E_INVALID; }
       g->twist[i] = (int8_t)sg;
       n_in[x[0]]++;
       n_out[x[2]]++;
