@@ -1310,13 +1310,14 @@ namespace {
 kn_status contract_plan(const kn_plan* p, const double* J, void* workspace,
                         size_t workspace_bytes, void* stream, kn_scalar* z_dev, double* grad) {
   if (!p || !workspace || !z_dev) return KN_E_INVALID;
-  if (p->image.empty()) return KN_E_BUDGET;
+  const Bytes& image = plan_image(p);
+  if (image.empty()) return KN_E_BUDGET;
   if (J && p->k.jones_only) return KN_E_UNSUPPORTED;
   if (!aligned256(workspace)) return KN_E_INVALID;
-  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(p->image.data());
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(image.data());
   if ((int64_t)workspace_bytes < h.workspace_bytes) return KN_E_BUDGET;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (hipMemcpyAsync(workspace, p->image.data(), (size_t)h.image_bytes, hipMemcpyHostToDevice, st) !=
+  if (hipMemcpyAsync(workspace, image.data(), (size_t)h.image_bytes, hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return KN_E_DEVICE;
   return launch(h, reinterpret_cast<uint8_t*>(workspace), st, J, z_dev, grad, 0);
@@ -1336,7 +1337,7 @@ extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_
   std::vector<const PlanKnot*> ks;
   bool jones_only = false, gradient = true;
   for (int32_t i = 0; i < n; ++i) {
-    if (!plans[i] || plans[i]->image.empty()) return KN_E_INVALID;
+    if (!plans[i] || !plans[i]->laid_out) return KN_E_INVALID;
     if (plans[i]->k.precision != plans[0]->k.precision) return KN_E_INVALID;
     jones_only |= plans[i]->k.jones_only;
     gradient &= plans[i]->k.gradient;

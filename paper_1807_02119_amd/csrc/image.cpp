@@ -31,23 +31,26 @@ namespace kn {
 
 namespace {
 
-// Element stride of every spin of `group` in a tensor stored in `order`
-// (row-major, last spin fastest), appended to `out`.
-void group_strides(const SpinList& group, const SpinList& order, int32_t q,
-                   std::vector<int32_t>& out) {
-  for (int32_t sp : group) {
-    int64_t s = 1;
-    bool found = false;
-    for (int32_t j = order.size() - 1; j >= 0; --j) {
-      if (order[j] == sp) {
-        found = true;
-        break;
-      }
-      s *= q;
+// Element strides of spins in tensors stored row-major in a spin order (last
+// spin fastest): load(order) records each spin's stride, 0 for spins the
+// order does not hold; append(group) writes the strides of a group's spins.
+struct StrideMap {
+  std::vector<int32_t> stride, stamp;
+  int32_t cur = 0;
+  const int32_t* qpow;
+  StrideMap(int32_t n_spins, const int32_t* qp) : stride(n_spins, 0), stamp(n_spins, 0), qpow(qp) {}
+  void load(const SpinList& order) {
+    ++cur;
+    const int32_t r = order.size();
+    for (int32_t j = 0; j < r; ++j) {
+      stride[order[j]] = qpow[r - 1 - j];
+      stamp[order[j]] = cur;
     }
-    out.push_back(found ? (int32_t)s : 0);
   }
-}
+  void append(const SpinList& group, std::vector<int32_t>& out) const {
+    for (int32_t sp : group) out.push_back(stamp[sp] == cur ? stride[sp] : 0);
+  }
+};
 
 // A knot's groups before they are laid out.
 struct PGroup {
@@ -78,7 +81,20 @@ void make_section(PlanKnot& k) {
   d.grad = k.gradient ? 1 : 0;
   d.n_slices = k.n_slices;
   d.n_slice_spins = k.n_slice_spins;
-  for (size_t m = 0; m + 1 < k.medge_off.size(); ++m) {
+  // spin ids are below n_spins; powers of q up to the largest rank
+  int32_t n_spins = 1, max_rank = 0;
+  for (const auto& t : k.tensors) {
+    max_rank = std::max(max_rank, t.spins.size());
+    for (int32_t sp : t.spins) n_spins = std::max(n_spins, sp + 1);
+  }
+  std::vector<int32_t> qpow(max_rank + 1);
+  qpow[0] = 1;
+  for (int32_t i = 1; i <= max_rank; ++i) qpow[i] = qpow[i - 1] * q;
+  StrideMap smap(n_spins, qpow.data());
+  const size_t n_md = k.medge_off.size() - 1;
+  S.md.reserve(n_md);
+  S.members.reserve(k.medge_mem.size());
+  for (size_t m = 0; m < n_md; ++m) {
     S.md.push_back({(int32_t)S.members.size(), k.medge_off[m + 1] - k.medge_off[m]});
     for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) S.members.push_back(k.medge_mem[j]);
   }
@@ -87,6 +103,20 @@ void make_section(PlanKnot& k) {
   S.td.reserve(k.tensors.size());
   for (auto& t : k.tensors) S.td.push_back({t.off, (int32_t)t.size, -1});
   S.arena_elems = (k.arena_elems + 15) / 16 * 16;
+  {
+    size_t n_tab = 0, n_slot = 0, n_pin = 0;
+    for (const auto& v : k.vtx) {
+      n_slot += v.medge.size();
+      n_pin += 2 * v.pin_medge.size();
+      if (v.adjoint >= 0) n_tab += 1 + v.nbr.size();
+    }
+    for (const auto& st : k.steps)
+      n_tab += 2 * st.bs.size() + st.ms.size() + 2 * st.ks.size() + st.ns.size();
+    S.strides.reserve(n_tab);
+    S.vslot.reserve(n_slot);
+    S.pins.reserve(n_pin);
+    S.vd.reserve(k.vtx.size());
+  }
   for (auto& v : k.vtx) {
     int32_t adj_str = -1;
     if (v.adjoint >= 0) {  // the adjoint's own spin order differs from F_v's
@@ -94,7 +124,8 @@ void make_section(PlanKnot& k) {
       SpinList vs;
       if (v.keep_center) vs.push_back(v.center);
       for (int32_t w : v.nbr) vs.push_back(w);
-      group_strides(vs, k.tensors[v.adjoint].spins, q, S.strides);
+      smap.load(k.tensors[v.adjoint].spins);
+      smap.append(vs, S.strides);
     }
     S.vd.push_back({v.tensor, (int32_t)v.nbr.size(), (int32_t)S.vslot.size(),
                     v.seed ? -1 : (v.keep_center ? 1 : 0), v.adjoint, v.comp, adj_str,
@@ -113,26 +144,21 @@ void make_section(PlanKnot& k) {
     x.a = s.a;
     x.b = s.b;
     x.c = s.c;
-    auto pw = [&](size_t r) {
-      int64_t v = 1;
-      for (size_t i = 0; i < r; ++i) v *= q;
-      return (int32_t)v;
-    };
-    x.nb = pw(s.bs.size());
-    x.nm = pw(s.ms.size());
-    x.nn = pw(s.ns.size());
-    x.nk = pw(s.ks.size());
+    x.nb = qpow[s.bs.size()];
+    x.nm = qpow[s.ms.size()];
+    x.nn = qpow[s.ns.size()];
+    x.nk = qpow[s.ks.size()];
     x.str = (int32_t)S.strides.size();
     x.ranks = (int32_t)(s.bs.size() | (s.ms.size() << 8) | (s.ks.size() << 16) |
                         (s.ns.size() << 24));
-    const auto& A = k.tensors[s.a].spins;
-    const auto& B = k.tensors[s.b].spins;
-    group_strides(s.bs, A, q, S.strides);
-    group_strides(s.ms, A, q, S.strides);
-    group_strides(s.ks, A, q, S.strides);
-    group_strides(s.bs, B, q, S.strides);
-    group_strides(s.ks, B, q, S.strides);
-    group_strides(s.ns, B, q, S.strides);
+    smap.load(k.tensors[s.a].spins);
+    smap.append(s.bs, S.strides);
+    smap.append(s.ms, S.strides);
+    smap.append(s.ks, S.strides);
+    smap.load(k.tensors[s.b].spins);
+    smap.append(s.bs, S.strides);
+    smap.append(s.ks, S.strides);
+    smap.append(s.ns, S.strides);
     const PTiling& t = k.tiling[si];
     x.mode = t.mode;
     x.n_tiles = t.mode == STEP_SERIAL ? 0 : t.n_tiles;
@@ -275,7 +301,7 @@ void make_section(PlanKnot& k) {
   }
 }
 
-Bytes build_image(const std::vector<const PlanKnot*>& knots) {
+Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
   ImgHeader h;
   std::memset(&h, 0, sizeof(h));
   h.magic = kMagic;
@@ -390,6 +416,32 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
   h.n_roots = (int32_t)n_roots;
   h.o_roots = reserve(n_roots, sizeof(int32_t));
   h.image_bytes = align256(top);
+  // runtime state: control words, ready queue, pending counters, tensor
+  // states, weights, gradients, slice results
+  h.state_off = h.image_bytes;
+  int64_t st = CTRL_WORDS * 4;
+  h.o_queue = st;
+  st = align256(st + 4 * (int64_t)nTask);
+  h.o_pending = st;
+  st = align256(st + 4 * (int64_t)nG);
+  h.o_tstate = st;
+  st = align256(st + (int64_t)nT * (int64_t)sizeof(TensorState));
+  h.o_weights = st;
+  st = align256(st + 16 * (int64_t)ut.W);
+  h.o_mgrad = st;
+  st = align256(st + 16 * (int64_t)nM);
+  h.o_zslice = st;
+  st = align256(st + (int64_t)sizeof(kn_scalar) * (int64_t)nU);
+  h.state_bytes = st;
+  h.arena_off = align256(h.state_off + h.state_bytes);
+  h.arena_elems = std::max<int64_t>(arena, 16);
+  if (h.arena_elems > INT32_MAX) return {};  // step homes hold int32 offsets
+  h.workspace_bytes = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
+  if (header_only) {
+    Bytes hb(sizeof(h));
+    std::memcpy(hb.data(), &h, sizeof(h));
+    return hb;
+  }
   Bytes img((size_t)h.image_bytes);
   uint8_t* base = img.data();
   {
@@ -537,27 +589,6 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots) {
     int32_t* root_tasks = arr(h.o_roots, (int32_t*)nullptr);
     for (size_t i = 0; i < rs.size(); ++i) root_tasks[i] = rs[i].second;
   }
-  // runtime state: control words, ready queue, pending counters, tensor
-  // states, weights, gradients, slice results
-  h.state_off = h.image_bytes;
-  int64_t st = CTRL_WORDS * 4;
-  h.o_queue = st;
-  st = align256(st + 4 * (int64_t)nTask);
-  h.o_pending = st;
-  st = align256(st + 4 * (int64_t)nG);
-  h.o_tstate = st;
-  st = align256(st + (int64_t)nT * (int64_t)sizeof(TensorState));
-  h.o_weights = st;
-  st = align256(st + 16 * (int64_t)ut.W);
-  h.o_mgrad = st;
-  st = align256(st + 16 * (int64_t)nM);
-  h.o_zslice = st;
-  st = align256(st + (int64_t)sizeof(kn_scalar) * (int64_t)nU);
-  h.state_bytes = st;
-  h.arena_off = align256(h.state_off + h.state_bytes);
-  h.arena_elems = std::max<int64_t>(arena, 16);
-  if (h.arena_elems > INT32_MAX) return {};  // step homes hold int32 offsets
-  h.workspace_bytes = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
   std::memcpy(img.data(), &h, sizeof(h));
   return img;
 }

@@ -2,8 +2,10 @@
 #pragma once
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -258,8 +260,9 @@ struct FitAlloc {
   }
   void release(int64_t off, int64_t len) {
     len = round(len);
-    size_t i = 0;
-    while (i < free_blk.size() && free_blk[i].off < off) ++i;
+    size_t i = (size_t)(std::lower_bound(free_blk.begin(), free_blk.end(), off,
+                                         [](const Blk& b, int64_t o) { return b.off < o; }) -
+                        free_blk.begin());
     free_blk.insert(free_blk.begin() + i, Blk{off, len});
     if (i + 1 < free_blk.size() && free_blk[i].off + free_blk[i].len == free_blk[i + 1].off) {
       free_blk[i].len += free_blk[i + 1].len;
@@ -276,8 +279,10 @@ struct FitAlloc {
 void make_section(PlanKnot& k);
 
 // Build the device image for a list of knots (a batch of one or more) by
-// concatenating their sections.  out_slot of knot i is i.
-Bytes build_image(const std::vector<const PlanKnot*>& knots);
+// concatenating their sections.  out_slot of knot i is i.  With header_only
+// the result is just the ImgHeader (every size and offset, nothing written).
+// Empty when the arena does not fit int32 offsets.
+Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only = false);
 
 int64_t elem_bytes(int32_t precision);
 
@@ -286,9 +291,18 @@ int64_t elem_bytes(int32_t precision);
 struct kn_plan {
   kn::PlanKnot k;
   kn_plan_stats stats{};
-  kn::Bytes image;  // single-knot device image
+  bool laid_out = false;  // the single-knot image fits (its header was built)
   uint64_t bwd_workspace = 0;
+  // single-knot device image, built on first use (plans planned for a batch
+  // never need it); guarded for concurrent users of one plan
+  mutable std::mutex image_mu;
+  mutable kn::Bytes image;
 };
+
+namespace kn {
+// The plan's single-knot image (empty when it does not fit).
+const Bytes& plan_image(const kn_plan* p);
+}  // namespace kn
 
 struct kn_batch {
   kn::Bytes image;

@@ -365,9 +365,14 @@ struct Orderer {
       c.a = std::min(a, b);
       c.b = std::max(a, b);
     };
-    std::vector<Cand> store;
-    store.reserve(16 * T.size() + 16);
-    std::priority_queue<Cand> pq(std::less<Cand>(), std::move(store));
+    // a binary heap (std::less<Cand>: top = best) with lazy deletion; pairs
+    // of contracted tensors are swept out in bulk every few contractions
+    std::vector<Cand> heap;
+    heap.reserve(16 * T.size() + 16);
+    auto push = [&](const Cand& c) {
+      heap.push_back(c);
+      std::push_heap(heap.begin(), heap.end());
+    };
     auto push_pairs = [&](int32_t a) {
       if ((size_t)a >= seen.size()) seen.resize(2 * a + 2, 0);
       ++tstamp;
@@ -378,22 +383,31 @@ struct Orderer {
           seen[b] = tstamp;
           Cand c;
           cost(a, b, c);
-          pq.push(c);
+          push(c);
         }
     };
     const int32_t n0 = (int32_t)T.size();
     for (int32_t t = 0; t < n0; ++t) push_pairs(t);
-    while (!pq.empty()) {
-      Cand c = pq.top();
-      pq.pop();
+    int32_t since_sweep = 0;
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end());
+      const Cand c = heap.back();
+      heap.pop_back();
       if (!alive[c.a] || !alive[c.b]) continue;
       Cand fresh;
       cost(c.a, c.b, fresh);
       if (fresh.k1 != c.k1 || fresh.k2 != c.k2) {  // counts changed since the push
-        pq.push(fresh);
+        push(fresh);
         continue;
       }
       push_pairs(contract(c.a, c.b));
+      if (++since_sweep == 16) {
+        since_sweep = 0;
+        heap.erase(std::remove_if(heap.begin(), heap.end(),
+                                  [&](const Cand& x) { return !alive[x.a] || !alive[x.b]; }),
+                   heap.end());
+        std::make_heap(heap.begin(), heap.end());
+      }
     }
   }
 
@@ -444,15 +458,22 @@ struct Orderer {
     uint32_t ts = 0;
     // next spin: least fill, then least degree, then lowest id (a linear scan
     // over packed keys; the graphs have a few hundred spins)
+    // over the spins still in the graph, kept packed: key[slot[v]] is v's
     std::vector<uint64_t> key(n);
+    std::vector<int32_t> slot(n);
+    int32_t live = n;
     auto pack = [&](int32_t v) {
-      key[v] = (uint64_t)fill[v] << 42 | (uint64_t)deg[v] << 21 | (uint64_t)v;
+      key[slot[v]] = (uint64_t)fill[v] << 42 | (uint64_t)deg[v] << 21 | (uint64_t)v;
     };
-    for (int32_t v = 0; v < n; ++v) pack(v);
+    for (int32_t v = 0; v < n; ++v) {
+      slot[v] = v;
+      pack(v);
+    }
+    constexpr uint64_t kIdMask = (uint64_t(1) << 21) - 1;
     for (int32_t it = 0; it < n; ++it) {
       uint64_t best = UINT64_MAX;
-      for (int32_t v = 0; v < n; ++v) best = std::min(best, key[v]);
-      const int32_t x = best == UINT64_MAX ? -1 : (int32_t)(best & ((1u << 21) - 1));
+      for (int32_t i = 0; i < live; ++i) best = std::min(best, key[i]);
+      const int32_t x = best == UINT64_MAX ? -1 : (int32_t)(best & kIdMask);
       if (x < 0) break;
       // contract the holders of x pairwise, smallest first
       if (cnt[x] > 0) {
@@ -518,7 +539,12 @@ struct Orderer {
         adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
       }
       for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
-      key[x] = UINT64_MAX;
+      {  // x leaves the packed keys: the last one takes its place
+        const int32_t i = slot[x], last = (int32_t)(key[live - 1] & kIdMask);
+        key[i] = key[live - 1];
+        slot[last] = i;
+        --live;
+      }
       for (int32_t z : touched)
         if (z != x) pack(z);
       for (int32_t a : nv) pack(a);
@@ -1068,6 +1094,19 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
 
 }  // namespace kn
 
+namespace kn {
+
+const Bytes& plan_image(const kn_plan* p) {
+  std::lock_guard<std::mutex> lock(p->image_mu);
+  if (p->image.empty() && p->laid_out) {
+    std::vector<const PlanKnot*> one{&p->k};
+    p->image = build_image(one);
+  }
+  return p->image;
+}
+
+}  // namespace kn
+
 static kn_plan_opts default_opts() {
   kn_plan_opts o;
   std::memset(&o, 0, sizeof(o));
@@ -1111,13 +1150,18 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
     if (rc == KN_OK) {
       kn::make_section(p->k);
       std::vector<const kn::PlanKnot*> one{&p->k};
-      p->image = kn::build_image(one);
-      if (p->image.empty()) rc = KN_E_BUDGET;
-      const auto* h = reinterpret_cast<const kn::ImgHeader*>(p->image.data());
-      p->stats.workspace_bytes = (uint64_t)h->workspace_bytes;
-      p->stats.image_bytes = (uint64_t)h->image_bytes;
-      p->stats.n_tasks = h->n_tasks;
-      if (o.mem_budget_bytes && p->stats.workspace_bytes > o.mem_budget_bytes) rc = KN_E_BUDGET;
+      const kn::Bytes hb = kn::build_image(one, true);
+      if (hb.empty()) {
+        rc = KN_E_BUDGET;
+      } else {
+        kn::ImgHeader h;
+        std::memcpy(&h, hb.data(), sizeof(h));
+        p->laid_out = true;
+        p->stats.workspace_bytes = (uint64_t)h.workspace_bytes;
+        p->stats.image_bytes = (uint64_t)h.image_bytes;
+        p->stats.n_tasks = h.n_tasks;
+        if (o.mem_budget_bytes && p->stats.workspace_bytes > o.mem_budget_bytes) rc = KN_E_BUDGET;
+      }
     }
   } catch (const std::bad_alloc&) {
     delete p;
@@ -1139,8 +1183,9 @@ extern "C" kn_status kn_plan_info(const kn_plan* p, kn_plan_stats* out) {
 
 extern "C" kn_status kn_plan_image(const kn_plan* p, const void** data, size_t* bytes) {
   if (!p || !data || !bytes) return KN_E_INVALID;
-  *data = p->image.empty() ? nullptr : p->image.data();
-  *bytes = p->image.size();
+  const kn::Bytes& img = kn::plan_image(p);
+  *data = img.empty() ? nullptr : img.data();
+  *bytes = img.size();
   return KN_OK;
 }
 
