@@ -213,6 +213,19 @@ struct PlanKnot {
   int32_t lds_bytes = 32768;
   std::vector<PTiling> tiling;                  // per step: how it is executed
   Section sec;  // device-program section (make_section)
+
+  // Once the section is made, images need only it, the Tait signs and the
+  // slice counts: the planning structures are freed on the planning thread.
+  void release_planning() {
+    std::vector<PTensor>().swap(tensors);
+    std::vector<PVertex>().swap(vtx);
+    std::vector<PStep>().swap(steps);
+    std::vector<PTiling>().swap(tiling);
+    std::vector<int32_t>().swap(comps);
+    std::vector<Factor>().swap(factors);
+    std::vector<int32_t>{0}.swap(medge_off);
+    std::vector<int32_t>().swap(medge_mem);
+  }
 };
 
 // Adjacent steps i and i + 1 run concurrently: both serial and of the same

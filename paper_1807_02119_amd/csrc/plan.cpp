@@ -769,21 +769,32 @@ kn_status build_network(const NetGraph& G, int32_t q, const kn_plan_opts& o, Pla
     maxd = std::max(maxd, deg[v]);
   }
   {
-    std::vector<std::vector<int32_t>> bucket(maxd + 1);
-    for (int32_t v = 0; v < n; ++v) bucket[deg[v]].push_back(v);
+    // degree buckets as stacks threaded through one pool (entry: vertex, next)
+    // with lazy deletion: a vertex whose degree dropped is pushed again and
+    // its old entry skipped
+    std::vector<int32_t> head(maxd + 1, -1), pool_v, pool_next;
+    pool_v.reserve(n + ne2);
+    pool_next.reserve(n + ne2);
+    auto push = [&](int32_t d, int32_t v) {
+      pool_v.push_back(v);
+      pool_next.push_back(head[d]);
+      head[d] = (int32_t)pool_v.size() - 1;
+    };
+    for (int32_t v = 0; v < n; ++v) push(deg[v], v);
     int32_t placed = 0, d = 0;
     while (placed < n) {
       d = std::max(0, d - 1);
-      while (d <= maxd && bucket[d].empty()) ++d;
-      int32_t v = bucket[d].back();
-      bucket[d].pop_back();
+      while (d <= maxd && head[d] < 0) ++d;
+      const int32_t e = head[d];
+      head[d] = pool_next[e];
+      const int32_t v = pool_v[e];
       if (pos[v] >= 0 || deg[v] != d) continue;
       pos[v] = placed++;
       for (int32_t j = aoff[v]; j < aoff[v + 1]; ++j) {
         const int32_t w = anb[j];
         if (pos[w] < 0) {
           --deg[w];
-          bucket[deg[w]].push_back(w);
+          push(deg[w], w);
         }
       }
     }
@@ -1149,6 +1160,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
     rc = kn::make_plan(*g, q, o, p->k, p->stats);
     if (rc == KN_OK) {
       kn::make_section(p->k);
+      p->k.release_planning();
       std::vector<const kn::PlanKnot*> one{&p->k};
       const kn::Bytes hb = kn::build_image(one, true);
       if (hb.empty()) {
@@ -1191,9 +1203,10 @@ extern "C" kn_status kn_plan_image(const kn_plan* p, const void** data, size_t* 
 
 extern "C" kn_status kn_plan_steps(const kn_plan* p, int32_t* ab) {
   if (!p || !ab) return KN_E_INVALID;
-  for (size_t i = 0; i < p->k.steps.size(); ++i) {
-    ab[2 * i] = p->k.steps[i].a;
-    ab[2 * i + 1] = p->k.steps[i].b;
+  const auto& sd = p->k.sec.sd;
+  for (size_t i = 0; i < sd.size(); ++i) {
+    ab[2 * i] = sd[i].a;
+    ab[2 * i + 1] = sd[i].b;
   }
   return KN_OK;
 }

@@ -46,23 +46,29 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
     return KN_E_INVALID;
   }
   const int32_t m = 2 * n;
+  const int32_t nc = 4 * n;
   try {
-    // every arc label used exactly twice; record its two slots
-    std::vector<int32_t> first(m, -1), second(m, -1);
-    for (int32_t s = 0; s < 4 * n; ++s) {
-      int32_t lab = pd[s];
-      if (lab < 0 || lab >= m) { delete g; return KN_E_INVALID; }
-      if (first[lab] < 0) first[lab] = s;
-      else if (second[lab] < 0) second[lab] = s;
-      else { delete g; return KN_E_INVALID; }
+    // every arc label used exactly twice: partner[s] is the other slot with
+    // the label of slot s (where[lab]: first slot seen, then -2 once paired)
+    std::vector<int32_t> partner(nc), where(m, -1);
+    for (int32_t s = 0; s < nc; ++s) {
+      const int32_t lab = pd[s];
+      if (lab < 0 || lab >= m || where[lab] == -2) { delete g; return KN_E_INVALID; }
+      if (where[lab] < 0) {
+        where[lab] = s;
+      } else {
+        partner[s] = where[lab];
+        partner[where[lab]] = s;
+        where[lab] = -2;
+      }
     }
     for (int32_t lab = 0; lab < m; ++lab)
-      if (second[lab] < 0) { delete g; return KN_E_INVALID; }
+      if (where[lab] != -2) { delete g; return KN_E_INVALID; }
 
     // crossing signs and orientation consistency: each label must be the
     // outgoing arc of one slot and the incoming arc of another
     g->twist.resize(n);
-    std::vector<int32_t> n_in(m, 0), n_out(m, 0);
+    std::vector<uint8_t> n_in(m, 0), n_out(m, 0);
     for (int32_t i = 0; i < n; ++i) {
       const int32_t* x = pd + 4 * i;
       int sg;
@@ -87,8 +93,11 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
     for (int32_t lab = 0; lab < m; ++lab)
       if (n_in[lab] != 1 || n_out[lab] != 1) { delete g; return KN_E_INVALID; }
 
-    // region tracing over corners
-    const int32_t nc = 4 * n;
+    // region tracing over corners: corner c continues in corner next(c)
+    auto next = [&](int32_t c) {
+      const int32_t far = partner[c];
+      return (far & ~3) | ((far + 3) & 3);
+    };
     std::vector<int32_t> region(nc, -1);
     int32_t nreg = 0;
     for (int32_t c0 = 0; c0 < nc; ++c0) {
@@ -96,55 +105,56 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
       int32_t c = c0;
       while (region[c] < 0) {
         region[c] = nreg;
-        int32_t lab = pd[c];  // slot c: leave along it
-        int32_t far = (first[lab] == c) ? second[lab] : first[lab];
-        c = (far & ~3) | ((far + 3) & 3);
+        c = next(c);
       }
       if (c != c0) { delete g; return KN_E_INVALID; }
       ++nreg;
     }
     if (nreg != n + 2) { delete g; return KN_E_INVALID; }  // not a plane diagram
 
-    // two-colouring by breadth-first search across arcs: the corners of each
-    // region (counting sort by region); corner c and corner (c & ~3) |
-    // ((c + 3) & 3) lie on the two sides of slot c
-    std::vector<int32_t> rc_off(nreg + 1, 0), rc(nc);
-    for (int32_t c = 0; c < nc; ++c) rc_off[region[c] + 1]++;
-    for (int32_t r = 0; r < nreg; ++r) rc_off[r + 1] += rc_off[r];
-    {
-      std::vector<int32_t> fillp(rc_off.begin(), rc_off.end() - 1);
-      for (int32_t c = 0; c < nc; ++c) rc[fillp[region[c]]++] = c;
-    }
+    // two-colouring.  Around a crossing the four corners alternate colours,
+    // so crossing i has a parity par[i]: corner slot k is black iff
+    // (k & 1) == par[i].  Corners c and next(c) lie in one region, which
+    // fixes par of next(c)'s crossing from c's; a breadth-first search over
+    // crossings starts from the outer corner, which is white.
     int32_t arc = outer_arc < 0 ? 0 : outer_arc;
     if (arc >= m) { delete g; return KN_E_INVALID; }
     // the slot where `arc` leaves its crossing
     int32_t leave = -1;
-    for (int32_t s : {first[arc], second[arc]}) {
-      int32_t i = s >> 2, k = s & 3;
-      if (k == 2 || k == out_over_slot(g->twist[i])) leave = s;
+    {
+      // the two slots carrying `arc`
+      int32_t s0 = -1;
+      for (int32_t s = 0; s < nc && s0 < 0; ++s)
+        if (pd[s] == arc) s0 = s;
+      for (int32_t s : {s0, partner[s0]}) {
+        int32_t i = s >> 2, k = s & 3;
+        if (k == 2 || k == out_over_slot(g->twist[i])) leave = s;
+      }
     }
     if (leave < 0) { delete g; return KN_E_INVALID; }
     int32_t outer_corner = outer_side == 0 ? leave : ((leave & ~3) | ((leave + 3) & 3));
-    std::vector<int8_t> colour(nreg, -1);  // 0 white, 1 black
+    std::vector<int8_t> par(n, -1);
     std::vector<int32_t> queue;
-    queue.reserve(nreg);
-    colour[region[outer_corner]] = 0;
-    queue.push_back(region[outer_corner]);
+    queue.reserve(n);
+    par[outer_corner >> 2] = (int8_t)(1 - (outer_corner & 1));
+    queue.push_back(outer_corner >> 2);
     for (size_t h = 0; h < queue.size(); ++h) {
-      int32_t r = queue[h];
-      for (int32_t j = rc_off[r]; j < rc_off[r + 1]; ++j) {
-        const int32_t c = rc[j];
-        for (int32_t s : {region[(c & ~3) | ((c + 3) & 3)], region[(c & ~3) | ((c + 1) & 3)]}) {
-          if (colour[s] < 0) {
-            colour[s] = (int8_t)(1 - colour[r]);
-            queue.push_back(s);
-          } else if (colour[s] == colour[r]) {
-            delete g;
-            return KN_E_INVALID;
-          }
+      const int32_t i = queue[h];
+      for (int32_t k = 0; k < 4; ++k) {
+        const int32_t c = 4 * i + k, d = next(c), j = d >> 2;
+        const int8_t pj = (int8_t)(par[i] ^ (c & 1) ^ (d & 1));
+        if (par[j] < 0) {
+          par[j] = pj;
+          queue.push_back(j);
+        } else if (par[j] != pj) {
+          delete g;
+          return KN_E_INVALID;
         }
       }
     }
+    if ((int32_t)queue.size() != n) { delete g; return KN_E_INVALID; }  // split diagram
+    std::vector<int8_t> colour(nreg, 0);  // 0 white, 1 black
+    for (int32_t c = 0; c < nc; ++c) colour[region[c]] = (int8_t)((c & 1) == par[c >> 2]);
     std::vector<int32_t> vid(nreg, -1);
     int32_t nv = 0;
     for (int32_t r = 0; r < nreg; ++r)
