@@ -31,6 +31,7 @@
 //           simplification factors (loops x_e, spikes x_m + q - 1) and q per
 //           isolated spin, renormalised after every product.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <climits>
 #include <cmath>
@@ -269,7 +270,8 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
         acc.re += prod.re;
         acc.im += prod.im;
       }
-      out[i] = Cx<T>{(T)acc.re, (T)acc.im};
+      if (td.lds_off >= 0) out[i] = Cx<T>{(T)acc.re, (T)acc.im};
+      else st_through(out + i, Cx<T>{(T)acc.re, (T)acc.im});
     }
     // entries are products of <= 8 weights: no scaling needed
     if (lane == 0) st.set(vd.tensor, 0, 0);
@@ -322,6 +324,17 @@ using GlbCx = __attribute__((address_space(1))) Cx<T>;
 
 // Loads and stores of complex entries through address-space-qualified
 // pointers (member-wise, merged into one wide access by the compiler).
+//
+// Tensor entries in global memory are written with system-scope stores,
+// which write through the L2 instead of leaving dirty lines there: a task
+// that finishes then has little left to write back when it releases its
+// results at device scope (the release itself is unchanged), which makes
+// the per-task release noticeably cheaper.
+template <class T>
+__device__ inline void st_through(Cx<T>* p, Cx<T> v) {
+  __hip_atomic_store(&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 template <class P>
 __device__ inline auto ldc(P p) {
   using T = decltype(+p->re);
@@ -329,8 +342,13 @@ __device__ inline auto ldc(P p) {
 }
 template <class P, class T>
 __device__ inline void stc(P p, Cx<T> v) {
-  p->re = v.re;
-  p->im = v.im;
+  if constexpr (std::is_same_v<P, GlbCx<T>*>) {
+    __hip_atomic_store((T*)&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store((T*)&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    p->re = v.re;
+    p->im = v.im;
+  }
 }
 
 // This lane's part of sum_k A[row, k] B[k, col] over k = k_first, k_first + L,
