@@ -563,19 +563,14 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
     }
   };
   // a few units per thread; small images are laid out on the calling thread
-  const size_t nth = std::min<size_t>(std::max<size_t>(1, nU / 16),
-                                      std::max(1u, std::thread::hardware_concurrency()));
+  const size_t nth = std::min<size_t>(std::max<size_t>(1, nU / 16), (size_t)usable_cpus());
   if (nth <= 1) {
     for (size_t ui = 0; ui < nU; ++ui) place(ui);
   } else {
     std::atomic<size_t> next{0};
-    auto worker = [&] {
+    parallel_run((int32_t)std::min<size_t>(nth, 16), [&] {
       for (size_t ui; (ui = next.fetch_add(1)) < nU;) place(ui);
-    };
-    std::vector<std::thread> pool;
-    for (size_t t = 1; t < std::min<size_t>(nth, 16); ++t) pool.emplace_back(worker);
-    worker();
-    for (auto& th : pool) th.join();
+    });
   }
   {
     std::vector<std::pair<double, int32_t>> rs;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -287,6 +288,16 @@ struct FitAlloc {
     }
   }
 };
+
+// Run f() on the calling thread and on up to n_threads - 1 threads of a
+// persistent host pool, returning when every call has returned (f pulls work
+// items itself, e.g. from an atomic counter).  Concurrent callers, and
+// callers in a process forked after the pool started, get threads of their
+// own for the call.
+void parallel_run(int32_t n_threads, const std::function<void()>& f);
+
+// CPUs this process may run on (its affinity mask), at least 1.
+int32_t usable_cpus();
 
 // Lay the knot's plan out as a relocatable device-program section.
 void make_section(PlanKnot& k);

@@ -2,16 +2,19 @@
 // threads, normalise many results (Eq. 4) in one call.
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
 #include <sched.h>
+#include <unistd.h>
 
 #include "internal.h"
 
-namespace {
+namespace kn {
 
-// CPUs this process may run on (its affinity mask), at least 1.
 int32_t usable_cpus() {
   cpu_set_t set;
   CPU_ZERO(&set);
@@ -22,7 +25,92 @@ int32_t usable_cpus() {
   return (int32_t)std::max(1u, std::thread::hardware_concurrency());
 }
 
+namespace {
+
+// Worker threads that sleep on a condition variable between calls.  A call
+// publishes the job under a new generation number; each of the first
+// `want` workers to wake runs it once.  The pool is never destroyed (its
+// threads end with the process).
+class Pool {
+ public:
+  explicit Pool(int32_t n) : pid_(getpid()) {
+    for (int32_t i = 0; i < n; ++i) threads_.emplace_back([this] { loop(); });
+  }
+  pid_t pid() const { return pid_; }
+  int32_t size() const { return (int32_t)threads_.size(); }
+  std::mutex call_mu;  // one call at a time
+
+  void run(int32_t helpers, const std::function<void()>& f) {
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      job_ = &f;
+      want_ = helpers;
+      left_ = helpers;
+      ++gen_;
+    }
+    cv_.notify_all();
+    f();
+    std::unique_lock<std::mutex> lock(mu_);
+    done_cv_.wait(lock, [this] { return left_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lock(mu_);
+    for (;;) {
+      cv_.wait(lock, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (want_ <= 0) continue;
+      --want_;
+      const std::function<void()>* f = job_;
+      lock.unlock();
+      (*f)();
+      lock.lock();
+      if (--left_ == 0) done_cv_.notify_all();
+    }
+  }
+  pid_t pid_;
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void()>* job_ = nullptr;
+  uint64_t gen_ = 0;
+  int32_t want_ = 0, left_ = 0;
+};
+
+std::mutex g_pool_mu;
+Pool* g_pool = nullptr;  // leaked on purpose, replaced in a forked child
+
+Pool* pool() {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (!g_pool || g_pool->pid() != getpid()) g_pool = new Pool(std::min(usable_cpus(), 64) - 1);
+  return g_pool;
+}
+
 }  // namespace
+
+void parallel_run(int32_t n_threads, const std::function<void()>& f) {
+  if (n_threads <= 1) {
+    f();
+    return;
+  }
+  Pool* pl = pool();
+  std::unique_lock<std::mutex> lock(pl->call_mu, std::try_to_lock);
+  if (lock.owns_lock() && pl->size() >= n_threads - 1) {
+    pl->run(n_threads - 1, f);
+    return;
+  }
+  std::vector<std::thread> extra;
+  for (int32_t t = 1; t < n_threads; ++t) extra.emplace_back(f);
+  f();
+  for (auto& th : extra) th.join();
+}
+
+}  // namespace kn
+
+using kn::usable_cpus;
 
 extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_t* pd,
                                   const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
@@ -41,12 +129,18 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
   }
   int32_t nt = n_threads > 0 ? n_threads : usable_cpus();
   nt = std::min(nt, std::max(1, n_knots));
+  // largest knots first, so that the last ones handed out are short
+  std::vector<int32_t> order(n_knots);
+  for (int32_t i = 0; i < n_knots; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return n_crossings[a] > n_crossings[b]; });
   std::atomic<int32_t> next{0};
   std::vector<kn_status> st(n_knots, KN_OK);
-  auto worker = [&]() {
+  std::function<void()> worker = [&]() {
     for (;;) {
-      int32_t i = next.fetch_add(1);
-      if (i >= n_knots) return;
+      const int32_t j = next.fetch_add(1);
+      if (j >= n_knots) return;
+      const int32_t i = order[j];
       kn_tait* g = nullptr;
       kn_status rc = kn_build_tait(n_crossings[i], pd ? pd + 4 * off[i] : nullptr,
                                    signs ? signs + off[i] : nullptr, -1, 0, &g);
@@ -59,10 +153,7 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
       st[i] = rc;
     }
   };
-  std::vector<std::thread> pool;
-  for (int32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
-  worker();
-  for (auto& th : pool) th.join();
+  kn::parallel_run(nt, worker);
   kn_status first = KN_OK;
   for (int32_t i = 0; i < n_knots; ++i) {
     if (status) status[i] = st[i];
