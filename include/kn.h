@@ -140,6 +140,18 @@ void kn_tait_free(kn_tait* g);
  *               Slices run as chains sharing one arena each, as many chains
  *               as mem_budget_bytes (default 16 GiB of arena) allows.  Not
  *               combinable with gradient.
+ * split_serial_log2  a run of small steps whose estimated time (one unit
+ *               per step plus one per 512 multiply-adds) is at least
+ *               2^split_serial_log2 is not executed by one workgroup but level
+ *               by level: the independent steps of each dependency level are
+ *               shared out to several workgroups, the levels one after
+ *               another (with vertex-tensor setup and the final product as
+ *               tasks of their own).  This shortens the longest knots' chains
+ *               at the price of more tasks.  0 = default 40 (never).
+ * gemm_tasks_log2  a step computed in 32 x 32 blocks over workgroups with
+ *               more than 2^gemm_tasks_log2 blocks gives each task several
+ *               blocks (at most 32), which saves per-task scheduling work.
+ *               0 = default 5; 30 = one block per task.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -167,6 +179,8 @@ typedef struct {
   int32_t gradient;
   int32_t tile_macs_log2;
   int32_t slice_log2_budget;
+  int32_t split_serial_log2;
+  int32_t gemm_tasks_log2;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

@@ -738,14 +738,14 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   const int32_t* sbk = sbb + rb;
   const int32_t* sbn = sbk + rk;
   const int32_t tid = threadIdx.x;
+  // this task: contracted range ks of the split, blocks [blk0, blk1) of the
+  // nb * n_mb * n_nb blocks (s.tile blocks per task)
   const int32_t mb_nb = s.n_mb * s.n_nb;
-  const int32_t base = s.nb * mb_nb;
+  const int32_t nblk = s.nb * mb_nb;
+  const int32_t per = s.tile;
+  const int32_t base = (nblk + per - 1) / per;
   const int32_t ks = tile_id / base;
-  int32_t r = tile_id - ks * base;
-  const int32_t b = r / mb_nb;
-  r -= b * mb_nb;
-  const int32_t mblk = r / s.n_nb, nblk = r - mblk * s.n_nb;
-  const int32_t m0 = mblk * BM, n0 = nblk * BM;
+  const int32_t blk0 = (tile_id - ks * base) * per, blk1 = min(nblk, blk0 + per);
   const int32_t k0 = ks * s.kseg, k1 = min(s.nk, k0 + s.kseg), kl = k1 - k0;
 
   Cx<T>* As = reinterpret_cast<Cx<T>*>(smem);
@@ -759,84 +759,90 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
       ktab[2 * i + 1] = group_off(k0 + i, sbk, rk, D);
     }
   }
-  // this thread's loads: contracted entry kk of rows/columns lr and lr + 16
-  const int32_t kk = tid & (BK - 1), lr = tid >> 4;
-  const GlbCx<T>* A = (const GlbCx<T>*)(arena + s.home_a);
-  const GlbCx<T>* B = (const GlbCx<T>*)(arena + s.home_b);
-  const bool am0 = m0 + lr < s.nm, am1 = m0 + lr + 16 < s.nm;
-  const bool bn0 = n0 + lr < s.nn, bn1 = n0 + lr + 16 < s.nn;
-  const int32_t oab = group_off(b, sab, rb, D), obb = group_off(b, sbb, rb, D);
-  const int32_t ra0 = am0 ? oab + group_off(m0 + lr, sam, rm, D) : 0;
-  const int32_t ra1 = am1 ? oab + group_off(m0 + lr + 16, sam, rm, D) : 0;
-  const int32_t cb0 = bn0 ? obb + group_off(n0 + lr, sbn, rn, D) : 0;
-  const int32_t cb1 = bn1 ? obb + group_off(n0 + lr + 16, sbn, rn, D) : 0;
   int64_t ec;
   const T scale = step_scale<T>(st, s.a, s.b, ec);
+  // this thread's loads: contracted entry kk of rows/columns lr and lr + 16
+  const int32_t kk = tid & (BK - 1), lr = tid >> 4;
+  const int32_t tx = tid & 15, ty = tid >> 4;
+  const GlbCx<T>* A = (const GlbCx<T>*)(arena + s.home_a);
+  const GlbCx<T>* B = (const GlbCx<T>*)(arena + s.home_b);
+  const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
+  GlbCx<T>* C = (GlbCx<T>*)(s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c);
+  T lm = 0;
   __syncthreads();
 
   struct Quad {
     Cx<T> a0, a1, b0, b1;
   };
-  auto load = [=](int32_t c0) -> Quad {
-    const int32_t k = c0 + kk;
-    Quad x{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    if (k < kl) {
-      int32_t oa, ob;
-      if (use_tab) {
-        oa = ktab[2 * k];
-        ob = ktab[2 * k + 1];
-      } else {
-        oa = group_off(k0 + k, sak, rk, D);
-        ob = group_off(k0 + k, sbk, rk, D);
+  for (int32_t blk = blk0; blk < blk1; ++blk) {
+    const int32_t b = blk / mb_nb;
+    const int32_t r = blk - b * mb_nb;
+    const int32_t mblk = r / s.n_nb, nbk = r - mblk * s.n_nb;
+    const int32_t m0 = mblk * BM, n0 = nbk * BM;
+    const bool am0 = m0 + lr < s.nm, am1 = m0 + lr + 16 < s.nm;
+    const bool bn0 = n0 + lr < s.nn, bn1 = n0 + lr + 16 < s.nn;
+    const int32_t oab = group_off(b, sab, rb, D), obb = group_off(b, sbb, rb, D);
+    const int32_t ra0 = am0 ? oab + group_off(m0 + lr, sam, rm, D) : 0;
+    const int32_t ra1 = am1 ? oab + group_off(m0 + lr + 16, sam, rm, D) : 0;
+    const int32_t cb0 = bn0 ? obb + group_off(n0 + lr, sbn, rn, D) : 0;
+    const int32_t cb1 = bn1 ? obb + group_off(n0 + lr + 16, sbn, rn, D) : 0;
+    auto load = [=](int32_t c0) -> Quad {
+      const int32_t k = c0 + kk;
+      Quad x{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      if (k < kl) {
+        int32_t oa, ob;
+        if (use_tab) {
+          oa = ktab[2 * k];
+          ob = ktab[2 * k + 1];
+        } else {
+          oa = group_off(k0 + k, sak, rk, D);
+          ob = group_off(k0 + k, sbk, rk, D);
+        }
+        if (am0) x.a0 = ldc(A + ra0 + oa);
+        if (am1) x.a1 = ldc(A + ra1 + oa);
+        if (bn0) x.b0 = ldc(B + cb0 + ob);
+        if (bn1) x.b1 = ldc(B + cb1 + ob);
       }
-      if (am0) x.a0 = ldc(A + ra0 + oa);
-      if (am1) x.a1 = ldc(A + ra1 + oa);
-      if (bn0) x.b0 = ldc(B + cb0 + ob);
-      if (bn1) x.b1 = ldc(B + cb1 + ob);
-    }
-    return x;
-  };
-  const int32_t tx = tid & 15, ty = tid >> 4;
-  T c00r = 0, c00i = 0, c01r = 0, c01i = 0, c10r = 0, c10i = 0, c11r = 0, c11i = 0;
-  Quad x = load(0);
-  for (int32_t c0 = 0; c0 < kl; c0 += BK) {
-    As[kk * P + lr] = x.a0;
-    As[kk * P + lr + 16] = x.a1;
-    Bs[kk * P + lr] = x.b0;
-    Bs[kk * P + lr + 16] = x.b1;
-    __syncthreads();
-    if (c0 + BK < kl) x = load(c0 + BK);
+      return x;
+    };
+    T c00r = 0, c00i = 0, c01r = 0, c01i = 0, c10r = 0, c10i = 0, c11r = 0, c11i = 0;
+    Quad x = load(0);
+    for (int32_t c0 = 0; c0 < kl; c0 += BK) {
+      As[kk * P + lr] = x.a0;
+      As[kk * P + lr + 16] = x.a1;
+      Bs[kk * P + lr] = x.b0;
+      Bs[kk * P + lr + 16] = x.b1;
+      __syncthreads();
+      if (c0 + BK < kl) x = load(c0 + BK);
 #pragma unroll 4
-    for (int32_t j = 0; j < BK; ++j) {
-      const Cx<T> a0 = As[j * P + ty], a1 = As[j * P + ty + 16];
-      const Cx<T> b0 = Bs[j * P + tx], b1 = Bs[j * P + tx + 16];
-      c00r = fma(a0.re, b0.re, c00r); c00r = fma(-a0.im, b0.im, c00r);
-      c00i = fma(a0.re, b0.im, c00i); c00i = fma(a0.im, b0.re, c00i);
-      c01r = fma(a0.re, b1.re, c01r); c01r = fma(-a0.im, b1.im, c01r);
-      c01i = fma(a0.re, b1.im, c01i); c01i = fma(a0.im, b1.re, c01i);
-      c10r = fma(a1.re, b0.re, c10r); c10r = fma(-a1.im, b0.im, c10r);
-      c10i = fma(a1.re, b0.im, c10i); c10i = fma(a1.im, b0.re, c10i);
-      c11r = fma(a1.re, b1.re, c11r); c11r = fma(-a1.im, b1.im, c11r);
-      c11i = fma(a1.re, b1.im, c11i); c11i = fma(a1.im, b1.re, c11i);
+      for (int32_t j = 0; j < BK; ++j) {
+        const Cx<T> a0 = As[j * P + ty], a1 = As[j * P + ty + 16];
+        const Cx<T> b0 = Bs[j * P + tx], b1 = Bs[j * P + tx + 16];
+        c00r = fma(a0.re, b0.re, c00r); c00r = fma(-a0.im, b0.im, c00r);
+        c00i = fma(a0.re, b0.im, c00i); c00i = fma(a0.im, b0.re, c00i);
+        c01r = fma(a0.re, b1.re, c01r); c01r = fma(-a0.im, b1.im, c01r);
+        c01i = fma(a0.re, b1.im, c01i); c01i = fma(a0.im, b1.re, c01i);
+        c10r = fma(a1.re, b0.re, c10r); c10r = fma(-a1.im, b0.im, c10r);
+        c10i = fma(a1.re, b0.im, c10i); c10i = fma(a1.im, b0.re, c10i);
+        c11r = fma(a1.re, b1.re, c11r); c11r = fma(-a1.im, b1.im, c11r);
+        c11i = fma(a1.re, b1.im, c11i); c11i = fma(a1.im, b1.re, c11i);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    const int64_t crow = (int64_t)b * s.nm;
+    auto put = [&](int32_t m, int32_t n, T cr, T ci) {
+      if (m < s.nm && n < s.nn) {
+        cr *= scale;
+        ci *= scale;
+        stc(C + (crow + m) * s.nn + n, Cx<T>{cr, ci});
+        lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
+      }
+    };
+    put(m0 + ty, n0 + tx, c00r, c00i);
+    put(m0 + ty, n0 + tx + 16, c01r, c01i);
+    put(m0 + ty + 16, n0 + tx, c10r, c10i);
+    put(m0 + ty + 16, n0 + tx + 16, c11r, c11i);
   }
-  const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
-  GlbCx<T>* C = (GlbCx<T>*)(s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c);
-  const int64_t crow = (int64_t)b * s.nm;
-  T lm = 0;
-  auto put = [&](int32_t m, int32_t n, T cr, T ci) {
-    if (m < s.nm && n < s.nn) {
-      cr *= scale;
-      ci *= scale;
-      stc(C + (crow + m) * s.nn + n, Cx<T>{cr, ci});
-      lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
-    }
-  };
-  put(m0 + ty, n0 + tx, c00r, c00i);
-  put(m0 + ty, n0 + tx + 16, c01r, c01i);
-  put(m0 + ty + 16, n0 + tx, c10r, c10i);
-  put(m0 + ty + 16, n0 + tx + 16, c11r, c11i);
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
 

@@ -58,7 +58,18 @@ struct PGroup {
   int32_t first, count;  // knot-local steps
   int32_t flags;
   int32_t n_tiles;       // tile and reduce groups: tasks
+  // serial groups of one dependency level: its steps shared out to several
+  // tasks as (first, count) chunks; empty = one task for all the steps
+  std::vector<std::pair<int32_t, int32_t>> chunks;
 };
+
+// Estimated time of a serial step (arbitrary units: one per step plus one per
+// 512 multiply-adds).  A task of a level-split run aims at 1/32 of the split
+// threshold, and a level has at most kSplitMaxChunks tasks.
+inline double step_est(const StepDesc& x) {
+  return 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
+}
+constexpr int32_t kSplitMaxChunks = 16;
 
 }  // namespace
 
@@ -200,6 +211,45 @@ void make_section(PlanKnot& k) {
     cur.flags |= TF_FINAL;
     pg.push_back(cur);
   }
+  // ---- long serial runs level by level: setup, one group per dependency
+  // level (its independent steps in chunks over several tasks), final product
+  {
+    std::vector<PGroup> out;
+    out.reserve(pg.size());
+    for (PGroup& g : pg) {
+      double est = 0;
+      if (g.kind == TASK_SERIAL)
+        for (int32_t si = g.first; si < g.first + g.count; ++si) est += step_est(S.sd[si]);
+      if (g.kind != TASK_SERIAL || g.count < 2 || est < k.split_est) {
+        out.push_back(std::move(g));
+        continue;
+      }
+      if (g.flags & TF_SETUP) out.push_back(PGroup{TASK_SERIAL, g.first, 0, TF_SETUP, 0, {}});
+      const int32_t end = g.first + g.count;
+      for (int32_t a = g.first; a < end;) {
+        int32_t b = a + 1;
+        while (b < end && k.tiling[b].level == k.tiling[a].level) ++b;
+        PGroup lg{TASK_SERIAL, a, b - a, 0, 0, {}};
+        double lev = 0;
+        for (int32_t si = a; si < b; ++si) lev += step_est(S.sd[si]);
+        const double target = std::max(k.split_est / 32.0, lev / kSplitMaxChunks);
+        double acc = 0;
+        int32_t c0 = a;
+        for (int32_t si = a; si < b; ++si) {
+          acc += step_est(S.sd[si]);
+          if (acc >= target || si + 1 == b) {
+            lg.chunks.emplace_back(c0, si + 1 - c0);
+            c0 = si + 1;
+            acc = 0;
+          }
+        }
+        out.push_back(std::move(lg));
+        a = b;
+      }
+      if (g.flags & TF_FINAL) out.push_back(PGroup{TASK_SERIAL, end, 0, TF_FINAL, 0, {}});
+    }
+    pg.swap(out);
+  }
 
   // ---- LDS homes: tensors produced and consumed inside one serial group
   // (gradient plans read every tensor again in the reverse pass: all global)
@@ -275,16 +325,24 @@ void make_section(PlanKnot& k) {
     G.first_task = (int32_t)S.tasks.size();
     G.next = gi + 1 < pg.size() ? (int32_t)gi + 1 : -1;
     G.n_pred = gi == 0 ? 0 : S.groups.back().n_tasks;
-    if (g.kind == TASK_SERIAL) {
+    if (g.kind == TASK_SERIAL && !g.chunks.empty()) {
+      // one dependency level over several tasks (no setup or final here)
+      double longest = 0;
+      for (const auto& [cf, cc] : g.chunks) {
+        S.tasks.push_back({TASK_SERIAL, 0, (int32_t)gi, cf, cc, 0, n_vt + cf, cc});
+        double e = 0;
+        for (int32_t si = cf; si < cf + cc; ++si) e += step_est(S.sd[si]);
+        longest = std::max(longest, e);
+      }
+      G.n_tasks = (int32_t)g.chunks.size();
+      S.est += 3.0 + longest;
+    } else if (g.kind == TASK_SERIAL) {
       // tensors made here: vertex tensors (ids 0..) and step outputs, consecutive
       int32_t lo = (g.flags & TF_SETUP) ? 0 : n_vt + g.first;
       int32_t len = ((g.flags & TF_SETUP) ? n_vt : 0) + g.count;
       S.tasks.push_back({TASK_SERIAL, 0, (int32_t)gi, g.first, g.count, g.flags, lo, len});
       G.n_tasks = 1;
-      for (int32_t si = g.first; si < g.first + g.count; ++si) {
-        const StepDesc& x = S.sd[si];
-        S.est += 1.0 + double(x.nb) * x.nm * x.nn * x.nk / 512.0;
-      }
+      for (int32_t si = g.first; si < g.first + g.count; ++si) S.est += step_est(S.sd[si]);
     } else if (g.kind == TASK_TILE) {
       for (int32_t tl = 0; tl < g.n_tiles; ++tl)
         S.tasks.push_back({TASK_TILE, 0, (int32_t)gi, g.first, tl, 0, 0, 0});

@@ -212,6 +212,8 @@ struct PlanKnot {
   int32_t tile = 256;
   int32_t big_log2 = 16;
   int32_t lds_bytes = 32768;
+  double split_est = 1024;                      // serial runs estimated at least this
+                                                // long run level by level
   std::vector<PTiling> tiling;                  // per step: how it is executed
   Section sec;  // device-program section (make_section)
 

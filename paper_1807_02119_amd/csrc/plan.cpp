@@ -51,6 +51,12 @@ constexpr double kSplitBelow = 256;
 // this many flops (below it the greedy plan rarely wins and planning time
 // matters more).
 constexpr double kAutoGreedyFrom = 1e8;
+// GEMM steps: tasks per step aimed at (log2) and most 32 x 32 blocks per task
+constexpr int32_t kGemmTasksLog2 = 5;
+constexpr int32_t kGemmMaxBlocks = 32;
+// default threshold (log2 of the estimated time) above which a serial run is
+// executed level by level over several workgroups
+constexpr int32_t kSplitSerialLog2 = 40;
 // Slicing fixes at most this many spins, and makes at most kMaxSlices slices.
 constexpr int32_t kMaxSliceSpins = 12;
 constexpr double kMaxSlices = 4096;  // each slice is a copy of the knot's descriptors
@@ -928,6 +934,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
   k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
   k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
+  k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
   {
     double qq = q;
     if (q < 4) {
@@ -1021,7 +1028,12 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       t.mode = STEP_GEMM;
       t.n_mb = (int32_t)std::ceil(nm / kGemmBlock);
       t.n_nb = (int32_t)std::ceil(nn / kGemmBlock);
-      base = nb * t.n_mb * t.n_nb;
+      // blocks per task: a step with many blocks gives each task several,
+      // so that it still has about 2^gemm_tasks_log2 tasks
+      const double blocks = nb * t.n_mb * t.n_nb;
+      const double target = std::ldexp(1.0, o.gemm_tasks_log2 > 0 ? o.gemm_tasks_log2 : kGemmTasksLog2);
+      t.tile = (int32_t)std::max(1.0, std::min((double)kGemmMaxBlocks, std::floor(blocks / target)));
+      base = std::ceil(blocks / t.tile);
     } else {
       // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
       t.mode = STEP_TILES;
@@ -1133,6 +1145,8 @@ static kn_plan_opts default_opts() {
   o.gradient = 0;
   o.tile_macs_log2 = 0;
   o.slice_log2_budget = 0;
+  o.split_serial_log2 = 0;
+  o.gemm_tasks_log2 = 0;
   return o;
 }
 
@@ -1152,6 +1166,8 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (o.gradient != 0 && o.gradient != 1) return KN_E_INVALID;
   if (o.gradient && (o.simplify & 2)) return KN_E_INVALID;
   if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
+  if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
+  if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;
   if (o.gradient && o.slice_log2_budget) return KN_E_UNSUPPORTED;
   kn_plan* p = new (std::nothrow) kn_plan();
   if (!p) return KN_E_NOMEM;

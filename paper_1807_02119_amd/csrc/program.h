@@ -141,7 +141,7 @@ struct StepDesc {
   int32_t str;              // strides: A_b[rb] A_m[rm] A_k[rk] B_b[rb] B_k[rk] B_n[rn]
   int32_t ranks;            // rb | rm << 8 | rk << 16 | rn << 24
   int32_t n_tiles;          // 0 for steps run inside a serial task
-  int32_t tile;             // STEP_TILES: outputs per tile
+  int32_t tile;             // STEP_TILES: outputs per tile; STEP_GEMM: blocks per task
   // where A, B, C live: >= 0 global arena offset (complex entries),
   // < 0 LDS arena offset -1 - value (serial steps only)
   int32_t home_a, home_b, home_c;

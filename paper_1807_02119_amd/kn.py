@@ -35,7 +35,8 @@ class PlanOpts(ctypes.Structure):
                 ("mem_budget_bytes", ctypes.c_uint64), ("tile_outputs", ctypes.c_int32),
                 ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32),
-                ("tile_macs_log2", ctypes.c_int32), ("slice_log2_budget", ctypes.c_int32)]
+                ("tile_macs_log2", ctypes.c_int32), ("slice_log2_budget", ctypes.c_int32),
+                ("split_serial_log2", ctypes.c_int32), ("gemm_tasks_log2", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -189,13 +190,15 @@ class Plan:
     def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
                  paper_stats=False, lds_bytes=0, gradient=False, tile_macs_log2=0,
-                 slice_log2_budget=0, allow_budget=False):
+                 slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
+                 allow_budget=False):
         L = lib()
         if simplify is None:
             simplify = 1 if (gradient or not jones_only) else 3
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
                      tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
-                     1 if gradient else 0, tile_macs_log2, slice_log2_budget)
+                     1 if gradient else 0, tile_macs_log2, slice_log2_budget, split_serial_log2,
+                     gemm_tasks_log2)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -266,7 +269,7 @@ def _wrap_plan(h, tait, q, opts):
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
               tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-              tile_macs_log2=0, slice_log2_budget=0):
+              tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0):
     """Tait graphs and plans for many knots on the library's host thread pool
     (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
     L = lib()
@@ -279,7 +282,7 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
         simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
                  big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
-                 slice_log2_budget)
+                 slice_log2_budget, split_serial_log2, gemm_tasks_log2)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)

@@ -5,7 +5,9 @@ How a step runs is decided by a few planner knobs:
   into tiles over workgroups instead of running inside a serial task;
 - tile_macs_log2: how much work one tile of outputs carries;
 - lds_bytes: the per-workgroup LDS arena for tensors that stay inside one
-  serial task, which also sets how many workgroups fit on a compute unit.
+  serial task, which also sets how many workgroups fit on a compute unit;
+- gemm_tasks_log2: how many tasks a step computed in 32 x 32 blocks is cut
+  into (several blocks per task above that).
 The persistent kernel's grid is the fourth knob.  The tuner times
 kn_batch_contract with HIP events (on the launch stream) on a sample of a
 workload, searches the knobs by coordinate descent from the defaults, and
@@ -28,8 +30,10 @@ SPACE = {
     "big_step_macs_log2": [14, 15, 16, 17, 18],
     "tile_macs_log2": [13, 14, 15, 16, 17],
     "lds_bytes": [16384, 24576, 32768, 49152],
+    "gemm_tasks_log2": [4, 5, 6, 7, 30],
 }
-DEFAULTS = {"big_step_macs_log2": 16, "tile_macs_log2": 15, "lds_bytes": 24576, "grid": 0}
+DEFAULTS = {"big_step_macs_log2": 16, "tile_macs_log2": 15, "lds_bytes": 24576,
+            "gemm_tasks_log2": 5, "grid": 0}
 TUNED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
 
 

@@ -214,8 +214,8 @@ def run(raw: bytes, J=None, want_grad=False):
                 tile = int(s["tile"])
                 assert base * tile >= outs and (base - 1) * tile < outs
             else:
-                n_mb, n_nb = int(s["n_mb"]), int(s["n_nb"])
-                assert base == nb * n_mb * n_nb
+                n_mb, n_nb, per = int(s["n_mb"]), int(s["n_nb"]), int(s["tile"])
+                assert per >= 1 and base == -(-nb * n_mb * n_nb // per)
                 assert n_mb * GEMM_BLOCK >= nm and (n_mb - 1) * GEMM_BLOCK < nm
                 assert n_nb * GEMM_BLOCK >= nn and (n_nb - 1) * GEMM_BLOCK < nn
         Am = A[tAb[:, None, None] + tAm[None, :, None] + tAk[None, None, :]]

@@ -151,6 +151,11 @@ def test_gemm_and_split_parity():
     for k in range(3):
         cases.append((f"lattice{k}", gen.lattice_knot((63, k), 100, 400),
                       dict(big_step_macs_log2=4)))
+    # several 32 x 32 blocks per task (ragged last task of a step)
+    cases.append((71, work[71][0], dict(strategy=0, gemm_tasks_log2=1)))
+    cases.append((11, work[11][0], dict(gemm_tasks_log2=3)))
+    cases.append(("lattice0", gen.lattice_knot((63, 0), 100, 400),
+                  dict(big_step_macs_log2=4, gemm_tasks_log2=2)))
     for name, d, kw in cases:
         _log(f"gemm/split case {name} {kw}")
         tg, mo, eo = oracle_z(d, 3)
@@ -158,6 +163,29 @@ def test_gemm_and_split_parity():
             t, p, m, e = gpu_z(d, 3, precision=prec, **kw)
             tol = TOL if prec == 0 else 1e-3
             assert z_close(m, e, mo, eo, tol), (name, kw, prec)
+
+
+def test_level_split_parity():
+    """Serial runs executed level by level over several workgroups (setup and
+    final product as tasks of their own, each level's steps in chunks), for
+    single plans and a batch, complex128 and complex64."""
+    cases = [gen.lattice_knot((84, k), 60, 200) for k in range(4)]
+    cases.append(gen.config_knots("q3_200_600", 0, count=72)[11][0])
+    for d in cases:
+        tg, mo, eo = oracle_z(d, 3)
+        for split in (3, 6):
+            _log(f"level split {d.label} n={d.n} split_serial_log2={split}")
+            for prec in (0, 1):
+                t, p, m, e = gpu_z(d, 3, precision=prec, split_serial_log2=split)
+                tol = TOL if prec == 0 else 1e-3
+                assert z_close(m, e, mo, eo, tol), (d.label, split, prec)
+    taits = [kn.Tait(d.pd) for d in cases]
+    plans = [kn.Plan(t, 3, split_serial_log2=(3 if i % 2 else 40)) for i, t in enumerate(taits)]
+    z = kn.Batch(plans).contract()
+    torch.cuda.synchronize()
+    for (m, e), d in zip(kn.scalars_from_device(z), cases):
+        tg, mo, eo = oracle_z(d, 3)
+        assert z_close(m, e, mo, eo, TOL), d.label
 
 
 def test_exact_ring_parity():

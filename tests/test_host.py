@@ -142,7 +142,9 @@ def test_plan_model_tiled_and_options():
                    dict(simplify=1, jones_only=True),
                    dict(simplify=1, jones_only=False),
                    dict(strategy=0), dict(strategy=1), dict(strategy=2),
-                   dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1)):
+                   dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1),
+                   dict(split_serial_log2=3), dict(split_serial_log2=40),
+                   dict(big_step_macs_log2=4, gemm_tasks_log2=1)):
             _check_model(d, 3, **kw)
 
 
