@@ -116,62 +116,134 @@ def main():
     knots = gen.config_knots("q3_200_600", args.seed, count=B)
     pds = [np.ascontiguousarray(d.pd, dtype=np.int32) for d, _ in knots]
     ncross = [d.n for d, _ in knots]
+    # the batch's input as the library takes it: crossing counts and the PD
+    # codes concatenated
+    ncr_arr = np.asarray(ncross, np.int32)
+    flat_pd = np.concatenate([p.reshape(-1) for p in pds])
     stream = torch.cuda.current_stream()
 
     # ---------------------------------------------------------------- pipeline
-    # Host work of a batch (Tait graphs and plans on the library's thread pool,
-    # then the batch device program) runs on a helper thread while the GPU
-    # contracts the previous batch; the library calls release the GIL.
+    # Two threads.  A helper prepares batch i+1 (Tait graphs and plans on the
+    # library's thread pool, the batch device program, its upload on a side
+    # stream into one of two alternating workspaces) while the launch thread
+    # contracts batch i and, while the GPU runs it, forms V = A Z of batch i - 1
+    # and releases that batch.  The library calls release the GIL.
     state = {}
+    # the threads hand the interpreter lock to each other often: switch fast
+    sys.setswitchinterval(1e-4)
     pool = ThreadPoolExecutor(max_workers=1)
+    up_stream = torch.cuda.Stream()
 
     # knob settings recorded by the autotuner for this workload (plan options
     # and the persistent grid), per precision; defaults when none was recorded
     tuned = {p: tune.load("q3_200_600", p) for p in (0, 1)} if not args.untuned else {0: {}, 1: {}}
 
+    # wall time of each part of the pipeline, summed over the timed steps
+    phase = {k: 0.0 for k in ("prepare", "plan", "batch", "upload", "handoff", "device", "launch",
+                              "wait", "jones")}
+    counter = [0]
+
+    def workspace(slot, need, precision):
+        ws = state.get(("ws", precision, slot))
+        if ws is None or ws.numel() < need + 256:
+            ws = kn.alloc_workspace(need)
+            state[("ws", precision, slot)] = ws
+        return ws
+
     def prepare(precision=0):
+        tp = time.perf_counter()
         opts = {k: v for k, v in tuned[precision].items() if k != "grid"}
-        taits, plans = kn.plan_many(pds, q, n_threads=args.threads, precision=precision, **opts)
+        plans = kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, precision=precision,
+                            **opts)
+        taits = plans  # the set holds the Tait graphs too
+        t1 = time.perf_counter()
         batch = kn.Batch(plans)
         if tuned[precision].get("grid"):
             batch.set_grid(int(tuned[precision]["grid"]))
-        return taits, plans, batch
+        t2 = time.perf_counter()
+        # the workspace this batch uses was last used two batches ago, whose
+        # contraction the launch thread has waited for
+        slot = counter[0] % 2
+        counter[0] += 1
+        ws = workspace(slot, batch.workspace_bytes, precision)
+        batch.upload(ws, up_stream)
+        uploaded = torch.cuda.Event()
+        uploaded.record(up_stream)
+        t3 = time.perf_counter()
+        phase["plan"] += t1 - tp
+        phase["batch"] += t2 - t1
+        phase["upload"] += t3 - t2
+        phase["prepare"] += t3 - tp
+        return taits, plans, batch, uploaded
 
-    def device(prepared, precision=0):
-        taits, plans, batch = prepared
-        need = batch.workspace_bytes
-        ws = state.get(("ws", precision))
-        if ws is None or ws.numel() < need + 256:
-            ws = kn.alloc_workspace(need)
-            state[("ws", precision)] = ws
+    def launch(prepared, precision=0):
+        """Queue batch i's contraction behind its upload."""
+        taits, plans, batch, uploaded = prepared
         z = state.get(("z", precision))
         if z is None:
             z = kn.alloc_scalars(B)
             state[("z", precision)] = z
-        batch.upload(ws, stream)
+        t1 = time.perf_counter()
+        stream.wait_event(uploaded)
         batch.contract(stream=stream, z=z)
-        zh = z.cpu().numpy()  # synchronises
+        done = torch.cuda.Event()
+        done.record(stream)
+        phase["launch"] += time.perf_counter() - t1
+        return done, z
+
+    def finish(prepared, done, z, hand=None):
+        """While the GPU runs batch i: form V = A Z of batch i - 1 (handed over
+        in the list `hand`, which holds the only reference) and release that
+        batch; then wait for batch i's Z."""
+        taits, plans, batch, _ = prepared
+        previous = hand.pop() if hand else None
+        t2 = time.perf_counter()
+        if previous is not None:
+            ptaits, _, _, pzh = previous
+            kn.jones_many(q, ptaits, pzh)
+            del previous, ptaits
+        t3 = time.perf_counter()
+        # wait without spinning: the planning threads need every core
+        while not done.query():
+            time.sleep(50e-6)
+        zh = z.cpu().numpy()
+        t4 = time.perf_counter()
+        phase["jones"] += t3 - t2
+        phase["wait"] += t4 - t3
+        return taits, plans, batch, zh
+
+    def run_steps(n, precision=0):
+        """n whole batches, host preparation (and upload) of batch i+1
+        overlapped with the device work of batch i; returns the last batch's
+        results (every batch's V is formed before this returns)."""
+        fut = pool.submit(prepare, precision)
+        cur = None
+        for i in range(n):
+            t0 = time.perf_counter()
+            prepared = fut.result()
+            t1 = time.perf_counter()
+            done, z = launch(prepared, precision)
+            if i + 1 < n:
+                fut = pool.submit(prepare, precision)
+            hand = [cur] if cur is not None else None
+            cur = None
+            cur = finish(prepared, done, z, hand)
+            del prepared
+            phase["handoff"] += t1 - t0
+            phase["device"] += time.perf_counter() - t1
+        taits, plans, batch, zh = cur
         v, l2, ar = kn.jones_many(q, taits, zh)
         return taits, plans, batch, zh, v, l2, ar
 
-    def run_steps(n, precision=0):
-        """n whole batches, host preparation of batch i+1 overlapped with the
-        device work of batch i; returns the last batch's results."""
-        fut = pool.submit(prepare, precision)
-        out = None
-        for i in range(n):
-            prepared = fut.result()
-            if i + 1 < n:
-                fut = pool.submit(prepare, precision)
-            out = device(prepared, precision)
-        return out
-
     run_steps(max(1, args.warmup))
     torch.cuda.synchronize()
+    for k in phase:
+        phase[k] = 0.0
     t0 = time.perf_counter()
     taits, plans, batch, zh, v, l2, ar = run_steps(args.steps)
     torch.cuda.synchronize()
     ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    pipeline_ms = {k: round(1e3 * t / args.steps, 3) for k, t in phase.items()}
     value = B / (ms_step / 1e3)
 
     # ---------------------------------------------------------------- GPU contraction alone
@@ -196,8 +268,8 @@ def main():
 
     # host-only breakdown of one step: plans, then plans + device program
     t0 = time.perf_counter()
-    kn.plan_many(pds, q, n_threads=args.threads,
-                 **{k: v for k, v in tuned[0].items() if k != "grid"})
+    kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads,
+                **{k: v for k, v in tuned[0].items() if k != "grid"})
     ms_plan = 1e3 * (time.perf_counter() - t0)
     t0 = time.perf_counter()
     prepare()
@@ -252,6 +324,7 @@ def main():
         "host_prepare_ms": ms_prepare,
         "host_threads": args.threads if args.threads > 0 else len(os.sched_getaffinity(0)),
         "pipelined": "host preparation of batch i+1 overlaps the GPU work of batch i",
+        "pipeline_ms": pipeline_ms,
         "tuned": tuned[0] or None,
         "gpu_contract": {
             "ms_per_batch": ms_gpu,
@@ -293,13 +366,14 @@ def main():
 
     # ---------------------------------------------------------------- one knot per call
     if not args.no_single:
-        ws = kn.alloc_workspace(max(p.workspace_bytes for p in plans))
+        single = [plans.plan(i) for i in range(len(plans))]
+        ws = kn.alloc_workspace(max(p.workspace_bytes for p in single))
         z1 = kn.alloc_scalars(1)
-        for p in plans[:4]:
+        for p in single[:4]:
             kn.contract(p, workspace=ws, stream=stream, z=z1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for p in plans:
+        for p in single:
             kn.contract(p, workspace=ws, stream=stream, z=z1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0

@@ -281,6 +281,9 @@ kn_status kn_jones_variable(int32_t q, double* t_re, double* t_im);
 kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_t* pd,
                        const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
                        int32_t n_threads, kn_tait** taits, kn_plan** plans, kn_status* status);
+/* Free n Tait graphs and n plans (as returned by kn_plan_many; null entries
+ * are skipped; either array may be NULL). */
+void kn_free_many(int32_t n, kn_tait** taits, kn_plan** plans);
 /* kn_jones for n knots: v (nullable) receives 2n doubles (re, im). */
 kn_status kn_jones_many(int32_t n, const int32_t* q, const kn_tait* const* g,
                         const kn_scalar* z_host, double* v, double* log2_abs_v, double* arg_v);

@@ -37,6 +37,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <algorithm>
 #include <new>
@@ -1252,6 +1253,57 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
 
 // ------------------------------------------------------------------ host side
 
+// Pool of host buffers for batch images.  Page-locked memory (hipHostMalloc)
+// makes an image upload a DMA transfer with no staging copy on the CPU; it is
+// slow to allocate, so buffers are kept and reused (best fit by capacity).
+// Without a usable device the buffers are ordinary heap memory.
+namespace {
+
+std::mutex g_buf_mu;
+std::multimap<size_t, std::pair<uint8_t*, bool>> g_buf_free;  // capacity -> (buffer, pinned)
+
+}  // namespace
+
+uint8_t* host_buf_get(size_t bytes, size_t* capacity, bool* pinned) {
+  {
+    std::lock_guard<std::mutex> lock(g_buf_mu);
+    auto it = g_buf_free.lower_bound(bytes);
+    if (it != g_buf_free.end() && it->first <= 2 * bytes + (1u << 20)) {
+      *capacity = it->first;
+      *pinned = it->second.second;
+      uint8_t* p = it->second.first;
+      g_buf_free.erase(it);
+      return p;
+    }
+  }
+  const size_t cap = (std::max<size_t>(bytes, 1) + (1u << 20) - 1) & ~size_t((1u << 20) - 1);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, cap, hipHostMallocDefault) == hipSuccess && p) {
+    *capacity = cap;
+    *pinned = true;
+    return static_cast<uint8_t*>(p);
+  }
+  (void)hipGetLastError();  // no device: fall back to the heap
+  p = std::malloc(cap);
+  if (!p) return nullptr;
+  *capacity = cap;
+  *pinned = false;
+  return static_cast<uint8_t*>(p);
+}
+
+void host_buf_put(uint8_t* p, size_t capacity, bool pinned) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_buf_mu);
+  g_buf_free.emplace(capacity, std::make_pair(p, pinned));
+  // keep the pool bounded: drop the largest buffers beyond 8
+  while (g_buf_free.size() > 8) {
+    auto last = std::prev(g_buf_free.end());
+    if (last->second.second) (void)hipHostFree(last->second.first);
+    else std::free(last->second.first);
+    g_buf_free.erase(last);
+  }
+}
+
 namespace {
 
 int device_cus() {
@@ -1370,10 +1422,11 @@ extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_
   kn_batch* b = new (std::nothrow) kn_batch();
   if (!b) return KN_E_NOMEM;
   try {
-    b->image = build_image(ks);
-    if (b->image.empty()) {
+    const int64_t nb = build_image_into(
+        ks, [&](size_t bytes) { return b->image.allocate(bytes); }, nullptr);
+    if (nb < 0) {
       delete b;
-      return KN_E_BUDGET;
+      return nb == -2 ? KN_E_NOMEM : KN_E_BUDGET;
     }
     b->precision = plans[0]->k.precision;
     b->jones_only = jones_only;

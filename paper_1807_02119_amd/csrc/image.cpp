@@ -22,6 +22,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -359,7 +360,8 @@ void make_section(PlanKnot& k) {
   }
 }
 
-Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
+int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
+                         const std::function<uint8_t*(size_t)>& buffer, ImgHeader* header) {
   ImgHeader h;
   std::memset(&h, 0, sizeof(h));
   h.magic = kMagic;
@@ -493,15 +495,11 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
   h.state_bytes = st;
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);
-  if (h.arena_elems > INT32_MAX) return {};  // step homes hold int32 offsets
+  if (h.arena_elems > INT32_MAX) return -1;  // step homes hold int32 offsets
   h.workspace_bytes = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
-  if (header_only) {
-    Bytes hb(sizeof(h));
-    std::memcpy(hb.data(), &h, sizeof(h));
-    return hb;
-  }
-  Bytes img((size_t)h.image_bytes);
-  uint8_t* base = img.data();
+  if (header) *header = h;
+  uint8_t* base = buffer ? buffer((size_t)h.image_bytes) : nullptr;
+  if (!base) return buffer ? -2 : h.image_bytes;  // -2: no memory; header only
   {
     int64_t end = sizeof(ImgHeader);
     for (auto [o, n] : used) {
@@ -642,7 +640,27 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
     int32_t* root_tasks = arr(h.o_roots, (int32_t*)nullptr);
     for (size_t i = 0; i < rs.size(); ++i) root_tasks[i] = rs[i].second;
   }
-  std::memcpy(img.data(), &h, sizeof(h));
+  std::memcpy(base, &h, sizeof(h));
+  return h.image_bytes;
+}
+
+Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
+  Bytes img;
+  ImgHeader h;
+  if (header_only) {
+    if (build_image_into(knots, nullptr, &h) < 0) return {};
+    img.resize(sizeof(h));
+    std::memcpy(img.data(), &h, sizeof(h));
+    return img;
+  }
+  const int64_t n = build_image_into(
+      knots,
+      [&](size_t bytes) {
+        img.resize(bytes);
+        return img.data();
+      },
+      nullptr);
+  if (n < 0) return {};
   return img;
 }
 

@@ -310,6 +310,64 @@ void make_section(PlanKnot& k);
 // Empty when the arena does not fit int32 offsets.
 Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only = false);
 
+// The same image written into a buffer that buffer(bytes) provides (the image
+// is not zero-filled beyond what it writes: every array and all padding are
+// written).  Returns the image size, -1 when the arena does not fit int32
+// offsets, -2 when buffer returned null.  header (may be null) receives the
+// header.  With a null buffer only the header is computed.
+int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
+                         const std::function<uint8_t*(size_t)>& buffer, ImgHeader* header);
+
+// Host buffers for batch images, page-locked when the HIP runtime can provide
+// them (uploads are then plain DMA), kept in a pool for reuse.  host_buf_get
+// returns at least `bytes` bytes and its capacity; host_buf_put takes it back.
+uint8_t* host_buf_get(size_t bytes, size_t* capacity, bool* pinned);
+void host_buf_put(uint8_t* p, size_t capacity, bool pinned);
+
+// Move-only owner of a host_buf_get buffer.
+class HostBuf {
+ public:
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  HostBuf(HostBuf&& o) noexcept { swap(o); }
+  HostBuf& operator=(HostBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      swap(o);
+    }
+    return *this;
+  }
+  ~HostBuf() { reset(); }
+  // a buffer of `bytes` (nullptr when out of memory)
+  uint8_t* allocate(size_t bytes) {
+    reset();
+    p_ = host_buf_get(bytes, &cap_, &pinned_);
+    n_ = p_ ? bytes : 0;
+    return p_;
+  }
+  void reset() {
+    if (p_) host_buf_put(p_, cap_, pinned_);
+    p_ = nullptr;
+    n_ = cap_ = 0;
+    pinned_ = false;
+  }
+  uint8_t* data() const { return p_; }
+  size_t size() const { return n_; }
+  bool empty() const { return n_ == 0; }
+
+ private:
+  void swap(HostBuf& o) {
+    std::swap(p_, o.p_);
+    std::swap(n_, o.n_);
+    std::swap(cap_, o.cap_);
+    std::swap(pinned_, o.pinned_);
+  }
+  uint8_t* p_ = nullptr;
+  size_t n_ = 0, cap_ = 0;
+  bool pinned_ = false;
+};
+
 int64_t elem_bytes(int32_t precision);
 
 }  // namespace kn
@@ -331,7 +389,7 @@ const Bytes& plan_image(const kn_plan* p);
 }  // namespace kn
 
 struct kn_batch {
-  kn::Bytes image;
+  kn::HostBuf image;  // page-locked when possible: uploaded by DMA
   kn_batch_stats stats{};
   std::vector<int64_t> edge_offset;
   int32_t precision = 0;

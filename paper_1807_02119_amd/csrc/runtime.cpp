@@ -162,6 +162,13 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
   return first;
 }
 
+extern "C" void kn_free_many(int32_t n, kn_tait** taits, kn_plan** plans) {
+  for (int32_t i = 0; i < n; ++i) {
+    if (plans && plans[i]) kn_plan_free(plans[i]);
+    if (taits && taits[i]) kn_tait_free(taits[i]);
+  }
+}
+
 extern "C" kn_status kn_jones_many(int32_t n, const int32_t* q, const kn_tait* const* g,
                                    const kn_scalar* z_host, double* v, double* log2_abs_v,
                                    double* arg_v) {

@@ -92,6 +92,7 @@ _SIGS = {
     "kn_jones": (I32, [I32, P, ctypes.POINTER(Scalar), PD, PD, PD, PD]),
     "kn_jones_variable": (I32, [I32, PD, PD]),
     "kn_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
+    "kn_free_many": (None, [I32, ctypes.POINTER(P), ctypes.POINTER(P)]),
     "kn_batch_info": (I32, [P, ctypes.POINTER(BatchStats)]),
     "kn_batch_edge_offset": (I32, [P, I32, ctypes.POINTER(ctypes.c_int64)]),
     "kn_batch_upload": (I32, [P, P, ctypes.c_size_t, P]),
@@ -179,9 +180,9 @@ class Tait:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib is not None:
+        if h and _lib is not None and getattr(self, "_owner", None) is None:
             _lib.kn_tait_free(h)
-            self._h = None
+        self._h = None
 
 
 class Plan:
@@ -242,9 +243,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib is not None:
+        if h and _lib is not None and getattr(self, "_owner", None) is None:
             _lib.kn_plan_free(h)
-            self._h = None
+        self._h = None
 
 
 def _wrap_tait(h):
@@ -265,6 +266,71 @@ def _wrap_plan(h, tait, q, opts):
     p.gradient = bool(opts.gradient)
     p._stats = None
     return p
+
+
+class PlanSet:
+    """Tait graphs and plans of many knots kept as two handle arrays (one
+    Python object for the whole set, freed with one kn_free_many call).  For
+    pipelines that plan thousands of knots per second; ``plan(i)`` and
+    ``tait(i)`` give views of single members."""
+
+    def __init__(self, taits, plans, qs, opts):
+        self.n = len(plans)
+        self._th = taits
+        self._ph = plans
+        self.q = qs
+        self._opts = opts
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        return self.plan(i)
+
+    def tait(self, i):
+        t = _wrap_tait(P(self._th[i]))
+        t._owner = self  # a view: the set frees it
+        return t
+
+    def plan(self, i):
+        p = _wrap_plan(P(self._ph[i]), self.tait(i), int(self.q[i]), self._opts)
+        p._owner = self
+        return p
+
+    def __del__(self):
+        if getattr(self, "_ph", None) is not None and _lib is not None:
+            _lib.kn_free_many(self.n, self._th, self._ph)
+            self._ph = self._th = None
+
+
+def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, simplify=None,
+             jones_only=True, tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
+             tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0):
+    """kn_plan_many over knots given as one int32 crossing-count array and
+    their PD codes concatenated in one flat int32 array.  Returns a PlanSet."""
+    L = lib()
+    ncr = np.ascontiguousarray(n_crossings, np.int32)
+    n = len(ncr)
+    flat = np.ascontiguousarray(flat_pd, np.int32)
+    if flat.size == 0:
+        flat = np.zeros(4, np.int32)
+    qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
+    if simplify is None:
+        simplify = 1 if (gradient or not jones_only) else 3
+    o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
+                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
+                 slice_log2_budget, split_serial_log2, gemm_tasks_log2)
+    th = (P * n)()
+    ph = (P * n)()
+    stv = np.zeros(n, np.int32)
+    rc = L.kn_plan_many(n, ncr.ctypes.data_as(PI32), flat.ctypes.data_as(PI32), None,
+                        qa.ctypes.data_as(PI32), ctypes.byref(o), n_threads, th, ph,
+                        stv.ctypes.data_as(PI32))
+    ps = PlanSet(th, ph, qa, o)
+    if rc != KN_OK:
+        del ps
+        raise KnError(rc, "kn_plan_many")
+    return ps
 
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
@@ -300,12 +366,13 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
 
 
 def jones_many(qs, taits, z):
-    """kn_jones for many knots; z: (n, 3) float64 host array of kn_scalar.
-    Returns (v complex array, log2|v|, arg v)."""
+    """kn_jones for many knots; z: (n, 3) float64 host array of kn_scalar;
+    taits: a list of Tait objects or a PlanSet.  Returns (v complex array,
+    log2|v|, arg v)."""
     n = len(taits)
     z = np.ascontiguousarray(z, dtype=np.float64).reshape(n, 3)
     qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
-    th = (P * n)(*[t._h for t in taits])
+    th = taits._th if isinstance(taits, PlanSet) else (P * n)(*[t._h for t in taits])
     v = np.zeros(2 * n)
     l2 = np.zeros(n)
     ar = np.zeros(n)
@@ -410,10 +477,15 @@ class Batch:
 
     def __init__(self, plans):
         L = lib()
-        self.plans = list(plans)
-        arr = (P * len(self.plans))(*[p._h for p in self.plans])
+        if isinstance(plans, PlanSet):
+            self.plans = plans  # kept alive with the batch
+            arr, n = plans._ph, plans.n
+        else:
+            self.plans = list(plans)
+            n = len(self.plans)
+            arr = (P * n)(*[p._h for p in self.plans])
         h = P()
-        _check(L.kn_batch_create(arr, len(self.plans), ctypes.byref(h)), "kn_batch_create")
+        _check(L.kn_batch_create(arr, n, ctypes.byref(h)), "kn_batch_create")
         self._h = h
         st = BatchStats()
         _check(L.kn_batch_info(h, ctypes.byref(st)), "kn_batch_info")

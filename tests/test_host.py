@@ -425,3 +425,25 @@ def test_slicing_makes_wide_knots_fit():
     assert 1 <= p.stats["slice_chains"] <= min(64, p.stats["n_slices"])
     with pytest.raises(kn.KnError):
         kn.Plan(t, 3, slice_log2_budget=24, gradient=True)
+
+
+def test_plan_set_handles():
+    """PlanSet: the same plans as plan_many, views that do not free, one batch
+    image, and Jones values from the set's Tait graphs."""
+    knots = [gen.lattice_knot((85, k), 20, 80) for k in range(6)]
+    ncr = np.array([d.n for d in knots], np.int32)
+    flat = np.concatenate([np.asarray(d.pd, np.int32).reshape(-1) for d in knots])
+    ps = kn.plan_set(ncr, flat, 3)
+    _, plans = kn.plan_many([d.pd for d in knots], 3)
+    assert len(ps) == len(plans)
+    for i, p in enumerate(plans):
+        v = ps.plan(i)
+        assert v.stats == p.stats
+        assert v.image() == p.image()
+        del v  # a view: the set still owns the plan
+    assert kn.Batch(ps).image() == kn.Batch(plans).image()
+    z = np.tile([1.0, 0.0, 0.0], (len(knots), 1))
+    a = kn.jones_many(3, ps, z)
+    b = kn.jones_many(3, [p.tait for p in plans], z)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
