@@ -114,11 +114,23 @@ void kn_tait_free(kn_tait* g);
  *               int64 / FP64.
  * simplify   bit 0: Reidemeister I (loops and degree-1 vertices);
  *            bit 1: Reidemeister II (parallel edges of opposite Tait sign;
- *                   only valid for the Jones couplings).  Parallel edges are
- *                   always merged into one q x q matrix (elementwise product).
- *            Default (opts == NULL): 3.
+ *                   only valid for the Jones couplings);
+ *            bit 2: exact series-parallel reduction at the Jones couplings
+ *                   (their values are known when planning): a degree-2 spin
+ *                   between edges x1, x2 is summed out into one edge
+ *                   x' = (x1 x2 + q - 1) / (x1 + x2 + q - 2) times the
+ *                   constant x1 + x2 + q - 2, spikes give x + q - 1, and
+ *                   new parallel edges multiply, until every spin left has
+ *                   degree three or more.  It removes about a fifth of the
+ *                   spins of lattice knots, but the contraction order found
+ *                   on the reduced graph is better for some knots and worse
+ *                   for others (on a 256-knot q = 3 batch the total work
+ *                   grew by a third), so it is not in the default.
+ *            Parallel edges are always merged into one q x q matrix
+ *            (elementwise product).  Default (opts == NULL): 3.
  * jones_only 1: the plan may only be contracted with the Jones couplings
- *               (J == NULL); required for simplify bit 1.  0: any couplings.
+ *               (J == NULL); required for simplify bits 1 and 2.  0: any
+ *               couplings.
  * mem_budget_bytes  0 = no limit; otherwise a plan whose workspace exceeds it
  *               returns KN_E_BUDGET (and still fills *out so that its
  *               statistics can be read, see kn_plan_info).
@@ -162,7 +174,7 @@ void kn_tait_free(kn_tait* g);
  *               adjoint of every intermediate is contracted back to the vertex
  *               tensors (for C = A.B: dS/dA = dS/dC . B, dS/dB = A . dS/dC),
  *               and every intermediate is kept until its reverse step.
- *               Requires simplify without bit 1 (Reidemeister II drops edges
+ *               Requires simplify without bits 1 and 2 (they drop edges
  *               whose derivative is not zero).  kn_contract on such a plan
  *               computes Z and runs the reverse steps without writing them out.
  */

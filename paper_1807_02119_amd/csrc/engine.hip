@@ -104,6 +104,13 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   return p;
 }
 
+// The plan constants of a knot (derived merged edges, FAC_CONST factors).
+__device__ inline const Cx<double>* plan_consts(const DevProg& p, const KnotDesc& kd) {
+  return reinterpret_cast<const Cx<double>*>(reinterpret_cast<const uint8_t*>(p.h) +
+                                              p.h->o_consts) +
+         kd.const_off;
+}
+
 __device__ inline Cx<double> cmul(Cx<double> a, Cx<double> b) {
   return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
@@ -230,6 +237,7 @@ __device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
   for (int m = tid; m < kd.n_medges; m += kBlock) {
     const MEdge me = p.medges[kd.medge_off + m];
     Cx<double> x{1.0, 0.0};
+    if (me.n_members < 0) x = plan_consts(p, kd)[me.member_off];  // derived edge
     for (int i = 0; i < me.n_members; ++i) x = cmul(x, xe[p.members[me.member_off + i]]);
     xm[m] = x;
   }
@@ -895,7 +903,9 @@ __device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, C
   }
   for (int i = 0; i < kd.n_factors; ++i) {
     const Factor f = p.factors[kd.factor_off + i];
-    Cx<double> x = f.kind == FAC_LOOP ? xe[f.id] : xm[f.id];
+    Cx<double> x = f.kind == FAC_LOOP ? xe[f.id]
+                   : f.kind == FAC_CONST ? plan_consts(p, kd)[f.id]
+                                         : xm[f.id];
     if (f.kind == FAC_LEAF) x.re += (double)(kd.q - 1);
     if (f.kind == FAC_PAIR) {  // equal fixed values: x_m, else 1
       int sa = kd.slice, sb = kd.slice;

@@ -107,8 +107,17 @@ void make_section(PlanKnot& k) {
   S.md.reserve(n_md);
   S.members.reserve(k.medge_mem.size());
   for (size_t m = 0; m < n_md; ++m) {
+    if (m < k.medge_const.size() && k.medge_const[m] >= 0) {
+      S.md.push_back({k.medge_const[m], -1});  // derived: x is a constant
+      continue;
+    }
     S.md.push_back({(int32_t)S.members.size(), k.medge_off[m + 1] - k.medge_off[m]});
     for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j) S.members.push_back(k.medge_mem[j]);
+  }
+  S.consts.reserve(2 * k.consts.size());
+  for (const auto& c : k.consts) {
+    S.consts.push_back(c.real());
+    S.consts.push_back(c.imag());
   }
   S.fac = k.factors;
   S.comps = k.comps;
@@ -376,7 +385,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   // of a chain share one arena region.  Offsets are prefix sums; the units are
   // then written in parallel straight into the image.
   struct PlanOff {
-    size_t VS, M, MEM, F, TAB, E, PIN, unit;
+    size_t VS, M, MEM, F, TAB, E, PIN, CONST, unit;
     int64_t arena;
   };
   struct UnitOff {
@@ -402,6 +411,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
       po.TAB += S.strides.size();
       po.E += k.eps.size();
       po.PIN += S.pins.size() / 2;
+      po.CONST += S.consts.size() / 2;
       po.unit += k.n_slices;
       po.arena += S.arena_elems * std::max(1, k.slice_chains);
       lds_used = std::max(lds_used, S.lds_used);
@@ -426,7 +436,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   const PlanOff& pt = poff[nP];
   const size_t nT = ut.T, nS = ut.S, nV = ut.V, nC = ut.C, nTask = ut.TK, nG = ut.G;
   const size_t nVS = pt.VS, nM = pt.M, nMem = pt.MEM, nF = pt.F, nTab = pt.TAB, nE = pt.E,
-               nPin = pt.PIN;
+               nPin = pt.PIN, nConst = pt.CONST;
   const int64_t arena = pt.arena;
   // image layout: header, then each array 256-byte aligned; the buffer is
   // not zero-filled (every array is written in full below, the padding is
@@ -446,6 +456,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.n_wslots = (int32_t)ut.W;
   h.n_outputs = (int32_t)nP;
   h.sliced = sliced ? 1 : 0;
+  h.n_consts = (int32_t)nConst;
   h.lds_bytes = (lds_used + 255) / 256 * 256;
   std::vector<std::pair<int64_t, int64_t>> used;  // (offset, bytes) of each array
   int64_t top = sizeof(ImgHeader);
@@ -469,6 +480,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.o_eps = reserve(nE, sizeof(int8_t));
   h.o_comps = reserve(nC, sizeof(int32_t));
   h.o_pins = reserve(2 * nPin, sizeof(int32_t));
+  h.o_consts = reserve(2 * nConst, sizeof(double));
   // roots last: their count is known once the chains are laid out
   size_t n_roots = 0;
   for (size_t ki = 0; ki < nP; ++ki)
@@ -521,6 +533,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   int8_t* eps = arr(h.o_eps, (int8_t*)nullptr);
   int32_t* comps = arr(h.o_comps, (int32_t*)nullptr);
   int32_t* pins = arr(h.o_pins, (int32_t*)nullptr);
+  double* consts = arr(h.o_consts, (double*)nullptr);
   TaskDesc* tasks = arr(h.o_tasks, (TaskDesc*)nullptr);
   GroupDesc* groups = arr(h.o_groups, (GroupDesc*)nullptr);
   // (-estimated chain time, root task) of the first unit of every chain
@@ -539,7 +552,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
       std::copy(S.vslot.begin(), S.vslot.end(), vslot + VS0);
       for (size_t i = 0; i < S.md.size(); ++i) {
         MEdge m = S.md[i];
-        m.member_off += (int32_t)MEM0;
+        if (m.n_members >= 0) m.member_off += (int32_t)MEM0;  // constants stay plan-local
         md[o.M + i] = m;
       }
       std::copy(S.members.begin(), S.members.end(), members + MEM0);
@@ -547,6 +560,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
       std::copy(S.strides.begin(), S.strides.end(), strides + TAB0);
       std::copy(k.eps.begin(), k.eps.end(), eps + o.E);
       std::copy(S.pins.begin(), S.pins.end(), pins + 2 * PIN0);
+      std::copy(S.consts.begin(), S.consts.end(), consts + 2 * o.CONST);
     }
     KnotDesc x = S.kd;
     x.edge_off = (int32_t)o.E;
@@ -559,6 +573,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
     x.plan_slot = (int32_t)pk;
     x.out_slot = k.n_slices > 1 ? (int32_t)ui : (int32_t)pk;
     x.w_off = (int32_t)u.W;
+    x.const_off = (int32_t)o.CONST;
     kd[ui] = x;
     const int32_t t0 = (int32_t)u.T, s0 = (int32_t)u.S, g0 = (int32_t)u.G, tk0 = (int32_t)u.TK;
     for (size_t i = 0; i < S.td.size(); ++i) {

@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -144,6 +145,7 @@ struct Section {
   std::vector<int32_t> strides;     // spin-group strides of every step
   std::vector<int32_t> comps;       // knot-local tensor ids
   std::vector<int32_t> pins;        // (merged edge, sliced spin) pairs of the vertices
+  std::vector<double> consts;       // complex constants (re, im), plan-local ids
   std::vector<TaskDesc> tasks;      // group, first, state_lo knot-local
   std::vector<GroupDesc> groups;    // first_task, next knot-local
   double est = 0;                   // estimated chain time (start priority)
@@ -200,8 +202,10 @@ struct PlanKnot {
   int32_t slice_chains = 1;                     // slices run as this many chains
   int32_t n_edges = 0;                          // original Tait edges
   std::vector<int8_t> eps;                      // original Tait signs
-  // merged edge m: original edges medge_mem[medge_off[m] .. medge_off[m + 1])
-  std::vector<int32_t> medge_off{0}, medge_mem;
+  // merged edge m: original edges medge_mem[medge_off[m] .. medge_off[m + 1]),
+  // or, when medge_const[m] >= 0, none: x_m is the constant consts[medge_const[m]]
+  std::vector<int32_t> medge_off{0}, medge_mem, medge_const;
+  std::vector<std::complex<double>> consts;     // derived edges, FAC_CONST factors
   std::vector<Factor> factors;                  // simplification factors
   int32_t n_iso = 0;                            // isolated spins
   std::vector<PTensor> tensors;                 // vertex tensors, then step outputs
@@ -228,6 +232,8 @@ struct PlanKnot {
     std::vector<Factor>().swap(factors);
     std::vector<int32_t>{0}.swap(medge_off);
     std::vector<int32_t>().swap(medge_mem);
+    std::vector<int32_t>().swap(medge_const);
+    std::vector<std::complex<double>>().swap(consts);
   }
 };
 

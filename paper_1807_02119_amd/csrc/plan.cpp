@@ -27,6 +27,7 @@
 // 4. Memory: first-fit arena over the tensors' live ranges.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <new>
@@ -70,6 +71,110 @@ struct Simplified {
   // paper-model edge multiplicity of each remaining edge (for delta_h_paper)
   std::vector<int32_t> e_mult;
 };
+
+// Exact series-parallel reduction of the Potts network at the Jones couplings
+// (their values are known at planning time), together with R-I on spikes.
+// With T_e(a, b) = 1 + (x_e - 1) [a = b]:
+//  - spike: a vertex on one edge m sums to the constant x_m + q - 1
+//    (factor FAC_LEAF m);
+//  - series: a vertex v on exactly two edges, x1 to u and x2 to w (u != w),
+//    sums to c T'(s_u, s_w) with c = x1 + x2 + q - 2 and
+//    x' = (x1 x2 + q - 1) / c, since for s_u = s_w the sum over s_v is
+//    x1 x2 + (q - 1) and otherwise x1 + x2 + (q - 2);
+//  - parallel: two edges between the same spins multiply their x.
+// Series and parallel results are new merged edges whose x is a constant
+// (k.consts, referenced by k.medge_const), c becomes a FAC_CONST factor.  A
+// series step whose c is (nearly) zero is skipped.  Reductions repeat until
+// every remaining spin has degree three or more.
+void series_parallel(const kn_tait& g, PlanKnot& k, int32_t nv,
+                     std::vector<std::pair<int32_t, int32_t>>& ends, std::vector<uint8_t>& alive_e,
+                     std::vector<int32_t>& mult, const std::vector<int32_t>& ioff,
+                     const std::vector<int32_t>& inc, std::vector<int32_t>& deg,
+                     std::vector<uint8_t>& alive_v) {
+  using C = std::complex<double>;
+  const int32_t q = k.q;
+  const C t(k.t_re, k.t_im);
+  const int32_t nm = (int32_t)alive_e.size();
+  // x of every merged edge: product of its members' Jones couplings -t^(-eps)
+  std::vector<C> x(nm);
+  for (int32_t m = 0; m < nm; ++m) {
+    C v(1.0, 0.0);
+    for (int32_t j = k.medge_off[m]; j < k.medge_off[m + 1]; ++j)
+      v *= -(g.eps[k.medge_mem[j]] > 0 ? 1.0 / t : t);
+    x[m] = v;
+  }
+  // live incident edges per spin (lists compacted lazily)
+  std::vector<SpinList> adj(nv);
+  for (int32_t v = 0; v < nv; ++v)
+    for (int32_t j = ioff[v]; j < ioff[v + 1]; ++j) adj[v].push_back(inc[j]);
+  auto live_edges = [&](int32_t v) -> const SpinList& {
+    SpinList& l = adj[v];
+    int32_t* h = l.mut();
+    int32_t w = 0;
+    for (int32_t i = 0; i < l.size(); ++i)
+      if (alive_e[h[i]]) h[w++] = h[i];
+    l.truncate(w);
+    return l;
+  };
+  auto other = [&](int32_t m, int32_t v) { return ends[m].first == v ? ends[m].second : ends[m].first; };
+  auto derived = [&](int32_t a, int32_t b, C val) {
+    const int32_t m = (int32_t)alive_e.size();
+    ends.emplace_back(std::min(a, b), std::max(a, b));
+    alive_e.push_back(1);
+    mult.push_back(1);
+    x.push_back(val);
+    k.medge_const.push_back((int32_t)k.consts.size());
+    k.consts.push_back(val);
+    k.medge_off.push_back(k.medge_off.back());  // no member edges
+    adj[a].push_back(m);
+    adj[b].push_back(m);
+    return m;
+  };
+  std::vector<int32_t> stack;
+  for (int32_t v = nv - 1; v >= 0; --v)
+    if (deg[v] == 1 || deg[v] == 2) stack.push_back(v);
+  while (!stack.empty()) {
+    const int32_t v = stack.back();
+    stack.pop_back();
+    if (!alive_v[v] || deg[v] < 1 || deg[v] > 2) continue;
+    const SpinList& l = live_edges(v);
+    if (deg[v] == 1) {
+      const int32_t m = l[0];
+      alive_e[m] = 0;
+      k.factors.push_back({FAC_LEAF, m});
+      alive_v[v] = 0;
+      deg[v] = 0;
+      const int32_t w = other(m, v);
+      if (--deg[w] == 1 || deg[w] == 2) stack.push_back(w);
+      continue;
+    }
+    const int32_t m1 = l[0], m2 = l[1];
+    const int32_t u = other(m1, v), w = other(m2, v);
+    if (u == w) continue;  // cannot happen: parallel edges are merged
+    const C c = x[m1] + x[m2] + (double)(q - 2);
+    if (std::abs(c) <= 1e-9 * (std::abs(x[m1] * x[m2]) + (double)q)) continue;
+    const C xs = (x[m1] * x[m2] + (double)(q - 1)) / c;
+    alive_e[m1] = alive_e[m2] = 0;
+    alive_v[v] = 0;
+    deg[v] = 0;
+    k.factors.push_back({FAC_CONST, (int32_t)k.consts.size()});
+    k.consts.push_back(c);
+    // an existing edge u - w absorbs the new one (parallel merge)
+    int32_t m3 = -1;
+    for (int32_t e : live_edges(u))
+      if (other(e, u) == w) m3 = e;
+    if (m3 >= 0) {
+      alive_e[m3] = 0;
+      derived(u, w, xs * x[m3]);
+      --deg[u];
+      --deg[w];
+    } else {
+      derived(u, w, xs);
+    }
+    for (int32_t z : {u, w})
+      if (deg[z] == 1 || deg[z] == 2) stack.push_back(z);
+  }
+}
 
 // Simplification of Sec. III.A; fills k.medges, k.factors, k.n_iso.
 Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& k) {
@@ -147,7 +252,11 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
   std::vector<int32_t> deg(nv);
   for (int32_t v = 0; v < nv; ++v) deg[v] = ioff[v + 1] - ioff[v];
   std::vector<uint8_t> alive_v(nv, 1);
-  if (flags & 1) {
+  k.medge_const.assign(nm, -1);
+  k.consts.clear();
+  if ((flags & 4) && jones_only) {
+    series_parallel(g, k, nv, ends, alive_e, mult, ioff, inc, deg, alive_v);
+  } else if (flags & 1) {
     // Reidemeister I on spikes: peel degree-1 vertices repeatedly
     std::vector<int32_t> stack;
     for (int32_t v = 0; v < nv; ++v)
@@ -179,7 +288,7 @@ Simplified simplify(const kn_tait& g, int32_t flags, bool jones_only, PlanKnot& 
     }
     sid[v] = s.n_spins++;
   }
-  for (int32_t m = 0; m < nm; ++m)
+  for (int32_t m = 0; m < (int32_t)alive_e.size(); ++m)
     if (alive_e[m]) {
       s.e.emplace_back(sid[ends[m].first], sid[ends[m].second]);
       s.e_medge.push_back(m);
@@ -1158,13 +1267,13 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (q < 2 || q > 8) return KN_E_UNSUPPORTED;
   kn_plan_opts o = opts ? *opts : default_opts();
   if (o.strategy < 0 || o.strategy > 3 || o.precision < 0 || o.precision > 1 ||
-      o.simplify < 0 || o.simplify > 3 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
+      o.simplify < 0 || o.simplify > 7 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
       o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304 ||
       o.tile_macs_log2 < 0 || o.tile_macs_log2 > 30)
     return KN_E_INVALID;
-  if ((o.simplify & 2) && !o.jones_only) return KN_E_INVALID;
+  if ((o.simplify & 6) && !o.jones_only) return KN_E_INVALID;  // need the Jones couplings
   if (o.gradient != 0 && o.gradient != 1) return KN_E_INVALID;
-  if (o.gradient && (o.simplify & 2)) return KN_E_INVALID;
+  if (o.gradient && (o.simplify & 6)) return KN_E_INVALID;
   if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
   if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
   if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;

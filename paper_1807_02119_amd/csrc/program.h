@@ -53,6 +53,7 @@ enum FactorKind : int32_t {
   FAC_LEAF = 1,  // degree-1 vertex on merged edge m: factor x_m + q - 1
   FAC_PAIR = 2,  // merged edge m between sliced spins a and b: x_m if their
                  // fixed values are equal, else 1
+  FAC_CONST = 3,  // constant id of the plan (series reduction at known couplings)
 };
 
 struct ImgHeader {
@@ -68,8 +69,9 @@ struct ImgHeader {
   int32_t n_wslots;   // complex weight slots over all knots (x_e then x_m per knot)
   int32_t n_outputs;  // entries of the output scalar array
   int32_t sliced;     // 1: some knots are slices; their sums are formed after the launch
+  int32_t n_consts;   // complex128 constants over all plans
   int64_t o_tasks, o_groups, o_roots, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
-  int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps, o_pins;
+  int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps, o_pins, o_consts;
   int64_t image_bytes;
   // runtime state (relative to the workspace base)
   int64_t state_off, state_bytes;
@@ -120,7 +122,7 @@ struct KnotDesc {
   // sum over slices to output plan_slot.  n_slices == 1: not sliced.
   int32_t slice, n_slices, n_slice_spins, plan_slot;
   int32_t w_off;  // this knot's weight slots: x_e at w_off, x_m at w_off + n_edges
-  int32_t pad;
+  int32_t const_off;  // this plan's constants (derived merged edges, FAC_CONST)
 };
 
 struct TensorDesc {
@@ -172,7 +174,9 @@ struct VtxDesc {
 };
 
 struct MEdge {
-  int32_t member_off, n_members;  // original edge ids (knot-local)
+  // original edge ids (knot-local); n_members == -1: a derived edge whose x
+  // is the plan's constant member_off (series-parallel reduction)
+  int32_t member_off, n_members;
 };
 
 struct Factor {

@@ -22,11 +22,12 @@ HDR = np.dtype([
     ("n_tensors", "<i4"), ("n_steps", "<i4"), ("n_vtx", "<i4"), ("n_medges", "<i4"),
     ("n_members", "<i4"), ("n_factors", "<i4"), ("n_strides", "<i4"), ("n_groups", "<i4"),
     ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("n_pins", "<i4"),
-    ("n_wslots", "<i4"), ("n_outputs", "<i4"), ("sliced", "<i4"),
+    ("n_wslots", "<i4"), ("n_outputs", "<i4"), ("sliced", "<i4"), ("n_consts", "<i4"),
     ("o_tasks", "<i8"), ("o_groups", "<i8"), ("o_roots", "<i8"), ("o_knots", "<i8"),
     ("o_tensors", "<i8"), ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"),
     ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_strides", "<i8"),
-    ("o_eps", "<i8"), ("o_comps", "<i8"), ("o_pins", "<i8"), ("image_bytes", "<i8"),
+    ("o_eps", "<i8"), ("o_comps", "<i8"), ("o_pins", "<i8"), ("o_consts", "<i8"),
+    ("image_bytes", "<i8"),
     ("state_off", "<i8"),
     ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
     ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("o_zslice", "<i8"), ("arena_off", "<i8"),
@@ -39,7 +40,7 @@ GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", 
 KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
     "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps", "grad",
-    "slice", "n_slices", "n_slice_spins", "plan_slot", "w_off", "pad")], align=True)
+    "slice", "n_slices", "n_slice_spins", "plan_slot", "w_off", "const_off")], align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
                                       "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
@@ -85,6 +86,8 @@ class Image:
         self.pins = arr(PAIR, h["o_pins"], h["n_pins"])
         self.strides = arr("<i4", h["o_strides"], h["n_strides"])
         self.eps = arr("<i1", h["o_eps"], h["n_edges"])
+        c = arr("<f8", h["o_consts"], 2 * int(h["n_consts"]))
+        self.consts = c[0::2] + 1j * c[1::2]
         n_comps = int(sum(int(k["n_comps"]) for k in self.knots))
         self.comps = arr("<i4", h["o_comps"], n_comps)
 
@@ -366,6 +369,9 @@ def run(raw: bytes, J=None, want_grad=False):
                 for m in range(int(k["n_medges"])):
                     me = im.medges[mo + m]
                     x = 1.0 + 0j
+                    if int(me["y"]) < 0:  # derived edge: a constant of the plan
+                        assert int(me["y"]) == -1
+                        x = im.consts[int(k["const_off"]) + int(me["x"])]
                     for i in range(int(me["y"])):
                         x *= weights[wo + int(im.members[int(me["x"]) + i])]
                     weights[wm + m] = x
@@ -441,6 +447,8 @@ def run(raw: bytes, J=None, want_grad=False):
                         x = weights[wo + int(f["y"])]
                     elif f["x"] == 1:
                         x = weights[wm + int(f["y"])] + (q - 1)
+                    elif f["x"] == 3:  # constant of the plan (series reduction)
+                        x = im.consts[int(k["const_off"]) + int(f["y"])]
                     else:  # edge between two fixed spins
                         x = weights[wm + int(f["y"])] if sigma[int(f["a"])] == sigma[int(f["b"])] else 1.0
                     z, e = mul(z, e, x)

@@ -147,12 +147,13 @@ def test_gemm_and_split_parity():
     """32 x 32 GEMM tiles (ragged row and column blocks), GEMM tiles over a
     split contracted range with their reduction, and split output tiles."""
     work = gen.config_knots("q3_200_600", 0, count=72)
-    cases = [(71, work[71][0], dict(strategy=0)), (11, work[11][0], {})]
+    cases = [(71, work[71][0], dict(strategy=0, simplify=3)), (11, work[11][0], dict(simplify=3)),
+             (11, work[11][0], {})]
     for k in range(3):
         cases.append((f"lattice{k}", gen.lattice_knot((63, k), 100, 400),
                       dict(big_step_macs_log2=4)))
     # several 32 x 32 blocks per task (ragged last task of a step)
-    cases.append((71, work[71][0], dict(strategy=0, gemm_tasks_log2=1)))
+    cases.append((71, work[71][0], dict(strategy=0, simplify=3, gemm_tasks_log2=1)))
     cases.append((11, work[11][0], dict(gemm_tasks_log2=3)))
     cases.append(("lattice0", gen.lattice_knot((63, 0), 100, 400),
                   dict(big_step_macs_log2=4, gemm_tasks_log2=2)))
@@ -163,6 +164,18 @@ def test_gemm_and_split_parity():
             t, p, m, e = gpu_z(d, 3, precision=prec, **kw)
             tol = TOL if prec == 0 else 1e-3
             assert z_close(m, e, mo, eo, tol), (name, kw, prec)
+
+
+def test_series_parallel_parity():
+    """simplify bit 2 (exact series-parallel reduction at the Jones couplings:
+    derived edges and constant factors from the plan's constants)."""
+    for k in range(6):
+        d = gen.lattice_knot((87, k), 40, 200)
+        tg, mo, eo = oracle_z(d, 3 + (k % 3))
+        for prec in (0, 1):
+            t, p, m, e = gpu_z(d, 3 + (k % 3), precision=prec, simplify=7)
+            tol = TOL if prec == 0 else 1e-3
+            assert z_close(m, e, mo, eo, tol), (d.label, prec)
 
 
 def test_level_split_parity():

@@ -144,7 +144,8 @@ def test_plan_model_tiled_and_options():
                    dict(strategy=0), dict(strategy=1), dict(strategy=2),
                    dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1),
                    dict(split_serial_log2=3), dict(split_serial_log2=40),
-                   dict(big_step_macs_log2=4, gemm_tasks_log2=1)):
+                   dict(big_step_macs_log2=4, gemm_tasks_log2=1),
+                   dict(simplify=7), dict(simplify=5)):
             _check_model(d, 3, **kw)
 
 
@@ -152,7 +153,10 @@ def _split_gemm_cases():
     """Knots whose plans hold every kind of large step: 32 x 32 GEMM tiles,
     GEMM tiles over a split contracted range, and split output tiles."""
     work = gen.config_knots("q3_200_600", 0, count=72)
-    cases = [(work[71][0], dict(strategy=0)), (work[11][0], {})]
+    # without the series-parallel reduction (simplify 3) these plans keep the
+    # step shapes that split the contracted index of a GEMM step
+    cases = [(work[71][0], dict(strategy=0, simplify=3)), (work[11][0], dict(simplify=3)),
+             (work[11][0], {})]
     for k in range(2):
         cases.append((gen.lattice_knot((63, k), 100, 400), dict(big_step_macs_log2=4)))
     return cases
@@ -447,3 +451,25 @@ def test_plan_set_handles():
     b = kn.jones_many(3, [p.tait for p in plans], z)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_series_parallel_reduction():
+    """simplify bit 2: fewer spins, the same Z (CPU model against the oracle
+    and against the unreduced plan), constants in the image, and only for
+    plans bound to the Jones couplings."""
+    for k in range(6):
+        d = gen.lattice_knot((86, k), 40, 160)
+        t = kn.Tait(d.pd)
+        p3 = kn.Plan(t, 3, simplify=3)
+        p7 = kn.Plan(t, 3, simplify=7)
+        assert p7.stats["n_vertices_simplified"] < p3.stats["n_vertices_simplified"]
+        im = image_model.Image(p7.image())
+        assert int(im.h["n_consts"]) > 0 and (im.medges["y"] == -1).any()
+        (m3, e3), = image_model.run(p3.image())
+        (m7, e7), = image_model.run(p7.image())
+        assert abs(m7 * 2.0 ** (e7 - e3) - m3) <= 1e-12 * abs(m3)
+        _check_model(d, 3, simplify=7)
+        _check_model(d, 5, simplify=7)
+    t = kn.Tait(gen.lattice_knot((86, 0), 40, 160).pd)
+    with pytest.raises(kn.KnError):
+        kn.Plan(t, 3, jones_only=False, simplify=5)
