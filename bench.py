@@ -140,7 +140,7 @@ def main():
 
     # wall time of each part of the pipeline, summed over the timed steps
     phase = {k: 0.0 for k in ("prepare", "plan", "batch", "upload", "handoff", "device", "launch",
-                              "wait", "jones")}
+                              "submit", "finish", "wait", "jones")}
     counter = [0]
 
     def workspace(slot, need, precision):
@@ -223,14 +223,19 @@ def main():
             prepared = fut.result()
             t1 = time.perf_counter()
             done, z = launch(prepared, precision)
+            ts = time.perf_counter()
             if i + 1 < n:
                 fut = pool.submit(prepare, precision)
             hand = [cur] if cur is not None else None
             cur = None
+            tf = time.perf_counter()
             cur = finish(prepared, done, z, hand)
             del prepared
+            te = time.perf_counter()
             phase["handoff"] += t1 - t0
-            phase["device"] += time.perf_counter() - t1
+            phase["submit"] += tf - ts
+            phase["finish"] += te - tf
+            phase["device"] += te - t1
         taits, plans, batch, zh = cur
         v, l2, ar = kn.jones_many(q, taits, zh)
         return taits, plans, batch, zh, v, l2, ar

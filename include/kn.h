@@ -160,10 +160,18 @@ void kn_tait_free(kn_tait* g);
  *               another (with vertex-tensor setup and the final product as
  *               tasks of their own).  This shortens the longest knots' chains
  *               at the price of more tasks.  0 = default 40 (never).
- * gemm_tasks_log2  a step computed in 32 x 32 blocks over workgroups with
+ * gemm_tasks_log2  a step computed in output blocks over workgroups with
  *               more than 2^gemm_tasks_log2 blocks gives each task several
- *               blocks (at most 32), which saves per-task scheduling work.
+ *               blocks (at most 32 of 32 x 32 or 8 of 64 x 64), which saves
+ *               per-task scheduling work.
  *               0 = default 5; 30 = one block per task.
+ * gemm64_pct    a step computed in blocks uses 64 x 64 blocks instead of
+ *               32 x 32 when both its output sides are at least 64 and the
+ *               64-blocks' padded output count is at most gemm64_pct percent
+ *               of the 32-blocks' (0 = default 300; 1 = never).  A 64-block
+ *               does four times the multiply-adds per staged chunk, which
+ *               hides the operand loads better, and needs 2 x 16 x 65 entries
+ *               of LDS (33 KiB in complex128; the launch grows to fit).
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -193,6 +201,7 @@ typedef struct {
   int32_t slice_log2_budget;
   int32_t split_serial_log2;
   int32_t gemm_tasks_log2;
+  int32_t gemm64_pct;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

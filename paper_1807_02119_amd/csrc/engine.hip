@@ -209,7 +209,7 @@ __device__ inline T block_max(T v, T* red) {
 // ------------------------------------------------------------------ setup
 
 template <class T>
-__device__ void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
+__device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
                            const double* J, const States& st) {
   const int tid = threadIdx.x;
   const ImgHeader& h = *p.h;
@@ -405,7 +405,7 @@ __device__ inline void lane_dot(PA ra, PB rb, const Ix& ix, int32_t k, int32_t n
 // stores either, so its stores overlap the next pair's loads.  Returns this
 // thread's max |.|.
 template <class T, class Ix, class PA, class PB, class PC>
-__device__ T step_outputs(PA pa, PB pb, PC pc, const Ix& ix, int32_t nm, int32_t nn, int32_t k0,
+__device__ __attribute__((always_inline)) T step_outputs(PA pa, PB pb, PC pc, const Ix& ix, int32_t nm, int32_t nn, int32_t k0,
                           int32_t nk, int64_t o_begin, int64_t o_end, T scale, int32_t L,
                           int32_t tid, int32_t nthr) {
   const int32_t mn = nm * nn;
@@ -457,7 +457,7 @@ __device__ T step_outputs(PA pa, PB pb, PC pc, const Ix& ix, int32_t nm, int32_t
 // step_outputs with each operand's home (>= 0 global arena offset, < 0 LDS
 // arena offset -1 - home) resolved to a pointer of its address space.
 template <class T, class Ix>
-__device__ T step_outputs_homes(int32_t ha, int32_t hb, int32_t hc, Cx<T>* arena, Cx<T>* lds,
+__device__ __attribute__((always_inline)) T step_outputs_homes(int32_t ha, int32_t hb, int32_t hc, Cx<T>* arena, Cx<T>* lds,
                                 const Ix& ix, int32_t nm, int32_t nn, int32_t k0, int32_t nk,
                                 int64_t o_begin, int64_t o_end, T scale, int32_t L, int32_t tid,
                                 int32_t nthr) {
@@ -549,7 +549,7 @@ __device__ inline T serial_step(const StepDesc& d, const int32_t* tab, Cx<T>* ar
 constexpr int64_t kWaveMacs = 2048;
 
 template <class T>
-__device__ void serial_steps(const DevProg& p, int32_t first, int32_t count, int32_t q,
+__device__ __attribute__((always_inline)) void serial_steps(const DevProg& p, int32_t first, int32_t count, int32_t q,
                              Cx<T>* arena, Cx<T>* lds, int32_t* s_tab, StepDesc* s_desc,
                              int32_t* s_tb, TensorState* s_ext, const States& st, T* s_red,
                              int64_t* ph) {
@@ -695,7 +695,7 @@ __device__ inline GenIx step_ix(const DevProg& p, const StepDesc& s, int32_t q) 
 // LDS areas, so the whole dynamic LDS (tab_cap entries) holds generated offset
 // tables: contracted group first, then columns, rows, batch.
 template <class T>
-__device__ void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
+__device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* arena, int32_t* s_tab, int32_t tab_cap, const States& st,
                           T* s_red) {
   GenIx ix = step_ix(p, s, q);
@@ -725,18 +725,22 @@ __device__ void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
 
-// STEP_GEMM: a 32 x 32 block of C[b] over contracted range ks of the split.
-// Chunks of 16 contracted entries of A (32 rows) and B (32 columns) are
-// gathered into LDS (row pitch 33 entries, no bank conflicts on the
-// k-fastest stores) and every thread accumulates a 2 x 2 block of outputs.
-// The next chunk's operands are loaded into registers while the current one
-// is multiplied.  The contracted offsets come from tables generated in LDS
+// STEP_GEMM / STEP_GEMM64: BM x BM output blocks of C[b] (BM = 16 TM: 32
+// or 64) over contracted range ks of the split, `tile` consecutive blocks per
+// task.  Chunks of 16 contracted entries of A (BM rows) and B (BM columns)
+// are gathered into LDS (row pitch BM + 1 entries, no bank conflicts on the
+// k-fastest stores) and every thread accumulates a TM x TM block of outputs:
+// rows ty + 16 i and columns tx + 16 j.  The next chunk's operands are loaded
+// into registers while the current one is multiplied; 64 x 64 blocks do four
+// times the products of 32 x 32 ones per chunk, enough to cover the latency
+// of those loads.  The contracted offsets come from a table generated in LDS
 // when the range fits, else they are decoded from the strides.
-template <class T>
-__device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
+template <class T, int TM>
+__device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* __restrict__ arena, uint8_t* smem, int32_t smem_bytes,
                           const States& st, T* s_red) {
-  constexpr int32_t BM = kGemmBlock, BK = kGemmChunk, P = kGemmBlock + 1;
+  constexpr int32_t BM = 16 * TM, BK = kGemmChunk, P = BM + 1;
+  static_assert(BK == 16 && kBlock == 256, "thread layout: 16 x 16 threads, 16 entries per chunk");
   const QDiv D(q);
   const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
                 rn = (s.ranks >> 24) & 255;
@@ -770,7 +774,7 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   }
   int64_t ec;
   const T scale = step_scale<T>(st, s.a, s.b, ec);
-  // this thread's loads: contracted entry kk of rows/columns lr and lr + 16
+  // this thread's loads: contracted entry kk of rows / columns lr + 16 i
   const int32_t kk = tid & (BK - 1), lr = tid >> 4;
   const int32_t tx = tid & 15, ty = tid >> 4;
   const GlbCx<T>* A = (const GlbCx<T>*)(arena + s.home_a);
@@ -780,24 +784,32 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
   T lm = 0;
   __syncthreads();
 
-  struct Quad {
-    Cx<T> a0, a1, b0, b1;
+  struct Ops {
+    Cx<T> a[TM], b[TM];
   };
   for (int32_t blk = blk0; blk < blk1; ++blk) {
     const int32_t b = blk / mb_nb;
     const int32_t r = blk - b * mb_nb;
     const int32_t mblk = r / s.n_nb, nbk = r - mblk * s.n_nb;
     const int32_t m0 = mblk * BM, n0 = nbk * BM;
-    const bool am0 = m0 + lr < s.nm, am1 = m0 + lr + 16 < s.nm;
-    const bool bn0 = n0 + lr < s.nn, bn1 = n0 + lr + 16 < s.nn;
     const int32_t oab = group_off(b, sab, rb, D), obb = group_off(b, sbb, rb, D);
-    const int32_t ra0 = am0 ? oab + group_off(m0 + lr, sam, rm, D) : 0;
-    const int32_t ra1 = am1 ? oab + group_off(m0 + lr + 16, sam, rm, D) : 0;
-    const int32_t cb0 = bn0 ? obb + group_off(n0 + lr, sbn, rn, D) : 0;
-    const int32_t cb1 = bn1 ? obb + group_off(n0 + lr + 16, sbn, rn, D) : 0;
-    auto load = [=](int32_t c0) -> Quad {
+    bool am[TM], bn[TM];
+    int32_t ra[TM], cb[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      am[i] = m0 + lr + 16 * i < s.nm;
+      bn[i] = n0 + lr + 16 * i < s.nn;
+      ra[i] = am[i] ? oab + group_off(m0 + lr + 16 * i, sam, rm, D) : 0;
+      cb[i] = bn[i] ? obb + group_off(n0 + lr + 16 * i, sbn, rn, D) : 0;
+    }
+    auto load = [&](int32_t c0) -> Ops {
       const int32_t k = c0 + kk;
-      Quad x{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      Ops x;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        x.a[i] = Cx<T>{0, 0};
+        x.b[i] = Cx<T>{0, 0};
+      }
       if (k < kl) {
         int32_t oa, ob;
         if (use_tab) {
@@ -807,50 +819,60 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
           oa = group_off(k0 + k, sak, rk, D);
           ob = group_off(k0 + k, sbk, rk, D);
         }
-        if (am0) x.a0 = ldc(A + ra0 + oa);
-        if (am1) x.a1 = ldc(A + ra1 + oa);
-        if (bn0) x.b0 = ldc(B + cb0 + ob);
-        if (bn1) x.b1 = ldc(B + cb1 + ob);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          if (am[i]) x.a[i] = ldc(A + ra[i] + oa);
+          if (bn[i]) x.b[i] = ldc(B + cb[i] + ob);
+        }
       }
       return x;
     };
-    T c00r = 0, c00i = 0, c01r = 0, c01i = 0, c10r = 0, c10i = 0, c11r = 0, c11i = 0;
-    Quad x = load(0);
+    T cr[TM][TM], ci[TM][TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) cr[i][j] = ci[i][j] = 0;
+    Ops x = load(0);
     for (int32_t c0 = 0; c0 < kl; c0 += BK) {
-      As[kk * P + lr] = x.a0;
-      As[kk * P + lr + 16] = x.a1;
-      Bs[kk * P + lr] = x.b0;
-      Bs[kk * P + lr + 16] = x.b1;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        As[kk * P + lr + 16 * i] = x.a[i];
+        Bs[kk * P + lr + 16 * i] = x.b[i];
+      }
       __syncthreads();
       if (c0 + BK < kl) x = load(c0 + BK);
-#pragma unroll 4
-      for (int32_t j = 0; j < BK; ++j) {
-        const Cx<T> a0 = As[j * P + ty], a1 = As[j * P + ty + 16];
-        const Cx<T> b0 = Bs[j * P + tx], b1 = Bs[j * P + tx + 16];
-        c00r = fma(a0.re, b0.re, c00r); c00r = fma(-a0.im, b0.im, c00r);
-        c00i = fma(a0.re, b0.im, c00i); c00i = fma(a0.im, b0.re, c00i);
-        c01r = fma(a0.re, b1.re, c01r); c01r = fma(-a0.im, b1.im, c01r);
-        c01i = fma(a0.re, b1.im, c01i); c01i = fma(a0.im, b1.re, c01i);
-        c10r = fma(a1.re, b0.re, c10r); c10r = fma(-a1.im, b0.im, c10r);
-        c10i = fma(a1.re, b0.im, c10i); c10i = fma(a1.im, b0.re, c10i);
-        c11r = fma(a1.re, b1.re, c11r); c11r = fma(-a1.im, b1.im, c11r);
-        c11i = fma(a1.re, b1.im, c11i); c11i = fma(a1.im, b1.re, c11i);
+#pragma unroll(TM == 2 ? 2 : 1)
+      for (int32_t jk = 0; jk < BK; ++jk) {
+        Cx<T> a[TM], bb[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          a[i] = As[jk * P + ty + 16 * i];
+          bb[i] = Bs[jk * P + tx + 16 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TM; ++j) {
+            cr[i][j] = fma(a[i].re, bb[j].re, cr[i][j]);
+            cr[i][j] = fma(-a[i].im, bb[j].im, cr[i][j]);
+            ci[i][j] = fma(a[i].re, bb[j].im, ci[i][j]);
+            ci[i][j] = fma(a[i].im, bb[j].re, ci[i][j]);
+          }
       }
       __syncthreads();
     }
     const int64_t crow = (int64_t)b * s.nm;
-    auto put = [&](int32_t m, int32_t n, T cr, T ci) {
-      if (m < s.nm && n < s.nn) {
-        cr *= scale;
-        ci *= scale;
-        stc(C + (crow + m) * s.nn + n, Cx<T>{cr, ci});
-        lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) {
+        const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+        if (m < s.nm && n < s.nn) {
+          const T vr = cr[i][j] * scale, vi = ci[i][j] * scale;
+          stc(C + (crow + m) * s.nn + n, Cx<T>{vr, vi});
+          lm = fmax(lm, fmax(fabs(vr), fabs(vi)));
+        }
       }
-    };
-    put(m0 + ty, n0 + tx, c00r, c00i);
-    put(m0 + ty, n0 + tx + 16, c01r, c01i);
-    put(m0 + ty + 16, n0 + tx, c10r, c10i);
-    put(m0 + ty + 16, n0 + tx + 16, c11r, c11i);
   }
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
@@ -858,7 +880,7 @@ __device__ void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, 
 // Outputs [part * kReduceChunk, ...) of a split step: C = sum over the n_ks
 // partial results, in split order (the same bits on every run).
 template <class T>
-__device__ void reduce_step(const DevProg& p, const StepDesc& s, int32_t part, Cx<T>* arena,
+__device__ __attribute__((always_inline)) void reduce_step(const DevProg& p, const StepDesc& s, int32_t part, Cx<T>* arena,
                             const States& st, T* s_red) {
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
   const int64_t o0 = (int64_t)part * kReduceChunk;
@@ -884,7 +906,7 @@ __device__ void reduce_step(const DevProg& p, const StepDesc& s, int32_t part, C
 // ------------------------------------------------------------------ final
 
 template <class T>
-__device__ void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
+__device__ __attribute__((always_inline)) void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
                            kn_scalar* zout, const States& st) {
   if (threadIdx.x != 0) return;
   const ImgHeader& h = *p.h;
@@ -1226,7 +1248,9 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
       if (td.kind == TASK_REDUCE)
         reduce_step<T>(p, sd, td.count, arena, st, s_red);
       else if (sd.mode == STEP_GEMM)
-        gemm_tile<T>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
+        gemm_tile<T, 2>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
+      else if (sd.mode == STEP_GEMM64)
+        gemm_tile<T, 4>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
       else
         tile_step<T>(p, sd, td.count, q, arena, s_tab, dyn / 4, st, s_red);
     }

@@ -55,6 +55,9 @@ constexpr double kAutoGreedyFrom = 1e8;
 // GEMM steps: tasks per step aimed at (log2) and most 32 x 32 blocks per task
 constexpr int32_t kGemmTasksLog2 = 5;
 constexpr int32_t kGemmMaxBlocks = 32;
+// a GEMM step takes 64 x 64 blocks when their padded output count is at most
+// this percentage of the 32 x 32 blocks' (both sides at least 64)
+constexpr int32_t kGemm64Pct = 300;
 // default threshold (log2 of the estimated time) above which a serial run is
 // executed level by level over several workgroups
 constexpr int32_t kSplitSerialLog2 = 40;
@@ -1134,14 +1137,22 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     const double outs = nb * nm * nn;
     double base;
     if (o.tile_outputs == 0 && nm >= 16 && nn >= 16) {
-      t.mode = STEP_GEMM;
-      t.n_mb = (int32_t)std::ceil(nm / kGemmBlock);
-      t.n_nb = (int32_t)std::ceil(nn / kGemmBlock);
+      // 64 x 64 blocks do four times the work per staged chunk of 32 x 32
+      // ones (better hiding of the operand loads) but pad ragged sides more
+      const double pad32 = std::ceil(nm / 32) * std::ceil(nn / 32) * 1024.0;
+      const double pad64 = std::ceil(nm / 64) * std::ceil(nn / 64) * 4096.0;
+      const int32_t pct = o.gemm64_pct > 0 ? o.gemm64_pct : kGemm64Pct;
+      const bool wide = nm >= 64 && nn >= 64 && pad64 * 100 <= pad32 * pct;
+      const double bm = wide ? 64 : kGemmBlock;
+      t.mode = wide ? STEP_GEMM64 : STEP_GEMM;
+      t.n_mb = (int32_t)std::ceil(nm / bm);
+      t.n_nb = (int32_t)std::ceil(nn / bm);
       // blocks per task: a step with many blocks gives each task several,
       // so that it still has about 2^gemm_tasks_log2 tasks
       const double blocks = nb * t.n_mb * t.n_nb;
       const double target = std::ldexp(1.0, o.gemm_tasks_log2 > 0 ? o.gemm_tasks_log2 : kGemmTasksLog2);
-      t.tile = (int32_t)std::max(1.0, std::min((double)kGemmMaxBlocks, std::floor(blocks / target)));
+      const double most = wide ? kGemmMaxBlocks / 4 : kGemmMaxBlocks;
+      t.tile = (int32_t)std::max(1.0, std::min(most, std::floor(blocks / target)));
       base = std::ceil(blocks / t.tile);
     } else {
       // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
@@ -1256,6 +1267,7 @@ static kn_plan_opts default_opts() {
   o.slice_log2_budget = 0;
   o.split_serial_log2 = 0;
   o.gemm_tasks_log2 = 0;
+  o.gemm64_pct = 0;
   return o;
 }
 
@@ -1277,6 +1289,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
   if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
   if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;
+  if (o.gemm64_pct < 0 || o.gemm64_pct > 100000) return KN_E_INVALID;
   if (o.gradient && o.slice_log2_budget) return KN_E_UNSUPPORTED;
   kn_plan* p = new (std::nothrow) kn_plan();
   if (!p) return KN_E_NOMEM;

@@ -41,6 +41,7 @@ enum StepMode : int32_t {
   STEP_SERIAL = 0,  // done inside a serial task
   STEP_TILES = 1,   // tiles of `tile` consecutive outputs (all L lanes per output)
   STEP_GEMM = 2,    // 32 x 32 output blocks per batch index, LDS-staged, 2x2 per thread
+  STEP_GEMM64 = 3,  // 64 x 64 output blocks, LDS-staged, 4x4 per thread
 };
 constexpr int32_t kGemmBlock = 32;  // rows and columns of a STEP_GEMM tile
 constexpr int32_t kGemmChunk = 16;  // contracted entries staged per LDS round

@@ -36,7 +36,8 @@ class PlanOpts(ctypes.Structure):
                 ("big_step_macs_log2", ctypes.c_int32), ("paper_stats", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32),
                 ("tile_macs_log2", ctypes.c_int32), ("slice_log2_budget", ctypes.c_int32),
-                ("split_serial_log2", ctypes.c_int32), ("gemm_tasks_log2", ctypes.c_int32)]
+                ("split_serial_log2", ctypes.c_int32), ("gemm_tasks_log2", ctypes.c_int32),
+                ("gemm64_pct", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -191,7 +192,7 @@ class Plan:
     def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
                  jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
                  paper_stats=False, lds_bytes=0, gradient=False, tile_macs_log2=0,
-                 slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
+                 slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0, gemm64_pct=0,
                  allow_budget=False):
         L = lib()
         if simplify is None:
@@ -199,7 +200,7 @@ class Plan:
         o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
                      tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
                      1 if gradient else 0, tile_macs_log2, slice_log2_budget, split_serial_log2,
-                     gemm_tasks_log2)
+                     gemm_tasks_log2, gemm64_pct)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -305,7 +306,8 @@ class PlanSet:
 
 def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, simplify=None,
              jones_only=True, tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-             tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0):
+             tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
+              gemm64_pct=0):
     """kn_plan_many over knots given as one int32 crossing-count array and
     their PD codes concatenated in one flat int32 array.  Returns a PlanSet."""
     L = lib()
@@ -319,7 +321,7 @@ def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, sim
         simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
                  big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
-                 slice_log2_budget, split_serial_log2, gemm_tasks_log2)
+                 slice_log2_budget, split_serial_log2, gemm_tasks_log2, gemm64_pct)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)
@@ -335,7 +337,8 @@ def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, sim
 
 def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
               tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-              tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0):
+              tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
+              gemm64_pct=0):
     """Tait graphs and plans for many knots on the library's host thread pool
     (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
     L = lib()
@@ -348,7 +351,7 @@ def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jone
         simplify = 1 if (gradient or not jones_only) else 3
     o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
                  big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
-                 slice_log2_budget, split_serial_log2, gemm_tasks_log2)
+                 slice_log2_budget, split_serial_log2, gemm_tasks_log2, gemm64_pct)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)

@@ -51,8 +51,14 @@ VTX = np.dtype([(f, "<i4") for f in ("tensor", "n_slots", "slot_off", "keep_cent
 PAIR = np.dtype([("x", "<i4"), ("y", "<i4")], align=True)
 FACTOR = np.dtype([("x", "<i4"), ("y", "<i4"), ("a", "<i4"), ("b", "<i4")], align=True)
 TAB_CAP = 3072
-STEP_SERIAL, STEP_TILES, STEP_GEMM = 0, 1, 2
-GEMM_BLOCK = 32
+STEP_SERIAL, STEP_TILES, STEP_GEMM, STEP_GEMM64 = 0, 1, 2, 3
+GEMM_BLOCK = {STEP_GEMM: 32, STEP_GEMM64: 64}
+GEMM_CHUNK = 16
+# byte offset of the LDS tensor arena (program.h): gather tables (3072 int32),
+# 64 step descriptors, 768 int32 shifts, 768 int64 exponents, 128 operand
+# states of 16 bytes
+LDS_ARENA = (((3072 * 4 + 64 * STEP.itemsize + 768 * 4 + 7) // 8 * 8 + 768 * 8 + 15) // 16 * 16
+             + 128 * 16)
 REDUCE_CHUNK = 8192
 TASK_SERIAL, TASK_TILE, TASK_REDUCE = 0, 1, 2
 
@@ -217,10 +223,14 @@ def run(raw: bytes, J=None, want_grad=False):
                 tile = int(s["tile"])
                 assert base * tile >= outs and (base - 1) * tile < outs
             else:
+                assert mode in GEMM_BLOCK
+                bm = GEMM_BLOCK[mode]
+                # both staged operand chunks fit in the launch's LDS
+                assert 2 * GEMM_CHUNK * (bm + 1) * es <= LDS_ARENA + int(h["lds_bytes"])
                 n_mb, n_nb, per = int(s["n_mb"]), int(s["n_nb"]), int(s["tile"])
                 assert per >= 1 and base == -(-nb * n_mb * n_nb // per)
-                assert n_mb * GEMM_BLOCK >= nm and (n_mb - 1) * GEMM_BLOCK < nm
-                assert n_nb * GEMM_BLOCK >= nn and (n_nb - 1) * GEMM_BLOCK < nn
+                assert n_mb * bm >= nm and (n_mb - 1) * bm < nm
+                assert n_nb * bm >= nn and (n_nb - 1) * bm < nn
         Am = A[tAb[:, None, None] + tAm[None, :, None] + tAk[None, None, :]]
         Bm = B[tBb[:, None, None] + tBk[None, :, None] + tBn[None, None, :]]
         scale = math.ldexp(1.0, -(sh(a) + sh(b)))
@@ -468,7 +478,7 @@ def run(raw: bytes, J=None, want_grad=False):
                     finished[t] = True
         elif task["kind"] == TASK_TILE:
             sd = im.steps[int(task["first"])]
-            assert int(sd["mode"]) in (STEP_TILES, STEP_GEMM)
+            assert int(sd["mode"]) in (STEP_TILES, STEP_GEMM, STEP_GEMM64)
             assert 0 <= int(task["count"]) < int(sd["n_tiles"])
             if task["count"] == 0:
                 step(int(task["first"]), local)  # the model computes the whole step once

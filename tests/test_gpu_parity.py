@@ -166,6 +166,37 @@ def test_gemm_and_split_parity():
             assert z_close(m, e, mo, eo, tol), (name, kw, prec)
 
 
+def test_gemm64_parity():
+    """64 x 64 GEMM blocks (4 x 4 outputs per thread): ragged sides, several
+    blocks per task, a split contracted range with its reduction; complex128
+    and complex64."""
+    from tests.test_host import gemm64_cases
+    for label, d, q, kw in gemm64_cases():
+        _log(f"gemm64 case {label} q={q} {kw}")
+        tg, mo, eo = oracle_z(d, q)
+        for prec in (0, 1):
+            t, p, m, e = gpu_z(d, q, precision=prec, **kw)
+            tol = TOL if prec == 0 else 1e-3
+            assert z_close(m, e, mo, eo, tol), (label, kw, prec)
+
+
+def test_gemm64_split_ragged_full_size():
+    """The workload's largest knot (571 crossings) with its ragged split GEMM
+    step in 64 x 64 blocks, one block per task and grouped: checked against
+    the q=3 Lickorish-Millett class of V(e^{i pi/3}) (the oracle takes too long
+    at this size)."""
+    d = gen.config_knots("q3_200_600", 0, count=79)[78][0]
+    tg = oracle_tait(d)
+    dd, unit = invariants.q3_class(tg.n_vertices, tg.edges, tg.eps)
+    for kw in (dict(gemm64_pct=100000, gemm_tasks_log2=30), dict(gemm64_pct=100000, gemm_tasks_log2=1)):
+        _log(f"gemm64 knot 78 {kw}")
+        t, p, m, e = gpu_z(d, 3, **kw)
+        v, l2, ar = kn.jones(3, t, m, e)
+        assert abs(l2 - dd * math.log2(3) / 2) < 1e-9, kw
+        ratio = complex(math.cos(ar), math.sin(ar)) / unit
+        assert min(abs(ratio - 1), abs(ratio + 1)) < 1e-9, kw
+
+
 def test_series_parallel_parity():
     """simplify bit 2 (exact series-parallel reduction at the Jones couplings:
     derived edges and constant factors from the plan's constants)."""

@@ -145,6 +145,8 @@ def test_plan_model_tiled_and_options():
                    dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1),
                    dict(split_serial_log2=3), dict(split_serial_log2=40),
                    dict(big_step_macs_log2=4, gemm_tasks_log2=1),
+                   dict(big_step_macs_log2=4, gemm64_pct=100000),
+                   dict(big_step_macs_log2=4, gemm64_pct=1),
                    dict(simplify=7), dict(simplify=5)):
             _check_model(d, 3, **kw)
 
@@ -160,6 +162,60 @@ def _split_gemm_cases():
     for k in range(2):
         cases.append((gen.lattice_knot((63, k), 100, 400), dict(big_step_macs_log2=4)))
     return cases
+
+
+def gemm64_cases():
+    """(label, knot, q, plan options) whose plans hold 64 x 64 GEMM steps:
+    ragged sides, several blocks per task, and a split contracted range."""
+    work = gen.config_knots("q3_200_600", 0, count=103)
+    wide = dict(gemm64_pct=100000)
+    return [("work71", work[71][0], 3, dict(strategy=0, simplify=3, **wide)),
+            ("work94", work[94][0], 3, dict(gemm_tasks_log2=1, **wide)),
+            ("work102", work[102][0], 3, dict(strategy=0, simplify=3, **wide)),
+            ("lattice61_2", gen.lattice_knot((61, 2), 60, 250), 4,
+             dict(big_step_macs_log2=4, **wide)),
+            ("lattice61_2", gen.lattice_knot((61, 2), 60, 250), 4,
+             dict(big_step_macs_log2=4, gemm_tasks_log2=1, **wide)),
+            ("lattice61_5", gen.lattice_knot((61, 5), 150, 400), 3,
+             dict(big_step_macs_log2=4, gemm_tasks_log2=1, **wide))]
+
+
+def test_plan_model_gemm64_steps():
+    seen = set()
+    for label, d, q, kw in gemm64_cases():
+        p = kn.Plan(kn.Tait(d.pd), q, **kw)
+        for s in image_model.Image(p.image()).steps:
+            if int(s["mode"]) == image_model.STEP_GEMM64:
+                seen.add(("split", int(s["n_ks"]) > 1))
+                seen.add(("grouped", int(s["tile"]) > 1))
+                seen.add(("ragged", int(s["nm"]) % 64 != 0 or int(s["nn"]) % 64 != 0))
+        _check_model(d, q, **kw)
+    assert {("split", True), ("grouped", True), ("ragged", True)} <= seen
+    # gemm64_pct=1 keeps every GEMM step in 32 x 32 blocks
+    d = gemm64_cases()[0][1]
+    p = kn.Plan(kn.Tait(d.pd), 3, strategy=0, simplify=3, gemm64_pct=1)
+    modes = {int(s["mode"]) for s in image_model.Image(p.image()).steps}
+    assert image_model.STEP_GEMM in modes and image_model.STEP_GEMM64 not in modes
+
+
+def test_plan_model_gemm64_split_ragged_full_size():
+    """The workload's largest knot (571 crossings) in 64 x 64 blocks, with a
+    ragged split GEMM step: too slow for the oracle, so the model's Z is
+    checked against the q=3 Lickorish-Millett class of V(e^{i pi/3})."""
+    from oracle import invariants
+    d = gen.config_knots("q3_200_600", 0, count=79)[78][0]
+    t = kn.Tait(d.pd)
+    p = kn.Plan(t, 3, gemm64_pct=100000, gemm_tasks_log2=1)
+    steps = image_model.Image(p.image()).steps
+    assert any(int(s["mode"]) == image_model.STEP_GEMM64 and int(s["n_ks"]) > 1
+               and int(s["nm"]) % 64 != 0 for s in steps)
+    zm, ze = _model_z(p)
+    v, l2, ar = kn.jones(3, t, zm, ze)
+    tg = oracle_tait(d)
+    dd, unit = invariants.q3_class(tg.n_vertices, tg.edges, tg.eps)
+    assert abs(l2 - dd * math.log2(3) / 2) < 1e-9
+    ratio = complex(math.cos(ar), math.sin(ar)) / unit
+    assert min(abs(ratio - 1), abs(ratio + 1)) < 1e-9
 
 
 def test_plan_model_gemm_and_split_steps():
