@@ -6,9 +6,11 @@ How a step runs is decided by a few planner knobs:
 - tile_macs_log2: how much work one tile of outputs carries;
 - lds_bytes: the per-workgroup LDS arena for tensors that stay inside one
   serial task, which also sets how many workgroups fit on a compute unit;
-- gemm_tasks_log2: how many tasks a step computed in 32 x 32 blocks is cut
-  into (several blocks per task above that).
-The persistent kernel's grid is the fourth knob.  The tuner times
+- gemm_tasks_log2: how many tasks a step computed in output blocks is cut
+  into (several blocks per task above that);
+- gemm64_pct: how much padding a step accepts to use 64 x 64 output blocks
+  instead of 32 x 32 ones.
+The persistent kernel's grid is the last knob.  The tuner times
 kn_batch_contract with HIP events (on the launch stream) on a sample of a
 workload, searches the knobs by coordinate descent from the defaults, and
 writes the best setting with the full table of measurements to a JSON file.
@@ -31,9 +33,10 @@ SPACE = {
     "tile_macs_log2": [13, 14, 15, 16, 17],
     "lds_bytes": [16384, 24576, 32768, 49152],
     "gemm_tasks_log2": [4, 5, 6, 7, 30],
+    "gemm64_pct": [1, 150, 300],
 }
 DEFAULTS = {"big_step_macs_log2": 16, "tile_macs_log2": 15, "lds_bytes": 24576,
-            "gemm_tasks_log2": 5, "grid": 0}
+            "gemm_tasks_log2": 5, "gemm64_pct": 300, "grid": 0}
 TUNED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
 
 
