@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=256, help="knots per step")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0, help="host planning threads (0 = all)")
+    ap.add_argument("--prefetch", type=int, default=2, choices=(1, 2, 3),
+                    help="batches the helper thread prepares ahead of the launch thread")
     ap.add_argument("--kernel-reps", type=int, default=20,
                     help="launches of the contraction kernel timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -123,11 +125,13 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---------------------------------------------------------------- pipeline
-    # Two threads.  A helper prepares batch i+1 (Tait graphs and plans on the
-    # library's thread pool, the batch device program, its upload on a side
-    # stream into one of two alternating workspaces) while the launch thread
-    # contracts batch i and, while the GPU runs it, forms V = A Z of batch i - 1
-    # and releases that batch.  The library calls release the GIL.
+    # Two threads.  A helper prepares batches i+1 .. i+prefetch back to back
+    # (Tait graphs and plans on the library's thread pool, the batch device
+    # program, its upload on a side stream into one of prefetch + 1 workspaces
+    # in turn) while
+    # the launch thread contracts batch i and, while the GPU runs it, forms
+    # V = A Z of batch i - 1 and releases that batch.  The library calls
+    # release the GIL.
     state = {}
     # the threads hand the interpreter lock to each other often: switch fast
     sys.setswitchinterval(1e-4)
@@ -140,7 +144,7 @@ def main():
 
     # wall time of each part of the pipeline, summed over the timed steps
     phase = {k: 0.0 for k in ("prepare", "plan", "batch", "upload", "handoff", "device", "launch",
-                              "submit", "finish", "wait", "jones")}
+                              "submit", "finish", "wait", "jones", "release", "gpu")}
     counter = [0]
 
     def workspace(slot, need, precision):
@@ -161,11 +165,16 @@ def main():
         if tuned[precision].get("grid"):
             batch.set_grid(int(tuned[precision]["grid"]))
         t2 = time.perf_counter()
-        # the workspace this batch uses was last used two batches ago, whose
-        # contraction the launch thread has waited for
-        slot = counter[0] % 2
+        # prefetch + 1 workspaces in turn: the upload into this one waits (on
+        # the GPU, not here) for the contraction that used it last, prefetch + 1
+        # batches ago; that contraction's launch came before this preparation
+        # was queued
+        slot = counter[0] % (args.prefetch + 1)
         counter[0] += 1
         ws = workspace(slot, batch.workspace_bytes, precision)
+        last = state.get(("done", precision, slot))
+        if last is not None:
+            up_stream.wait_event(last)
         batch.upload(ws, up_stream)
         uploaded = torch.cuda.Event()
         uploaded.record(up_stream)
@@ -174,41 +183,57 @@ def main():
         phase["batch"] += t2 - t1
         phase["upload"] += t3 - t2
         phase["prepare"] += t3 - tp
-        return taits, plans, batch, uploaded
+        return taits, plans, batch, uploaded, slot
 
     def launch(prepared, precision=0):
         """Queue batch i's contraction behind its upload."""
-        taits, plans, batch, uploaded = prepared
+        taits, plans, batch, uploaded, slot = prepared
         z = state.get(("z", precision))
         if z is None:
             z = kn.alloc_scalars(B)
             state[("z", precision)] = z
         t1 = time.perf_counter()
         stream.wait_event(uploaded)
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
         batch.contract(stream=stream, z=z)
-        done = torch.cuda.Event()
+        done = torch.cuda.Event(enable_timing=True)
         done.record(stream)
+        state["start"] = start
+        state[("done", precision, slot)] = done
         phase["launch"] += time.perf_counter() - t1
         return done, z
+
+    def release(box):
+        box.pop()
 
     def finish(prepared, done, z, hand=None):
         """While the GPU runs batch i: form V = A Z of batch i - 1 (handed over
         in the list `hand`, which holds the only reference) and release that
         batch; then wait for batch i's Z."""
-        taits, plans, batch, _ = prepared
+        taits, plans, batch = prepared[:3]
         previous = hand.pop() if hand else None
         t2 = time.perf_counter()
         if previous is not None:
-            ptaits, _, _, pzh = previous
-            kn.jones_many(q, ptaits, pzh)
-            del previous, ptaits
+            kn.jones_many(q, previous[0], previous[3])
+        t21 = time.perf_counter()
+        # batch i - 1 (plans, Tait graphs, device program) is released by the
+        # helper thread between two preparations: freed while the planning
+        # threads allocate, its many small blocks would contend for the
+        # allocator's locks (several ms instead of a fraction of one)
+        if previous is not None:
+            pool.submit(release, [previous])
+        del previous
         t3 = time.perf_counter()
+        phase["release"] += t3 - t21
         # wait without spinning: the planning threads need every core
         while not done.query():
             time.sleep(50e-6)
         zh = z.cpu().numpy()
         t4 = time.perf_counter()
-        phase["jones"] += t3 - t2
+        # the contraction's own time inside the pipeline (device clock)
+        phase["gpu"] += state["start"].elapsed_time(done) / 1e3
+        phase["jones"] += t21 - t2
         phase["wait"] += t4 - t3
         return taits, plans, batch, zh
 
@@ -216,16 +241,18 @@ def main():
         """n whole batches, host preparation (and upload) of batch i+1
         overlapped with the device work of batch i; returns the last batch's
         results (every batch's V is formed before this returns)."""
-        fut = pool.submit(prepare, precision)
+        # the helper runs up to two preparations ahead, back to back (one
+        # worker), so it never waits for the launch thread
+        futs = [pool.submit(prepare, precision) for _ in range(min(args.prefetch, n))]
         cur = None
         for i in range(n):
             t0 = time.perf_counter()
-            prepared = fut.result()
+            prepared = futs.pop(0).result()
             t1 = time.perf_counter()
             done, z = launch(prepared, precision)
             ts = time.perf_counter()
-            if i + 1 < n:
-                fut = pool.submit(prepare, precision)
+            if i + args.prefetch < n:
+                futs.append(pool.submit(prepare, precision))
             hand = [cur] if cur is not None else None
             cur = None
             tf = time.perf_counter()
@@ -328,7 +355,8 @@ def main():
         "host_plan_ms": ms_plan,
         "host_prepare_ms": ms_prepare,
         "host_threads": args.threads if args.threads > 0 else len(os.sched_getaffinity(0)),
-        "pipelined": "host preparation of batch i+1 overlaps the GPU work of batch i",
+        "pipelined": f"host preparation of batches i+1..i+{args.prefetch} overlaps the GPU work "
+                     "of batch i",
         "pipeline_ms": pipeline_ms,
         "tuned": tuned[0] or None,
         "gpu_contract": {

@@ -49,21 +49,20 @@ extern "C" kn_status kn_build_tait(int32_t n, const int32_t* pd, const int8_t* s
   const int32_t nc = 4 * n;
   try {
     // every arc label used exactly twice: partner[s] is the other slot with
-    // the label of slot s (where[lab]: first slot seen, then -2 once paired)
-    std::vector<int32_t> partner(nc), where(m, -1);
+    // the label of slot s.  Without branches: x[lab] is the XOR of the slots
+    // carrying lab, so with exactly two of them x[lab] ^ s is the other one.
+    std::vector<int32_t> partner(nc), x(m, 0), uses(m, 0);
+    uint32_t bad = 0;
     for (int32_t s = 0; s < nc; ++s) {
-      const int32_t lab = pd[s];
-      if (lab < 0 || lab >= m || where[lab] == -2) { delete g; return KN_E_INVALID; }
-      if (where[lab] < 0) {
-        where[lab] = s;
-      } else {
-        partner[s] = where[lab];
-        partner[where[lab]] = s;
-        where[lab] = -2;
-      }
+      const uint32_t lab = (uint32_t)pd[s];
+      bad |= (uint32_t)(lab >= (uint32_t)m);
+      const uint32_t l = lab < (uint32_t)m ? lab : 0;
+      x[l] ^= s;
+      uses[l]++;
     }
-    for (int32_t lab = 0; lab < m; ++lab)
-      if (where[lab] != -2) { delete g; return KN_E_INVALID; }
+    for (int32_t lab = 0; lab < m; ++lab) bad |= (uint32_t)(uses[lab] != 2);
+    if (bad) { delete g; return KN_E_INVALID; }
+    for (int32_t s = 0; s < nc; ++s) partner[s] = x[pd[s]] ^ s;
 
     // crossing signs and orientation consistency: each label must be the
     // outgoing arc of one slot and the incoming arc of another
