@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--batch", type=int, default=256, help="knots per step")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0, help="host planning threads (0 = all)")
+    ap.add_argument("--strategy", type=int, default=2, choices=(0, 1, 2, 3),
+                    help="contraction-order strategy of the planner (kn_plan_opts.strategy); "
+                         "default min-fill only: the pipeline is bound by host planning, and "
+                         "the greedy alternative that auto also builds for the heaviest knots "
+                         "costs more host time than it saves on the device")
     ap.add_argument("--prefetch", type=int, default=2, choices=(1, 2, 3),
                     help="batches the helper thread prepares ahead of the launch thread")
     ap.add_argument("--kernel-reps", type=int, default=20,
@@ -157,6 +162,7 @@ def main():
     def prepare(precision=0):
         tp = time.perf_counter()
         opts = {k: v for k, v in tuned[precision].items() if k != "grid"}
+        opts["strategy"] = args.strategy
         plans = kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, precision=precision,
                             **opts)
         taits = plans  # the set holds the Tait graphs too
@@ -300,7 +306,7 @@ def main():
 
     # host-only breakdown of one step: plans, then plans + device program
     t0 = time.perf_counter()
-    kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads,
+    kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, strategy=args.strategy,
                 **{k: v for k, v in tuned[0].items() if k != "grid"})
     ms_plan = 1e3 * (time.perf_counter() - t0)
     t0 = time.perf_counter()
