@@ -94,7 +94,7 @@ def measured_traffic(kernel: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the contraction runs on one GPU only (asked for --gpus {args.gpus}); "
               "knots are independent and would shard across GPUs with no communication, "
               "but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
