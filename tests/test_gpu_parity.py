@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 from oracle import exact, invariants, kauffman
 from oracle import jones as ojones
 from oracle import potts
-from paper_1807_02119_amd import gen, kn
+from paper_1807_02119_amd import gen, kn, tune
 from tests.oracle_helpers import oracle_tait, oracle_v, oracle_z, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -259,6 +259,51 @@ def test_batch_parity():
     z2 = b.contract()
     torch.cuda.synchronize()
     assert torch.equal(z, z2)
+
+
+def test_bench_configuration_parity():
+    """The batch exactly as bench.py times it: the 256 knots of the 200-600
+    crossing workload planned as one PlanSet (min-fill orders, the tuned
+    setting and grid), uploaded on a side stream and contracted on another
+    behind the upload event; complex128 and complex64.  The first 24 knots are
+    checked against the oracle; every fourth knot and the largest (571
+    crossings) against the q=3 Lickorish-Millett class of V(e^{i pi/3})."""
+    _log("bench configuration: 256 knots, plan set, tuned setting")
+    knots = gen.config_knots("q3_200_600", 0, count=256)
+    ncr = np.array([d.n for d, _ in knots], np.int32)
+    flat = np.concatenate([np.asarray(d.pd, np.int32).reshape(-1) for d, _ in knots])
+    oracle = {i: oracle_z(knots[i][0], 3) for i in range(24)}
+    inv = {}
+    for i in sorted(set(range(0, 256, 4)) | {78}):
+        tg = oracle_tait(knots[i][0])
+        inv[i] = invariants.q3_class(tg.n_vertices, tg.edges, tg.eps)
+    for prec in (0, 1):
+        _log(f"bench configuration, precision {prec}")
+        setting = tune.load("q3_200_600", prec)
+        opts = {k: v for k, v in setting.items() if k != "grid"}
+        ps = kn.plan_set(ncr, flat, 3, strategy=2, precision=prec, **opts)
+        b = kn.Batch(ps)
+        if setting.get("grid"):
+            b.set_grid(int(setting["grid"]))
+        side, main = torch.cuda.Stream(), torch.cuda.current_stream()
+        ws = kn.alloc_workspace(b.workspace_bytes)
+        b.upload(ws, side)
+        uploaded = torch.cuda.Event()
+        uploaded.record(side)
+        main.wait_event(uploaded)
+        z = b.contract(stream=main)
+        torch.cuda.synchronize()
+        out = kn.scalars_from_device(z)
+        tol, itol = (TOL, 1e-9) if prec == 0 else (1e-3, 1e-4)
+        for i, (tg, mo, eo) in oracle.items():
+            m, e = out[i]
+            assert z_close(m, e, mo, eo, tol), (i, prec)
+        for i, (dd, unit) in inv.items():
+            m, e = out[i]
+            v, l2, ar = kn.jones(3, ps.tait(i), m, e)
+            assert abs(l2 - dd * math.log2(3) / 2) < itol, (i, prec)
+            ratio = complex(math.cos(ar), math.sin(ar)) / unit
+            assert min(abs(ratio - 1), abs(ratio + 1)) < itol, (i, prec)
 
 
 def test_batch_small_grid():
