@@ -509,6 +509,46 @@ def test_plan_set_handles():
         assert np.array_equal(x, y)
 
 
+def test_plan_sets_freed_while_planning():
+    """The bench's pattern: plan sets and batches released on one thread while
+    another plans on the library's thread pool.  Every plan set made
+    meanwhile still gives the same batch image."""
+    import threading
+    knots = [gen.lattice_knot((86, k), 40, 160) for k in range(24)]
+    ncr = np.array([d.n for d in knots], np.int32)
+    flat = np.concatenate([np.asarray(d.pd, np.int32).reshape(-1) for d in knots])
+    ref = kn.Batch(kn.plan_set(ncr, flat, 3, strategy=2)).image()
+    old = [kn.plan_set(ncr, flat, 3) for _ in range(6)]
+    errors = []
+
+    def release():
+        try:
+            while old:
+                ps = old.pop()
+                b = kn.Batch(ps)
+                del b, ps
+        except Exception as ex:  # pragma: no cover - reported below
+            errors.append(ex)
+
+    th = threading.Thread(target=release)
+    th.start()
+    images = [kn.Batch(kn.plan_set(ncr, flat, 3, strategy=2)).image() for _ in range(6)]
+    th.join()
+    assert not errors
+    assert all(im == ref for im in images)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with a message."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+
+
 def test_series_parallel_reduction():
     """simplify bit 2: fewer spins, the same Z (CPU model against the oracle
     and against the unreduced plan), constants in the image, and only for
