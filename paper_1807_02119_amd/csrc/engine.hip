@@ -787,6 +787,9 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
                           Cx<T>* __restrict__ arena, uint8_t* smem, int32_t smem_bytes,
                           const States& st, T* s_red) {
   constexpr int32_t BM = 16 * TM, BK = kGemmChunk, P = BM + 1;
+  // the contracted loop unrolled twice for 32-blocks (4x4 blocks already
+  // keep 32 products in flight per entry)
+  constexpr int32_t kUnrollK = TM == 2 ? 2 : 1;
   static_assert(BK == 16 && kBlock == 256, "thread layout: 16 x 16 threads, 16 entries per chunk");
   const QDiv D(q);
   const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
@@ -888,7 +891,7 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
       }
       __syncthreads();
       if (c0 + BK < kl) x = load(c0 + BK);
-#pragma unroll(TM == 2 ? 2 : 1)
+#pragma unroll kUnrollK
       for (int32_t jk = 0; jk < BK; ++jk) {
         Cx<T> a[TM], bb[TM];
 #pragma unroll
