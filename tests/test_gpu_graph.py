@@ -40,6 +40,33 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(z.cpu().numpy().view(np.int64), ref.view(np.int64)), rep
 
 
+def test_graph_replay_negative_exponent():
+    """Result records compare by bit pattern: knot 373 of the mixed batch (q=6,
+    21 crossings) has Z = -0.551 * 2^-4, whose int64 exponent read as a double
+    is a NaN.  Its value matches the oracle, and graph replays reproduce the
+    eager launch bit for bit."""
+    from tests.oracle_helpers import oracle_z
+    knots = gen.config_knots("batched", 0, count=512)[368:380]
+    plans = [kn.Plan(kn.Tait(d.pd), q) for d, q in knots]
+    b = kn.Batch(plans)
+    b.upload()
+    z_eager = b.contract()
+    torch.cuda.synchronize()
+    ref = z_eager.cpu().numpy().copy()
+    exps = ref.view(np.int64)[:, 2]
+    assert (exps < 0).any()
+    for (d, q), (m, e) in zip(knots, kn.scalars_from_device(z_eager)):
+        tg, mo, eo = oracle_z(d, q)
+        assert abs(m * 2.0 ** (e - eo) - mo) <= 1e-10 * abs(mo), d.label
+    z = kn.alloc_scalars(len(plans))
+    g = b.graph(z)
+    for rep in range(3):
+        z.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(z.cpu().numpy().view(np.int64), ref.view(np.int64)), rep
+
+
 def test_graph_replay_gradients():
     rng = np.random.default_rng(21)
     knots = [gen.lattice_knot((79, k), 20, 70) for k in range(6)]
