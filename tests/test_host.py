@@ -549,6 +549,48 @@ def test_bench_refuses_several_gpus():
     assert "one GPU only" in r.stderr
 
 
+def test_bench_traffic_record_matches_source(tmp_path, monkeypatch):
+    """bench.py reports measured HBM traffic only from a record taken on the
+    current kernel source: the committed record matches it, and a record with
+    another source hash gives none."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rec = bench.measured_traffic("engine<double>")
+    assert rec is not None and rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
+    with open(os.path.join(root, "profiles", "engine_traffic.json")) as f:
+        d = json.load(f)
+    d["engine<double>"]["source_hash"] = "0" * 16
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "engine_traffic.json").write_text(json.dumps(d))
+    csrc = tmp_path / "paper_1807_02119_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("engine.hip", "program.h"):
+        (csrc / f).write_bytes(open(os.path.join(root, "paper_1807_02119_amd", "csrc", f), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("engine<double>") is None
+
+
+def test_tuner_space_is_valid():
+    """Every value the autotuner tries, and its recorded settings, are plan
+    options the planner accepts."""
+    from paper_1807_02119_amd import tune
+    d = gen.lattice_knot((88, 0), 40, 120)
+    t = kn.Tait(d.pd)
+    for knob, values in tune.SPACE.items():
+        for v in values:
+            opts = dict((k, x) for k, x in tune.DEFAULTS.items() if k != "grid")
+            opts[knob] = v
+            kn.Plan(t, 3, **opts)
+    for prec in (0, 1):
+        rec = tune.load("q3_200_600", prec)
+        assert rec, prec
+        kn.Plan(t, 3, precision=prec, **{k: x for k, x in rec.items() if k != "grid"})
+
+
 def test_series_parallel_reduction():
     """simplify bit 2: fewer spins, the same Z (CPU model against the oracle
     and against the unreduced plan), constants in the image, and only for
