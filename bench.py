@@ -71,9 +71,13 @@ def parse():
     return ap.parse_args()
 
 
+# the sources the contraction kernel is compiled from
+KERNEL_SOURCES = ("engine.hip", "program.h", "decode.h")
+
+
 def source_hash():
     h = hashlib.sha256()
-    for f in ("engine.hip", "program.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1807_02119_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

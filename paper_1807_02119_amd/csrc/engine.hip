@@ -42,6 +42,7 @@
 #include <algorithm>
 #include <new>
 
+#include "decode.h"
 #include "internal.h"
 
 namespace kn {
@@ -128,28 +129,6 @@ __device__ inline void acc_mul(Cx<double>& z, int64_t& e, Cx<double> f) {
 }
 
 __device__ inline int32_t shift_of(int32_t s) { return s == kShiftNone ? 0 : s; }
-
-// Exact division by q (2 <= q <= 8) for 0 <= x < 2^31: with m = ceil(2^40 / q),
-// (x m) >> 40 = floor(x / q + e), 0 <= e < x / 2^40 < 2^-9, and the fractional
-// part of x / q is at most 7/8, so the floor is never pushed past an integer.
-struct QDiv {
-  uint64_t m;
-  int32_t q;
-  __device__ explicit QDiv(int32_t q_) : m(((uint64_t(1) << 40) + q_ - 1) / q_), q(q_) {}
-  __device__ inline int32_t div(int32_t x) const { return (int32_t)(((uint64_t)x * m) >> 40); }
-};
-
-// Offset of value `idx` of a spin group (r spins, strides str[], first spin
-// most significant) in its operand.
-__device__ inline int32_t group_off(int32_t idx, const int32_t* str, int32_t r, const QDiv& D) {
-  int32_t off = 0;
-  for (int32_t j = r - 1; j >= 0; --j) {
-    const int32_t qd = D.div(idx);
-    off += (idx - qd * D.q) * str[j];
-    idx = qd;
-  }
-  return off;
-}
 
 // Tensor data: the workgroup's LDS arena or the global arena (generic pointer).
 template <class T>
@@ -1131,10 +1110,16 @@ __device__ void knot_gradient(const DevProg& p, const KnotDesc& kd, const Cx<T>*
 // ------------------------------------------------------------------ kernels
 
 // Reset the runtime state of an image: control words, ready queue seeded
-// with the knots' first groups, pending counters, tensor states.
-__global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict__ state) {
+// with the knots' first groups, pending counters, tensor states; the results
+// (every output scalar and slice value) start as NaN, so a knot whose final
+// task never runs (the engine gave up on a queue slot) reads as NaN.
+__global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict__ state,
+                            kn_scalar* __restrict__ zout) {
   const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(img);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const kn_scalar nan{__builtin_nan(""), __builtin_nan(""), 0};
+  if (i < h.n_outputs) zout[i] = nan;
+  if (h.sliced && i < h.n_knots) reinterpret_cast<kn_scalar*>(state + h.o_zslice)[i] = nan;
   int32_t* ctrl = reinterpret_cast<int32_t*>(state);
   if (i < CTRL_WORDS) ctrl[i] = (i == CTRL_TAIL) ? h.n_roots : 0;
   if (i < h.n_tasks) {
@@ -1209,10 +1194,11 @@ __global__ __launch_bounds__(kBlock) void gradient_kernel(const uint8_t* __restr
   knot_gradient<T>(p, kd, arena, grad);
 }
 
-// Bound on the wait for a queue slot (sleep iterations): a slot that is never
-// filled (a planner bug) ends the kernel with the error flag set instead of
-// hanging the device.
-constexpr int32_t kSpinLimit = 1 << 24;
+// Bound on the wait for a queue slot, in ticks of the 100 MHz device clock
+// (20 s, far beyond any launch's critical path): a slot that is never filled
+// (a planner bug) ends the kernel with the error flag set instead of hanging
+// the device; the knots left unfinished keep the NaN that clear_state wrote.
+constexpr int64_t kWaitTicks = 20LL * 100000000LL;
 
 extern __shared__ __align__(16) uint8_t kn_dyn_smem[];
 
@@ -1244,7 +1230,8 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
       const int32_t slot = atomicAdd(&p.ctrl[CTRL_HEAD], 1);
       int32_t t = -1;
       if (slot < n_tasks) {
-        int32_t spins = 0, nap = 1;
+        int32_t nap = 1;
+        const int64_t t_wait = wall_clock64();
         while ((t = __hip_atomic_load(&p.queue[slot], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT)) < 0) {
           if (nap < 16) {
@@ -1253,7 +1240,7 @@ __global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img
           } else {
             __builtin_amdgcn_s_sleep(8);
           }
-          if (++spins > kSpinLimit) {
+          if (wall_clock64() - t_wait > kWaitTicks) {
             __hip_atomic_store(&p.ctrl[CTRL_ERROR], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
@@ -1451,8 +1438,9 @@ kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* 
   n_clear = std::max<int64_t>(n_clear, h.n_tasks);
   n_clear = std::max<int64_t>(n_clear, h.n_groups);
   n_clear = std::max<int64_t>(n_clear, h.n_tensors);
+  n_clear = std::max<int64_t>(n_clear, h.n_knots);
   hipLaunchKernelGGL(clear_state, dim3((unsigned)((n_clear + 255) / 256)), dim3(256), 0, st, ws,
-                     ws + h.state_off);
+                     ws + h.state_off, z);
   if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
   if (h.precision == 1) return launch_engine<float>(h, ws, st, J, z, grad, grid_override, trace);
   return launch_engine<double>(h, ws, st, J, z, grad, grid_override, trace);

@@ -36,6 +36,7 @@
 #include <set>
 #include <unordered_map>
 
+#include "decode.h"
 #include "internal.h"
 
 namespace kn {
@@ -1128,6 +1129,13 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
            nk = qpow[sp.ks.size()];
     flops += 8.0 * nb * nm * nn * nk;
     bytes += es * double(k.tensors[sp.a].size + k.tensors[sp.b].size + k.tensors[sp.c].size);
+    // every group index and operand offset the engine decodes must lie in
+    // the range of its exact division by q (QDiv, decode.h)
+    if (std::max({nb, nm, nn, nk, nb * nm * nn}) > (double)kDecodeMax) {
+      st.max_rank = maxrank;
+      st.log2_max_entries = maxlog;
+      return KN_E_BUDGET;
+    }
     double macs = nb * nm * nn * nk;
     bool big = macs >= std::ldexp(1.0, k.big_log2);
     // a serial step generates its gather tables in LDS; larger ones are tiled

@@ -420,6 +420,45 @@ def _aligned_ptr(ws):
     return (p + 255) & ~255, ws.numel() - ((p + 255 & ~255) - p)
 
 
+def _device_f64(t, n, what):
+    """Pointer of a contiguous float64 GPU tensor of exactly n entries (a
+    complex128 one counts as two float64 per entry); anything else raises
+    ValueError before a pointer reaches the kernels."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what} must be a torch tensor, not {type(t).__name__}")
+    if t.dtype == torch.complex128:
+        t = torch.view_as_real(t)
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what} must be float64 (or complex128), not {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be in GPU memory, not on {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{what} must hold {n} float64 values, not {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _couplings(J, n_edges):
+    """Device pointer of the couplings J (2 float64 per original edge), or None
+    for the Jones couplings."""
+    return None if J is None else _device_f64(J, 2 * n_edges, "J")
+
+
+def _scalars(z, n):
+    return _device_f64(z, 3 * n, "z")
+
+
+def _workspace(ws):
+    """Aligned pointer and usable bytes of a workspace tensor (the library
+    itself rejects one that is too small, with KN_E_BUDGET)."""
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous torch tensor in GPU memory")
+    return _aligned_ptr(ws)
+
+
 def contract(plan: Plan, J=None, workspace=None, stream=None, z=None):
     """Z of the plan's knot on the GPU (kn_contract).  Returns the (1, 3)
     float64 device tensor holding the kn_scalar; see scalars_from_device."""
@@ -427,8 +466,9 @@ def contract(plan: Plan, J=None, workspace=None, stream=None, z=None):
         workspace = alloc_workspace(plan.workspace_bytes)
     if z is None:
         z = alloc_scalars(1)
-    ptr, nbytes = _aligned_ptr(workspace)
-    jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+    ptr, nbytes = _workspace(workspace)
+    jp = _couplings(J, plan.tait.n_edges)
+    _scalars(z, 1)
     rc = lib().kn_contract(plan._h, jp, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream),
                            ctypes.c_void_p(z.data_ptr()))
     _check(rc, "kn_contract")
@@ -451,11 +491,12 @@ def contract_backward(plan: Plan, J=None, workspace=None, stream=None, z=None, g
         z = alloc_scalars(1)
     if grad is None:
         grad = torch.empty((plan.tait.n_edges, 2), dtype=torch.float64, device="cuda")
-    ptr, nbytes = _aligned_ptr(workspace)
-    jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+    ptr, nbytes = _workspace(workspace)
+    ne = plan.tait.n_edges
+    jp = _couplings(J, ne)
     rc = lib().kn_contract_backward(plan._h, jp, ctypes.c_void_p(ptr), nbytes,
-                                    _stream_ptr(stream), ctypes.c_void_p(z.data_ptr()),
-                                    ctypes.c_void_p(grad.data_ptr()))
+                                    _stream_ptr(stream), _scalars(z, 1),
+                                    _device_f64(grad, 2 * ne, "grad"))
     _check(rc, "kn_contract_backward")
     return z, grad
 
@@ -532,7 +573,7 @@ class Batch:
     def upload(self, workspace=None, stream=None):
         if workspace is None:
             workspace = alloc_workspace(self.workspace_bytes)
-        ptr, nbytes = _aligned_ptr(workspace)
+        ptr, nbytes = _workspace(workspace)
         _check(lib().kn_batch_upload(self._h, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream)),
                "kn_batch_upload")
         self.workspace = workspace
@@ -543,10 +584,10 @@ class Batch:
             self.upload(stream=stream)
         if z is None:
             z = alloc_scalars(len(self.plans))
-        ptr, nbytes = _aligned_ptr(self.workspace)
-        jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+        ptr, nbytes = _workspace(self.workspace)
+        jp = _couplings(J, int(self.stats["total_edges"]))
         _check(lib().kn_batch_contract(self._h, jp, ctypes.c_void_p(ptr), nbytes,
-                                       _stream_ptr(stream), ctypes.c_void_p(z.data_ptr())),
+                                       _stream_ptr(stream), _scalars(z, len(self.plans))),
                "kn_batch_contract")
         return z
 
@@ -579,11 +620,12 @@ class Batch:
         if grad is None:
             grad = torch.empty((max(1, int(self.stats["total_edges"])), 2), dtype=torch.float64,
                                device="cuda")
-        ptr, nbytes = _aligned_ptr(self.workspace)
-        jp = None if J is None else ctypes.c_void_p(J.data_ptr())
+        ptr, nbytes = _workspace(self.workspace)
+        ne = int(self.stats["total_edges"])
+        jp = _couplings(J, ne)
         _check(lib().kn_batch_contract_backward(self._h, jp, ctypes.c_void_p(ptr), nbytes,
-                                                _stream_ptr(stream), ctypes.c_void_p(z.data_ptr()),
-                                                ctypes.c_void_p(grad.data_ptr())),
+                                                _stream_ptr(stream), _scalars(z, len(self.plans)),
+                                                _device_f64(grad, 2 * max(1, ne), "grad")),
                "kn_batch_contract_backward")
         return z, grad
 
@@ -620,6 +662,8 @@ def _make_logz():
 
         @staticmethod
         def forward(ctx, J, plan):
+            if J.dtype != torch.complex128:
+                raise ValueError(f"J must be complex128, not {J.dtype}")
             Jr = torch.view_as_real(J.detach().contiguous()).reshape(-1)
             z, g = contract_backward(plan, Jr)
             (m, e), = scalars_from_device(z)

