@@ -264,6 +264,23 @@ kn_status kn_plan_steps(const kn_plan* p, int32_t* ab);
 kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
                       size_t workspace_bytes, void* stream, kn_scalar* z_dev);
 
+/* kn_contract without a workspace argument and without any device allocation,
+ * for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * library-owned array of KN_NOALLOC_MAX_BYTES in device memory, one per
+ * device, held until the process ends; the call uploads the plan's image
+ * there and launches the same kernels as kn_contract (same results, bit for
+ * bit).  Every call on one device shares that device's array and leaves its
+ * contents behind (the kernels reset the state they need), so calls that
+ * overlap on one device -- on different streams, or from different host
+ * threads without ordering -- race and give undefined results.
+ *   J, stream, z_dev  as in kn_contract.
+ * Errors: KN_E_BUDGET when the plan's workspace_bytes exceeds
+ * KN_NOALLOC_MAX_BYTES (or the plan has no image); KN_E_DEVICE when the
+ * array's device address cannot be obtained. */
+#define KN_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+kn_status kn_contract_noalloc(const kn_plan* p, const double* J, void* stream, kn_scalar* z_dev);
+
 /* d log Z / d J_e (holomorphic derivative, dT_e/dJ_e = e^{J_e} delta) for
  * every ORIGINAL edge, written to grad_dev (device, 2*n_edges doubles, re/im
  * interleaved, edge order of kn_tait_edges).  One launch runs the forward

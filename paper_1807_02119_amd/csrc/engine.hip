@@ -1478,6 +1478,52 @@ extern "C" kn_status kn_contract(const kn_plan* p, const double* J, void* worksp
   return contract_plan(p, J, workspace, workspace_bytes, stream, z_dev, nullptr);
 }
 
+// ------------------------------------------------------------------ fixed scratch
+// Workspace of kn_contract_noalloc: one library-owned array per device, in
+// place of the caller's workspace, so that the call allocates nothing.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// its device address is looked up once per device (hipGetSymbolAddress) and
+// only that address is handed to the kernels.
+static __device__ __align__(256) uint8_t scratch[KN_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (null: not looked up)
+
+// Device address of the current device's copy of `scratch`.
+kn_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KN_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return KN_E_DEVICE;
+    }
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return KN_OK;
+}
+
+}  // namespace
+
+extern "C" kn_status kn_contract_noalloc(const kn_plan* p, const double* J, void* stream,
+                                         kn_scalar* z_dev) {
+  if (!p || !z_dev) return KN_E_INVALID;
+  const Bytes& image = plan_image(p);
+  if (image.empty()) return KN_E_BUDGET;
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(image.data());
+  if (h.workspace_bytes > (int64_t)KN_NOALLOC_MAX_BYTES) return KN_E_BUDGET;
+  void* ws = nullptr;
+  const kn_status rc = scratch_address(&ws);
+  if (rc != KN_OK) return rc;
+  return contract_plan(p, J, ws, KN_NOALLOC_MAX_BYTES, stream, z_dev, nullptr);
+}
+
 extern "C" kn_status kn_batch_create(const kn_plan* const* plans, int32_t n, kn_batch** out) {
   if (!out) return KN_E_INVALID;
   *out = nullptr;

@@ -88,6 +88,7 @@ _SIGS = {
     "kn_plan_image": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
     "kn_plan_free": (None, [P]),
     "kn_contract": (I32, [P, P, P, ctypes.c_size_t, P, P]),
+    "kn_contract_noalloc": (I32, [P, P, P, P]),
     "kn_backward_workspace": (I32, [P, ctypes.POINTER(ctypes.c_uint64)]),
     "kn_contract_backward": (I32, [P, P, P, ctypes.c_size_t, P, P, P]),
     "kn_jones": (I32, [I32, P, ctypes.POINTER(Scalar), PD, PD, PD, PD]),
@@ -472,6 +473,18 @@ def contract(plan: Plan, J=None, workspace=None, stream=None, z=None):
     rc = lib().kn_contract(plan._h, jp, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream),
                            ctypes.c_void_p(z.data_ptr()))
     _check(rc, "kn_contract")
+    return z
+
+
+def contract_noalloc(plan: Plan, J=None, stream=None, z=None):
+    """Z of the plan's knot with the library's own fixed device array as the
+    workspace (kn_contract_noalloc): the call allocates no device memory.
+    Calls that overlap on one device race.  Returns z."""
+    if z is None:
+        z = alloc_scalars(1)
+    jp = _couplings(J, plan.tait.n_edges)
+    rc = lib().kn_contract_noalloc(plan._h, jp, _stream_ptr(stream), _scalars(z, 1))
+    _check(rc, "kn_contract_noalloc")
     return z
 
 
