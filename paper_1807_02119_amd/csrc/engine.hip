@@ -136,6 +136,65 @@ __device__ inline Cx<T>* tptr(const TensorDesc& d, Cx<T>* arena, Cx<T>* lds) {
   return d.lds_off >= 0 ? lds + d.lds_off : arena + d.off;
 }
 
+// Operand pointers with their address space fixed at compile time: LDS
+// operands are read with LDS instructions and global ones with global
+// instructions.  A generic (flat) load shares the vector-memory counter with
+// stores, so a flat operand load would wait for every earlier output store.
+template <class T>
+using LdsCx = __attribute__((address_space(3))) Cx<T>;
+template <class T>
+using GlbCx = __attribute__((address_space(1))) Cx<T>;
+
+// Loads of complex entries through address-space-qualified pointers
+// (member-wise, merged into one wide access by the compiler).
+template <class P>
+__device__ inline auto ldc(P p) {
+  using T = decltype(+p->re);
+  return Cx<T>{p->re, p->im};
+}
+
+// Output entries.  Tensor entries in global memory are written through the
+// L2 to memory (system-scope cache policy, sc0 sc1) instead of leaving dirty
+// lines there: a task that finishes then has little left to write back when
+// it releases its results at device scope (the release itself is
+// unchanged), which makes the per-task release noticeably cheaper.  One
+// entry is one store instruction (16 bytes in complex128, 8 in complex64),
+// so the lanes of a wavefront that write consecutive entries write whole
+// lines.  The stores are buffer stores with the cache policy as an operand,
+// through a buffer resource whose base is the start of the output range a
+// workgroup or wavefront writes (uniform over the wavefront); offsets are
+// byte offsets from it, below kOutRangeBytes (the planner keeps every
+// range a step writes from one base below that size), and a store past the
+// range is dropped by the hardware bounds check rather than written.
+constexpr int32_t kOutRangeBytes = 0x7fffffff;
+constexpr int32_t kRawBufferWord3 = 0x00020000;  // raw buffer, 32-bit elements
+constexpr int32_t kWriteThrough = 1 | 16;        // sc0 | sc1: system scope
+
+template <class T>
+struct GlbOut {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ explicit GlbOut(GlbCx<T>* base)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)base, 0, kOutRangeBytes, kRawBufferWord3)) {}
+};
+
+__device__ inline void put(const GlbOut<double>& o, int32_t i, Cx<double> v) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+  const D2 x = {v.re, v.im};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, x), o.r, i * 16, 0, kWriteThrough);
+}
+__device__ inline void put(const GlbOut<float>& o, int32_t i, Cx<float> v) {
+  typedef float F2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t U2 __attribute__((ext_vector_type(2)));
+  const F2 x = {v.re, v.im};
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, x), o.r, i * 8, 0, kWriteThrough);
+}
+template <class T>
+__device__ inline void put(LdsCx<T>* p, int32_t i, Cx<T> v) {
+  p[i].re = v.re;
+  p[i].im = v.im;
+}
+
 // Tensor states: those produced by the running serial task are cached in LDS,
 // the rest live in global memory.
 struct States {
@@ -228,6 +287,8 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
     const VtxDesc vd = p.vtx[kd.vtx_off + v];
     const TensorDesc td = p.tens[vd.tensor];
     Cx<T>* out = tptr<T>(td, arena, lds);
+    const bool in_lds = td.lds_off >= 0;
+    const GlbOut<T> gout((GlbCx<T>*)(in_lds ? arena : out));
     const int32_t* slot_me = p.vslot + vd.slot_off;
     int32_t qn = 1;  // q^n_slots
     for (int j = 0; j < vd.n_slots; ++j) qn *= q;
@@ -258,8 +319,8 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
         acc.re += prod.re;
         acc.im += prod.im;
       }
-      if (td.lds_off >= 0) out[i] = Cx<T>{(T)acc.re, (T)acc.im};
-      else st_through(out + i, Cx<T>{(T)acc.re, (T)acc.im});
+      if (in_lds) out[i] = Cx<T>{(T)acc.re, (T)acc.im};
+      else put(gout, i, Cx<T>{(T)acc.re, (T)acc.im});
     }
     // entries are products of <= 8 weights: no scaling needed
     if (lane == 0) st.set(vd.tensor, 0, 0);
@@ -300,44 +361,6 @@ struct GenIx {
   __device__ inline int32_t a_k(int32_t k) const { return off(2, k); }
   __device__ inline int32_t b_k(int32_t k) const { return off(4, k); }
 };
-
-// Operand pointers with their address space fixed at compile time: LDS
-// operands are read with LDS instructions and global ones with global
-// instructions.  A generic (flat) load shares the vector-memory counter with
-// stores, so a flat operand load would wait for every earlier output store.
-template <class T>
-using LdsCx = __attribute__((address_space(3))) Cx<T>;
-template <class T>
-using GlbCx = __attribute__((address_space(1))) Cx<T>;
-
-// Loads and stores of complex entries through address-space-qualified
-// pointers (member-wise, merged into one wide access by the compiler).
-//
-// Tensor entries in global memory are written with system-scope stores,
-// which write through the L2 instead of leaving dirty lines there: a task
-// that finishes then has little left to write back when it releases its
-// results at device scope (the release itself is unchanged), which makes
-// the per-task release noticeably cheaper.
-template <class T>
-__device__ inline void st_through(Cx<T>* p, Cx<T> v) {
-  __hip_atomic_store(&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-template <class P>
-__device__ inline auto ldc(P p) {
-  using T = decltype(+p->re);
-  return Cx<T>{p->re, p->im};
-}
-template <class P, class T>
-__device__ inline void stc(P p, Cx<T> v) {
-  if constexpr (std::is_same_v<P, GlbCx<T>*>) {
-    __hip_atomic_store((T*)&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store((T*)&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  } else {
-    p->re = v.re;
-    p->im = v.im;
-  }
-}
 
 // This lane's part of sum_k A[row, k] B[k, col] over k = k_first, k_first + L,
 // ... < nk: four entries per round, the loads of a round issued before its
@@ -427,7 +450,8 @@ __device__ inline void lane_dot2(PA ra, PB rb, PA ra2, PB rb2, const Ix& ix, int
 
 // Outputs [o_begin, o_end) of C = A . B, each summed over k in [k0, nk) by L
 // lanes of one wavefront; threads tid = 0..nthr-1 (a whole workgroup or one
-// wavefront) share the outputs.  A thread computes two outputs together (their
+// wavefront) share the outputs.  pc addresses the range itself: output o is
+// entry o - o_begin of pc.  A thread computes two outputs together (their
 // loads interleaved) before it stores either, so its stores overlap the next
 // pair's loads.  Returns this thread's max |.|.
 template <class T, class Ix, class PA, class PB, class PC>
@@ -435,6 +459,7 @@ __device__ __attribute__((always_inline)) T step_outputs(PA pa, PB pb, PC pc, co
                           int32_t nk, int64_t o_begin, int64_t o_end, T scale, int32_t L,
                           int32_t tid, int32_t nthr) {
   const int32_t mn = nm * nn;
+  const int32_t ob = (int32_t)o_begin;
   const int32_t lsub = tid & (L - 1);
   const int32_t slot = tid / L;
   const int32_t nslot = nthr / L;
@@ -467,12 +492,12 @@ __device__ __attribute__((always_inline)) T step_outputs(PA pa, PB pb, PC pc, co
     if (lsub == 0) {
       cr *= scale;
       ci *= scale;
-      stc(pc + oi, Cx<T>{cr, ci});
+      put(pc, oi - ob, Cx<T>{cr, ci});
       lmax = fmax(lmax, fmax(fabs(cr), fabs(ci)));
       if (two) {
         cr2 *= scale;
         ci2 *= scale;
-        stc(pc + oi2, Cx<T>{cr2, ci2});
+        put(pc, oi2 - ob, Cx<T>{cr2, ci2});
         lmax = fmax(lmax, fmax(fabs(cr2), fabs(ci2)));
       }
     }
@@ -489,22 +514,25 @@ __device__ __attribute__((always_inline)) T step_outputs_homes(int32_t ha, int32
                                 int32_t nthr) {
   auto gl = [&](int32_t h) { return (GlbCx<T>*)(arena + h); };
   auto ld = [&](int32_t h) { return (LdsCx<T>*)(lds + (-1 - h)); };
+  // the output range [o_begin, o_end) of C
+  auto glo = [&](int32_t h) { return GlbOut<T>((GlbCx<T>*)(arena + h) + o_begin); };
+  auto ldo = [&](int32_t h) { return (LdsCx<T>*)(lds + (-1 - h)) + o_begin; };
 #define KN_RUN(A, B, C) \
   return step_outputs<T>(A(ha), B(hb), C(hc), ix, nm, nn, k0, nk, o_begin, o_end, scale, L, tid, nthr)
   if (ha < 0) {
     if (hb < 0) {
-      if (hc < 0) KN_RUN(ld, ld, ld);
-      KN_RUN(ld, ld, gl);
+      if (hc < 0) KN_RUN(ld, ld, ldo);
+      KN_RUN(ld, ld, glo);
     }
-    if (hc < 0) KN_RUN(ld, gl, ld);
-    KN_RUN(ld, gl, gl);
+    if (hc < 0) KN_RUN(ld, gl, ldo);
+    KN_RUN(ld, gl, glo);
   }
   if (hb < 0) {
-    if (hc < 0) KN_RUN(gl, ld, ld);
-    KN_RUN(gl, ld, gl);
+    if (hc < 0) KN_RUN(gl, ld, ldo);
+    KN_RUN(gl, ld, glo);
   }
-  if (hc < 0) KN_RUN(gl, gl, ld);
-  KN_RUN(gl, gl, gl);
+  if (hc < 0) KN_RUN(gl, gl, ldo);
+  KN_RUN(gl, gl, glo);
 #undef KN_RUN
 }
 
@@ -746,30 +774,59 @@ __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const
   const int32_t L = lanes_per_output(o1 - o0, k1 - k0);
   Cx<T>* pc = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
   T lm = step_outputs<T>((const GlbCx<T>*)(arena + s.home_a), (const GlbCx<T>*)(arena + s.home_b),
-                         (GlbCx<T>*)pc, ix, s.nm, s.nn, k0, k1, o0, o1, scale, L,
-                         (int32_t)threadIdx.x, kBlock);
+                         GlbOut<T>((GlbCx<T>*)pc + o0), ix, s.nm, s.nn, k0, k1, o0, o1, scale,
+                         L, (int32_t)threadIdx.x, kBlock);
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
+
+// Matrix-core products for the GEMM blocks: D = A B + C on one 16 x 16
+// tile per wavefront, K = 4 (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four
+// accumulator registers of lane l hold column l % 16 of D, at rows row(l, r)
+// (measured lane layouts of the two instructions on gfx950).
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double V __attribute__((ext_vector_type(4)));
+  static __device__ inline V mac(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int32_t row(int32_t l, int32_t r) { return (l >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  static __device__ inline V mac(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int32_t row(int32_t l, int32_t r) { return 4 * (l >> 4) + r; }
+};
 
 // STEP_GEMM / STEP_GEMM64: BM x BM output blocks of C[b] (BM = 16 TM: 32
 // or 64) over contracted range ks of the split, `tile` consecutive blocks per
 // task.  Chunks of 16 contracted entries of A (BM rows) and B (BM columns)
-// are gathered into LDS (row pitch BM + 1 entries, no bank conflicts on the
-// k-fastest stores) and every thread accumulates a TM x TM block of outputs:
-// rows ty + 16 i and columns tx + 16 j.  The next chunk's operands are loaded
-// into registers while the current one is multiplied; 64 x 64 blocks do four
-// times the products of 32 x 32 ones per chunk, enough to cover the latency
-// of those loads.  The contracted offsets come from a table generated in LDS
-// when the range fits, else they are decoded from the strides.
+// are gathered into LDS (row pitch BM + 1 entries), the next chunk's operands
+// loaded into registers while the current one is multiplied.  The products
+// run on the matrix cores: the four wavefronts split the block into 2 x 2
+// quarters of WT x WT tiles of 16 x 16 (WT = TM / 2), and a complex tile
+// takes four real MFMAs per 4 contracted entries,
+//   Re += Re A Re B, Re += (-Im A) Im B, Im += Re A Im B, Im += Im A Re B.
+// The contributions go to independent accumulators (with one tile per
+// wavefront the real and imaginary parts are split once more) so that
+// consecutive MFMAs do not wait on each other.  The contracted offsets come
+// from a table generated in LDS when the range fits, else they are decoded
+// from the strides.
 template <class T, int TM>
 __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* __restrict__ arena, uint8_t* smem, int32_t smem_bytes,
                           const States& st, T* s_red) {
   constexpr int32_t BM = 16 * TM, BK = kGemmChunk, P = BM + 1;
-  // the contracted loop unrolled twice for 32-blocks (4x4 blocks already
-  // keep 32 products in flight per entry)
-  constexpr int32_t kUnrollK = TM == 2 ? 2 : 1;
+  constexpr int32_t WT = TM / 2;             // 16 x 16 tiles per wavefront side
+  constexpr int32_t NS = WT == 1 ? 2 : 1;    // accumulator chains per part
   static_assert(BK == 16 && kBlock == 256, "thread layout: 16 x 16 threads, 16 entries per chunk");
+  using M = Mfma<T>;
+  using V = typename M::V;
   const QDiv D(q);
   const int32_t rb = s.ranks & 255, rm = (s.ranks >> 8) & 255, rk = (s.ranks >> 16) & 255,
                 rn = (s.ranks >> 24) & 255;
@@ -805,7 +862,10 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
   const T scale = step_scale<T>(st, s.a, s.b, ec);
   // this thread's loads: contracted entry kk of rows / columns lr + 16 i
   const int32_t kk = tid & (BK - 1), lr = tid >> 4;
-  const int32_t tx = tid & 15, ty = tid >> 4;
+  // this wavefront's quarter of the block and its lane
+  const int32_t lane = tid & 63, wv = tid >> 6;
+  const int32_t qr = (wv >> 1) * 16 * WT, qc = (wv & 1) * 16 * WT;
+  const int32_t l16 = lane & 15, lk = lane >> 4;
   const GlbCx<T>* A = (const GlbCx<T>*)(arena + s.home_a);
   const GlbCx<T>* B = (const GlbCx<T>*)(arena + s.home_b);
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
@@ -856,11 +916,17 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
       }
       return x;
     };
-    T cr[TM][TM], ci[TM][TM];
+    // accumulators: [row tile][column tile][chain], real and imaginary parts
+    V cre[WT][WT][NS], cim[WT][WT][NS];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int j = 0; j < TM; ++j) cr[i][j] = ci[i][j] = 0;
+      for (int j = 0; j < WT; ++j)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+          cre[i][j][c] = V{0, 0, 0, 0};
+          cim[i][j][c] = V{0, 0, 0, 0};
+        }
     Ops x = load(0);
     for (int32_t c0 = 0; c0 < kl; c0 += BK) {
 #pragma unroll
@@ -870,36 +936,58 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
       }
       __syncthreads();
       if (c0 + BK < kl) x = load(c0 + BK);
-#pragma unroll kUnrollK
-      for (int32_t jk = 0; jk < BK; ++jk) {
-        Cx<T> a[TM], bb[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          a[i] = As[jk * P + ty + 16 * i];
-          bb[i] = Bs[jk * P + tx + 16 * i];
+      for (int32_t j4 = 0; j4 < BK; j4 += 4) {
+        const int32_t kr = (j4 + lk) * P;
+        Cx<T> a[WT], bb[WT];
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+          a[i] = As[kr + qr + 16 * i + l16];
+          bb[i] = Bs[kr + qc + 16 * i + l16];
         }
+        // the four contributions in turn over all tiles: each accumulator is
+        // used again only after every other tile's MFMA of the same kind
+        constexpr int c2 = NS - 1;
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-          for (int j = 0; j < TM; ++j) {
-            cr[i][j] = fma(a[i].re, bb[j].re, cr[i][j]);
-            cr[i][j] = fma(-a[i].im, bb[j].im, cr[i][j]);
-            ci[i][j] = fma(a[i].re, bb[j].im, ci[i][j]);
-            ci[i][j] = fma(a[i].im, bb[j].re, ci[i][j]);
-          }
+          for (int j = 0; j < WT; ++j) cre[i][j][0] = M::mac(a[i].re, bb[j].re, cre[i][j][0]);
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+          for (int j = 0; j < WT; ++j) cim[i][j][0] = M::mac(a[i].re, bb[j].im, cim[i][j][0]);
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+          for (int j = 0; j < WT; ++j) cre[i][j][c2] = M::mac(-a[i].im, bb[j].im, cre[i][j][c2]);
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+          for (int j = 0; j < WT; ++j) cim[i][j][c2] = M::mac(a[i].im, bb[j].re, cim[i][j][c2]);
       }
       __syncthreads();
     }
-    const int64_t crow = (int64_t)b * s.nm;
+    // the block's outputs from its first entry C[b, m0, n0] (the planner
+    // keeps BM rows of C within one output range)
+    const GlbOut<T> out(C + ((int64_t)b * s.nm + m0) * s.nn + n0);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int j = 0; j < TM; ++j) {
-        const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-        if (m < s.nm && n < s.nn) {
-          const T vr = cr[i][j] * scale, vi = ci[i][j] * scale;
-          stc(C + (crow + m) * s.nn + n, Cx<T>{vr, vi});
-          lm = fmax(lm, fmax(fabs(vr), fabs(vi)));
+      for (int j = 0; j < WT; ++j) {
+        V vre = cre[i][j][0], vim = cim[i][j][0];
+        if constexpr (NS == 2) {
+          vre += cre[i][j][1];
+          vim += cim[i][j][1];
+        }
+        const int32_t n = n0 + qc + 16 * j + l16;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int32_t mr = qr + 16 * i + M::row(lane, rr);
+          if (m0 + mr < s.nm && n < s.nn) {
+            const T vr = vre[rr] * scale, vi = vim[rr] * scale;
+            put(out, mr * s.nn + (n - n0), Cx<T>{vr, vi});
+            lm = fmax(lm, fmax(fabs(vr), fabs(vi)));
+          }
         }
       }
   }
@@ -915,7 +1003,7 @@ __device__ __attribute__((always_inline)) void reduce_step(const DevProg& p, con
   const int64_t o0 = (int64_t)part * kReduceChunk;
   const int64_t o1 = o0 + kReduceChunk < outs ? o0 + kReduceChunk : outs;
   const GlbCx<T>* P = (const GlbCx<T>*)(arena + s.partial);
-  GlbCx<T>* C = (GlbCx<T>*)(arena + s.home_c);
+  const GlbOut<T> C((GlbCx<T>*)(arena + s.home_c) + o0);
   T lm = 0;
   for (int64_t o = o0 + threadIdx.x; o < o1; o += kBlock) {
     T cr = 0, ci = 0;
@@ -924,7 +1012,7 @@ __device__ __attribute__((always_inline)) void reduce_step(const DevProg& p, con
       cr += v.re;
       ci += v.im;
     }
-    stc(C + o, Cx<T>{cr, ci});
+    put(C, (int32_t)(o - o0), Cx<T>{cr, ci});
     lm = fmax(lm, fmax(fabs(cr), fabs(ci)));
   }
   int64_t ec;
@@ -1203,7 +1291,7 @@ constexpr int64_t kWaitTicks = 20LL * 100000000LL;
 extern __shared__ __align__(16) uint8_t kn_dyn_smem[];
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void engine(const uint8_t* __restrict__ img,
+__global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ img,
                                                  uint8_t* __restrict__ state,
                                                  Cx<T>* __restrict__ arena,
                                                  const double* __restrict__ J,

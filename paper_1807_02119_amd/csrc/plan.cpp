@@ -46,6 +46,7 @@ int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
 // Upper bound on the tiles of one step (a few per compute unit), and the
 // multiply-adds one tile aims at.
 constexpr double kMaxTiles = 1024;
+constexpr double kMaxTileOutputs = 1 << 24;  // outputs of one tile (2^28 bytes in complex128)
 constexpr double kTileMacs = 32768;
 // Steps with fewer tiles than this split a long contracted index.
 constexpr double kSplitBelow = 256;
@@ -1045,7 +1046,9 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.n_edges = (int32_t)g.eps.size();
   k.eps = g.eps;
   k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
-  k.big_log2 = o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16;
+  // steps below 2^big_log2 multiply-adds run inside serial tasks, which write
+  // a step's outputs from one base (at most 2^24 of them)
+  k.big_log2 = std::min(o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16, 24);
   k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
   k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
   {
@@ -1144,7 +1147,10 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
     PTiling& t = k.tiling[i];
     const double outs = nb * nm * nn;
     double base;
-    if (o.tile_outputs == 0 && nm >= 16 && nn >= 16) {
+    // the engine writes each output block (BM rows of C) from one base, with
+    // byte offsets below 2^31 (kOutRangeBytes in the engine)
+    const bool block_range_ok = 64.0 * nn * es < 2147483647.0;
+    if (o.tile_outputs == 0 && nm >= 16 && nn >= 16 && block_range_ok) {
       // 64 x 64 blocks do four times the work per staged chunk of 32 x 32
       // ones (better hiding of the operand loads) but pad ragged sides more
       const double pad32 = std::ceil(nm / 32) * std::ceil(nn / 32) * 1024.0;
@@ -1169,7 +1175,8 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
                                        : std::max(1.0, std::floor(tile_macs / std::min(nk, 1024.0)));
       if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
-      tile = std::min(tile, outs);
+      // a tile's outputs are written from one base, byte offsets below 2^31
+      tile = std::min({tile, outs, kMaxTileOutputs});
       t.tile = (int32_t)tile;
       base = std::ceil(outs / tile);
     }
