@@ -63,6 +63,20 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the mixed batch (512 knots of 20-250 crossings, q in 2,3,5,6) "
                          "launched through a captured graph")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision workload (16 knots of 300-600 crossings)")
+    ap.add_argument("--no-fp64-single", action="store_true",
+                    help="skip the 50-200 crossing workload at q=3 and 5, one knot per launch")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the gradient workload (32 knots of 150-300 crossings)")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the unsliced 351-crossing grid-walk knot (GEMM-heavy)")
+    ap.add_argument("--wide-only", action="store_true",
+                    help="run only the 351-crossing knot leg (for counter profiles) and print "
+                         "its record")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-cores CPU oracle leg (0 = the host's CPUs, "
+                         "at most 16)")
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's recorded setting (library defaults)")
     ap.add_argument("--pmc-calibrate", type=int, default=0, metavar="BYTES",
@@ -98,6 +112,64 @@ def measured_traffic(kernel: str):
     return rec
 
 
+def oracle_knot(pd, q):
+    """(seconds, Z mantissa, Z exponent) of one knot by the CPU oracle."""
+    import numpy as np
+
+    from oracle import diagram, jones, potts
+
+    t0 = time.perf_counter()
+    tg = diagram.tait_graph(np.asarray(pd))
+    x = potts.jones_weights(tg.eps, jones.t_of_q(q))
+    mo, eo = potts.partition_function(tg.n_vertices, tg.edges, x, q)
+    jones.jones_value(q, tg.n_vertices, tg.writhe, tg.tait_number, mo, eo)
+    return time.perf_counter() - t0, mo, eo
+
+
+def _one_blas_thread():
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+
+
+def _oracle_job(job):
+    return oracle_knot(*job)[0]
+
+
+def cpu_parallel(knots, q, workers, seconds):
+    """The oracle on `workers` fresh processes (spawned: they never touch the
+    GPU), knots handed out in order, until `seconds` of wall time have
+    passed; returns the knots finished and the wall time."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_one_blas_thread) as pool:
+        pool.map(_oracle_job, [(knots[0][0].pd, q)] * workers)  # start-up outside the timing
+        t0 = time.perf_counter()
+        done = 0
+        for _ in pool.imap(_oracle_job, [(d.pd, q) for d, _ in knots], chunksize=1):
+            done += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        wall = time.perf_counter() - t0
+        pool.terminate()
+    return {"knots": done, "wall_s": wall, "knots_per_s": done / wall}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+            else:
+                name = "unknown"
+    except OSError:
+        name = "unknown"
+    return {"model": name, "usable_cpus": len(os.sched_getaffinity(0)),
+            "os_cpu_count": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,9 +179,22 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    from paper_1807_02119_amd import gen
+
+    q = 3
+    B = args.batch
+    knots = gen.config_knots("q3_200_600", args.seed, count=B)
+    # the all-cores CPU oracle leg runs first, before this process touches the
+    # GPU (its worker processes are spawned fresh and never use the GPU)
+    cpu_par = None
+    if not args.no_cpu_baseline and not args.pmc_calibrate:
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        cpu_par = dict(cpu_parallel(knots, q, workers, args.cpu_seconds), workers=workers)
+
     import torch
 
-    from paper_1807_02119_amd import gen, kn, tune
+    from paper_1807_02119_amd import kn, tune
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -125,9 +210,41 @@ def main():
         print(json.dumps({"calibration_copy_bytes": 4 * n, "launches": 3}), flush=True)
         return
     kn.lib()
-    q = 3
-    B = args.batch
-    knots = gen.config_knots("q3_200_600", args.seed, count=B)
+
+    def wide_knot_leg(reps=5):
+        """The paper-model grid walk of Sec. III.A with L = 60 (351 crossings,
+        seed 60), q = 3, unsliced: its largest tensor has 2^25.4 entries and its
+        big steps run as GEMM blocks on the matrix cores."""
+        rng = np.random.default_rng(60)
+        d = gen.random_grid_diagram(rng, 60)
+        t = kn.Tait(d.pd)
+        leg = {"workload": f"paper-model grid-walk knot L=60 ({d.n} crossings, seed 60), q=3, "
+                           "unsliced, one knot per launch"}
+        st_ = torch.cuda.current_stream()
+        for prec, name in ((0, "c128"), (1, "c64")):
+            p_ = kn.Plan(t, 3, precision=prec)
+            ws_ = kn.alloc_workspace(p_.workspace_bytes)
+            z_ = kn.alloc_scalars(1)
+            kn.contract(p_, workspace=ws_, stream=st_, z=z_)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st_)
+            for _ in range(reps):
+                kn.contract(p_, workspace=ws_, stream=st_, z=z_)
+            e1.record(st_)
+            torch.cuda.synchronize()
+            ms_ = e0.elapsed_time(e1) / reps
+            leg[name] = {"ms": ms_, "gflop": p_.stats["flops"] / 1e9,
+                         "tflops": p_.stats["flops"] / (ms_ * 1e-3) / 1e12,
+                         "log2_max_entries": p_.stats["log2_max_entries"]}
+            leg[name]["frac_of_peak"] = leg[name]["tflops"] / (FP64_PEAK_TFLOPS if prec == 0
+                                                                 else FP32_PEAK_TFLOPS)
+        return leg
+
+    if args.wide_only:
+        print(json.dumps({"wide_knot": wide_knot_leg()}), flush=True)
+        return
     pds = [np.ascontiguousarray(d.pd, dtype=np.int32) for d, _ in knots]
     ncross = [d.n for d, _ in knots]
     # the batch's input as the library takes it: crossing counts and the PD
@@ -438,9 +555,13 @@ def main():
     # against eager launches of the same batch and one knot per call
     if not args.no_batched:
         mixed = gen.config_knots("batched", args.seed, count=512)
+        mtuned = tune.load("batched", 0) if not args.untuned else {}
         mtaits, mplans = kn.plan_many([np.ascontiguousarray(d.pd, dtype=np.int32)
-                                       for d, _ in mixed], [mq for _, mq in mixed])
+                                       for d, _ in mixed], [mq for _, mq in mixed],
+                                      **tune.plan_options(mtuned))
         mb = kn.Batch(mplans)
+        if mtuned.get("grid"):
+            mb.set_grid(int(mtuned["grid"]))
         mb.upload(stream=stream)
         zm = kn.alloc_scalars(len(mplans))
         mb.contract(stream=stream, z=zm)
@@ -486,37 +607,166 @@ def main():
             "speedup_vs_one_at_a_time": len(mplans) / (ms_graph * 1e-3) / single_kps,
             "graph_replays_equal_eager_bits": replay_ok,
             "tflops": mb.stats["flops"] / (ms_graph * 1e-3) / 1e12,
+            "tuned": mtuned or None,
         }
+
+    def golden(workload):
+        """Oracle values stored for seed 0 of a workload (written by
+        tests/golden/make_oracle_values.py from the oracle alone), or None."""
+        path = os.path.join(ROOT, "tests", "golden", f"oracle_{workload}_seed{args.seed}.json")
+        try:
+            with open(path) as f:
+                return json.load(f)["knots"]
+        except (OSError, ValueError):
+            return None
+
+    def errs_vs(zh_, gold):
+        ez = []
+        for i, g in enumerate(gold):
+            m = complex(zh_[i, 0], zh_[i, 1])
+            e = int(zh_.view(np.int64)[i, 2])
+            mo = complex(g["z_re"], g["z_im"])
+            ez.append(abs(m * 2.0 ** (e - g["z_exp2"]) - mo) / abs(mo))
+        return ez
+
+    def time_batch(b, reps=20):
+        z = kn.alloc_scalars(len(b.plans))
+        b.contract(stream=stream, z=z)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.contract(stream=stream, z=z)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, z.cpu().numpy()
+
+    # ---------------------------------------------------------------- mixed precision workload
+    # 16 knots of 300-600 crossings (at least 4 of 560-600), q = 3, one batch
+    # launch in complex128 and in complex64, each knot against the oracle
+    if not args.no_mixed:
+        mk = gen.config_knots("mixed", args.seed)
+        mpds = [np.ascontiguousarray(d.pd, np.int32) for d, _ in mk]
+        gold = golden("mixed")
+        leg = {"workload": "16 seeded lattice-walk knots, 300-600 raw crossings (>= 4 of "
+                           "560-600), q=3, one batch launch",
+               "crossings": [d.n for d, _ in mk]}
+        ms_by = {}
+        for prec, name in ((0, "c128"), (1, "c64")):
+            setting = tuned[prec]
+            _, plans_m = kn.plan_many(mpds, 3, precision=prec, **tune.plan_options(setting))
+            bm = kn.Batch(plans_m)
+            if setting.get("grid"):
+                bm.set_grid(int(setting["grid"]))
+            bm.upload(stream=stream)
+            ms_m, zm_h = time_batch(bm)
+            ms_by[prec] = ms_m
+            rec_m = {"ms_per_launch": ms_m, "knots_per_s": len(mk) / (ms_m * 1e-3),
+                     "tflops": bm.stats["flops"] / (ms_m * 1e-3) / 1e12}
+            if gold is not None:
+                ez = errs_vs(zm_h, gold)
+                rec_m["rel_err_vs_oracle_per_knot"] = [float("%.3g" % x) for x in ez]
+                rec_m["rel_err_vs_oracle_max"] = max(ez)
+            leg[name] = rec_m
+        leg["c64_speedup_vs_c128"] = ms_by[0] / ms_by[1]
+        out["mixed_precision"] = leg
+
+    # ---------------------------------------------------------------- 50-200 crossings, one knot per launch
+    if not args.no_fp64_single:
+        fk = gen.config_knots("fp64", args.seed)
+        gold = golden("fp64")
+        leg = {"workload": "64 seeded lattice-walk knots, 50-200 raw crossings, q=3 and q=5, "
+                           "complex128, one knot per launch (kn_contract)"}
+        for qv in (3, 5):
+            idx = [i for i, (_, qq) in enumerate(fk) if qq == qv]
+            single = [kn.Plan(kn.Tait(fk[i][0].pd), qv) for i in idx]
+            wsf = kn.alloc_workspace(max(p_.workspace_bytes for p_ in single))
+            zf = kn.alloc_scalars(len(single))
+            for p_ in single[:4]:
+                kn.contract(p_, workspace=wsf, stream=stream, z=zf[:1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j, p_ in enumerate(single):
+                kn.contract(p_, workspace=wsf, stream=stream, z=zf[j:j + 1])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec_f = {"knots_per_s": len(single) / dt, "ms_per_knot": 1e3 * dt / len(single),
+                     "tflops": sum(p_.stats["flops"] for p_ in single) / dt / 1e12}
+            if gold is not None:
+                rec_f["rel_err_vs_oracle_max"] = max(errs_vs(zf.cpu().numpy(),
+                                                             [gold[i] for i in idx]))
+            leg[f"q{qv}"] = rec_f
+        out["fp64_one_knot_per_launch"] = leg
+
+    # ---------------------------------------------------------------- gradients
+    if not args.no_grad:
+        gk = gen.config_knots("grad", args.seed)
+        gpds = [np.ascontiguousarray(d.pd, np.int32) for d, _ in gk]
+        _, gplans = kn.plan_many(gpds, 3, gradient=True, jones_only=False)
+        gb = kn.Batch(gplans)
+        gb.upload(stream=stream)
+        zg = kn.alloc_scalars(len(gplans))
+        gg = torch.empty((max(1, int(gb.stats["total_edges"])), 2), dtype=torch.float64,
+                         device="cuda")
+        gb.contract_backward(stream=stream, z=zg, grad=gg)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            gb.contract_backward(stream=stream, z=zg, grad=gg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_g = e0.elapsed_time(e1) / reps
+        out["gradient"] = {
+            "workload": "32 seeded lattice-walk knots, 150-300 raw crossings, q=3, d log Z / d J_e "
+                        "for every edge (forward and reverse sweep, one batch launch), complex128",
+            "ms_per_launch": ms_g, "knots_per_s": len(gplans) / (ms_g * 1e-3),
+            "edges_per_s": int(gb.stats["total_edges"]) / (ms_g * 1e-3),
+            "tflops": gb.stats["flops"] / (ms_g * 1e-3) / 1e12,
+        }
+
+    if not args.no_wide:
+        out["wide_knot"] = wide_knot_leg()
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu_baseline:
-        from oracle import diagram, jones, potts
+        from threadpoolctl import threadpool_limits
 
+        # single thread: the oracle knot after knot, BLAS limited to one thread
         t_cpu = 0.0
         n_done = 0
         worst = 0.0
-        for i, (d, _) in enumerate(knots):
-            t0 = time.perf_counter()
-            tg = diagram.tait_graph(d.pd)
-            x = potts.jones_weights(tg.eps, jones.t_of_q(q))
-            mo, eo = potts.partition_function(tg.n_vertices, tg.edges, x, q)
-            jones.jones_value(q, tg.n_vertices, tg.writhe, tg.tait_number, mo, eo)
-            t_cpu += time.perf_counter() - t0
-            n_done += 1
-            m = complex(zh[i, 0], zh[i, 1])
-            e = int(zh.view(np.int64)[i, 2])
-            worst = max(worst, abs(m * 2.0 ** (e - eo) - mo) / abs(mo))
-            if t_cpu >= args.cpu_seconds:
-                break
+        with threadpool_limits(limits=1):
+            for i, (d, _) in enumerate(knots):
+                dt, mo, eo = oracle_knot(d.pd, q)
+                t_cpu += dt
+                n_done += 1
+                m = complex(zh[i, 0], zh[i, 1])
+                e = int(zh.view(np.int64)[i, 2])
+                worst = max(worst, abs(m * 2.0 ** (e - eo) - mo) / abs(mo))
+                if t_cpu >= args.cpu_seconds:
+                    break
+        single = {"value": n_done / t_cpu, "unit": "knots/s", "cores": 1,
+                  "sample": f"first {n_done} of the {B} knots of the step, {t_cpu:.1f} s",
+                  "gpu_vs_oracle_max_rel_err": worst}
+        # all cores: one oracle process per usable CPU (at most 16), each with
+        # one BLAS thread, over the knots of the step in order, for a bounded
+        # wall time; whole-job knots/s
+        par = cpu_par
+        workers = par["workers"]
         out["cpu_baseline"] = {
-            "value": n_done / t_cpu,
+            "value": par["knots_per_s"],
             "unit": "knots/s",
-            "cores": 1,
+            "cores": workers,
             "kind": "oracle",
-            "sample": f"first {n_done} of the {B} knots of the step (same seed), numpy "
-                      f"complex128 min-fill variable elimination, single thread, "
-                      f"{t_cpu:.1f} s",
-            "gpu_vs_oracle_max_rel_err": worst,
+            "sample": f"first {par['knots']} of the {B} knots of the step (same seed), numpy "
+                      f"complex128 min-fill variable elimination, {workers} processes with one "
+                      f"BLAS thread each, {par['wall_s']:.1f} s wall",
+            "cpu": cpu_model(),
+            "single_thread": single,
         }
     print(json.dumps(out), flush=True)
 

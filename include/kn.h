@@ -172,6 +172,19 @@ void kn_tait_free(kn_tait* g);
  *               does four times the multiply-adds per staged chunk, which
  *               hides the operand loads better, and needs 2 x 16 x 65 entries
  *               of LDS (33 KiB in complex128; the launch grows to fit).
+ * big_step_outs_log2  a step with at least 2^big_step_outs_log2 outputs is
+ *               split into tiles over workgroups too, whatever its
+ *               multiply-add count: with a short contracted index its time on
+ *               one workgroup is set by rounds of gathered loads, one round
+ *               per 512 outputs (0 = default 12; 31 = by multiply-adds only).
+ * tile_outs_log2  most outputs one tile of a tiled step computes, 2^value
+ *               (0 = default 10).
+ * bucket        per intermediate-size bucket overrides of the tile shape: a
+ *               step whose output C has at most 2^8, 2^12, 2^16, 2^20 or more
+ *               entries takes bucket 0, 1, 2, 3 or 4, and any non-zero field
+ *               of that bucket replaces the plan-wide value (tile_macs_log2,
+ *               tile_outs_log2, gemm64_pct, gemm_tasks_log2).  The autotuner
+ *               searches them per workload.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -186,6 +199,13 @@ void kn_tait_free(kn_tait* g);
  *               whose derivative is not zero).  kn_contract on such a plan
  *               computes Z and runs the reverse steps without writing them out.
  */
+#define KN_N_BUCKETS 5
+typedef struct {
+  int32_t tile_macs_log2;
+  int32_t tile_outs_log2;
+  int32_t gemm64_pct;
+  int32_t gemm_tasks_log2;
+} kn_bucket_opts;
 typedef struct {
   int32_t strategy;
   int32_t precision;
@@ -202,6 +222,9 @@ typedef struct {
   int32_t split_serial_log2;
   int32_t gemm_tasks_log2;
   int32_t gemm64_pct;
+  int32_t big_step_outs_log2;
+  int32_t tile_outs_log2;
+  kn_bucket_opts bucket[KN_N_BUCKETS];
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).
@@ -362,7 +385,8 @@ kn_status kn_batch_contract_backward(const kn_batch* b, const double* J, void* w
 /* Read-only view of the batch's device image (see kn_plan_image). */
 kn_status kn_batch_image(const kn_batch* b, const void** data, size_t* bytes);
 /* Override the persistent grid size (workgroups) of later kn_batch_contract
-   calls; 0 restores the default (derived from the device's CU count). */
+   calls; 0 restores the default (one workgroup per compute unit, at most one
+   per task). */
 kn_status kn_batch_set_grid(kn_batch* b, int32_t grid);
 /* Per-task timing of later kn_batch_contract calls: trace_dev (device, at
    least 64 * n_tasks bytes; NULL switches tracing off) receives for task i the

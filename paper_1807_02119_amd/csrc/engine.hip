@@ -936,8 +936,11 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
       }
       __syncthreads();
       if (c0 + BK < kl) x = load(c0 + BK);
+      // only the groups of 4 contracted entries this chunk holds (a short
+      // contracted index, K = 3 or 9, would otherwise multiply zero padding)
+      const int32_t kv = min(BK, kl - c0);
 #pragma unroll
-      for (int32_t j4 = 0; j4 < BK; j4 += 4) {
+      for (int32_t j4 = 0; j4 < kv; j4 += 4) {
         const int32_t kr = (j4 + lk) * P;
         Cx<T> a[WT], bb[WT];
 #pragma unroll
@@ -1480,15 +1483,6 @@ int device_cus() {
 }
 
 template <class T>
-int32_t resident_per_cu(size_t dyn_lds) {
-  int32_t nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, engine<T>, kBlock, dyn_lds) != hipSuccess ||
-      nb <= 0)
-    nb = 1;
-  return nb;
-}
-
-template <class T>
 kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
                         kn_scalar* z, double* grad, int32_t grid_override, TraceRec* trace) {
   const size_t dyn = (size_t)kLdsArena + (size_t)h.lds_bytes;
@@ -1500,8 +1494,11 @@ kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const d
                                   160 * 1024 - 1024) == hipSuccess;
   });
   if (!attr_ok) return KN_E_DEVICE;
+  // default: one workgroup per compute unit (measured faster than filling
+  // each CU with as many as fit: a workgroup running a knot's critical chain
+  // then has its CU to itself)
   int32_t grid = grid_override;
-  if (grid <= 0) grid = device_cus() * resident_per_cu<T>(dyn);
+  if (grid <= 0) grid = device_cus();
   if (grid > h.n_tasks) grid = h.n_tasks;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(engine<T>, dim3(grid), dim3(kBlock), dyn, st, ws, ws + h.state_off,

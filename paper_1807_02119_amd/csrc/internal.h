@@ -215,6 +215,7 @@ struct PlanKnot {
   int64_t arena_elems = 0;
   int32_t tile = 256;
   int32_t big_log2 = 16;
+  int32_t big_outs_log2 = 12;
   int32_t lds_bytes = 32768;
   double split_est = 1024;                      // serial runs estimated at least this
                                                 // long run level by level

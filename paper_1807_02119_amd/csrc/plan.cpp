@@ -47,7 +47,17 @@ int64_t elem_bytes(int32_t precision) { return precision == 1 ? 8 : 16; }
 // multiply-adds one tile aims at.
 constexpr double kMaxTiles = 1024;
 constexpr double kMaxTileOutputs = 1 << 24;  // outputs of one tile (2^28 bytes in complex128)
-constexpr double kTileMacs = 32768;
+constexpr int32_t kTileMacsLog2 = 15;    // multiply-adds a tile of outputs aims at
+constexpr int32_t kTileOutsLog2 = 10;    // most outputs of one tile
+constexpr int32_t kBigOutsLog2 = 12;     // steps with this many outputs are tiled
+
+// Intermediate-size bucket of a step (its output C): at most 2^8, 2^12,
+// 2^16, 2^20 entries, or more.
+inline int32_t bucket_of(double outs) {
+  int32_t b = 0;
+  for (double lim = 256.0; b < KN_N_BUCKETS - 1 && outs > lim; lim *= 16.0) ++b;
+  return b;
+}
 // Steps with fewer tiles than this split a long contracted index.
 constexpr double kSplitBelow = 256;
 // Auto ordering also tries the greedy plan when the min-fill plan has at least
@@ -1049,6 +1059,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   // steps below 2^big_log2 multiply-adds run inside serial tasks, which write
   // a step's outputs from one base (at most 2^24 of them)
   k.big_log2 = std::min(o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16, 24);
+  k.big_outs_log2 = std::min(o.big_step_outs_log2 > 0 ? o.big_step_outs_log2 : kBigOutsLog2, 24);
   k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
   k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
   {
@@ -1140,12 +1151,18 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       return KN_E_BUDGET;
     }
     double macs = nb * nm * nn * nk;
-    bool big = macs >= std::ldexp(1.0, k.big_log2);
+    const double outs = nb * nm * nn;
+    // the tile shape knobs of this step's intermediate-size bucket
+    const int32_t bk = bucket_of(outs);
+    auto knob = [&](int32_t per_bucket, int32_t plan_wide, int32_t dflt) {
+      return per_bucket > 0 ? per_bucket : plan_wide > 0 ? plan_wide : dflt;
+    };
+    const kn_bucket_opts& bo = o.bucket[bk];
+    bool big = macs >= std::ldexp(1.0, k.big_log2) || outs >= std::ldexp(1.0, k.big_outs_log2);
     // a serial step generates its gather tables in LDS; larger ones are tiled
     if (2 * nb + nm + 2 * nk + nn > kTabBuf) big = true;
     if (!big) continue;
     PTiling& t = k.tiling[i];
-    const double outs = nb * nm * nn;
     double base;
     // the engine writes each output block (BM rows of C) from one base, with
     // byte offsets below 2^31 (kOutRangeBytes in the engine)
@@ -1155,7 +1172,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       // ones (better hiding of the operand loads) but pad ragged sides more
       const double pad32 = std::ceil(nm / 32) * std::ceil(nn / 32) * 1024.0;
       const double pad64 = std::ceil(nm / 64) * std::ceil(nn / 64) * 4096.0;
-      const int32_t pct = o.gemm64_pct > 0 ? o.gemm64_pct : kGemm64Pct;
+      const int32_t pct = knob(bo.gemm64_pct, o.gemm64_pct, kGemm64Pct);
       const bool wide = nm >= 64 && nn >= 64 && pad64 * 100 <= pad32 * pct;
       const double bm = wide ? 64 : kGemmBlock;
       t.mode = wide ? STEP_GEMM64 : STEP_GEMM;
@@ -1164,16 +1181,18 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       // blocks per task: a step with many blocks gives each task several,
       // so that it still has about 2^gemm_tasks_log2 tasks
       const double blocks = nb * t.n_mb * t.n_nb;
-      const double target = std::ldexp(1.0, o.gemm_tasks_log2 > 0 ? o.gemm_tasks_log2 : kGemmTasksLog2);
+      const double target = std::ldexp(1.0, knob(bo.gemm_tasks_log2, o.gemm_tasks_log2, kGemmTasksLog2));
       const double most = wide ? kGemmMaxBlocks / 4 : kGemmMaxBlocks;
       t.tile = (int32_t)std::max(1.0, std::min(most, std::floor(blocks / target)));
       base = std::ceil(blocks / t.tile);
     } else {
       // tiles carry about kTileMacs multiply-adds (at most kMaxTiles per step)
       t.mode = STEP_TILES;
-      const double tile_macs = o.tile_macs_log2 > 0 ? std::ldexp(1.0, o.tile_macs_log2) : kTileMacs;
-      double tile = o.tile_outputs > 0 ? (double)o.tile_outputs
-                                       : std::max(1.0, std::floor(tile_macs / std::min(nk, 1024.0)));
+      const double tile_macs = std::ldexp(1.0, knob(bo.tile_macs_log2, o.tile_macs_log2, kTileMacsLog2));
+      const double tile_outs = std::ldexp(1.0, knob(bo.tile_outs_log2, o.tile_outs_log2, kTileOutsLog2));
+      double tile = o.tile_outputs > 0
+                        ? (double)o.tile_outputs
+                        : std::max(1.0, std::min(tile_outs, std::floor(tile_macs / std::min(nk, 1024.0))));
       if (outs > tile * kMaxTiles) tile = std::ceil(outs / kMaxTiles);
       // a tile's outputs are written from one base, byte offsets below 2^31
       tile = std::min({tile, outs, kMaxTileOutputs});
@@ -1305,6 +1324,13 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
   if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;
   if (o.gemm64_pct < 0 || o.gemm64_pct > 100000) return KN_E_INVALID;
+  if (o.big_step_outs_log2 < 0 || o.big_step_outs_log2 > 31) return KN_E_INVALID;
+  if (o.tile_outs_log2 < 0 || o.tile_outs_log2 > 24) return KN_E_INVALID;
+  for (const kn_bucket_opts& b : o.bucket)
+    if (b.tile_macs_log2 < 0 || b.tile_macs_log2 > 30 || b.tile_outs_log2 < 0 ||
+        b.tile_outs_log2 > 24 || b.gemm64_pct < 0 || b.gemm64_pct > 100000 ||
+        b.gemm_tasks_log2 < 0 || b.gemm_tasks_log2 > 30)
+      return KN_E_INVALID;
   if (o.gradient && o.slice_log2_budget) return KN_E_UNSUPPORTED;
   kn_plan* p = new (std::nothrow) kn_plan();
   if (!p) return KN_E_NOMEM;

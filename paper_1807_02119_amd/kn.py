@@ -29,6 +29,14 @@ class KnError(RuntimeError):
         super().__init__(f"{where}: {STATUS.get(code, code)}")
 
 
+N_BUCKETS = 5  # KN_N_BUCKETS: intermediate sizes <= 2^8, 2^12, 2^16, 2^20, larger
+BUCKET_KNOBS = ("tile_macs_log2", "tile_outs_log2", "gemm64_pct", "gemm_tasks_log2")
+
+
+class BucketOpts(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in BUCKET_KNOBS]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("simplify", ctypes.c_int32), ("jones_only", ctypes.c_int32),
@@ -37,7 +45,37 @@ class PlanOpts(ctypes.Structure):
                 ("lds_bytes", ctypes.c_int32), ("gradient", ctypes.c_int32),
                 ("tile_macs_log2", ctypes.c_int32), ("slice_log2_budget", ctypes.c_int32),
                 ("split_serial_log2", ctypes.c_int32), ("gemm_tasks_log2", ctypes.c_int32),
-                ("gemm64_pct", ctypes.c_int32)]
+                ("gemm64_pct", ctypes.c_int32), ("big_step_outs_log2", ctypes.c_int32),
+                ("tile_outs_log2", ctypes.c_int32), ("bucket", BucketOpts * N_BUCKETS)]
+
+
+def plan_opts(strategy=3, precision=0, simplify=None, jones_only=True, mem_budget_bytes=0,
+              tile_outputs=0, big_step_macs_log2=0, paper_stats=False, lds_bytes=0,
+              gradient=False, tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0,
+              gemm_tasks_log2=0, gemm64_pct=0, big_step_outs_log2=0, tile_outs_log2=0,
+              buckets=None):
+    """kn_plan_opts from keyword arguments (0 = the library default).
+    ``buckets``: {bucket index: {knob: value}} overrides of the tile-shape knobs
+    (BUCKET_KNOBS) per intermediate-size bucket (keys may be strings)."""
+    if simplify is None:
+        simplify = 1 if (gradient or not jones_only) else 3
+    o = PlanOpts()
+    for name, v in (("strategy", strategy), ("precision", precision), ("simplify", simplify),
+                    ("jones_only", 1 if jones_only else 0), ("mem_budget_bytes", mem_budget_bytes),
+                    ("tile_outputs", tile_outputs), ("big_step_macs_log2", big_step_macs_log2),
+                    ("paper_stats", 1 if paper_stats else 0), ("lds_bytes", lds_bytes),
+                    ("gradient", 1 if gradient else 0), ("tile_macs_log2", tile_macs_log2),
+                    ("slice_log2_budget", slice_log2_budget),
+                    ("split_serial_log2", split_serial_log2), ("gemm_tasks_log2", gemm_tasks_log2),
+                    ("gemm64_pct", gemm64_pct), ("big_step_outs_log2", big_step_outs_log2),
+                    ("tile_outs_log2", tile_outs_log2)):
+        setattr(o, name, int(v))
+    for b, knobs in (buckets or {}).items():
+        for name, v in knobs.items():
+            if name not in BUCKET_KNOBS:
+                raise ValueError(f"unknown bucket knob {name}")
+            setattr(o.bucket[int(b)], name, int(v))
+    return o
 
 
 class PlanStats(ctypes.Structure):
@@ -190,18 +228,13 @@ class Tait:
 class Plan:
     """Contraction plan for one knot at one q (kn_plan_create)."""
 
-    def __init__(self, tait: Tait, q: int, strategy=3, precision=0, simplify=None,
-                 jones_only=True, mem_budget_bytes=0, tile_outputs=0, big_step_macs_log2=0,
-                 paper_stats=False, lds_bytes=0, gradient=False, tile_macs_log2=0,
-                 slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0, gemm64_pct=0,
-                 allow_budget=False):
+    def __init__(self, tait: Tait, q: int, allow_budget=False, **opts):
+        """``opts``: the keyword arguments of plan_opts (kn_plan_opts fields)."""
         L = lib()
-        if simplify is None:
-            simplify = 1 if (gradient or not jones_only) else 3
-        o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, mem_budget_bytes,
-                     tile_outputs, big_step_macs_log2, 1 if paper_stats else 0, lds_bytes,
-                     1 if gradient else 0, tile_macs_log2, slice_log2_budget, split_serial_log2,
-                     gemm_tasks_log2, gemm64_pct)
+        o = plan_opts(**opts)
+        gradient = bool(o.gradient)
+        precision = o.precision
+        jones_only = bool(o.jones_only)
         h = P()
         rc = L.kn_plan_create(tait._h, q, ctypes.byref(o), ctypes.byref(h))
         self._h = h if h.value else None
@@ -305,12 +338,10 @@ class PlanSet:
             self._ph = self._th = None
 
 
-def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, simplify=None,
-             jones_only=True, tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-             tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
-              gemm64_pct=0):
+def plan_set(n_crossings, flat_pd, qs, n_threads=0, **opts):
     """kn_plan_many over knots given as one int32 crossing-count array and
-    their PD codes concatenated in one flat int32 array.  Returns a PlanSet."""
+    their PD codes concatenated in one flat int32 array (``opts``: the keyword
+    arguments of plan_opts).  Returns a PlanSet."""
     L = lib()
     ncr = np.ascontiguousarray(n_crossings, np.int32)
     n = len(ncr)
@@ -318,11 +349,7 @@ def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, sim
     if flat.size == 0:
         flat = np.zeros(4, np.int32)
     qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
-    if simplify is None:
-        simplify = 1 if (gradient or not jones_only) else 3
-    o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
-                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
-                 slice_log2_budget, split_serial_log2, gemm_tasks_log2, gemm64_pct)
+    o = plan_opts(**opts)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)
@@ -336,23 +363,17 @@ def plan_set(n_crossings, flat_pd, qs, n_threads=0, strategy=3, precision=0, sim
     return ps
 
 
-def plan_many(pds, qs, n_threads=0, strategy=3, precision=0, simplify=None, jones_only=True,
-              tile_outputs=0, big_step_macs_log2=0, lds_bytes=0, gradient=False,
-              tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0, gemm_tasks_log2=0,
-              gemm64_pct=0):
+def plan_many(pds, qs, n_threads=0, **opts):
     """Tait graphs and plans for many knots on the library's host thread pool
-    (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4).  Returns (taits, plans)."""
+    (kn_plan_many).  ``pds``: list of int32 arrays (n_i, 4); ``opts``: the
+    keyword arguments of plan_opts.  Returns (taits, plans)."""
     L = lib()
     n = len(pds)
     ncr = np.array([np.asarray(p).reshape(-1, 4).shape[0] for p in pds], np.int32)
     flat = np.ascontiguousarray(np.concatenate([np.asarray(p, np.int32).reshape(-1) for p in pds])
                                 if ncr.sum() else np.zeros(4, np.int32))
     qa = np.ascontiguousarray(np.broadcast_to(np.asarray(qs, np.int32), (n,)))
-    if simplify is None:
-        simplify = 1 if (gradient or not jones_only) else 3
-    o = PlanOpts(strategy, precision, simplify, 1 if jones_only else 0, 0, tile_outputs,
-                 big_step_macs_log2, 0, lds_bytes, 1 if gradient else 0, tile_macs_log2,
-                 slice_log2_budget, split_serial_log2, gemm_tasks_log2, gemm64_pct)
+    o = plan_opts(**opts)
     th = (P * n)()
     ph = (P * n)()
     stv = np.zeros(n, np.int32)

@@ -59,7 +59,40 @@ def source_hash(root):
     return h.hexdigest()[:16]
 
 
+def counters_main(argv):
+    """Median per dispatch of every counter in one or more --pmc runs, for the
+    kernels whose name contains --kernel: a markdown table (and JSON)."""
+    ap = argparse.ArgumentParser(prog="pmc_summary counters")
+    ap.add_argument("--kernel", default="engine")
+    ap.add_argument("--dirs", nargs="+", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--title", default="rocprofv3 counters")
+    ap.add_argument("--note", default="")
+    ap.add_argument("--command", default="")
+    args = ap.parse_args(argv)
+    table = {}
+    for d in args.dirs:
+        names = sorted({r["Counter_Name"] for r in _rows(d)})
+        for c in names:
+            vals, kn_ = per_dispatch(d, c, args.kernel)
+            if vals:
+                table[c] = (statistics.median(vals.values()), len(vals), sorted(set(kn_.values())))
+    with open(args.md, "w") as f:
+        f.write(f"# {args.title}\n\n")
+        if args.note:
+            f.write(args.note + "\n\n")
+        f.write("| counter | median per dispatch | dispatches | kernel |\n|---|---|---|---|\n")
+        for c, (v, n, k) in sorted(table.items()):
+            f.write(f"| {c} | {v:.6g} | {n} | `{', '.join(k)}` |\n")
+        if args.command:
+            f.write("\nCommands:\n\n```\n" + args.command + "\n```\n")
+    print(json.dumps({c: v for c, (v, n, k) in table.items()}))
+
+
 def main():
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        return counters_main(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", default="engine")
     ap.add_argument("--fetch", required=True)

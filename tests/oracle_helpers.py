@@ -7,6 +7,16 @@ import numpy as np
 from oracle import diagram, jones, potts
 
 
+# Tolerances.  complex128: 1e-10 relative (the target for the exact method;
+# measured ~1e-14).  complex64 (FP32 storage and accumulation, FP64/int64
+# exponents): a few times the error of a random walk of FP32 roundings,
+# u sqrt(n) with u = 2^-24 and n ~ 10^3 roundings along a knot's
+# contraction chain (several per step over ~400 steps), i.e. ~2e-6; measured
+# up to 2.5e-6 on 200-600 crossing knots.
+TOL64 = 1e-10
+TOL32 = 1e-5
+
+
 def oracle_tait(d, outer_left=True):
     return diagram.tait_graph(d.pd, d.signs if d.n == 1 else None, outer_left=outer_left)
 

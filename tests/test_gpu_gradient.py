@@ -6,7 +6,8 @@ own autograd through a plain dense contraction on tiny graphs.
 Tolerances: 1e-10 relative for complex128 against the oracle (the gradient
 is a ratio of two exactly contracted networks, each good to ~1e-15);
 finite differences with step 1e-6 are good to ~1e-7 absolute for gradients of
-order one; complex64 plans are checked to 1e-3 relative.
+order one; complex64 plans are checked to TOL32 (Z, and the gradient vector
+normwise).
 """
 
 from __future__ import annotations
@@ -21,7 +22,7 @@ torch = pytest.importorskip("torch")
 from oracle import jones as ojones
 from oracle import potts
 from paper_1807_02119_amd import gen, kn
-from tests.oracle_helpers import rel_err
+from tests.oracle_helpers import TOL32, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -196,8 +197,14 @@ def test_gradient_fp32():
         p = kn.Plan(t, 3, jones_only=False, gradient=True, precision=1)
         m, e, g = _gpu_grad(p, Jd)
         mo, eo, go = _oracle(t, J, 3)
-        assert rel_err(m * 2.0 ** (e - eo), mo) <= 1e-3
-        assert np.max(np.abs(g - go) / np.abs(go)) <= 1e-3
+        ez = rel_err(m * 2.0 ** (e - eo), mo)
+        # the gradient vector normwise (an edge whose derivative is small
+        # next to the others carries the error of the whole contraction)
+        eg = np.max(np.abs(g - go)) / np.max(np.abs(go))
+        ee = np.max(np.abs(g - go) / np.abs(go))
+        print(f"fp32 gradient {d.label}: Z {ez:.1e}, normwise {eg:.1e}, elementwise {ee:.1e}",
+              flush=True)
+        assert ez <= TOL32 and eg <= TOL32
 
 
 def test_backward_api_errors():

@@ -20,7 +20,7 @@ from oracle import exact, invariants, kauffman
 from oracle import jones as ojones
 from oracle import potts
 from paper_1807_02119_amd import gen, kn, tune
-from tests.oracle_helpers import oracle_tait, oracle_v, oracle_z, rel_err
+from tests.oracle_helpers import TOL32, oracle_tait, oracle_v, oracle_z, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -84,13 +84,25 @@ def test_paper_printed_values():
 
 @pytest.mark.parametrize("q", [3, 5])
 def test_fp64_config_parity(q):
+    """The 50-200 crossing workload (64 knots, one knot per launch) against
+    the oracle's stored values (tests/golden/oracle_fp64_seed0.json)."""
+    import json
     _log(f"fp64 config q={q}")
-    for d, qq in gen.config_knots("fp64", 0, count=32):
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "oracle_fp64_seed0.json")) as f:
+        gold = json.load(f)["knots"]
+    knots = gen.config_knots("fp64", 0)
+    assert len(knots) == len(gold) == 128
+    worst = 0.0
+    for (d, qq), g in zip(knots, gold):
+        assert (d.label, d.n, qq) == (g["label"], g["crossings"], g["q"])
         if qq != q:
             continue
         t, p, m, e = gpu_z(d, q)
-        tg, mo, eo = oracle_z(d, q)
-        assert z_close(m, e, mo, eo), (d.label, q)
+        err = rel_err(m * 2.0 ** (e - g["z_exp2"]), complex(g["z_re"], g["z_im"]))
+        worst = max(worst, err)
+        assert err <= TOL, (d.label, q, err)
+    _log(f"worst relative error {worst:.1e}")
 
 
 @pytest.mark.parametrize("q", [2, 4, 6, 7, 8])
@@ -162,7 +174,7 @@ def test_gemm_and_split_parity():
         tg, mo, eo = oracle_z(d, 3)
         for prec in (0, 1):
             t, p, m, e = gpu_z(d, 3, precision=prec, **kw)
-            tol = TOL if prec == 0 else 1e-3
+            tol = TOL if prec == 0 else TOL32
             assert z_close(m, e, mo, eo, tol), (name, kw, prec)
 
 
@@ -176,7 +188,7 @@ def test_gemm64_parity():
         tg, mo, eo = oracle_z(d, q)
         for prec in (0, 1):
             t, p, m, e = gpu_z(d, q, precision=prec, **kw)
-            tol = TOL if prec == 0 else 1e-3
+            tol = TOL if prec == 0 else TOL32
             assert z_close(m, e, mo, eo, tol), (label, kw, prec)
 
 
@@ -197,6 +209,14 @@ def test_gemm64_split_ragged_full_size():
         assert min(abs(ratio - 1), abs(ratio + 1)) < 1e-9, kw
 
 
+# complex64 with the series-parallel reduction at real t (q >= 4): the
+# derived couplings x' = (x1 x2 + q - 1) / (x1 + x2 + q - 2) mix terms of
+# both signs, and the contraction of such couplings loses a few more bits to
+# cancellation than the Jones point of the workloads (measured 1.7e-5 at
+# q = 5 against ~2e-6 at q = 3): ten times TOL32.
+TOL32_SP = 10 * TOL32
+
+
 def test_series_parallel_parity():
     """simplify bit 2 (exact series-parallel reduction at the Jones couplings:
     derived edges and constant factors from the plan's constants)."""
@@ -205,7 +225,9 @@ def test_series_parallel_parity():
         tg, mo, eo = oracle_z(d, 3 + (k % 3))
         for prec in (0, 1):
             t, p, m, e = gpu_z(d, 3 + (k % 3), precision=prec, simplify=7)
-            tol = TOL if prec == 0 else 1e-3
+            tol = TOL if prec == 0 else TOL32_SP
+            _log(f"series-parallel {k} q={3 + k % 3} precision {prec}: "
+                 f"{rel_err(m * 2.0 ** (e - eo), mo):.1e}")
             assert z_close(m, e, mo, eo, tol), (d.label, prec)
 
 
@@ -221,7 +243,7 @@ def test_level_split_parity():
             _log(f"level split {d.label} n={d.n} split_serial_log2={split}")
             for prec in (0, 1):
                 t, p, m, e = gpu_z(d, 3, precision=prec, split_serial_log2=split)
-                tol = TOL if prec == 0 else 1e-3
+                tol = TOL if prec == 0 else TOL32
                 assert z_close(m, e, mo, eo, tol), (d.label, split, prec)
     taits = [kn.Tait(d.pd) for d in cases]
     plans = [kn.Plan(t, 3, split_serial_log2=(3 if i % 2 else 40)) for i, t in enumerate(taits)]
@@ -294,7 +316,7 @@ def test_bench_configuration_parity():
         z = b.contract(stream=main)
         torch.cuda.synchronize()
         out = kn.scalars_from_device(z)
-        tol, itol = (TOL, 1e-9) if prec == 0 else (1e-3, 1e-4)
+        tol, itol = (TOL, 1e-9) if prec == 0 else (TOL32, TOL32)
         for i, (tg, mo, eo) in oracle.items():
             m, e = out[i]
             assert z_close(m, e, mo, eo, tol), (i, prec)
@@ -338,18 +360,16 @@ def test_general_couplings_parity():
 
 
 def test_fp32_path_error_bound():
-    """complex64 tensors, FP32 accumulation: error against the FP64 oracle.
-
-    Each step adds at most ~K unit roundoffs (2^-24) relative to the largest
-    entry; over the whole plan the relative error of Z stays far below 1e-3
-    for these sizes (measured ~1e-6), while complex128 stays below 1e-10."""
+    """complex64 tensors, FP32 accumulation: error against the FP64 oracle,
+    per knot within TOL32 (a few times the FP32 rounding random walk along
+    the contraction; see tests/oracle_helpers)."""
     errs = []
     for d, q in gen.config_knots("q3_200_600", 0, count=8):
         t, p, m, e = gpu_z(d, q, precision=1)
         tg, mo, eo = oracle_z(d, q)
         errs.append(rel_err(m * 2.0 ** (e - eo), mo))
     _log(f"fp32 rel errors: {['%.1e' % x for x in errs]}")
-    assert max(errs) < 1e-3
+    assert max(errs) < TOL32
 
 
 def test_special_cases():

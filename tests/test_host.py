@@ -577,20 +577,66 @@ def test_bench_traffic_record_matches_source(tmp_path, monkeypatch):
 
 
 def test_tuner_space_is_valid():
-    """Every value the autotuner tries, and its recorded settings, are plan
-    options the planner accepts."""
+    """Every value the autotuner tries, plan-wide and per intermediate-size
+    bucket, and its recorded settings, are plan options the planner accepts."""
     from paper_1807_02119_amd import tune
     d = gen.lattice_knot((88, 0), 40, 120)
     t = kn.Tait(d.pd)
+    base = tune.plan_options(tune.DEFAULTS)
     for knob, values in tune.SPACE.items():
         for v in values:
-            opts = dict((k, x) for k, x in tune.DEFAULTS.items() if k != "grid")
-            opts[knob] = v
-            kn.Plan(t, 3, **opts)
-    for prec in (0, 1):
-        rec = tune.load("q3_200_600", prec)
-        assert rec, prec
-        kn.Plan(t, 3, precision=prec, **{k: x for k, x in rec.items() if k != "grid"})
+            kn.Plan(t, 3, **dict(base, **{knob: v}))
+    for coord, values in tune.bucket_space().items():
+        for v in values:
+            flat = dict(tune.DEFAULTS, **{coord: v})
+            kn.Plan(t, 3, **tune.plan_options(tune.split_setting(flat)))
+    for workload in ("q3_200_600", "batched"):
+        for prec in (0, 1):
+            rec = tune.load(workload, prec)
+            if workload == "q3_200_600" or rec:
+                assert rec, (workload, prec)
+                kn.Plan(t, 3, precision=prec, **tune.plan_options(rec))
+
+
+def test_bucket_knobs_change_only_their_bucket():
+    """A per-bucket override of the tile shape changes the tiling of the steps
+    whose output falls in that bucket and of no other step."""
+    from tests import image_model as im
+    d = gen.lattice_knot((89, 4), 300, 420)
+    t = kn.Tait(d.pd)
+
+    def tiling(**kw):
+        st = im.Image(kn.Plan(t, 3, strategy=2, **kw).image()).steps
+        return [(int(s["mode"]), int(s["tile"]), int(s["n_tiles"])) for s in st], st
+
+    ref, st = tiling()
+    outs = [int(s["nb"]) * int(s["nm"]) * int(s["nn"]) for s in st]
+    buckets = [0 if o <= 2**8 else 1 if o <= 2**12 else 2 if o <= 2**16 else 3 if o <= 2**20
+               else 4 for o in outs]
+    # buckets holding a tiled step whose tiles have more than 8 outputs
+    wide = {b for b, r in zip(buckets, ref) if r[0] == 1 and r[1] > 8}
+    assert wide
+    for b in range(5):
+        new, _ = tiling(buckets={b: {"tile_outs_log2": 3}})
+        changed = {buckets[i] for i in range(len(ref)) if new[i] != ref[i]}
+        assert changed == ({b} if b in wide else set()), (b, changed)
+
+
+def test_output_heavy_steps_are_tiled():
+    """A step with at least 2^big_step_outs_log2 outputs runs as tiles, and no
+    tile of a tiled step has more than 2^tile_outs_log2 outputs."""
+    from tests import image_model as im
+    d = gen.lattice_knot((89, 4), 400, 520)
+    t = kn.Tait(d.pd)
+    for outs_log2, tile_log2 in ((10, 8), (12, 10), (31, 10)):
+        img = im.Image(kn.Plan(t, 3, strategy=2, big_step_outs_log2=outs_log2,
+                               tile_outs_log2=tile_log2).image())
+        for s in img.steps:
+            outs = int(s["nb"]) * int(s["nm"]) * int(s["nn"])
+            if outs_log2 < 31 and outs >= 2**outs_log2:
+                assert int(s["mode"]) != 0, (outs, int(s["mode"]))
+            if int(s["mode"]) == 1 and int(s["tile"]) > 1:
+                assert int(s["tile"]) <= 2**tile_log2
 
 
 def test_series_parallel_reduction():
