@@ -150,22 +150,3 @@ def tait_graph(pd, signs=None, outer_arc: int = 0, outer_left: bool = True) -> T
         eps.append(e)
     return TaitGraph(len(black), edges, eps, int(sum(signs)), int(sum(eps)), signs)
 
-
-def components(n_vertices: int, edges) -> list:
-    """Connected components of a graph as lists of vertex ids."""
-    parent = list(range(n_vertices))
-
-    def find(a):
-        while parent[a] != a:
-            parent[a] = parent[parent[a]]
-            a = parent[a]
-        return a
-
-    for u, v in edges:
-        ru, rv = find(u), find(v)
-        if ru != rv:
-            parent[ru] = rv
-    groups = {}
-    for v in range(n_vertices):
-        groups.setdefault(find(v), []).append(v)
-    return list(groups.values())

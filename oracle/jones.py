@@ -55,6 +55,3 @@ def jones_value(q: int, n_v: int, writhe: int, tau: int, z_mant: complex, z_exp2
     mag = math.pow(2.0, log2_abs) if log2_abs < 1023 else math.inf
     return complex(mag * math.cos(ph), mag * math.sin(ph)), log2_abs
 
-
-def prefactor(q: int, n_v: int, writhe: int, tau: int) -> complex:
-    return cmath.exp(log_prefactor(q, n_v, writhe, tau))
