@@ -1,10 +1,16 @@
 """Build libkn.so (host C++ planner + gfx950 HIP engine) in-tree.
 
-    python -m paper_1807_02119_amd.build
+    python -m paper_1807_02119_amd.build            # libkn.so
+    python -m paper_1807_02119_amd.build --sanitize # _build/san/libkn_san.so
 
 Host sources are compiled with g++, the HIP source with hipcc for gfx950
 (packed-FP32 instruction selection disabled), and everything is linked by
 hipcc into ``paper_1807_02119_amd/libkn.so``.  Always recompiles.
+
+``--sanitize`` builds a checking variant for the CPU tests: the host
+sources with AddressSanitizer and UndefinedBehaviorSanitizer (g++), the
+engine as usual, linked with g++ against the HIP runtime.  Load it with
+KN_LIBRARY=<path> and the ASan runtime preloaded (see ``sanitizer_env``).
 """
 
 from __future__ import annotations
@@ -66,9 +72,58 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libkn_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libkn with the host code under ASan + UBSan (host-only instrumentation)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    host_flags = [f for f in HOST_FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_FLAGS
+    jobs, objs = [], []
+    for s in HOST_SOURCES:
+        o = os.path.join(SAN_DIR, s.replace(".cpp", ".o"))
+        jobs.append([CXX, *host_flags, "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in HIP_SOURCES:
+        o = os.path.join(SAN_DIR, s.replace(".hip", ".o"))
+        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        outs = list(ex.map(_run, jobs))
+    if verbose:
+        for o in outs:
+            if o.strip():
+                print(o)
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    _run([CXX, "-shared", "-fPIC", *SAN_FLAGS, *objs, "-o", SAN_LIB,
+          "-L" + os.path.join(rocm, "lib"), "-Wl,-rpath," + os.path.join(rocm, "lib"),
+          "-lamdhip64", "-lpthread"])
+    return SAN_LIB
+
+
+def sanitizer_env(env=None):
+    """Environment for a process that loads the sanitized library: its path,
+    the ASan runtime preloaded (the interpreter itself is not instrumented) and
+    leak checking off (the interpreter and the HIP runtime keep memory to the
+    end by design)."""
+    env = dict(os.environ if env is None else env)
+    asan = subprocess.run([CXX, "-print-file-name=libasan.so"], capture_output=True,
+                          text=True).stdout.strip()
+    env["KN_LIBRARY"] = SAN_LIB
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    return env
+
+
 def clean():
     shutil.rmtree(BUILD, ignore_errors=True)
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

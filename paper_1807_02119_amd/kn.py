@@ -16,7 +16,9 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkn.so")
+# KN_LIBRARY selects another build of the same library (the sanitized one
+# that the CPU tests can be run against, see build.py)
+LIB_PATH = os.environ.get("KN_LIBRARY") or os.path.join(_HERE, "libkn.so")
 
 KN_OK = 0
 STATUS = {0: "KN_OK", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_BUDGET",
