@@ -194,7 +194,13 @@ void kn_tait_free(kn_tait* g);
  *               (for kn_contract_backward): after the forward steps, the
  *               adjoint of every intermediate is contracted back to the vertex
  *               tensors (for C = A.B: dS/dA = dS/dC . B, dS/dB = A . dS/dC),
- *               and every intermediate is kept until its reverse step.
+ *               and every intermediate is kept until its reverse step.  With
+ *               mem_budget_bytes set, forward intermediates from the largest
+ *               rank down are dropped after their forward use and computed
+ *               again from their operands just before the reverse step that
+ *               needs them, in chains of at most 1, 2, 4 or 8 such steps
+ *               (shallow first), until the plan's arena fits the budget
+ *               (stats: n_recompute_steps; the flops include the recompute).
  *               Requires simplify without bits 1 and 2 (they drop edges
  *               whose derivative is not zero).  kn_contract on such a plan
  *               computes Z and runs the reverse steps without writing them out.
@@ -254,6 +260,8 @@ typedef struct {
   int32_t max_rank;
   int32_t n_slices;       /* q^(fixed spins); flops and bytes cover all slices */
   int32_t slice_chains;   /* slices run as this many concurrent chains */
+  int32_t n_recompute_steps; /* gradient plans: forward steps run again in the reverse
+                                pass for tensors dropped to fit mem_budget_bytes */
 } kn_plan_stats;
 
 /* Build a plan for q.  opts == NULL selects the defaults above (Jones-only,

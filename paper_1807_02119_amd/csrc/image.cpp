@@ -313,9 +313,12 @@ void make_section(PlanKnot& k) {
       }
       S.lds_used = std::max<int32_t>(S.lds_used, (int32_t)(peak * es));
     }
-    // a 64 x 64 GEMM step stages two 16 x 65 operand chunks in LDS from its
-    // start, followed by the offset table of up to 1024 contracted entries;
-    // the launch's LDS must hold them
+  }
+  // a 64 x 64 GEMM step stages two 16 x 65 operand chunks in LDS from its
+  // start, followed by the offset table of up to 1024 contracted entries; the
+  // launch's LDS must hold them (gradient plans included)
+  {
+    const int64_t es = elem_bytes(k.precision);
     for (const StepDesc& x : S.sd)
       if (x.mode == STEP_GEMM64) {
         const int64_t need = 2 * kGemmChunk * 65 * es + 8 * std::min<int64_t>(x.kseg, 1024);

@@ -720,9 +720,11 @@ struct Orderer {
 // Seeds are numbered after the vertex tensors (n_vt grows by the number of
 // components) so that step i still produces tensor n_vt + i.  Each vertex
 // learns the id of its adjoint and its component.
-void add_reverse(PlanKnot& k, int32_t& n_vt) {
+void add_reverse(PlanKnot& k, int32_t& n_vt, int32_t drop_rank, int32_t max_depth,
+                 int32_t& n_recompute) {
   const int32_t nc = (int32_t)k.comps.size();
   const int32_t ns = (int32_t)k.steps.size();
+  n_recompute = 0;
   auto shifted = [&](int32_t t) { return t < n_vt ? t : t + nc; };
   std::vector<PTensor> tensors;
   tensors.reserve(k.tensors.size() + nc + 2 * ns);
@@ -745,25 +747,60 @@ void add_reverse(PlanKnot& k, int32_t& n_vt) {
     k.vtx.push_back(std::move(pv));
   }
   n_vt += nc;
-  const size_t total = tensors.size() + 2 * (size_t)ns;
+  const size_t total = tensors.size();
   std::vector<int32_t> adj(total, -1), comp(total, 0);
   for (int32_t c = 0; c < nc; ++c) {
     adj[k.comps[c]] = n_vt - nc + c;
     comp[k.comps[c]] = c;
   }
+  // Checkpoints: the output of a forward step whose rank is at least
+  // drop_rank is dropped after its forward use (its arena is reused) and
+  // computed again from its operands just before the reverse step that reads
+  // it, unless that would chain more than max_depth dropped steps (then it is
+  // kept).  Component scalars are always kept.
+  std::vector<int32_t> producer(total, -1);
+  std::vector<uint8_t> depth(total, 0), dropped(total, 0), keep(total, 0);
+  for (int32_t c : k.comps) keep[c] = 1;
+  for (int32_t s = 0; s < ns; ++s) {
+    const PStep& fw = k.steps[s];
+    producer[fw.c] = s;
+    if (keep[fw.c] || tensors[fw.c].spins.size() < drop_rank) continue;
+    const int32_t d = 1 + std::max(depth[fw.a], depth[fw.b]);
+    if (d > max_depth) continue;
+    dropped[fw.c] = 1;
+    depth[fw.c] = (uint8_t)d;
+  }
+  // a dropped tensor's fresh copy: its step again, on fresh copies of its
+  // dropped operands (new tensor ids, the same spins in the same order)
+  std::function<int32_t(int32_t)> remat = [&](int32_t x) -> int32_t {
+    if (!dropped[x]) return x;
+    PStep r = k.steps[producer[x]];
+    r.a = remat(r.a);
+    r.b = remat(r.b);
+    r.c = (int32_t)tensors.size();
+    PTensor t;
+    t.spins = tensors[x].spins;
+    tensors.push_back(std::move(t));
+    adj.push_back(-1);
+    comp.push_back(0);
+    k.steps.push_back(std::move(r));
+    ++n_recompute;
+    return (int32_t)tensors.size() - 1;
+  };
   k.steps.reserve(3 * (size_t)ns);
   for (int32_t s = ns - 1; s >= 0; --s) {
     const PStep fw = k.steps[s];
     const int32_t cbar = adj[fw.c];
+    const int32_t fa = remat(fw.a), fb = remat(fw.b);
     PStep ra;  // dS/dA
     ra.a = cbar;
-    ra.b = fw.b;
+    ra.b = fb;
     ra.bs = fw.bs;
     ra.ms = fw.ms;
     ra.ns = fw.ks;
     ra.ks = fw.ns;
     PStep rb;  // dS/dB
-    rb.a = fw.a;
+    rb.a = fa;
     rb.b = cbar;
     rb.bs = fw.bs;
     rb.ms = fw.ks;
@@ -776,6 +813,8 @@ void add_reverse(PlanKnot& k, int32_t& n_vt) {
       for (int32_t x : r->ms) t.spins.push_back(x);
       for (int32_t x : r->ns) t.spins.push_back(x);
       tensors.push_back(std::move(t));
+      adj.push_back(-1);
+      comp.push_back(0);
     }
     adj[fw.a] = ra.c;
     adj[fw.b] = rb.c;
@@ -1047,73 +1086,10 @@ NetGraph sliced_graph(const Simplified& s, const std::vector<int32_t>& sliced,
 }
 
 // Build tensors, order and arena for one knot.  Returns KN_OK or an error.
-kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
-                    kn_plan_stats& st) {
-  k.q = q;
-  k.precision = o.precision;
-  k.jones_only = o.jones_only != 0;
-  k.gradient = o.gradient != 0;
-  k.n_edges = (int32_t)g.eps.size();
-  k.eps = g.eps;
-  k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
-  // steps below 2^big_log2 multiply-adds run inside serial tasks, which write
-  // a step's outputs from one base (at most 2^24 of them)
-  k.big_log2 = std::min(o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16, 24);
-  k.big_outs_log2 = std::min(o.big_step_outs_log2 > 0 ? o.big_step_outs_log2 : kBigOutsLog2, 24);
-  k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
-  k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
-  {
-    double qq = q;
-    if (q < 4) {
-      k.t_re = (qq - 2.0) / 2.0;
-      k.t_im = std::sqrt(qq * (4.0 - qq)) / 2.0;
-    } else {
-      k.t_re = (qq - 2.0 + std::sqrt(qq * (qq - 4.0))) / 2.0;
-      k.t_im = 0.0;
-    }
-  }
-  Simplified s = simplify(g, o.simplify, k.jones_only, k);
-  const int32_t n = s.n_spins;
-  st.n_edges_simplified = (int32_t)s.e.size();
-  st.n_vertices_simplified = n;
-  st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
-
-  // ---- slicing (optional), then absorption and order of the network
-  int32_t n_vt = 0;
-  {
-    std::vector<int32_t> sliced, new_id;
-    std::vector<Factor> pairs;
-    const double lq = std::log2((double)q);
-    for (;;) {
-      NetGraph G = sliced_graph(s, sliced, new_id, pairs);
-      kn_status rc = build_network(G, q, o, k, n_vt);
-      if (rc != KN_OK) return rc;
-      if (o.slice_log2_budget <= 0) break;
-      int32_t maxr = 0;
-      for (const auto& t : k.tensors) maxr = std::max(maxr, (int32_t)t.spins.size());
-      double slices = 1;
-      for (size_t j = 0; j <= sliced.size(); ++j) slices *= q;  // after one more spin
-      if (maxr * lq <= o.slice_log2_budget || (int32_t)sliced.size() >= kMaxSliceSpins ||
-          slices > kMaxSlices || G.n == 0)
-        break;
-      // fix the spin held by most of the largest tensors (ties: lowest id)
-      std::vector<int32_t> hits(G.n, 0);
-      for (const auto& t : k.tensors)
-        if ((int32_t)t.spins.size() >= maxr - 1)
-          for (int32_t x : t.spins) hits[x]++;
-      int32_t best = 0;
-      for (int32_t v = 1; v < G.n; ++v)
-        if (hits[v] > hits[best]) best = v;
-      for (int32_t v = 0; v < s.n_spins; ++v)
-        if (new_id[v] == best) sliced.push_back(v);
-    }
-    k.n_slice_spins = (int32_t)sliced.size();
-    k.n_slices = 1;
-    for (size_t j = 0; j < sliced.size(); ++j) k.n_slices *= q;
-    for (const Factor& f : pairs) k.factors.push_back(f);
-  }
-  st.n_components = (int32_t)k.comps.size();
-  if (k.gradient) add_reverse(k, n_vt);
+// Statistics, how each step runs (tiles or inside a serial task),
+// dependency levels and the arena of a plan whose steps are final.
+kn_status lay_out(PlanKnot& k, const kn_plan_opts& o, kn_plan_stats& st, int32_t n_vt) {
+  const int32_t q = k.q;
   st.n_vertex_tensors = n_vt;
   st.n_steps = (int32_t)k.steps.size();
 
@@ -1221,8 +1197,18 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   st.max_rank = maxrank;
   level_schedule(k, n_vt);
 
-  // ---- arena: first fit over live ranges, in execution order
+  // ---- arena: first fit over live ranges, in execution order.  A tensor
+  // lives from its step to its last use; component scalars and the adjoints
+  // of the vertex tensors (read after the last step) to the end.
   {
+    std::vector<int32_t> last(k.tensors.size(), -1);
+    for (size_t u = 0; u < k.steps.size(); ++u) {
+      last[k.steps[u].a] = (int32_t)u;
+      last[k.steps[u].b] = (int32_t)u;
+    }
+    for (int32_t c : k.comps) last[c] = INT32_MAX;
+    for (const auto& v : k.vtx)
+      if (v.adjoint >= 0) last[v.adjoint] = INT32_MAX;
     FitAlloc fa(INT64_MAX, 16);
     auto alloc = [&](int64_t len) { return fa.alloc(len); };
     auto release = [&](int64_t off, int64_t len) { fa.release(off, len); };
@@ -1243,17 +1229,140 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
           release(t.partial, len);
         }
       }
-      // gradient plans keep every tensor: forward ones are operands of the
-      // reverse steps, adjoints of the final gradient evaluation
-      for (size_t u = i; u < j && !k.gradient; ++u) {
+      // operands leave at their last use (the consumer of a plain plan; in a
+      // gradient plan the forward tensors are read again by the reverse steps)
+      for (size_t u = i; u < j; ++u) {
         const auto& sp = k.steps[u];
-        release(k.tensors[sp.a].off, k.tensors[sp.a].size);
-        release(k.tensors[sp.b].off, k.tensors[sp.b].size);
+        if (last[sp.a] == (int32_t)u) release(k.tensors[sp.a].off, k.tensors[sp.a].size);
+        if (sp.b != sp.a && last[sp.b] == (int32_t)u)
+          release(k.tensors[sp.b].off, k.tensors[sp.b].size);
       }
       i = j;
     }
     k.arena_elems = std::max<int64_t>(fa.top, 16);
   }
+  return KN_OK;
+}
+
+// A gradient plan: the reverse pass appended to the forward steps, with
+// forward tensors of rank >= r dropped and recomputed in chains of at most d
+// steps (add_reverse).  The search takes d = 1, 2, 4, 8 in turn and for each
+// the largest r (none dropped first) whose arena fits mem_budget_bytes next
+// to an allowance for the device program.  Without a budget nothing is
+// dropped.
+kn_status plan_gradient(PlanKnot& k, const kn_plan_opts& o, kn_plan_stats& st, int32_t& n_vt) {
+  const std::vector<PTensor> T0 = k.tensors;
+  const std::vector<PStep> S0 = k.steps;
+  const std::vector<PVertex> V0 = k.vtx;
+  const std::vector<int32_t> C0 = k.comps;
+  const int32_t nvt0 = n_vt;
+  std::vector<int32_t> ranks{INT32_MAX};
+  for (const auto& stp : S0) ranks.push_back(T0[stp.c].spins.size());
+  std::sort(ranks.begin(), ranks.end(), std::greater<int32_t>());
+  ranks.erase(std::unique(ranks.begin(), ranks.end()), ranks.end());
+  const double es = (double)elem_bytes(o.precision);
+  auto build = [&](int32_t rank, int32_t depth, double& need) {
+    k.tensors = T0;
+    k.steps = S0;
+    k.vtx = V0;
+    k.comps = C0;
+    n_vt = nvt0;
+    int32_t n_re = 0;
+    add_reverse(k, n_vt, rank, depth, n_re);
+    const kn_status rc = lay_out(k, o, st, n_vt);
+    st.n_recompute_steps = n_re;
+    // the arena plus an allowance for the device program and runtime state
+    need = (double)k.arena_elems * es + 512.0 * (double)(k.steps.size() + k.tensors.size()) +
+           65536.0;
+    return rc;
+  };
+  // shallow recompute chains first, for each the largest rank that fits; if
+  // nothing fits, the setting with the least memory
+  int32_t best_rank = ranks[0], best_depth = 1;
+  double best_need = -1, need = 0;
+  for (int32_t depth : {1, 2, 4, 8}) {
+    for (size_t i = depth == 1 ? 0 : 1; i < ranks.size(); ++i) {
+      const kn_status rc = build(ranks[i], depth, need);
+      if (rc != KN_OK) return rc;
+      if (!o.mem_budget_bytes || need <= (double)o.mem_budget_bytes) return KN_OK;
+      if (best_need < 0 || need < best_need) {
+        best_rank = ranks[i];
+        best_depth = depth;
+        best_need = need;
+      }
+    }
+  }
+  return build(best_rank, best_depth, need);  // over budget: kn_plan_create says so
+}
+
+kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot& k,
+                    kn_plan_stats& st) {
+  k.q = q;
+  k.precision = o.precision;
+  k.jones_only = o.jones_only != 0;
+  k.gradient = o.gradient != 0;
+  k.n_edges = (int32_t)g.eps.size();
+  k.eps = g.eps;
+  k.tile = o.tile_outputs > 0 ? o.tile_outputs : 256;
+  // steps below 2^big_log2 multiply-adds run inside serial tasks, which write
+  // a step's outputs from one base (at most 2^24 of them)
+  k.big_log2 = std::min(o.big_step_macs_log2 > 0 ? o.big_step_macs_log2 : 16, 24);
+  k.big_outs_log2 = std::min(o.big_step_outs_log2 > 0 ? o.big_step_outs_log2 : kBigOutsLog2, 24);
+  k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
+  k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
+  {
+    double qq = q;
+    if (q < 4) {
+      k.t_re = (qq - 2.0) / 2.0;
+      k.t_im = std::sqrt(qq * (4.0 - qq)) / 2.0;
+    } else {
+      k.t_re = (qq - 2.0 + std::sqrt(qq * (qq - 4.0))) / 2.0;
+      k.t_im = 0.0;
+    }
+  }
+  Simplified s = simplify(g, o.simplify, k.jones_only, k);
+  const int32_t n = s.n_spins;
+  st.n_edges_simplified = (int32_t)s.e.size();
+  st.n_vertices_simplified = n;
+  st.delta_h_paper = o.paper_stats ? paper_delta_h(s) : -1;
+
+  // ---- slicing (optional), then absorption and order of the network
+  int32_t n_vt = 0;
+  {
+    std::vector<int32_t> sliced, new_id;
+    std::vector<Factor> pairs;
+    const double lq = std::log2((double)q);
+    for (;;) {
+      NetGraph G = sliced_graph(s, sliced, new_id, pairs);
+      kn_status rc = build_network(G, q, o, k, n_vt);
+      if (rc != KN_OK) return rc;
+      if (o.slice_log2_budget <= 0) break;
+      int32_t maxr = 0;
+      for (const auto& t : k.tensors) maxr = std::max(maxr, (int32_t)t.spins.size());
+      double slices = 1;
+      for (size_t j = 0; j <= sliced.size(); ++j) slices *= q;  // after one more spin
+      if (maxr * lq <= o.slice_log2_budget || (int32_t)sliced.size() >= kMaxSliceSpins ||
+          slices > kMaxSlices || G.n == 0)
+        break;
+      // fix the spin held by most of the largest tensors (ties: lowest id)
+      std::vector<int32_t> hits(G.n, 0);
+      for (const auto& t : k.tensors)
+        if ((int32_t)t.spins.size() >= maxr - 1)
+          for (int32_t x : t.spins) hits[x]++;
+      int32_t best = 0;
+      for (int32_t v = 1; v < G.n; ++v)
+        if (hits[v] > hits[best]) best = v;
+      for (int32_t v = 0; v < s.n_spins; ++v)
+        if (new_id[v] == best) sliced.push_back(v);
+    }
+    k.n_slice_spins = (int32_t)sliced.size();
+    k.n_slices = 1;
+    for (size_t j = 0; j < sliced.size(); ++j) k.n_slices *= q;
+    for (const Factor& f : pairs) k.factors.push_back(f);
+  }
+  st.n_components = (int32_t)k.comps.size();
+  kn_status rc = k.gradient ? plan_gradient(k, o, st, n_vt) : lay_out(k, o, st, n_vt);
+  if (rc != KN_OK) return rc;
   // slices: work and traffic of all slices; chains share arenas within the
   // memory budget (16 GiB of arena by default)
   st.n_slices = k.n_slices;
@@ -1261,7 +1370,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   st.bytes *= k.n_slices;
   {
     const double budget = o.mem_budget_bytes ? (double)o.mem_budget_bytes : 16.0 * (1 << 30);
-    const double per = (double)k.arena_elems * (double)es;
+    const double per = (double)k.arena_elems * (double)elem_bytes(o.precision);
     const double fit = std::floor(budget / std::max(per, 1.0));
     k.slice_chains = (int32_t)std::max(1.0, std::min({(double)k.n_slices, fit, 64.0}));
     st.slice_chains = k.slice_chains;

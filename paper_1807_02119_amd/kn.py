@@ -88,7 +88,7 @@ class PlanStats(ctypes.Structure):
                 ("n_edges_simplified", ctypes.c_int32), ("n_vertices_simplified", ctypes.c_int32),
                 ("n_tasks", ctypes.c_int32), ("n_components", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("n_slices", ctypes.c_int32),
-                ("slice_chains", ctypes.c_int32)]
+                ("slice_chains", ctypes.c_int32), ("n_recompute_steps", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

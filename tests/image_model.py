@@ -115,8 +115,24 @@ def run(raw: bytes, J=None, want_grad=False):
     out = [None] * int(h["n_outputs"])
     zslice = {}
     grads = np.full(int(h["n_edges"]), np.nan, np.complex128)
-    # gradient plans read every tensor again in the reverse pass: nothing dies
-    keep_all = any(int(k["grad"]) for k in im.knots)
+    # a tensor dies after the last step that reads it (its consumer; in a
+    # gradient plan forward tensors are read again by the reverse steps); the
+    # component scalars of gradient plans and the adjoints of vertex tensors
+    # are read after the last step and never die
+    last_use = {}
+    for si in range(int(h["n_steps"])):
+        for op in (int(im.steps[si]["a"]), int(im.steps[si]["b"])):
+            last_use[op] = si
+    forever = set()
+    for k in im.knots:
+        if int(k["grad"]):
+            forever.update(int(im.comps[int(k["comp_off"]) + i]) for i in range(int(k["n_comps"])))
+    for v in im.vtx:
+        if int(v["adjoint"]) >= 0:
+            forever.add(int(v["adjoint"]))
+
+    def dies_at(op, si):
+        return op not in forever and last_use.get(op) == si
 
     # layout checks
     assert int(h["image_bytes"]) == len(raw)
@@ -267,8 +283,8 @@ def run(raw: bytes, J=None, want_grad=False):
     def finish_step(si, C, local, task_local):
         commit_step(si, C, local, task_local)
         s = im.steps[si]
-        for op in (int(s["a"]), int(s["b"])):  # operands are consumed exactly once
-            if not keep_all:
+        for op in (int(s["a"]), int(s["b"])):
+            if dies_at(op, si):
                 live_g.pop(op, None)
             live_l.pop(op, None)
 
@@ -436,7 +452,7 @@ def run(raw: bytes, J=None, want_grad=False):
                     commit_step(u, C, local)
                 for u in range(i, j):
                     for op in (int(im.steps[u]["a"]), int(im.steps[u]["b"])):
-                        if not keep_all:
+                        if dies_at(op, u):
                             live_g.pop(op, None)
                         live_l.pop(op, None)
                 i = j
@@ -447,7 +463,7 @@ def run(raw: bytes, J=None, want_grad=False):
                     e += exp2[t]
                     z, e = mul(z, e, read(t, local)[0])
                     live_l.pop(t, None)
-                    if not keep_all:
+                    if t not in forever:
                         live_g.pop(t, None)
                 wo, wm = int(k["w_off"]), int(k["w_off"]) + int(k["n_edges"])
                 sigma = [(int(k["slice"]) // q ** j) % q for j in range(int(k["n_slice_spins"]))]

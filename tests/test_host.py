@@ -659,3 +659,51 @@ def test_series_parallel_reduction():
     t = kn.Tait(gen.lattice_knot((86, 0), 40, 160).pd)
     with pytest.raises(kn.KnError):
         kn.Plan(t, 3, jones_only=False, simplify=5)
+
+
+def test_gradient_recompute_under_budget():
+    """Gradient plans under mem_budget_bytes drop forward intermediates after
+    their forward use and recompute them before their reverse use: the
+    workspace shrinks, the recompute shows in the statistics, and the CPU model
+    of the device program gives the unbudgeted Z and gradient (to rounding),
+    with the arena reused without overwriting a live tensor."""
+    rng = np.random.default_rng(1)
+    d = gen.random_grid_diagram(rng, 36)
+    t = kn.Tait(d.pd)
+    p = kn.Plan(t, 3, jones_only=False, gradient=True)
+    W = p.workspace_bytes
+    pb = kn.Plan(t, 3, jones_only=False, gradient=True, mem_budget_bytes=int(0.75 * W))
+    assert pb.status == 0 and pb.workspace_bytes <= 0.75 * W
+    assert pb.stats["n_recompute_steps"] > 0 and pb.stats["flops"] > p.stats["flops"]
+    J = rng.normal(scale=0.3, size=2 * t.n_edges)
+    ((zm, ze),), g = image_model.run(pb.image(), J, want_grad=True)
+    ((zm0, ze0),), g0 = image_model.run(p.image(), J, want_grad=True)
+    assert rel_err(zm * 2.0 ** (ze - ze0), zm0) < 1e-12
+    assert np.max(np.abs(g - g0) / np.abs(g0)) < 1e-12
+
+
+def test_gradient_recompute_matches_oracle():
+    """A budget below what the gradient plan can reach: the planner keeps the
+    setting with the least memory (recompute chains included) and reports
+    KN_E_BUDGET; that plan's reverse pass still gives the oracle's
+    d log Z / d J_e (CPU model of the device program)."""
+    rng = np.random.default_rng(5)
+    # knots of 54-59 crossings at q = 5 and 8, whose intermediates (up to
+    # 2^14-2^15 entries) are large next to the device program
+    for k, q in ((0, 8), (3, 5)):
+        d = gen.lattice_knot((75, k), 30, 60)
+        t = kn.Tait(d.pd)
+        full = kn.Plan(t, q, jones_only=False, gradient=True)
+        p = kn.Plan(t, q, jones_only=False, gradient=True,
+                    mem_budget_bytes=full.workspace_bytes // 2, allow_budget=True)
+        assert p.status == -3 and p.stats["n_recompute_steps"] > 0, d.label
+        assert p.workspace_bytes < full.workspace_bytes
+        J = rng.normal(scale=0.4, size=2 * t.n_edges)
+        ((zm, ze),), g = image_model.run(p.image(), J, want_grad=True)
+        uv, eps = t.edges()
+        x = np.exp(J[0::2] + 1j * J[1::2])
+        edges = [tuple(a) for a in uv]
+        m, e = potts.partition_function(t.n_vertices, edges, x, q)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+        go = potts.dlogz_dj(t.n_vertices, edges, x, q)
+        assert np.max(np.abs(g - go) / np.abs(go)) < 1e-12, d.label
