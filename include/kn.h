@@ -143,15 +143,16 @@ void kn_tait_free(kn_tait* g);
  * slice_log2_budget  0: no slicing.  Otherwise spins are fixed one at a time
  *               (each time the spin held by most of the plan's largest
  *               tensors) until the largest tensor has at most 2^budget
- *               entries, 12 spins are fixed or one more would exceed 4096
+ *               entries, 24 spins are fixed or one more would exceed 2^24
  *               slices.  The plan then covers q^k
  *               slices, each the same network with those spins at fixed
  *               values: an edge to a fixed spin becomes a diagonal factor on
  *               its other end, an edge between two fixed spins a constant, and
  *               Z is the sum of the slices' values (formed on the device).
- *               Slices run as chains sharing one arena each, as many chains
- *               as mem_budget_bytes (default 16 GiB of arena) allows.  Not
- *               combinable with gradient.
+ *               Slices run as chains (at most 64, as many as mem_budget_bytes,
+ *               default 16 GiB of arena, allows): one copy of the knot's
+ *               device program per chain, whose final task starts the chain's
+ *               next slice on the device.  Not combinable with gradient.
  * split_serial_log2  a run of small steps whose estimated time (one unit
  *               per step plus one per 512 multiply-adds) is at least
  *               2^split_serial_log2 is not executed by one workgroup but level

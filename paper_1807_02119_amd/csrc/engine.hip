@@ -75,6 +75,7 @@ struct DevProg {
   Cx<double>* weights;  // x_e (n_edges) then x_m (n_medges)
   Cx<double>* mgrad;    // d log Z / d J per merged edge (gradient plans)
   kn_scalar* zslice;    // result of every slice (sliced plans)
+  int32_t* uslice;      // the slice each knot descriptor is running
 };
 
 __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
@@ -102,6 +103,7 @@ __device__ inline DevProg make_prog(const uint8_t* img, uint8_t* state) {
   p.weights = reinterpret_cast<Cx<double>*>(state + h.o_weights);
   p.mgrad = reinterpret_cast<Cx<double>*>(state + h.o_mgrad);
   p.zslice = reinterpret_cast<kn_scalar*>(state + h.o_zslice);
+  p.uslice = reinterpret_cast<int32_t*>(state + h.o_uslice);
   return p;
 }
 
@@ -248,7 +250,7 @@ __device__ inline T block_max(T v, T* red) {
 
 template <class T>
 __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
-                           const double* J, const States& st) {
+                           const double* J, const States& st, int32_t slice) {
   const int tid = threadIdx.x;
   const ImgHeader& h = *p.h;
   Cx<double>* xe = p.weights + kd.w_off;
@@ -312,7 +314,7 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
         // takes the fixed value (digit j of the slice number, base q)
         for (int j = 0; j < vd.n_pins; ++j) {
           const int32_t* pn = p.pins + 2 * (vd.pin_off + j);
-          int sv = kd.slice;
+          int sv = slice;
           for (int r = 0; r < pn[1]; ++r) sv /= q;
           if (sv % q == a) prod = cmul(prod, xm[pn[0]]);
         }
@@ -1027,7 +1029,7 @@ __device__ __attribute__((always_inline)) void reduce_step(const DevProg& p, con
 
 template <class T>
 __device__ __attribute__((always_inline)) void knot_final(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
-                           kn_scalar* zout, const States& st) {
+                           kn_scalar* zout, const States& st, int32_t slice) {
   if (threadIdx.x != 0) return;
   const ImgHeader& h = *p.h;
   const Cx<double>* xe = p.weights + kd.w_off;
@@ -1050,7 +1052,7 @@ __device__ __attribute__((always_inline)) void knot_final(const DevProg& p, cons
                                          : xm[f.id];
     if (f.kind == FAC_LEAF) x.re += (double)(kd.q - 1);
     if (f.kind == FAC_PAIR) {  // equal fixed values: x_m, else 1
-      int sa = kd.slice, sb = kd.slice;
+      int sa = slice, sb = slice;
       for (int r = 0; r < f.a; ++r) sa /= kd.q;
       for (int r = 0; r < f.b; ++r) sb /= kd.q;
       if (sa % kd.q != sb % kd.q) x = Cx<double>{1.0, 0.0};
@@ -1068,7 +1070,7 @@ __device__ __attribute__((always_inline)) void knot_final(const DevProg& p, cons
     out.exp2 = (z.re == 0.0 && z.im == 0.0) ? 0 : e;
   }
   // a slice's value goes to the slice array; sum_slices adds them up
-  if (kd.n_slices > 1) p.zslice[kd.out_slot] = out;
+  if (kd.n_slices > 1) p.zslice[kd.out_slot + slice] = out;
   else zout[kd.out_slot] = out;
 }
 
@@ -1210,10 +1212,13 @@ __global__ void clear_state(const uint8_t* __restrict__ img, uint8_t* __restrict
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const kn_scalar nan{__builtin_nan(""), __builtin_nan(""), 0};
   if (i < h.n_outputs) zout[i] = nan;
-  if (h.sliced && i < h.n_knots) reinterpret_cast<kn_scalar*>(state + h.o_zslice)[i] = nan;
+  if (i < h.n_zslice) reinterpret_cast<kn_scalar*>(state + h.o_zslice)[i] = nan;
+  if (i < h.n_knots)
+    reinterpret_cast<int32_t*>(state + h.o_uslice)[i] =
+        reinterpret_cast<const KnotDesc*>(img + h.o_knots)[i].slice;
   int32_t* ctrl = reinterpret_cast<int32_t*>(state);
   if (i < CTRL_WORDS) ctrl[i] = (i == CTRL_TAIL) ? h.n_roots : 0;
-  if (i < h.n_tasks) {
+  if (i < h.n_queue) {
     const int32_t* roots = reinterpret_cast<const int32_t*>(img + h.o_roots);
     reinterpret_cast<int32_t*>(state + h.o_queue)[i] = i < h.n_roots ? roots[i] : -1;
   }
@@ -1239,7 +1244,7 @@ __global__ void sum_slices(const uint8_t* __restrict__ img, uint8_t* __restrict_
   if (i >= h.n_knots) return;
   const KnotDesc* kds = reinterpret_cast<const KnotDesc*>(img + h.o_knots);
   const KnotDesc kd = kds[i];
-  if (kd.n_slices <= 1 || kd.slice != 0) return;
+  if (kd.n_slices <= 1 || kd.slice != 0) return;  // the plan's first chain adds its slices
   const kn_scalar* zs = reinterpret_cast<const kn_scalar*>(state + h.o_zslice) + kd.out_slot;
   int64_t emax = INT64_MIN;
   bool bad = false;
@@ -1312,7 +1317,7 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
   TensorState* s_ext = reinterpret_cast<TensorState*>(kn_dyn_smem + kLdsExt);
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(kn_dyn_smem + kLdsArena);
   const DevProg p = make_prog(img, state);
-  const int32_t n_tasks = p.h->n_tasks;
+  const int32_t n_queue = p.h->n_queue;
   const int tid = threadIdx.x;
   for (;;) {
     int64_t t_claim = 0;
@@ -1320,7 +1325,7 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
       if (trace) t_claim = wall_clock64();
       const int32_t slot = atomicAdd(&p.ctrl[CTRL_HEAD], 1);
       int32_t t = -1;
-      if (slot < n_tasks) {
+      if (slot < n_queue) {
         int32_t nap = 1;
         const int64_t t_wait = wall_clock64();
         while ((t = __hip_atomic_load(&p.queue[slot], __ATOMIC_RELAXED,
@@ -1346,25 +1351,42 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int64_t t_start = (trace && tid == 0) ? wall_clock64() : 0;
     const TaskDesc td = p.tasks[ti];
+    // a sliced unit that starts its next slice after this task (its final task)
+    int32_t next_slice = -1;
     if (td.kind == TASK_SERIAL) {
       const KnotDesc kd = p.knots[td.knot];
+      const int32_t slice = p.uslice[td.knot];
       const States st{p.ts, s_shift, s_exp, td.state_lo, min(td.state_len, kStateCap)};
       int64_t ph_buf[4] = {0, 0, 0, 0};
       int64_t* ph = (trace && tid == 0) ? ph_buf : nullptr;
       if (td.flags & TF_SETUP) {
-        knot_setup<T>(p, kd, arena, lds, J, st);
+        knot_setup<T>(p, kd, arena, lds, J, st, slice);
         __syncthreads();
       }
       if (ph) ph[0] = wall_clock64() - t_start;
       serial_steps<T>(p, td.first, td.count, kd.q, arena, lds, s_tab, s_desc, s_tb, s_ext, st,
                       s_red, ph);
-      if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, lds, zout, st);
+      if (td.flags & TF_FINAL) knot_final<T>(p, kd, arena, lds, zout, st, slice);
       if (ph)
         for (int i = 0; i < 4; ++i) s_ph[i] = ph[i];
       // states of this task's tensors go back to global memory for later groups
       for (int32_t i = tid; i < st.len; i += kBlock) {
         p.ts[st.lo + i].shift = s_shift[i];
         p.ts[st.lo + i].exp2 = s_exp[i];
+      }
+      // the last task of a slice whose chain has more: every group and tensor
+      // of the unit is done with, so its counters and tensor states are reset
+      // for the next slice here (published with this task's release below)
+      if ((td.flags & TF_FINAL) && kd.n_slices > 1 && slice + kd.slice_step < kd.n_slices) {
+        next_slice = slice + kd.slice_step;
+        __syncthreads();
+        for (int32_t g = tid; g < kd.n_groups; g += kBlock)
+          p.pending[kd.group_off + g] = p.groups[kd.group_off + g].n_pred;
+        for (int32_t t = tid; t < kd.n_tensors; t += kBlock) {
+          p.ts[kd.tensor_off + t].shift = kShiftNone;
+          p.ts[kd.tensor_off + t].exp2 = 0;
+        }
+        if (tid == 0) p.uslice[td.knot] = next_slice;
       }
     } else {
       const States st{p.ts, s_shift, s_exp, 0, 0};
@@ -1388,8 +1410,14 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
     if (tid == 0) {
       s_enq[0] = 0;
       const int32_t next = p.groups[td.group].next;
-      if (next >= 0 && __hip_atomic_fetch_add(&p.pending[next], -1, __ATOMIC_ACQ_REL,
-                                              __HIP_MEMORY_SCOPE_AGENT) == 1) {
+      if (next_slice >= 0) {
+        // the unit's first group again, for its next slice
+        const GroupDesc g = p.groups[p.knots[td.knot].group_off];
+        s_enq[0] = g.n_tasks;
+        s_enq[1] = g.first_task;
+        s_enq[2] = atomicAdd(&p.ctrl[CTRL_TAIL], g.n_tasks);
+      } else if (next >= 0 && __hip_atomic_fetch_add(&p.pending[next], -1, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT) == 1) {
         const GroupDesc g = p.groups[next];
         s_enq[0] = g.n_tasks;
         s_enq[1] = g.first_task;
@@ -1499,7 +1527,7 @@ kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const d
   // then has its CU to itself)
   int32_t grid = grid_override;
   if (grid <= 0) grid = device_cus();
-  if (grid > h.n_tasks) grid = h.n_tasks;
+  if (grid > h.n_queue) grid = h.n_queue;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(engine<T>, dim3(grid), dim3(kBlock), dyn, st, ws, ws + h.state_off,
                      reinterpret_cast<Cx<T>*>(ws + h.arena_off), J, z, trace);
@@ -1524,6 +1552,8 @@ kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* 
   n_clear = std::max<int64_t>(n_clear, h.n_groups);
   n_clear = std::max<int64_t>(n_clear, h.n_tensors);
   n_clear = std::max<int64_t>(n_clear, h.n_knots);
+  n_clear = std::max<int64_t>(n_clear, h.n_queue);
+  n_clear = std::max<int64_t>(n_clear, h.n_zslice);
   hipLaunchKernelGGL(clear_state, dim3((unsigned)((n_clear + 255) / 256)), dim3(256), 0, st, ws,
                      ws + h.state_off, z);
   if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;

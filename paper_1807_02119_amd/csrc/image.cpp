@@ -387,16 +387,16 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.magic = kMagic;
   h.precision = knots.empty() ? 0 : knots[0]->precision;
 
-  // Every plan contributes n_slices units (knot descriptors), one per slice
-  // (one for an unsliced plan).  Arrays that do not depend on the slice
-  // (merged edges, members, factors, slot lists, pins, strides, Tait signs)
-  // are stored once per plan; tensors, steps, vertices, components, tasks,
-  // groups and weight slots once per unit.  The units of a plan run as
-  // slice_chains chains: unit c follows unit c - slice_chains, and the units
-  // of a chain share one arena region.  Offsets are prefix sums; the units are
-  // then written in parallel straight into the image.
+  // Every plan contributes one unit (knot descriptor) per chain of slices
+  // (one for an unsliced plan): unit c of a plan with C chains runs slices
+  // c, c + C, ... one after another in its own arena region, its final task
+  // starting the next slice on the device.  Arrays that do not depend on the
+  // slice (merged edges, members, factors, slot lists, pins, strides, Tait
+  // signs) are stored once per plan; tensors, steps, vertices, components,
+  // tasks, groups and weight slots once per unit.  Offsets are prefix sums;
+  // the units are then written in parallel straight into the image.
   struct PlanOff {
-    size_t VS, M, MEM, F, TAB, E, PIN, CONST, unit;
+    size_t VS, M, MEM, F, TAB, E, PIN, CONST, unit, zslice;
     int64_t arena;
   };
   struct UnitOff {
@@ -405,9 +405,10 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   const size_t nP = knots.size();
   std::vector<PlanOff> poff(nP + 1);
   std::vector<UnitOff> uoff;
-  std::vector<std::pair<int32_t, int32_t>> unit_of;  // (plan, slice)
+  std::vector<std::pair<int32_t, int32_t>> unit_of;  // (plan, chain)
   int32_t lds_used = 0;
   bool sliced = false;
+  int64_t n_queue = 0;
   {
     PlanOff po{};
     UnitOff uo{};
@@ -423,11 +424,14 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
       po.E += k.eps.size();
       po.PIN += S.pins.size() / 2;
       po.CONST += S.consts.size() / 2;
-      po.unit += k.n_slices;
-      po.arena += S.arena_elems * std::max(1, k.slice_chains);
+      const int32_t chains = std::min(std::max(1, k.slice_chains), k.n_slices);
+      po.unit += chains;
+      if (k.n_slices > 1) po.zslice += k.n_slices;
+      po.arena += S.arena_elems * chains;
       lds_used = std::max(lds_used, S.lds_used);
       sliced |= k.n_slices > 1;
-      for (int32_t c = 0; c < k.n_slices; ++c) {
+      for (int32_t c = 0; c < chains; ++c) {
+        n_queue += (int64_t)S.tasks.size() * ((k.n_slices - c + chains - 1) / chains);
         uoff.push_back(uo);
         unit_of.emplace_back((int32_t)ki, c);
         uo.T += S.td.size();
@@ -468,6 +472,9 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.n_outputs = (int32_t)nP;
   h.sliced = sliced ? 1 : 0;
   h.n_consts = (int32_t)nConst;
+  if (n_queue > INT32_MAX - 1 || pt.zslice > (size_t)INT32_MAX) return -1;
+  h.n_queue = (int32_t)n_queue;
+  h.n_zslice = (int32_t)pt.zslice;
   h.lds_bytes = (lds_used + 255) / 256 * 256;
   std::vector<std::pair<int64_t, int64_t>> used;  // (offset, bytes) of each array
   int64_t top = sizeof(ImgHeader);
@@ -492,10 +499,8 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.o_comps = reserve(nC, sizeof(int32_t));
   h.o_pins = reserve(2 * nPin, sizeof(int32_t));
   h.o_consts = reserve(2 * nConst, sizeof(double));
-  // roots last: their count is known once the chains are laid out
-  size_t n_roots = 0;
-  for (size_t ki = 0; ki < nP; ++ki)
-    n_roots += (size_t)std::min(knots[ki]->n_slices, std::max(1, knots[ki]->slice_chains));
+  // roots last: the first group of every unit
+  const size_t n_roots = nU;
   h.n_roots = (int32_t)n_roots;
   h.o_roots = reserve(n_roots, sizeof(int32_t));
   h.image_bytes = align256(top);
@@ -504,7 +509,7 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.state_off = h.image_bytes;
   int64_t st = CTRL_WORDS * 4;
   h.o_queue = st;
-  st = align256(st + 4 * (int64_t)nTask);
+  st = align256(st + 4 * (int64_t)n_queue);
   h.o_pending = st;
   st = align256(st + 4 * (int64_t)nG);
   h.o_tstate = st;
@@ -514,7 +519,9 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.o_mgrad = st;
   st = align256(st + 16 * (int64_t)nM);
   h.o_zslice = st;
-  st = align256(st + (int64_t)sizeof(kn_scalar) * (int64_t)nU);
+  st = align256(st + (int64_t)sizeof(kn_scalar) * (int64_t)pt.zslice);
+  h.o_uslice = st;
+  st = align256(st + 4 * (int64_t)nU);
   h.state_bytes = st;
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);
@@ -556,8 +563,8 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
     const Section& S = k.sec;
     const PlanOff& o = poff[pk];
     const UnitOff& u = uoff[ui];
-    const int32_t chains = std::max(1, k.slice_chains);
-    const int64_t arena0 = o.arena + S.arena_elems * (slice % chains);
+    const int32_t chains = std::min(std::max(1, k.slice_chains), k.n_slices);
+    const int64_t arena0 = o.arena + S.arena_elems * slice;
     const size_t TAB0 = o.TAB, VS0 = o.VS, MEM0 = o.MEM, PIN0 = o.PIN;
     if (slice == 0) {  // per-plan arrays
       std::copy(S.vslot.begin(), S.vslot.end(), vslot + VS0);
@@ -581,8 +588,13 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
     x.comp_off = (int32_t)u.C;
     x.step_off = (int32_t)u.S;
     x.slice = slice;
+    x.slice_step = chains;
     x.plan_slot = (int32_t)pk;
-    x.out_slot = k.n_slices > 1 ? (int32_t)ui : (int32_t)pk;
+    x.out_slot = k.n_slices > 1 ? (int32_t)o.zslice : (int32_t)pk;
+    x.group_off = (int32_t)u.G;
+    x.n_groups = (int32_t)S.groups.size();
+    x.tensor_off = (int32_t)u.T;
+    x.n_tensors = (int32_t)S.td.size();
     x.w_off = (int32_t)u.W;
     x.const_off = (int32_t)o.CONST;
     kd[ui] = x;
@@ -632,17 +644,8 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
       if (g.next >= 0) g.next += g0;
       groups[g0 + i] = g;
     }
-    // chains: the last group of this unit releases the first group of the
-    // unit `chains` slices later, which waits for it
-    if (slice + chains < k.n_slices) {
-      const UnitOff& nxt = uoff[ui + chains];
-      groups[g0 + ng - 1].next = (int32_t)nxt.G;
-    }
-    if (slice >= chains) groups[g0].n_pred = S.groups.back().n_tasks;
-    if (slice < chains) {
-      const double per_chain = (double)((k.n_slices - slice + chains - 1) / chains);
-      roots[ui] = {-S.est * per_chain, tk0 + S.groups[0].first_task};
-    }
+    const double per_chain = (double)((k.n_slices - slice + chains - 1) / chains);
+    roots[ui] = {-S.est * per_chain, tk0 + S.groups[0].first_task};
   };
   // a few units per thread; small images are laid out on the calling thread
   const size_t nth = std::min<size_t>(std::max<size_t>(1, nU / 16), (size_t)usable_cpus());

@@ -73,9 +73,11 @@ constexpr int32_t kGemm64Pct = 300;
 // default threshold (log2 of the estimated time) above which a serial run is
 // executed level by level over several workgroups
 constexpr int32_t kSplitSerialLog2 = 40;
-// Slicing fixes at most this many spins, and makes at most kMaxSlices slices.
-constexpr int32_t kMaxSliceSpins = 12;
-constexpr double kMaxSlices = 4096;  // each slice is a copy of the knot's descriptors
+// Slicing fixes at most this many spins, and makes at most kMaxSlices slices
+// (the device runs the slices of a chain one after another from one copy of
+// the knot's descriptors; the queue holds one slot per task and slice).
+constexpr int32_t kMaxSliceSpins = 24;
+constexpr double kMaxSlices = 16777216;
 
 namespace {
 

@@ -71,17 +71,21 @@ struct ImgHeader {
   int32_t n_outputs;  // entries of the output scalar array
   int32_t sliced;     // 1: some knots are slices; their sums are formed after the launch
   int32_t n_consts;   // complex128 constants over all plans
+  int32_t n_queue;    // task executions (queue slots): a sliced unit runs its tasks
+                      // once per slice of its chain
+  int32_t n_zslice;   // slice results over all sliced plans
   int64_t o_tasks, o_groups, o_roots, o_knots, o_tensors, o_steps, o_vtx, o_vslot;
   int64_t o_medges, o_members, o_factors, o_strides, o_eps, o_comps, o_pins, o_consts;
   int64_t image_bytes;
   // runtime state (relative to the workspace base)
   int64_t state_off, state_bytes;
-  int64_t o_queue;    // int32[n_tasks] ready queue (-1 = slot not yet written)
+  int64_t o_queue;    // int32[n_queue] ready queue (-1 = slot not yet written)
   int64_t o_pending;  // int32[n_groups] unfinished predecessor tasks
   int64_t o_tstate;   // TensorState[n_tensors]
   int64_t o_weights;  // complex128 x_e per original edge, then x_m per merged edge
   int64_t o_mgrad;    // complex128 d log Z / d J per merged edge (gradient plans)
-  int64_t o_zslice;   // kn_scalar per knot: the result of each slice
+  int64_t o_zslice;   // kn_scalar per slice of every sliced plan
+  int64_t o_uslice;   // int32 per knot descriptor: the slice it is running
   // tensor arena (relative to the workspace base), in complex entries
   int64_t arena_off, arena_elems;
   int64_t workspace_bytes;
@@ -117,14 +121,22 @@ struct KnotDesc {
   int32_t step_off, n_steps;
   int32_t grad;  // 1: the steps include the reverse pass; the final task
                  // writes d log Z / d J_e for every original edge
-  // Slicing: the network of one plan with n_slice_spins spins fixed; this knot
-  // is slice number `slice` (digit j in base q = the value of sliced spin j)
-  // of n_slices.  Its Z goes to the slice array (out_slot indexes it) and the
-  // sum over slices to output plan_slot.  n_slices == 1: not sliced.
-  int32_t slice, n_slices, n_slice_spins, plan_slot;
+  // Slicing: the network of one plan with n_slice_spins spins fixed.  This
+  // descriptor is one chain of slice_step chains: it runs slices slice,
+  // slice + slice_step, ... < n_slices one after another (the slice running
+  // now is in the runtime state; digit j of a slice number in base q is the
+  // value of sliced spin j).  Slice s writes its Z to entry out_slot + s of
+  // the slice array, and the sum over slices goes to output plan_slot.
+  // n_slices == 1: not sliced (out_slot indexes the outputs).
+  int32_t slice, n_slices, n_slice_spins, plan_slot, slice_step;
+  // this descriptor's groups and tensors (reset between its slices)
+  int32_t group_off, n_groups, tensor_off, n_tensors;
   int32_t w_off;  // this knot's weight slots: x_e at w_off, x_m at w_off + n_edges
   int32_t const_off;  // this plan's constants (derived merged edges, FAC_CONST)
+  int32_t pad;        // explicit: no implicit padding, so images are byte-reproducible
 };
+
+static_assert(sizeof(KnotDesc) == 16 + 28 * 4, "KnotDesc has no implicit padding");
 
 struct TensorDesc {
   int64_t off;      // complex entries from the arena base (global home)

@@ -23,6 +23,7 @@ HDR = np.dtype([
     ("n_members", "<i4"), ("n_factors", "<i4"), ("n_strides", "<i4"), ("n_groups", "<i4"),
     ("n_edges", "<i4"), ("n_roots", "<i4"), ("lds_bytes", "<i4"), ("n_pins", "<i4"),
     ("n_wslots", "<i4"), ("n_outputs", "<i4"), ("sliced", "<i4"), ("n_consts", "<i4"),
+    ("n_queue", "<i4"), ("n_zslice", "<i4"),
     ("o_tasks", "<i8"), ("o_groups", "<i8"), ("o_roots", "<i8"), ("o_knots", "<i8"),
     ("o_tensors", "<i8"), ("o_steps", "<i8"), ("o_vtx", "<i8"), ("o_vslot", "<i8"),
     ("o_medges", "<i8"), ("o_members", "<i8"), ("o_factors", "<i8"), ("o_strides", "<i8"),
@@ -30,7 +31,8 @@ HDR = np.dtype([
     ("image_bytes", "<i8"),
     ("state_off", "<i8"),
     ("state_bytes", "<i8"), ("o_queue", "<i8"), ("o_pending", "<i8"), ("o_tstate", "<i8"),
-    ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("o_zslice", "<i8"), ("arena_off", "<i8"),
+    ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("o_zslice", "<i8"), ("o_uslice", "<i8"),
+    ("arena_off", "<i8"),
     ("arena_elems", "<i8"),
     ("workspace_bytes", "<i8")], align=True)
 TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "group", "first", "count", "flags",
@@ -40,7 +42,8 @@ GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", 
 KNOT = np.dtype([("t_re", "<f8"), ("t_im", "<f8")] + [(f, "<i4") for f in (
     "q", "edge_off", "n_edges", "medge_off", "n_medges", "vtx_off", "n_vtx", "factor_off",
     "n_factors", "comp_off", "n_comps", "n_iso", "out_slot", "step_off", "n_steps", "grad",
-    "slice", "n_slices", "n_slice_spins", "plan_slot", "w_off", "const_off")], align=True)
+    "slice", "n_slices", "n_slice_spins", "plan_slot", "slice_step", "group_off", "n_groups",
+    "tensor_off", "n_tensors", "w_off", "const_off", "pad")], align=True)
 TENSOR = np.dtype([("off", "<i8"), ("size", "<i4"), ("lds_off", "<i4")], align=True)
 STEP = np.dtype([(f, "<i4") for f in ("a", "b", "c", "nb", "nm", "nn", "nk", "str", "ranks",
                                       "n_tiles", "tile", "home_a", "home_b", "home_c", "mode",
@@ -364,6 +367,9 @@ def run(raw: bytes, J=None, want_grad=False):
 
     queue = deque(int(r) for r in im.roots)
     pending = {gi: int(g["n_pred"]) for gi, g in enumerate(im.groups)}
+    # the slice each knot descriptor (a chain of slices) is running
+    uslice = [int(k["slice"]) for k in im.knots]
+    assert len(queue) == len(im.knots), "one root group per knot descriptor"
     assert all(im.groups[im.tasks[r]["group"]]["n_pred"] == 0 for r in queue)
     done_in_group = {}
     executed = 0
@@ -401,7 +407,8 @@ def run(raw: bytes, J=None, want_grad=False):
                     for i in range(int(me["y"])):
                         x *= weights[wo + int(im.members[int(me["x"]) + i])]
                     weights[wm + m] = x
-                sigma = [(int(k["slice"]) // q ** j) % q for j in range(int(k["n_slice_spins"]))]
+                sigma = [(uslice[int(task["knot"])] // q ** j) % q
+                         for j in range(int(k["n_slice_spins"]))]
                 for v in range(int(k["n_vtx"])):
                     vd = im.vtx[int(k["vtx_off"]) + v]
                     ns = int(vd["n_slots"])
@@ -466,7 +473,8 @@ def run(raw: bytes, J=None, want_grad=False):
                     if t not in forever:
                         live_g.pop(t, None)
                 wo, wm = int(k["w_off"]), int(k["w_off"]) + int(k["n_edges"])
-                sigma = [(int(k["slice"]) // q ** j) % q for j in range(int(k["n_slice_spins"]))]
+                sigma = [(uslice[int(task["knot"])] // q ** j) % q
+                         for j in range(int(k["n_slice_spins"]))]
                 for i in range(int(k["n_factors"])):
                     f = im.factors[int(k["factor_off"]) + i]
                     if f["x"] == 0:
@@ -481,7 +489,9 @@ def run(raw: bytes, J=None, want_grad=False):
                 for i in range(int(k["n_iso"])):
                     z, e = mul(z, e, q)
                 if int(k["n_slices"]) > 1:
-                    zslice[int(k["out_slot"])] = (z, e, int(k["plan_slot"]))
+                    s_ = uslice[int(task["knot"])]
+                    assert int(k["out_slot"]) + s_ not in zslice, "slice computed twice"
+                    zslice[int(k["out_slot"]) + s_] = (z, e, int(k["plan_slot"]))
                 else:
                     out[int(k["out_slot"])] = (z, e)
                 if int(k["grad"]):
@@ -508,6 +518,26 @@ def run(raw: bytes, J=None, want_grad=False):
             if task["count"] == 0:
                 assert si in split_pending, "reduce before the step's tiles"
                 reduce(si, local)
+        # the final task of a slice whose chain has more: reset the unit and
+        # start its next slice
+        ki = int(task["knot"])
+        if (task["kind"] == TASK_SERIAL and task["flags"] & 2 and int(k["n_slices"]) > 1
+                and uslice[ki] + int(k["slice_step"]) < int(k["n_slices"])):
+            uslice[ki] += int(k["slice_step"])
+            g0, ng = int(k["group_off"]), int(k["n_groups"])
+            assert int(im.groups[g0 + ng - 1]["next"]) == -1
+            for gi in range(g0, g0 + ng):
+                pending[gi] = int(im.groups[gi]["n_pred"])
+                done_in_group.pop(gi, None)
+            t0, nt_ = int(k["tensor_off"]), int(k["n_tensors"])
+            for t in range(t0, t0 + nt_):
+                assert t not in live_g, f"tensor {t} still live at the end of a slice"
+                finished[t] = False
+                shift[t] = None
+                exp2[t] = 0
+            G = im.groups[g0]
+            queue.extend(range(int(G["first_task"]), int(G["first_task"] + G["n_tasks"])))
+            continue
         # group completion -> enqueue the next group
         g = int(task["group"])
         done_in_group[g] = done_in_group.get(g, 0) + 1
@@ -525,7 +555,12 @@ def run(raw: bytes, J=None, want_grad=False):
                 assert pending[nxt] == 0
                 G = im.groups[nxt]
                 queue.extend(range(int(G["first_task"]), int(G["first_task"] + G["n_tasks"])))
-    assert executed == int(h["n_tasks"]), "some tasks were never enqueued"
+    assert executed == int(h["n_queue"]), "some tasks were never enqueued"
+    assert all(int(h["n_queue"]) >= 0 for _ in [0])
+    for k in im.knots:  # every slice of every sliced plan computed once
+        if int(k["n_slices"]) > 1 and int(k["slice"]) == 0:
+            for s_ in range(int(k["n_slices"])):
+                assert int(k["out_slot"]) + s_ in zslice, "slice never computed"
     # sliced plans: Z is the sum over slices (exact complex sum, aligned exponents)
     acc = {}
     for z, e, slot in zslice.values():

@@ -104,3 +104,21 @@ def test_sliced_q2_arf_574_crossings():
     v, _, _ = kn.jones(2, t, m, e)
     tg = oracle_tait(d)
     assert abs(v - invariants.v_at_q2(tg.n_vertices, tg.edges, tg.eps)) < 1e-9
+
+
+@pytest.mark.parametrize("k,q,budget", [(0, 2, 1), (2, 3, 4)])
+def test_long_slice_loops(k, q, budget):
+    """Slice counts far beyond the chain count: 16384 slices at q = 2 and
+    19683 at q = 3, run as 64 device-side loops and as a single loop (one
+    chain, every slice on the same descriptors), against the oracle."""
+    d = gen.lattice_knot((84, k), 40, 70)
+    t = kn.Tait(d.pd)
+    tg, mo, eo = oracle_z(d, q)
+    for mem in (None, 1):
+        extra = {} if mem is None else {"mem_budget_bytes": mem, "allow_budget": True}
+        p = kn.Plan(t, q, slice_log2_budget=budget, **extra)
+        assert p.stats["n_slices"] >= 4096
+        _log(f"long loop q={q} n={d.n}: {p.stats['n_slices']} slices, "
+             f"{p.stats['slice_chains']} chains")
+        m, e = _z(p)
+        assert rel_err(m * 2.0 ** (e - eo), mo) <= 1e-10, (d.n, q, mem)

@@ -707,3 +707,36 @@ def test_gradient_recompute_matches_oracle():
         assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
         go = potts.dlogz_dj(t.n_vertices, edges, x, q)
         assert np.max(np.abs(g - go) / np.abs(go)) < 1e-12, d.label
+
+
+def test_slice_loop_on_the_device_model():
+    """Slices run as a loop on the device: each chain is one copy of the
+    knot's device program whose final task starts the chain's next slice.
+    With one chain, every slice runs on the same descriptors (the image does
+    not grow with the slice count) and Z matches the oracle."""
+    done = 0
+    for k, q in ((0, 2), (1, 3), (2, 3), (3, 2), (4, 3)):
+        d = gen.lattice_knot((86, k), 30, 70)
+        t = kn.Tait(d.pd)
+        plain = kn.Plan(t, q)
+        # the largest budget that needs between 9 and 729 slices
+        p = None
+        for budget in range(int(plain.stats["max_rank"] * math.log2(q)), 0, -1):
+            c = kn.Plan(t, q, slice_log2_budget=budget, mem_budget_bytes=1, allow_budget=True)
+            if 9 <= c.stats["n_slices"] <= 729:
+                p = c
+                break
+        if p is None:
+            continue
+        st = p.stats
+        assert st["slice_chains"] == 1, st
+        # one set of descriptors per chain, whatever the slice count
+        assert st["image_bytes"] < 4 * plain.stats["image_bytes"] + 65536
+        img = image_model.Image(p.image())
+        assert int(img.h["n_knots"]) == 1
+        assert int(img.h["n_queue"]) == int(img.h["n_tasks"]) * st["n_slices"]
+        tg, m, e = oracle_z(d, q)
+        (zm, ze), = image_model.run(p.image())
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, q)
+        done += 1
+    assert done >= 3
