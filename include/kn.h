@@ -106,9 +106,18 @@ void kn_tait_free(kn_tait* g);
  *            2: variable elimination in min-fill order, each spin's holders
  *               contracted pairwise, smallest first;
  *            3: auto (default) -- plan 2; when it has at least 1e8 flops
- *               plan 0 is built too and the one with the smaller modelled
- *               time (per step max(flops/peak, bytes/HBM bandwidth) plus a
- *               fixed per-step latency) is kept;
+ *               plan 0 is built too, when it has at least 1e11 flops the
+ *               plans of strategy 4 too, and the one with the smallest
+ *               modelled time (per step max(flops/peak, bytes/HBM
+ *               bandwidth) plus a fixed per-step latency) is kept;
+ *            4: separator hierarchy (the paper's METIS alternative to the
+ *               greedy order): the spin graph is split recursively by small
+ *               vertex separators into parts of comparable size, and spins
+ *               are eliminated part by part, a separator after the parts it
+ *               splits (least fill first among spins of one level).
+ *               order_trials hierarchies (seeds, leaf sizes 8, 24, 64 in
+ *               turn; 0 = default 12) are built and the plan with the
+ *               smallest modelled time is kept;
  * precision  0: complex128 (FP64) tensors; 1: complex64 (FP32) tensors with
  *               FP32 accumulation, exponents and normalisation kept in
  *               int64 / FP64.
@@ -186,6 +195,8 @@ void kn_tait_free(kn_tait* g);
  *               of that bucket replaces the plan-wide value (tile_macs_log2,
  *               tile_outs_log2, gemm64_pct, gemm_tasks_log2).  The autotuner
  *               searches them per workload.
+ * order_trials  separator hierarchies tried by strategies 3 and 4 (0 =
+ *               default 12, at most 4096).
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -232,6 +243,7 @@ typedef struct {
   int32_t big_step_outs_log2;
   int32_t tile_outs_log2;
   kn_bucket_opts bucket[KN_N_BUCKETS];
+  int32_t order_trials;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

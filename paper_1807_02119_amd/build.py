@@ -27,7 +27,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkn.so")
 
-HOST_SOURCES = ["tait.cpp", "plan.cpp", "image.cpp", "jones.cpp", "runtime.cpp"]
+HOST_SOURCES = ["tait.cpp", "plan.cpp", "separator.cpp", "image.cpp", "jones.cpp", "runtime.cpp"]
 HIP_SOURCES = ["engine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

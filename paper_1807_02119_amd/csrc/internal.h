@@ -377,6 +377,13 @@ class HostBuf {
 
 int64_t elem_bytes(int32_t precision);
 
+// Nested-dissection ranks of the n spins of a graph (compressed rows off, nb;
+// symmetric, no self-loops): recursive vertex separators down to parts of at
+// most `leaf` spins, `trials` search roots per split, roots after the first
+// drawn from `seed`.  rank[v] = height of v's node in the hierarchy.
+void separator_ranks(int32_t n, const std::vector<int32_t>& off, const std::vector<int32_t>& nb,
+                     int32_t leaf, int32_t trials, uint64_t seed, std::vector<int32_t>& rank);
+
 }  // namespace kn
 
 struct kn_plan {

@@ -64,6 +64,13 @@ constexpr double kSplitBelow = 256;
 // this many flops (below it the greedy plan rarely wins and planning time
 // matters more).
 constexpr double kAutoGreedyFrom = 1e8;
+// ... and separator orders when it has at least this many flops.
+constexpr double kAutoSeparatorFrom = 1e11;
+// Separator orders: hierarchies tried (default), their leaf sizes in turn,
+// and search roots per split.
+constexpr int32_t kSeparatorTrials = 12;
+constexpr int32_t kSeparatorLeaf[3] = {8, 24, 64};
+constexpr int32_t kSeparatorCandidates = 6;
 // GEMM steps: tasks per step aimed at (log2) and most 32 x 32 blocks per task
 constexpr int32_t kGemmTasksLog2 = 5;
 constexpr int32_t kGemmMaxBlocks = 32;
@@ -77,6 +84,8 @@ constexpr int32_t kSplitSerialLog2 = 40;
 // (the device runs the slices of a chain one after another from one copy of
 // the knot's descriptors; the queue holds one slot per task and slice).
 constexpr int32_t kMaxSliceSpins = 24;
+// spins tried at each slicing step
+constexpr int32_t kSliceCandidates = 4;
 constexpr double kMaxSlices = 16777216;
 
 namespace {
@@ -546,7 +555,10 @@ struct Orderer {
   // Variable elimination in min-fill order on the primal graph of the tensors
   // (spins adjacent when some tensor holds both); eliminating a spin contracts
   // its holders pairwise, smallest first, and the last pair sums it.
-  void minfill() {
+  //
+  // With `rank` (one value per spin), spins are eliminated in increasing rank
+  // and by least fill inside a rank: the order of a separator hierarchy.
+  void minfill(const std::vector<int32_t>* rank = nullptr) {
     const int32_t W = (n + 63) / 64;
     std::vector<uint64_t> adj((size_t)n * W, 0);
     auto has = [&](int32_t a, int32_t b) { return (adj[(size_t)a * W + (b >> 6)] >> (b & 63)) & 1; };
@@ -588,14 +600,19 @@ struct Orderer {
     std::vector<uint32_t> tmark(n, 0);
     std::vector<uint64_t> xm(W, 0);  // N(x) + x as a bit set
     uint32_t ts = 0;
-    // next spin: least fill, then least degree, then lowest id (a linear scan
-    // over packed keys; the graphs have a few hundred spins)
-    // over the spins still in the graph, kept packed: key[slot[v]] is v's
+    // next spin: lowest rank, then least fill, then least degree, then
+    // lowest id (a linear scan over packed keys; the graphs have a few
+    // hundred spins) over the spins still in the graph, kept packed:
+    // key[slot[v]] is v's.  Fields: rank 10 bits, fill 22, degree 11, id 21
+    // (fill and degree saturate).
     std::vector<uint64_t> key(n);
     std::vector<int32_t> slot(n);
     int32_t live = n;
     auto pack = [&](int32_t v) {
-      key[slot[v]] = (uint64_t)fill[v] << 42 | (uint64_t)deg[v] << 21 | (uint64_t)v;
+      const uint64_t r = rank ? (uint64_t)std::min((*rank)[v], 1023) : 0;
+      const uint64_t f = (uint64_t)std::min(fill[v], (1 << 22) - 1);
+      const uint64_t d = (uint64_t)std::min(deg[v], (1 << 11) - 1);
+      key[slot[v]] = r << 54 | f << 32 | d << 21 | (uint64_t)v;
     };
     for (int32_t v = 0; v < n; ++v) {
       slot[v] = v;
@@ -682,6 +699,25 @@ struct Orderer {
       for (int32_t a : nv) pack(a);
       touched.clear();
     }
+  }
+
+  // Primal graph of the tensors (spins adjacent when some tensor holds
+  // both) in compressed rows.
+  void primal(std::vector<int32_t>& off, std::vector<int32_t>& nb) const {
+    std::vector<std::pair<int32_t, int32_t>> e;
+    for (const auto& t : T)
+      for (int32_t i = 0; i < t.spins.size(); ++i)
+        for (int32_t j = 0; j < t.spins.size(); ++j)
+          if (i != j) e.emplace_back(t.spins[i], t.spins[j]);
+    std::sort(e.begin(), e.end());
+    e.erase(std::unique(e.begin(), e.end()), e.end());
+    off.assign(n + 1, 0);
+    nb.resize(e.size());
+    for (size_t i = 0; i < e.size(); ++i) {
+      off[e[i].first + 1]++;
+      nb[i] = e[i].second;
+    }
+    for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
   }
 
   // 8 flops per complex multiply-add over all steps.
@@ -908,7 +944,7 @@ struct NetGraph {
 // Absorption of the edge matrices into vertex tensors and the pairwise order
 // (Sec. III): fills k.vtx, k.tensors, k.steps, k.comps; n_vt = vertex tensors.
 kn_status build_network(const NetGraph& G, int32_t q, const kn_plan_opts& o, PlanKnot& k,
-                        int32_t& n_vt) {
+                        int32_t& n_vt, double* model_time = nullptr) {
   const int32_t n = G.n;
   k.vtx.clear();
   k.tensors.clear();
@@ -1023,10 +1059,18 @@ kn_status build_network(const NetGraph& G, int32_t q, const kn_plan_opts& o, Pla
   }
   {
     // auto (3): min-fill first; the greedy plan is also built, and the cheaper
-    // kept, only when the min-fill plan's modelled compute is material
+    // kept, only when the min-fill plan's modelled compute is material, and
+    // separator orders too when it is large
     const int32_t strat = o.strategy;
     std::unique_ptr<Orderer> best;
     double best_cost = 0;
+    auto consider = [&](std::unique_ptr<Orderer> cand) {
+      const double c = cand->model_cost(o.precision, true);
+      if (!best || c < best_cost) {
+        best = std::move(cand);
+        best_cost = c;
+      }
+    };
     for (int32_t sgy : {2, 0, 1}) {
       if (strat != 3 && sgy != strat) continue;
       if (strat == 3 && sgy == 1) continue;
@@ -1034,12 +1078,23 @@ kn_status build_network(const NetGraph& G, int32_t q, const kn_plan_opts& o, Pla
       auto cand = std::make_unique<Orderer>(n, q, k.tensors);
       if (sgy == 2) cand->minfill();
       else cand->greedy(sgy);
-      double c = cand->model_cost(o.precision, true);
-      if (!best || c < best_cost) {
-        best = std::move(cand);
-        best_cost = c;
+      consider(std::move(cand));
+    }
+    if (strat == 4 || (strat == 3 && best->flops() >= kAutoSeparatorFrom)) {
+      // separator hierarchies from several seeds and leaf sizes, each
+      // eliminated in rank order (least fill inside a rank)
+      const int32_t trials = o.order_trials > 0 ? o.order_trials : kSeparatorTrials;
+      std::vector<int32_t> off, nb, rank;
+      Orderer(n, q, k.tensors).primal(off, nb);
+      for (int32_t t = 0; t < trials; ++t) {
+        separator_ranks(n, off, nb, kSeparatorLeaf[t % 3], kSeparatorCandidates,
+                        (uint64_t)t + 1, rank);
+        auto cand = std::make_unique<Orderer>(n, q, k.tensors);
+        cand->minfill(&rank);
+        consider(std::move(cand));
       }
     }
+    if (model_time) *model_time = best_cost;
     k.tensors = std::move(best->T);
     k.steps = std::move(best->S);
     for (int32_t t = 0; t < (int32_t)k.tensors.size(); ++t)
@@ -1346,16 +1401,45 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
       if (maxr * lq <= o.slice_log2_budget || (int32_t)sliced.size() >= kMaxSliceSpins ||
           slices > kMaxSlices || G.n == 0)
         break;
-      // fix the spin held by most of the largest tensors (ties: lowest id)
+      // candidates: the spins held by most of the largest tensors (ties:
+      // lowest id); each is tried, and the one whose plan has the smallest
+      // largest tensor, then the smallest modelled time over all slices, is
+      // fixed
       std::vector<int32_t> hits(G.n, 0);
       for (const auto& t : k.tensors)
         if ((int32_t)t.spins.size() >= maxr - 1)
           for (int32_t x : t.spins) hits[x]++;
-      int32_t best = 0;
-      for (int32_t v = 1; v < G.n; ++v)
-        if (hits[v] > hits[best]) best = v;
+      std::vector<int32_t> cand(G.n);
+      for (int32_t v = 0; v < G.n; ++v) cand[v] = v;
+      const int32_t n_cand = std::min<int32_t>(G.n, kSliceCandidates);
+      std::partial_sort(cand.begin(), cand.begin() + n_cand, cand.end(),
+                        [&](int32_t a, int32_t b) {
+                          return hits[a] != hits[b] ? hits[a] > hits[b] : a < b;
+                        });
+      int32_t pick = -1, pick_rank = 0;
+      double pick_cost = 0;
+      for (int32_t c = 0; c < n_cand && n_cand > 1; ++c) {
+        std::vector<int32_t> trial = sliced, tid;
+        std::vector<Factor> tpairs;
+        for (int32_t v = 0; v < s.n_spins; ++v)
+          if (new_id[v] == cand[c]) trial.push_back(v);
+        NetGraph TG = sliced_graph(s, trial, tid, tpairs);
+        PlanKnot tk;
+        int32_t t_vt = 0;
+        double cost = 0;
+        if (build_network(TG, q, o, tk, t_vt, &cost) != KN_OK) continue;
+        int32_t r = 0;
+        for (const auto& t : tk.tensors) r = std::max(r, (int32_t)t.spins.size());
+        cost *= slices;
+        if (pick < 0 || r < pick_rank || (r == pick_rank && cost < pick_cost)) {
+          pick = cand[c];
+          pick_rank = r;
+          pick_cost = cost;
+        }
+      }
+      if (pick < 0) pick = cand[0];
       for (int32_t v = 0; v < s.n_spins; ++v)
-        if (new_id[v] == best) sliced.push_back(v);
+        if (new_id[v] == pick) sliced.push_back(v);
     }
     k.n_slice_spins = (int32_t)sliced.size();
     k.n_slices = 1;
@@ -1423,7 +1507,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (!g) return KN_E_INVALID;
   if (q < 2 || q > 8) return KN_E_UNSUPPORTED;
   kn_plan_opts o = opts ? *opts : default_opts();
-  if (o.strategy < 0 || o.strategy > 3 || o.precision < 0 || o.precision > 1 ||
+  if (o.strategy < 0 || o.strategy > 4 || o.order_trials < 0 || o.order_trials > 4096 || o.precision < 0 || o.precision > 1 ||
       o.simplify < 0 || o.simplify > 7 || o.tile_outputs < 0 || o.big_step_macs_log2 < 0 ||
       o.big_step_macs_log2 > 40 || o.lds_bytes < 0 || o.lds_bytes > 98304 ||
       o.tile_macs_log2 < 0 || o.tile_macs_log2 > 30)

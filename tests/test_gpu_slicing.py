@@ -122,3 +122,43 @@ def test_long_slice_loops(k, q, budget):
              f"{p.stats['slice_chains']} chains")
         m, e = _z(p)
         assert rel_err(m * 2.0 ** (e - eo), mo) <= 1e-10, (d.n, q, mem)
+
+
+# Paper-model grid-walk knots (Sec. III.A) of 521-574 crossings, too wide for
+# one tensor of at most 2^31 entries at q = 3 under the min-fill order: the
+# seed and walk size of each, and two plans with different orders and
+# slicings (strategy, log2 budget of the largest tensor).
+WIDE_Q3 = [(74, 80, (3, 26), (2, 26)), (72, 75, (3, 26), (2, 24)),
+           (71, 72, (3, 26), (2, 24)), (70, 70, (3, 26), (3, 24))]
+
+
+@pytest.mark.parametrize("seed,size,pa,pb", WIDE_Q3)
+def test_sliced_q3_paper_model_500_600(seed, size, pa, pb):
+    """Two sliced plans of one knot (different orders, spins fixed and slice
+    counts) agree to 1e-10, and |V| and the phase class of V(e^{i pi/3}) equal
+    the Lickorish-Millett value."""
+    import time
+    d = gen.random_grid_diagram(np.random.default_rng(seed), size)
+    assert 500 <= d.n <= 600
+    t = kn.Tait(d.pd)
+    vals = []
+    for strategy, budget in (pa, pb):
+        t0 = time.perf_counter()
+        p = kn.Plan(t, 3, strategy=strategy, slice_log2_budget=budget)
+        t1 = time.perf_counter()
+        assert p.stats["log2_max_entries"] <= budget + 1e-9
+        m, e = _z(p)
+        t2 = time.perf_counter()
+        _log(f"q=3 n={d.n} strategy {strategy} budget {budget}: {p.stats['n_slices']} slices, "
+             f"{p.stats['slice_chains']} chains, {p.stats['flops']:.3g} flop, "
+             f"plan {t1 - t0:.2f} s, contract {t2 - t1:.2f} s "
+             f"({p.stats['flops'] / (t2 - t1) / 1e12:.1f} TFLOP/s)")
+        vals.append((m, e))
+    (ma, ea), (mb, eb) = vals
+    assert rel_err(ma * 2.0 ** (ea - eb), mb) <= 1e-10
+    tg = oracle_tait(d)
+    v, l2, ar = kn.jones(3, t, ma, ea)
+    dd, unit = invariants.q3_class(tg.n_vertices, tg.edges, tg.eps)
+    assert abs(l2 - dd * math.log2(3) / 2) < 1e-9
+    ratio = complex(math.cos(ar), math.sin(ar)) / unit
+    assert min(abs(ratio - 1), abs(ratio + 1)) < 1e-9

@@ -142,6 +142,7 @@ def test_plan_model_tiled_and_options():
                    dict(simplify=1, jones_only=True),
                    dict(simplify=1, jones_only=False),
                    dict(strategy=0), dict(strategy=1), dict(strategy=2),
+                   dict(strategy=4, order_trials=3),
                    dict(lds_bytes=512), dict(lds_bytes=98304), dict(precision=1),
                    dict(split_serial_log2=3), dict(split_serial_log2=40),
                    dict(big_step_macs_log2=4, gemm_tasks_log2=1),
@@ -468,6 +469,48 @@ def test_sliced_batch_and_couplings():
         x = np.exp(J[2 * off:2 * (off + t.n_edges):2] + 1j * J[2 * off + 1:2 * (off + t.n_edges):2])
         m, e = potts.partition_function(t.n_vertices, [tuple(a) for a in uv], x, 3)
         assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+
+
+def test_separator_order_matches_oracle():
+    """Separator-hierarchy orders (strategy 4, several hierarchies), also
+    sliced, through the CPU model of the device program against the oracle."""
+    rng = np.random.default_rng(91)
+    cases = [gen.lattice_knot((90, k), 40, 140) for k in range(4)]
+    cases += [gen.random_grid_diagram(rng, 16), gen.trefoil()]
+    sliced = 0
+    for d in cases:
+        t = kn.Tait(d.pd, d.signs if d.n == 1 else None)
+        for q in (2, 3):
+            tg, m, e = oracle_z(d, q)
+            # a slicing budget one spin below the width
+            r = kn.Plan(t, q, strategy=4).stats["max_rank"]
+            budget = max(1, math.floor((r - 1) * math.log2(q)))
+            for kw in (dict(strategy=4), dict(strategy=4, order_trials=1),
+                       dict(strategy=4, slice_log2_budget=budget)):
+                p = kn.Plan(t, q, **kw)
+                if p.stats["n_slices"] > 729:  # the CPU model runs slices one by one
+                    continue
+                sliced += p.stats["n_slices"] > 1
+                (zm, ze), = image_model.run(p.image())
+                assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, q, kw)
+    assert sliced >= 4
+
+
+def test_separator_order_wins_on_large_grid_knots():
+    """On paper-model grid-walk knots of about 900 crossings the separator
+    hierarchy needs far less work than the greedy and min-fill orders (the
+    paper finds the METIS order ahead of greedy from about 900 crossings),
+    and the auto strategy takes it."""
+    for seed, size in ((77, 95), (76, 90)):
+        d = gen.random_grid_diagram(np.random.default_rng(seed), size)
+        assert d.n > 900
+        t = kn.Tait(d.pd)
+        f = {s: kn.Plan(t, 2, strategy=s, allow_budget=True).stats for s in (0, 2, 3, 4)}
+        sep = f[4]["flops"]
+        assert sep > 0
+        for s in (0, 2):  # a failed plan (a tensor over 2^31 entries) reports 0 flops
+            assert f[s]["flops"] == 0 or sep < 0.5 * f[s]["flops"], (seed, s, f[s]["flops"], sep)
+        assert f[3]["max_rank"] <= f[4]["max_rank"] + 1
 
 
 def test_slicing_makes_wide_knots_fit():
