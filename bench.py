@@ -86,7 +86,7 @@ def parse():
 
 
 # the sources the contraction kernel is compiled from
-KERNEL_SOURCES = ("engine.hip", "program.h", "decode.h")
+KERNEL_SOURCES = ("engine.hip", "program.h", "decode.h", "checks.h")
 
 
 def source_hash():
@@ -240,6 +240,33 @@ def main():
                          "log2_max_entries": p_.stats["log2_max_entries"]}
             leg[name]["frac_of_peak"] = leg[name]["tflops"] / (FP64_PEAK_TFLOPS if prec == 0
                                                                  else FP32_PEAK_TFLOPS)
+        # grid-walk knots of 521-574 crossings at q = 3, too wide for one
+        # tensor of at most 2^31 entries: sliced (largest tensor <= 2^26
+        # entries), auto order, slices as device-side loops over chains
+        leg["sliced_q3_500_600"] = []
+        for seed_, size_ in ((74, 80), (72, 75), (71, 72), (70, 70)):
+            d_ = gen.random_grid_diagram(np.random.default_rng(seed_), size_)
+            t0_ = time.perf_counter()
+            p_ = kn.Plan(kn.Tait(d_.pd), 3, slice_log2_budget=26)
+            plan_s = time.perf_counter() - t0_
+            ws_ = kn.alloc_workspace(p_.workspace_bytes)
+            z_ = kn.alloc_scalars(1)
+            kn.contract(p_, workspace=ws_, stream=st_, z=z_)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st_)
+            for _ in range(2):
+                kn.contract(p_, workspace=ws_, stream=st_, z=z_)
+            e1.record(st_)
+            torch.cuda.synchronize()
+            ms_ = e0.elapsed_time(e1) / 2
+            leg["sliced_q3_500_600"].append({
+                "crossings": d_.n, "seed": seed_, "walk": size_, "slices": p_.stats["n_slices"],
+                "chains": p_.stats["slice_chains"], "gflop": p_.stats["flops"] / 1e9,
+                "plan_s": plan_s, "ms": ms_, "tflops": p_.stats["flops"] / (ms_ * 1e-3) / 1e12,
+                "log2_max_entries": p_.stats["log2_max_entries"]})
+            del ws_
         return leg
 
     if args.wide_only:

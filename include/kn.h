@@ -325,6 +325,33 @@ kn_status kn_contract(const kn_plan* p, const double* J, void* workspace,
 #define KN_NOALLOC_MAX_BYTES ((size_t)64 << 20)
 kn_status kn_contract_noalloc(const kn_plan* p, const double* J, void* stream, kn_scalar* z_dev);
 
+/* ------------------------------------------------------------------ checking
+ * Error state of the last launch in a workspace (of a plan or a batch):
+ * status[0] the first error code, status[1] the task, status[2] the step,
+ * status[3] a detail (-1 where it does not apply).  Codes:
+ *   0 none
+ *   1 a ready-queue slot stayed empty past the engine's time limit (20 s):
+ *     the launch gave up, unfinished knots read NaN
+ *   checking build only (kn_device_checks() == 1), the task was skipped:
+ *   2 a task record out of range (kind, knot, group, steps, tile id)
+ *   3 a tensor outside the global or the LDS arena
+ *   4 spin-group extents disagree with their ranks or outputs with C's size
+ *   5 the largest offset a gather can form leaves its operand
+ *   6 a serial step's gather tables exceed the LDS table buffer
+ *   7 the guard zone after the arena (the last 4 KiB of every workspace) was
+ *     overwritten; status[3] is the first word found changed
+ * The call waits for `stream` and copies the error words to the host
+ * (synchronous).  workspace: the device workspace of a finished launch. */
+kn_status kn_workspace_status(const void* workspace, void* stream, int32_t* status);
+/* 1 when this library is the checking build (every task checked on the device
+ * before it runs, the guard zone checked after each launch), else 0. */
+int32_t kn_device_checks(void);
+/* The same checks on the host over a device image (kn_plan_image or
+ * kn_batch_image bytes, 8-byte aligned): every section inside the image and
+ * every task and step consistent.  status as in kn_workspace_status (0 = the
+ * image passes).  KN_E_INVALID when the header itself is unusable. */
+kn_status kn_image_check(const void* image, size_t bytes, int32_t* status);
+
 /* d log Z / d J_e (holomorphic derivative, dT_e/dJ_e = e^{J_e} delta) for
  * every ORIGINAL edge, written to grad_dev (device, 2*n_edges doubles, re/im
  * interleaved, edge order of kn_tait_edges).  One launch runs the forward

@@ -2,10 +2,16 @@
 
     python -m paper_1807_02119_amd.build            # libkn.so
     python -m paper_1807_02119_amd.build --sanitize # _build/san/libkn_san.so
+    python -m paper_1807_02119_amd.build --checked  # libkn_checked.so
 
 Host sources are compiled with g++, the HIP source with hipcc for gfx950
 (packed-FP32 instruction selection disabled), and everything is linked by
 hipcc into ``paper_1807_02119_amd/libkn.so``.  Always recompiles.
+
+``--checked`` builds ``paper_1807_02119_amd/libkn_checked.so``: the engine with
+device checks (KN_DEVICE_CHECKS: every task and its steps checked before they
+run, a failing task skipped and reported, the guard zone after the arena
+checked after each launch); load it with KN_LIBRARY=<path>.
 
 ``--sanitize`` builds a checking variant for the CPU tests: the host
 sources with AddressSanitizer and UndefinedBehaviorSanitizer (g++), the
@@ -48,17 +54,17 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def _build_lib(out_dir, lib, hip_defines=(), verbose=False) -> str:
+    os.makedirs(out_dir, exist_ok=True)
     jobs = []
     objs = []
     for s in HOST_SOURCES:
-        o = os.path.join(BUILD, s.replace(".cpp", ".o"))
+        o = os.path.join(out_dir, s.replace(".cpp", ".o"))
         jobs.append([CXX, *HOST_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in HIP_SOURCES:
-        o = os.path.join(BUILD, s.replace(".hip", ".o"))
-        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+        o = os.path.join(out_dir, s.replace(".hip", ".o"))
+        jobs.append([HIPCC, *HIP_FLAGS, *hip_defines, "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
@@ -66,10 +72,24 @@ def build(verbose: bool = False) -> str:
         for o in outs:
             if o.strip():
                 print(o)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    return _build_lib(BUILD, LIB, verbose=verbose)
+
+
+CHECKED_DIR = os.path.join(BUILD, "checked")
+CHECKED_LIB = os.path.join(PKG, "libkn_checked.so")
+
+
+def build_checked(verbose: bool = False) -> str:
+    """libkn with the engine's device checks (KN_DEVICE_CHECKS)."""
+    return _build_lib(CHECKED_DIR, CHECKED_LIB, hip_defines=("-DKN_DEVICE_CHECKS",),
+                      verbose=verbose)
 
 
 SAN_DIR = os.path.join(BUILD, "san")
@@ -125,5 +145,7 @@ def clean():
 if __name__ == "__main__":
     if "--sanitize" in sys.argv:
         print(build_sanitized(verbose="-v" in sys.argv))
+    elif "--checked" in sys.argv:
+        print(build_checked(verbose="-v" in sys.argv))
     else:
         print(build(verbose="-v" in sys.argv))

@@ -42,6 +42,7 @@
 #include <algorithm>
 #include <new>
 
+#include "checks.h"
 #include "decode.h"
 #include "internal.h"
 
@@ -1290,6 +1291,83 @@ __global__ __launch_bounds__(kBlock) void gradient_kernel(const uint8_t* __restr
   knot_gradient<T>(p, kd, arena, grad);
 }
 
+// The checking build (KN_DEVICE_CHECKS) checks each task and its steps just
+// before running it (checks.h) and skips a task that fails; it also fills the
+// guard zone after the arena before a launch and checks it after.
+#ifdef KN_DEVICE_CHECKS
+constexpr bool kChecks = true;
+#else
+constexpr bool kChecks = false;
+#endif
+
+// Record an error: the first code wins, with the task, step and detail.
+__device__ inline void report(const DevProg& p, int32_t code, int32_t task, int32_t step,
+                              int32_t info) {
+  int32_t expect = 0;
+  if (__hip_atomic_compare_exchange_strong(&p.ctrl[CTRL_ERROR], &expect, code, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    __hip_atomic_store(&p.ctrl[CTRL_ERR_TASK], task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p.ctrl[CTRL_ERR_STEP], step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p.ctrl[CTRL_ERR_INFO], info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Checks of task ti before it runs (whole workgroup): thread 0 checks the
+// record, then the threads share out its steps; the lowest failing step is
+// reported.  True when the task may run.
+template <class T>
+__device__ bool task_ok(const DevProg& p, int32_t ti, int32_t* s_code, int32_t* s_step) {
+  const ImageView v{p.h, p.tasks, p.groups, p.knots, p.tens, p.steps, p.vtx, p.strides, p.comps};
+  const int64_t lds_elems = p.h->lds_bytes / (int64_t)sizeof(Cx<T>);
+  if (threadIdx.x == 0) {
+    *s_code = task_record_check(v, ti, lds_elems);
+    *s_step = INT32_MAX;
+  }
+  __syncthreads();
+  if (*s_code != CHK_OK) {
+    if (threadIdx.x == 0) report(p, *s_code, ti, -1, 0);
+    __syncthreads();
+    return false;
+  }
+  const TaskDesc td = p.tasks[ti];
+  const int32_t q = p.knots[td.knot].q;
+  const int32_t n = td.kind == TASK_SERIAL ? td.count : 1;
+  for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+    const StepDesc& d = p.steps[td.first + i];
+    int32_t rc = step_check(d, p.tens, p.h->n_tensors, p.strides, p.h->n_strides, q,
+                            p.h->arena_elems, lds_elems);
+    if (td.kind == TASK_SERIAL && d.mode != STEP_SERIAL) rc = CHK_TASK;
+    if (rc != CHK_OK) atomicMin(s_step, td.first + i);
+  }
+  __syncthreads();
+  const int32_t bad = *s_step;
+  if (bad != INT32_MAX && threadIdx.x == 0) {
+    const StepDesc& d = p.steps[bad];
+    int32_t rc = step_check(d, p.tens, p.h->n_tensors, p.strides, p.h->n_strides, q,
+                            p.h->arena_elems, lds_elems);
+    if (rc == CHK_OK) rc = CHK_TASK;
+    report(p, rc, ti, bad, 0);
+  }
+  __syncthreads();
+  return bad == INT32_MAX;
+}
+
+// Guard zone after the arena: filled before a launch, checked after it.
+__global__ void fill_guard(uint8_t* __restrict__ ws) {
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(ws);
+  uint32_t* g = reinterpret_cast<uint32_t*>(ws + h.guard_off);
+  for (int32_t i = threadIdx.x; i < (int32_t)(kGuardBytes / 4); i += blockDim.x) g[i] = kGuardWord;
+}
+
+__global__ void check_guard(const uint8_t* __restrict__ ws, uint8_t* __restrict__ state) {
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(ws);
+  const uint32_t* g = reinterpret_cast<const uint32_t*>(ws + h.guard_off);
+  DevProg p;
+  p.ctrl = reinterpret_cast<int32_t*>(state);
+  for (int32_t i = threadIdx.x; i < (int32_t)(kGuardBytes / 4); i += blockDim.x)
+    if (g[i] != kGuardWord) report(p, CHK_GUARD, -1, -1, i);
+}
+
 // Bound on the wait for a queue slot, in ticks of the 100 MHz device clock
 // (20 s, far beyond any launch's critical path): a slot that is never filled
 // (a planner bug) ends the kernel with the error flag set instead of hanging
@@ -1310,6 +1388,7 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
   __shared__ T s_red[kBlock / 64];
   __shared__ int32_t s_tb[kDescBuf + 1];
   __shared__ int64_t s_ph[4];
+  __shared__ int32_t s_chk[2];
   int32_t* s_tab = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsTab);
   StepDesc* s_desc = reinterpret_cast<StepDesc*>(kn_dyn_smem + kLdsDesc);
   int32_t* s_shift = reinterpret_cast<int32_t*>(kn_dyn_smem + kLdsShift);
@@ -1335,9 +1414,13 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
             ++nap;
           } else {
             __builtin_amdgcn_s_sleep(8);
+            // after an error the slot may never be filled: give up at once
+            if (__hip_atomic_load(&p.ctrl[CTRL_ERROR], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) != 0)
+              break;
           }
           if (wall_clock64() - t_wait > kWaitTicks) {
-            __hip_atomic_store(&p.ctrl[CTRL_ERROR], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            report(p, CHK_QUEUE_WAIT, -1, -1, slot);
             break;
           }
         }
@@ -1353,7 +1436,12 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
     const TaskDesc td = p.tasks[ti];
     // a sliced unit that starts its next slice after this task (its final task)
     int32_t next_slice = -1;
-    if (td.kind == TASK_SERIAL) {
+    // the checking build skips a task that fails its checks and only
+    // publishes it, so the launch still drains
+    const bool run = !kChecks || task_ok<T>(p, ti, &s_chk[0], &s_chk[1]);
+    if (!run) {
+      // skipped: it writes nothing, and its knot's result stays NaN
+    } else if (td.kind == TASK_SERIAL) {
       const KnotDesc kd = p.knots[td.knot];
       const int32_t slice = p.uslice[td.knot];
       const States st{p.ts, s_shift, s_exp, td.state_lo, min(td.state_len, kStateCap)};
@@ -1557,8 +1645,17 @@ kn_status launch(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* 
   hipLaunchKernelGGL(clear_state, dim3((unsigned)((n_clear + 255) / 256)), dim3(256), 0, st, ws,
                      ws + h.state_off, z);
   if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
-  if (h.precision == 1) return launch_engine<float>(h, ws, st, J, z, grad, grid_override, trace);
-  return launch_engine<double>(h, ws, st, J, z, grad, grid_override, trace);
+  if (kChecks) {
+    hipLaunchKernelGGL(fill_guard, dim3(1), dim3(256), 0, st, ws);
+    if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
+  }
+  const kn_status rc = h.precision == 1
+                           ? launch_engine<float>(h, ws, st, J, z, grad, grid_override, trace)
+                           : launch_engine<double>(h, ws, st, J, z, grad, grid_override, trace);
+  if (rc != KN_OK || !kChecks) return rc;
+  hipLaunchKernelGGL(check_guard, dim3(1), dim3(256), 0, st, ws, ws + h.state_off);
+  if (hipGetLastError() != hipSuccess) return KN_E_DEVICE;
+  return KN_OK;
 }
 
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
@@ -1779,4 +1876,28 @@ extern "C" kn_status kn_contract_backward(const kn_plan* p, const double* J, voi
   if (!p || !grad_dev) return KN_E_INVALID;
   if (!p->k.gradient) return KN_E_UNSUPPORTED;
   return contract_plan(p, J, workspace, workspace_bytes, stream, z_dev, grad_dev);
+}
+
+// ------------------------------------------------------------------ status
+
+extern "C" int32_t kn_device_checks(void) { return kChecks ? 1 : 0; }
+
+extern "C" kn_status kn_workspace_status(const void* workspace, void* stream, int32_t* status) {
+  if (!workspace || !status) return KN_E_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  ImgHeader h;
+  int32_t w[CTRL_ERR_INFO + 1];
+  if (hipMemcpyAsync(&h, workspace, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return KN_E_DEVICE;
+  if (h.magic != kMagic) return KN_E_INVALID;
+  if (hipMemcpyAsync(w, reinterpret_cast<const uint8_t*>(workspace) + h.state_off, sizeof(w),
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return KN_E_DEVICE;
+  status[0] = w[CTRL_ERROR];
+  status[1] = w[CTRL_ERR_TASK];
+  status[2] = w[CTRL_ERR_STEP];
+  status[3] = w[CTRL_ERR_INFO];
+  return KN_OK;
 }

@@ -26,6 +26,7 @@
 #include <numeric>
 #include <thread>
 
+#include "checks.h"
 #include "internal.h"
 
 namespace kn {
@@ -526,7 +527,8 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
   h.arena_off = align256(h.state_off + h.state_bytes);
   h.arena_elems = std::max<int64_t>(arena, 16);
   if (h.arena_elems > INT32_MAX) return -1;  // step homes hold int32 offsets
-  h.workspace_bytes = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
+  h.guard_off = align256(h.arena_off + h.arena_elems * elem_bytes(h.precision));
+  h.workspace_bytes = h.guard_off + kGuardBytes;
   if (header) *header = h;
   uint8_t* base = buffer ? buffer((size_t)h.image_bytes) : nullptr;
   if (!base) return buffer ? -2 : h.image_bytes;  // -2: no memory; header only
@@ -694,3 +696,75 @@ Bytes build_image(const std::vector<const PlanKnot*>& knots, bool header_only) {
 }
 
 }  // namespace kn
+
+// ------------------------------------------------------------------ validation
+
+extern "C" kn_status kn_image_check(const void* image, size_t bytes, int32_t* status) {
+  using namespace kn;
+  if (!image || !status || bytes < sizeof(ImgHeader) ||
+      (reinterpret_cast<uintptr_t>(image) & 7) != 0)
+    return KN_E_INVALID;
+  const uint8_t* img = reinterpret_cast<const uint8_t*>(image);
+  const ImgHeader& h = *reinterpret_cast<const ImgHeader*>(img);
+  if (h.magic != kMagic || h.image_bytes < (int64_t)sizeof(ImgHeader) ||
+      (uint64_t)h.image_bytes > bytes)
+    return KN_E_INVALID;
+  status[0] = CHK_OK;
+  status[1] = status[2] = -1;
+  status[3] = 0;
+  // every section inside the image (info: the section's number)
+  const struct {
+    int64_t off, n, size;
+  } sec[] = {{h.o_tasks, h.n_tasks, sizeof(TaskDesc)},     {h.o_groups, h.n_groups, sizeof(GroupDesc)},
+             {h.o_knots, h.n_knots, sizeof(KnotDesc)},     {h.o_tensors, h.n_tensors, sizeof(TensorDesc)},
+             {h.o_steps, h.n_steps, sizeof(StepDesc)},     {h.o_vtx, h.n_vtx, sizeof(VtxDesc)},
+             {h.o_strides, h.n_strides, sizeof(int32_t)}, {h.o_roots, h.n_roots, sizeof(int32_t)}};
+  for (int32_t i = 0; i < (int32_t)(sizeof(sec) / sizeof(sec[0])); ++i)
+    if (sec[i].n < 0 || !range_in(sec[i].off, sec[i].n * sec[i].size, h.image_bytes) ||
+        (sec[i].off & 3) != 0) {
+      status[0] = CHK_TASK;
+      status[3] = i;
+      return KN_OK;
+    }
+  {  // the component list, whose length the knot records give
+    const KnotDesc* kds = reinterpret_cast<const KnotDesc*>(img + h.o_knots);
+    int64_t end = 0;
+    for (int32_t i = 0; i < h.n_knots; ++i) {
+      if (kds[i].comp_off < 0 || kds[i].n_comps < 0) {
+        status[0] = CHK_TASK;
+        return KN_OK;
+      }
+      end = std::max<int64_t>(end, (int64_t)kds[i].comp_off + kds[i].n_comps);
+    }
+    if (!range_in(h.o_comps, end * 4, h.image_bytes)) {
+      status[0] = CHK_TASK;
+      return KN_OK;
+    }
+  }
+  if (h.arena_elems < 0 || h.guard_off < h.arena_off + h.arena_elems * elem_bytes(h.precision) ||
+      h.workspace_bytes < h.guard_off + kGuardBytes) {
+    status[0] = CHK_EXTENT;
+    return KN_OK;
+  }
+  const ImageView v{&h,
+                    reinterpret_cast<const TaskDesc*>(img + h.o_tasks),
+                    reinterpret_cast<const GroupDesc*>(img + h.o_groups),
+                    reinterpret_cast<const KnotDesc*>(img + h.o_knots),
+                    reinterpret_cast<const TensorDesc*>(img + h.o_tensors),
+                    reinterpret_cast<const StepDesc*>(img + h.o_steps),
+                    reinterpret_cast<const VtxDesc*>(img + h.o_vtx),
+                    reinterpret_cast<const int32_t*>(img + h.o_strides),
+                    reinterpret_cast<const int32_t*>(img + h.o_comps)};
+  const int64_t lds_elems = h.lds_bytes / elem_bytes(h.precision);
+  for (int32_t t = 0; t < h.n_tasks; ++t) {
+    int32_t bad = -1;
+    const int32_t rc = task_check(v, t, lds_elems, &bad);
+    if (rc != CHK_OK) {
+      status[0] = rc;
+      status[1] = t;
+      status[2] = bad;
+      return KN_OK;
+    }
+  }
+  return KN_OK;
+}

@@ -89,6 +89,7 @@ struct ImgHeader {
   // tensor arena (relative to the workspace base), in complex entries
   int64_t arena_off, arena_elems;
   int64_t workspace_bytes;
+  int64_t guard_off;  // guard zone after the arena (relative to the workspace base)
 };
 
 struct TaskDesc {
@@ -228,7 +229,16 @@ constexpr int32_t kLdsExt = (kLdsExp + kStateCap * 8 + 15) / 16 * 16;  // operan
 constexpr int32_t kLdsArena = kLdsExt + 2 * kDescBuf * (int32_t)sizeof(TensorState);
 
 // control words at the start of the runtime state
-enum Ctrl : int32_t { CTRL_HEAD = 0, CTRL_TAIL = 1, CTRL_ERROR = 2, CTRL_WORDS = 64 };
+// (CTRL_ERROR: first error code, CTRL_ERR_*: the task, step and detail of it)
+enum Ctrl : int32_t {
+  CTRL_HEAD = 0,
+  CTRL_TAIL = 1,
+  CTRL_ERROR = 2,
+  CTRL_ERR_TASK = 3,
+  CTRL_ERR_STEP = 4,
+  CTRL_ERR_INFO = 5,
+  CTRL_WORDS = 64
+};
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 

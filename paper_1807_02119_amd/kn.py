@@ -148,6 +148,9 @@ _SIGS = {
     "kn_plan_many": (I32, [I32, PI32, PI32, PI8, PI32, ctypes.POINTER(PlanOpts), I32,
                            ctypes.POINTER(P), ctypes.POINTER(P), PI32]),
     "kn_jones_many": (I32, [I32, PI32, ctypes.POINTER(P), ctypes.POINTER(Scalar), PD, PD, PD]),
+    "kn_workspace_status": (I32, [P, P, PI32]),
+    "kn_device_checks": (I32, []),
+    "kn_image_check": (I32, [P, ctypes.c_size_t, PI32]),
     "kn_status_string": (ctypes.c_char_p, [I32]),
     "kn_version": (ctypes.c_char_p, []),
 }
@@ -510,6 +513,38 @@ def contract_noalloc(plan: Plan, J=None, stream=None, z=None):
     rc = lib().kn_contract_noalloc(plan._h, jp, _stream_ptr(stream), _scalars(z, 1))
     _check(rc, "kn_contract_noalloc")
     return z
+
+
+CHECK_CODES = {0: "ok", 1: "queue wait time limit", 2: "task record", 3: "tensor extent",
+               4: "group shape", 5: "gather bound", 6: "table buffer", 7: "guard zone"}
+
+
+def workspace_status(workspace, stream=None):
+    """Error words of the last launch in a workspace tensor
+    (kn_workspace_status): dict(code, name, task, step, info); code 0 = none."""
+    ptr, _ = _workspace(workspace)
+    st = (ctypes.c_int32 * 4)()
+    _check(lib().kn_workspace_status(ctypes.c_void_p(ptr), _stream_ptr(stream), st),
+           "kn_workspace_status")
+    return dict(code=st[0], name=CHECK_CODES.get(st[0], str(st[0])), task=st[1], step=st[2],
+                info=st[3])
+
+
+def device_checks() -> bool:
+    """True when the loaded library is the checking build."""
+    return bool(lib().kn_device_checks())
+
+
+def image_check(image: bytes):
+    """Host validation of a device image (kn_image_check): the same dict as
+    workspace_status (code 0 = the image passes)."""
+    buf = np.frombuffer(image, dtype=np.uint8)
+    al = np.empty((len(buf) + 15) // 8, dtype=np.int64)  # 8-byte aligned copy
+    al.view(np.uint8)[:len(buf)] = buf
+    st = (ctypes.c_int32 * 4)()
+    _check(lib().kn_image_check(ctypes.c_void_p(al.ctypes.data), len(buf), st), "kn_image_check")
+    return dict(code=st[0], name=CHECK_CODES.get(st[0], str(st[0])), task=st[1], step=st[2],
+                info=st[3])
 
 
 def backward_workspace_bytes(plan: Plan) -> int:

@@ -53,7 +53,7 @@ def per_dispatch(directory, counter, name_filter):
 
 def source_hash(root):
     h = hashlib.sha256()
-    for f in ("engine.hip", "program.h", "decode.h"):
+    for f in ("engine.hip", "program.h", "decode.h", "checks.h"):
         with open(os.path.join(root, "paper_1807_02119_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -34,7 +34,7 @@ HDR = np.dtype([
     ("o_weights", "<i8"), ("o_mgrad", "<i8"), ("o_zslice", "<i8"), ("o_uslice", "<i8"),
     ("arena_off", "<i8"),
     ("arena_elems", "<i8"),
-    ("workspace_bytes", "<i8")], align=True)
+    ("workspace_bytes", "<i8"), ("guard_off", "<i8")], align=True)
 TASK = np.dtype([(f, "<i4") for f in ("kind", "knot", "group", "first", "count", "flags",
                                       "state_lo", "state_len")], align=True)
 GROUP = np.dtype([(f, "<i4") for f in ("knot", "first_task", "n_tasks", "next", "n_pred")],
