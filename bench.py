@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=256, help="knots per step")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0, help="host planning threads (0 = all)")
-    ap.add_argument("--strategy", type=int, default=2, choices=(0, 1, 2, 3),
+    ap.add_argument("--strategy", type=int, default=2, choices=(0, 1, 2, 3, 4),
                     help="contraction-order strategy of the planner (kn_plan_opts.strategy); "
                          "default min-fill only: the pipeline is bound by host planning, and "
                          "the greedy alternative that auto also builds for the heaviest knots "
@@ -281,17 +281,18 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---------------------------------------------------------------- pipeline
-    # Two threads.  A helper prepares batches i+1 .. i+prefetch back to back
-    # (Tait graphs and plans on the library's thread pool, the batch device
-    # program, its upload on a side stream into one of prefetch + 1 workspaces
-    # in turn) while
-    # the launch thread contracts batch i and, while the GPU runs it, forms
-    # V = A Z of batch i - 1 and releases that batch.  The library calls
-    # release the GIL.
+    # Three threads.  Two helper stages prepare batches i+1 .. i+prefetch: the
+    # planner makes their Tait graphs and plans on the library's thread pool,
+    # the builder their batch device programs and uploads on a side stream
+    # into one of prefetch + 1 workspaces in turn (batch j's program is built
+    # while the planner works on batch j + 1).  Meanwhile the launch thread
+    # contracts batch i and, while the GPU runs it, forms V = A Z of batch
+    # i - 1 and releases that batch.  The library calls release the GIL.
     state = {}
     # the threads hand the interpreter lock to each other often: switch fast
     sys.setswitchinterval(1e-4)
-    pool = ThreadPoolExecutor(max_workers=1)
+    pool = ThreadPoolExecutor(max_workers=1)     # builder: device programs, uploads, releases
+    planner = ThreadPoolExecutor(max_workers=1)  # planner: plan sets (library thread pool)
     up_stream = torch.cuda.Stream()
 
     # knob settings recorded by the autotuner for this workload (plan options
@@ -310,12 +311,20 @@ def main():
             state[("ws", precision, slot)] = ws
         return ws
 
-    def prepare(precision=0):
+    def plan_stage(precision=0):
         tp = time.perf_counter()
         opts = {k: v for k, v in tuned[precision].items() if k != "grid"}
         opts["strategy"] = args.strategy
         plans = kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, precision=precision,
                             **opts)
+        phase["plan"] += time.perf_counter() - tp
+        return plans
+
+    def prepare(precision=0, planned=None):
+        """Plans (or the plan stage's future), then the batch device program
+        and its upload."""
+        tp = time.perf_counter()
+        plans = plan_stage(precision) if planned is None else planned.result()
         taits = plans  # the set holds the Tait graphs too
         t1 = time.perf_counter()
         batch = kn.Batch(plans)
@@ -336,10 +345,9 @@ def main():
         uploaded = torch.cuda.Event()
         uploaded.record(up_stream)
         t3 = time.perf_counter()
-        phase["plan"] += t1 - tp
         phase["batch"] += t2 - t1
         phase["upload"] += t3 - t2
-        phase["prepare"] += t3 - tp
+        phase["prepare"] += t3 - t1
         return taits, plans, batch, uploaded, slot
 
     def launch(prepared, precision=0):
@@ -398,9 +406,14 @@ def main():
         """n whole batches, host preparation (and upload) of batch i+1
         overlapped with the device work of batch i; returns the last batch's
         results (every batch's V is formed before this returns)."""
-        # the helper runs up to two preparations ahead, back to back (one
-        # worker), so it never waits for the launch thread
-        futs = [pool.submit(prepare, precision) for _ in range(min(args.prefetch, n))]
+        # two helper stages run up to `prefetch` batches ahead: the planner
+        # plans batch j + 1 on the library's thread pool while the builder
+        # makes batch j's device program and uploads it, so a step costs the
+        # longer of the two stages rather than their sum
+        def submit():
+            return pool.submit(prepare, precision, planner.submit(plan_stage, precision))
+
+        futs = [submit() for _ in range(min(args.prefetch, n))]
         cur = None
         for i in range(n):
             t0 = time.perf_counter()
@@ -409,7 +422,7 @@ def main():
             done, z = launch(prepared, precision)
             ts = time.perf_counter()
             if i + args.prefetch < n:
-                futs.append(pool.submit(prepare, precision))
+                futs.append(submit())
             hand = [cur] if cur is not None else None
             cur = None
             tf = time.perf_counter()
@@ -516,7 +529,7 @@ def main():
         "host_prepare_ms": ms_prepare,
         "host_threads": args.threads if args.threads > 0 else len(os.sched_getaffinity(0)),
         "pipelined": f"host preparation of batches i+1..i+{args.prefetch} overlaps the GPU work "
-                     "of batch i",
+                     "of batch i; planning batch j+1 overlaps building batch j's device program",
         "pipeline_ms": pipeline_ms,
         "tuned": tuned[0] or None,
         "gpu_contract": {

@@ -200,8 +200,10 @@ void kn_tait_free(kn_tait* g);
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
- *               (0 = default 24 KiB, at most 96 KiB).  All plans of a batch
- *               are launched with the largest value any of them uses.
+ *               (0 = default 24 KiB, at most 128 KiB: with the engine's own
+ *               28 KiB of tables and descriptors one workgroup then fills a
+ *               compute unit's 160 KiB).  All plans of a batch are launched
+ *               with the largest value any of them uses.
  * gradient      1: the plan also carries the reverse pass of the contraction
  *               (for kn_contract_backward): after the forward steps, the
  *               adjoint of every intermediate is contracted back to the vertex
