@@ -283,50 +283,93 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
     xm[m] = x;
   }
   __syncthreads();
-  // vertex tensors: one wavefront per tensor
+  // vertex tensors, one wavefront per tensor.  A wavefront takes its
+  // vertices 64 at a time: lane l first loads the records of vertex l of the
+  // block and its slot list (all lanes at once), and each vertex's values
+  // are then read from its lane, so a vertex waits only for its weights
   const int lane = tid & 63, wv = tid >> 6;
   const int q = kd.q;
-  for (int v = wv; v < kd.n_vtx; v += kBlock / 64) {
-    const VtxDesc vd = p.vtx[kd.vtx_off + v];
-    const TensorDesc td = p.tens[vd.tensor];
-    Cx<T>* out = tptr<T>(td, arena, lds);
-    const bool in_lds = td.lds_off >= 0;
-    const GlbOut<T> gout((GlbCx<T>*)(in_lds ? arena : out));
-    const int32_t* slot_me = p.vslot + vd.slot_off;
-    int32_t qn = 1;  // q^n_slots
-    for (int j = 0; j < vd.n_slots; ++j) qn *= q;
-    for (int i = lane; i < td.size; i += 64) {
-      // digits of i: last neighbour slot fastest; a kept centre is the leading
-      // index (i / q^n_slots), a private centre is summed over.  A reverse-pass
-      // seed (keep_center < 0, no slots, one entry) takes the kept branch with
-      // an empty product: the scalar 1.
-      const int a_lo = vd.keep_center ? i / qn : 0;
-      const int a_hi = vd.keep_center ? a_lo + 1 : q;
-      Cx<double> acc{0.0, 0.0};
-      for (int a = a_lo; a < a_hi; ++a) {
-        Cx<double> prod{1.0, 0.0};
-        int rem = i;
-        for (int j = vd.n_slots - 1; j >= 0; --j) {
-          const int d = rem % q;
-          rem /= q;
-          if (d == a) prod = cmul(prod, xm[slot_me[j]]);
-        }
-        // slices: an edge to a fixed spin contributes x_m where this spin
-        // takes the fixed value (digit j of the slice number, base q)
-        for (int j = 0; j < vd.n_pins; ++j) {
-          const int32_t* pn = p.pins + 2 * (vd.pin_off + j);
-          int sv = slice;
-          for (int r = 0; r < pn[1]; ++r) sv /= q;
-          if (sv % q == a) prod = cmul(prod, xm[pn[0]]);
-        }
-        acc.re += prod.re;
-        acc.im += prod.im;
-      }
-      if (in_lds) out[i] = Cx<T>{(T)acc.re, (T)acc.im};
-      else put(gout, i, Cx<T>{(T)acc.re, (T)acc.im});
+  const QDiv D(q);
+  constexpr int kSlots = 7;  // the planner rejects vertex tensors with more slots
+  for (int v0 = wv * 64; v0 < kd.n_vtx; v0 += kBlock) {
+    const int mine = v0 + lane;
+    const bool have = mine < kd.n_vtx;
+    VtxDesc my{};
+    int64_t my_off = 0;
+    int32_t my_size = 0, my_lds = -1;
+    if (have) {
+      my = p.vtx[kd.vtx_off + mine];
+      const TensorDesc t = p.tens[my.tensor];
+      my_off = t.off;
+      my_size = t.size;
+      my_lds = t.lds_off;
     }
-    // entries are products of <= 8 weights: no scaling needed
-    if (lane == 0) st.set(vd.tensor, 0, 0);
+    // the slot lists of the block, one merged-edge id per slot
+    int32_t sl[kSlots];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) sl[j] = have && j < my.n_slots ? p.vslot[my.slot_off + j] : 0;
+    const int nv = min(64, kd.n_vtx - v0);
+    for (int u = 0; u < nv; ++u) {
+      // uniform values of vertex v0 + u, read from its lane
+      auto from = [u](int32_t v) { return __builtin_amdgcn_readlane(v, u); };
+      const int32_t tensor = from(my.tensor);
+      const int32_t n_slots = from(my.n_slots);
+      const int32_t keep = from(my.keep_center);
+      const int32_t pin_off = from(my.pin_off);
+      const int32_t n_pins = from(my.n_pins);
+      const int32_t size = from(my_size);
+      const int32_t lds_off = from(my_lds);
+      const int64_t off = (int64_t)(((uint64_t)(uint32_t)from((int32_t)(my_off >> 32)) << 32) |
+                                    (uint32_t)from((int32_t)my_off));
+      int32_t slot[kSlots];
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j) slot[j] = __builtin_amdgcn_readlane(sl[j], u);
+      const bool in_lds = lds_off >= 0;
+      Cx<T>* out = in_lds ? lds + lds_off : arena + off;
+      const GlbOut<T> gout((GlbCx<T>*)(in_lds ? arena : out));
+      for (int i = lane; i < size; i += 64) {
+        // digits of i: last neighbour slot fastest (exact division by q
+        // through a multiply-high, once per entry); a kept centre is the
+        // leading index (what is left of i after the slot digits), a private
+        // centre is summed over.  A reverse-pass seed (keep_center < 0, no
+        // slots, one entry) takes the kept branch with an empty product: the
+        // scalar 1.
+        int dig[kSlots];
+        int rem = i;
+#pragma unroll
+        for (int j = kSlots - 1; j >= 0; --j) {
+          dig[j] = -1;
+          if (j < n_slots) {
+            const int32_t qt = D.div(rem);
+            dig[j] = rem - qt * q;
+            rem = qt;
+          }
+        }
+        const int a_lo = keep ? rem : 0;
+        const int a_hi = keep ? a_lo + 1 : q;
+        Cx<double> acc{0.0, 0.0};
+        for (int a = a_lo; a < a_hi; ++a) {
+          Cx<double> prod{1.0, 0.0};
+#pragma unroll
+          for (int j = kSlots - 1; j >= 0; --j)
+            if (dig[j] == a) prod = cmul(prod, xm[slot[j]]);
+          // slices: an edge to a fixed spin contributes x_m where this spin
+          // takes the fixed value (digit j of the slice number, base q)
+          for (int j = 0; j < n_pins; ++j) {
+            const int32_t* pn = p.pins + 2 * (pin_off + j);
+            int sv = slice;
+            for (int r = 0; r < pn[1]; ++r) sv /= q;
+            if (sv % q == a) prod = cmul(prod, xm[pn[0]]);
+          }
+          acc.re += prod.re;
+          acc.im += prod.im;
+        }
+        if (in_lds) out[i] = Cx<T>{(T)acc.re, (T)acc.im};
+        else put(gout, i, Cx<T>{(T)acc.re, (T)acc.im});
+      }
+      // entries are products of <= 8 weights: no scaling needed
+      if (lane == 0) st.set(tensor, 0, 0);
+    }
   }
 }
 
