@@ -188,7 +188,7 @@ def main():
     # the all-cores CPU oracle leg runs first, before this process touches the
     # GPU (its worker processes are spawned fresh and never use the GPU)
     cpu_par = None
-    if not args.no_cpu_baseline and not args.pmc_calibrate:
+    if not args.no_cpu_baseline and not args.pmc_calibrate and not args.wide_only:
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         cpu_par = dict(cpu_parallel(knots, q, workers, args.cpu_seconds), workers=workers)
 

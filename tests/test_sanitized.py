@@ -1,7 +1,8 @@
 """The host library built with AddressSanitizer and UndefinedBehaviorSanitizer
 (``python -m paper_1807_02119_amd.build --sanitize``) under the CPU tests of the
 host code: Tait graphs, planning, device programs and their CPU model,
-normalisation, the index decode.  Any invalid memory access or undefined
+normalisation, the index decode, and the image validator on valid and on
+deliberately corrupted images.  Any invalid memory access or undefined
 behaviour in the host C++ aborts the child process."""
 
 from __future__ import annotations
@@ -32,7 +33,9 @@ def test_host_code_under_asan_ubsan():
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_host.py"),
-                        os.path.join(ROOT, "tests", "test_decode.py")],
+                        os.path.join(ROOT, "tests", "test_decode.py"),
+                        os.path.join(ROOT, "tests", "test_checks.py"),
+                        "-k", "not checking_build"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0 and " passed" in r.stdout, (r.stdout[-2000:], r.stderr[-4000:])
     assert os.path.exists(lib)
