@@ -197,6 +197,15 @@ void kn_tait_free(kn_tait* g);
  *               searches them per workload.
  * order_trials  separator hierarchies tried by strategies 3 and 4 (0 =
  *               default 12, at most 4096).
+ * fork_serial_log2  a run of small steps whose estimated time (as for
+ *               split_serial_log2) is at least 2^fork_serial_log2 is forked:
+ *               its steps form a forest (every intermediate is read once), so
+ *               its heaviest subtrees are split at their roots until each
+ *               weighs at most 1/8 of the run, and the subtrees run as up to 8
+ *               concurrent tasks on their own workgroups, between a task for
+ *               the knot's vertex tensors (if the run starts the knot) and
+ *               one for the steps above them.  Not applied to gradient plans
+ *               (their tensors are read twice).  0 = default 10; 40 = never.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -246,6 +255,7 @@ typedef struct {
   int32_t tile_outs_log2;
   kn_bucket_opts bucket[KN_N_BUCKETS];
   int32_t order_trials;
+  int32_t fork_serial_log2;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

@@ -63,6 +63,7 @@ struct PGroup {
   // serial groups of one dependency level: its steps shared out to several
   // tasks as (first, count) chunks; empty = one task for all the steps
   std::vector<std::pair<int32_t, int32_t>> chunks;
+  bool fork = false;  // the chunks are the concurrent subtree tasks of a forked run
 };
 
 // Estimated time of a serial step (arbitrary units: one per step plus one per
@@ -222,6 +223,35 @@ void make_section(PlanKnot& k) {
     cur.flags |= TF_FINAL;
     pg.push_back(cur);
   }
+  // ---- forked serial runs (the planner ordered their steps task by task,
+  // the top last): the setup alone, the subtree tasks as one group, then the
+  // top with the final product
+  {
+    std::vector<PGroup> out;
+    out.reserve(pg.size() + 4);
+    for (PGroup& g : pg) {
+      if (g.kind != TASK_SERIAL || g.count == 0 || k.tiling[g.first].part < 0) {
+        out.push_back(std::move(g));
+        continue;
+      }
+      const int32_t end = g.first + g.count;
+      if (g.flags & TF_SETUP) out.push_back(PGroup{TASK_SERIAL, g.first, 0, TF_SETUP, 0, {}});
+      PGroup parts{TASK_SERIAL, g.first, 0, 0, 0, {}};
+      parts.fork = true;
+      int32_t a = g.first;
+      while (a < end && k.tiling[a].part != kForkTop) {
+        int32_t b = a + 1;
+        while (b < end && k.tiling[b].part == k.tiling[a].part) ++b;
+        parts.chunks.emplace_back(a, b - a);
+        a = b;
+      }
+      parts.count = a - g.first;
+      out.push_back(std::move(parts));
+      if (a < end || (g.flags & TF_FINAL))
+        out.push_back(PGroup{TASK_SERIAL, a, end - a, g.flags & TF_FINAL, 0, {}});
+    }
+    pg.swap(out);
+  }
   // ---- long serial runs level by level: setup, one group per dependency
   // level (its independent steps in chunks over several tasks), final product
   {
@@ -231,7 +261,8 @@ void make_section(PlanKnot& k) {
       double est = 0;
       if (g.kind == TASK_SERIAL)
         for (int32_t si = g.first; si < g.first + g.count; ++si) est += step_est(S.sd[si]);
-      if (g.kind != TASK_SERIAL || g.count < 2 || est < k.split_est) {
+      if (g.kind != TASK_SERIAL || g.count < 2 || est < k.split_est || g.fork ||
+          k.tiling[g.first].part >= 0) {
         out.push_back(std::move(g));
         continue;
       }
@@ -275,14 +306,27 @@ void make_section(PlanKnot& k) {
     for (int32_t c : k.comps) consumer[c] = ns;
     const int64_t es = elem_bytes(k.precision);
     const int64_t cap = k.lds_bytes / es;
+    // each task of a forked group runs on its own workgroup: one LDS arena
+    // per task, and its levels only
+    std::vector<std::pair<const PGroup*, std::pair<int32_t, int32_t>>> regions;
     for (const PGroup& g : pg) {
       if (g.kind != TASK_SERIAL) continue;
-      const int32_t lo = g.first, hi = g.first + g.count;  // steps [lo, hi)
+      if (g.fork)
+        for (const auto& c : g.chunks) regions.push_back({&g, c});
+      else
+        regions.push_back({&g, {g.first, g.count}});
+    }
+    for (const auto& [gp, range] : regions) {
+      const PGroup& g = *gp;
+      const int32_t lo = range.first, hi = range.first + range.second;  // steps [lo, hi)
       auto inside = [&](int32_t t) {
         int32_t c = consumer[t];
         if (c < 0) return false;
         if (c == ns) return (g.flags & TF_FINAL) != 0;
         return c >= lo && c < hi;
+      };
+      auto concurrent = [&](int32_t i) {  // steps i and i + 1 of this task
+        return g.fork ? k.tiling[i].level == k.tiling[i + 1].level : same_level(k, i);
       };
       FitAlloc la(cap, 8);
       int64_t peak = 0;
@@ -296,7 +340,7 @@ void make_section(PlanKnot& k) {
       // a level's outputs are placed before any of its operands is released
       for (int32_t si = lo; si < hi;) {
         int32_t sj = si + 1;
-        while (sj < hi && same_level(k, sj - 1)) ++sj;
+        while (sj < hi && concurrent(sj - 1)) ++sj;
         for (int32_t u = si; u < sj; ++u) {
           const PStep& s = k.steps[u];
           if (inside(s.c)) {

@@ -164,7 +164,13 @@ struct PTiling {
   int32_t n_tiles = 0;  // tasks of the tile group
   int64_t partial = -1; // arena offset of the n_ks x outputs partial sums
   int32_t level = 0;    // serial steps: dependency level inside its run (from 1)
+  // serial steps of a forked run: the concurrent task (0, 1, ...) whose
+  // subtrees hold the step, or kForkTop for the steps above them; -1: the
+  // run is not forked
+  int32_t part = -1;
 };
+
+constexpr int32_t kForkTop = 1 << 30;
 
 // One pairwise contraction C = A . B over spin groups.
 struct PStep {
@@ -219,6 +225,8 @@ struct PlanKnot {
   int32_t lds_bytes = 32768;
   double split_est = 1024;                      // serial runs estimated at least this
                                                 // long run level by level
+  double fork_est = 1e30;                       // ... or at least this long: forked into
+                                                // concurrent subtree tasks
   std::vector<PTiling> tiling;                  // per step: how it is executed
   Section sec;  // device-program section (make_section)
 
@@ -238,13 +246,16 @@ struct PlanKnot {
   }
 };
 
-// Adjacent steps i and i + 1 run concurrently: both serial and of the same
-// level (runs of serial steps are separated by tiled steps, and levels
-// ascend inside a run).
+// Adjacent steps i and i + 1 may run concurrently: both serial and of the
+// same level of one task (runs of serial steps are separated by tiled steps,
+// and levels ascend inside a task), or both in the concurrent tasks of a
+// forked run (each of which runs on its own workgroup, all at once).
 inline bool same_level(const PlanKnot& k, size_t i) {
   const PTiling& a = k.tiling[i];
   const PTiling& b = k.tiling[i + 1];
-  return a.mode == STEP_SERIAL && b.mode == STEP_SERIAL && a.level == b.level;
+  if (a.mode != STEP_SERIAL || b.mode != STEP_SERIAL) return false;
+  if (a.part >= 0 && a.part != kForkTop && b.part >= 0 && b.part != kForkTop) return true;
+  return a.part == b.part && a.level == b.level;
 }
 
 // First-fit allocator over [0, cap) entries, sizes rounded up to `align`

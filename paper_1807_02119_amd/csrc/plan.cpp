@@ -80,6 +80,11 @@ constexpr int32_t kGemm64Pct = 300;
 // default threshold (log2 of the estimated time) above which a serial run is
 // executed level by level over several workgroups
 constexpr int32_t kSplitSerialLog2 = 40;
+// ... and above which a run is forked into concurrent subtree tasks
+// (measured on 256 knots of 200-600 crossings at q = 3: 2^10 shortens the
+// launch by 4 % in complex128 and 7 % in complex64; 2^8-2^9 fork too many
+// runs, 2^11 and above too few)
+constexpr int32_t kForkSerialLog2 = 10;
 // Slicing fixes at most this many spins, and makes at most kMaxSlices slices
 // (the device runs the slices of a chain one after another from one copy of
 // the knot's descriptors; the queue holds one slot per task and slice).
@@ -885,11 +890,93 @@ void add_reverse(PlanKnot& k, int32_t& n_vt, int32_t drop_rank, int32_t max_dept
 // steps is reordered by dependency level (1 + the highest level among the
 // producers of its operands inside the run; stable within a level), and the
 // tensors are renumbered so that step i still produces tensor n_vt + i.
+// Estimated time of a serial step: one unit per step plus one per 512
+// multiply-adds (the unit the image builder uses for its runs).
+double serial_est(const PStep& s, int32_t q) {
+  double macs = 1;
+  for (size_t r = 0; r < s.bs.size() + s.ms.size() + s.ns.size() + s.ks.size(); ++r) macs *= q;
+  return 1.0 + macs / 512.0;
+}
+
+// Fork of a serial run: in a plain plan every intermediate is read by one
+// step only, so the run's steps form a forest (a step's children are the
+// steps of the run that produce its operands).  The heaviest subtrees are
+// split at their root until every remaining subtree weighs at most 1/8 of
+// the run; the split roots form the top, and the remaining subtrees are
+// packed into at most kForkTasks tasks by weight (largest first, each to the
+// lightest task).  part[u - i] receives the task of step u, or kForkTop.
+// Returns false (no fork) when fewer than two tasks would result.
+constexpr int32_t kForkTasks = 8;
+
+bool fork_run(const PlanKnot& k, int32_t n_vt, int32_t i, int32_t j, std::vector<int32_t>& part) {
+  const int32_t n = j - i;
+  std::vector<int32_t> ch0(n, -1), ch1(n, -1);
+  std::vector<uint8_t> used(n, 0);
+  std::vector<double> w(n, 0.0);
+  for (int32_t u = i; u < j; ++u) {
+    int32_t nc = 0;
+    for (int32_t op : {k.steps[u].a, k.steps[u].b}) {
+      const int32_t ps = op - n_vt;
+      if (ps < i || ps >= u) continue;
+      if (used[ps - i]) return false;  // read twice: not a forest
+      used[ps - i] = 1;
+      (nc++ == 0 ? ch0 : ch1)[u - i] = ps - i;
+    }
+    w[u - i] = serial_est(k.steps[u], k.q) + (ch0[u - i] >= 0 ? w[ch0[u - i]] : 0.0) +
+               (ch1[u - i] >= 0 ? w[ch1[u - i]] : 0.0);
+  }
+  double total = 0;
+  std::vector<std::pair<double, int32_t>> heap;  // max-heap of subtree roots by weight
+  for (int32_t u = 0; u < n; ++u)
+    if (!used[u]) {
+      heap.emplace_back(w[u], u);
+      total += w[u];
+    }
+  std::make_heap(heap.begin(), heap.end());
+  part.assign(n, -1);
+  const double cap = total / kForkTasks;
+  for (int32_t splits = 0; !heap.empty() && heap.front().first > cap && splits < 4 * kForkTasks;
+       ++splits) {
+    std::pop_heap(heap.begin(), heap.end());
+    const int32_t u = heap.back().second;
+    heap.pop_back();
+    part[u] = kForkTop;
+    for (int32_t c : {ch0[u], ch1[u]})
+      if (c >= 0) {
+        heap.emplace_back(w[c], c);
+        std::push_heap(heap.begin(), heap.end());
+      }
+  }
+  std::sort(heap.begin(), heap.end(), [](const std::pair<double, int32_t>& x,
+                                         const std::pair<double, int32_t>& y) {
+    return x.first != y.first ? x.first > y.first : x.second < y.second;
+  });
+  const int32_t n_tasks = std::min<int32_t>(kForkTasks, (int32_t)heap.size());
+  if (n_tasks < 2) return false;
+  std::vector<double> load(n_tasks, 0.0);
+  std::vector<int32_t> stack;
+  for (const auto& [wr, r] : heap) {
+    const int32_t t = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[t] += wr;
+    stack.push_back(r);
+    while (!stack.empty()) {  // the subtree of r, all to task t
+      const int32_t u = stack.back();
+      stack.pop_back();
+      part[u] = t;
+      for (int32_t c : {ch0[u], ch1[u]})
+        if (c >= 0) stack.push_back(c);
+    }
+  }
+  return true;
+}
+
 void level_schedule(PlanKnot& k, int32_t n_vt) {
   const int32_t ns = (int32_t)k.steps.size();
   std::vector<int32_t> order;
   order.reserve(ns);
-  std::vector<int32_t> lvl(ns, 0);  // by old step index
+  std::vector<int32_t> lvl(ns, 0);    // by old step index
+  std::vector<int32_t> prt(ns, -1);   // fork task by old step index
+  std::vector<int32_t> fpart;
   for (int32_t i = 0; i < ns;) {
     if (k.tiling[i].mode != STEP_SERIAL) {
       order.push_back(i++);
@@ -897,23 +984,36 @@ void level_schedule(PlanKnot& k, int32_t n_vt) {
     }
     int32_t j = i;
     while (j < ns && k.tiling[j].mode == STEP_SERIAL) ++j;
+    double est = 0;
+    for (int32_t u = i; u < j; ++u) est += serial_est(k.steps[u], k.q);
+    const bool forked = !k.gradient && est >= k.fork_est && fork_run(k, n_vt, i, j, fpart);
+    if (forked)
+      for (int32_t u = i; u < j; ++u) prt[u] = fpart[u - i];
+    // levels inside each task of the run (operands made by another task or
+    // before the run count as ready)
     int32_t top = 0;
     for (int32_t u = i; u < j; ++u) {
       int32_t l = 0;
       for (int32_t op : {k.steps[u].a, k.steps[u].b}) {
         const int32_t ps = op - n_vt;  // producing step
-        if (ps >= i && ps < u) l = std::max(l, lvl[ps]);
+        if (ps >= i && ps < u && prt[ps] == prt[u]) l = std::max(l, lvl[ps]);
       }
       lvl[u] = l + 1;
       top = std::max(top, l + 1);
     }
-    // counting sort by level keeps the original order within a level
-    std::vector<int32_t> cnt(top + 2, 0);
-    for (int32_t u = i; u < j; ++u) cnt[lvl[u] + 1]++;
-    for (int32_t l = 1; l <= top + 1; ++l) cnt[l] += cnt[l - 1];
+    // counting sort by (task, level) keeps the original order within a level;
+    // the tasks in turn, the top last
+    const int32_t n_keys = forked ? kForkTasks + 1 : 1;
+    auto key = [&](int32_t u) {
+      const int32_t t = prt[u] < 0 ? 0 : (prt[u] == kForkTop ? kForkTasks : prt[u]);
+      return t * (top + 1) + lvl[u];
+    };
+    std::vector<int32_t> cnt((size_t)n_keys * (top + 1) + 1, 0);
+    for (int32_t u = i; u < j; ++u) cnt[key(u) + 1]++;
+    for (size_t l = 1; l < cnt.size(); ++l) cnt[l] += cnt[l - 1];
     const size_t base = order.size();
     order.resize(base + (j - i));
-    for (int32_t u = i; u < j; ++u) order[base + cnt[lvl[u]]++] = u;
+    for (int32_t u = i; u < j; ++u) order[base + cnt[key(u)]++] = u;
     i = j;
   }
   std::vector<int32_t> pos(ns);
@@ -933,6 +1033,7 @@ void level_schedule(PlanKnot& k, int32_t n_vt) {
     steps[r] = std::move(st);
     tiling[r] = k.tiling[u];
     tiling[r].level = tiling[r].mode == STEP_SERIAL ? lvl[u] : 0;
+    tiling[r].part = tiling[r].mode == STEP_SERIAL ? prt[u] : -1;
   }
   for (auto& c : k.comps) c = remap(c);
   for (auto& v : k.vtx)
@@ -1379,6 +1480,7 @@ kn_status make_plan(const kn_tait& g, int32_t q, const kn_plan_opts& o, PlanKnot
   k.big_outs_log2 = std::min(o.big_step_outs_log2 > 0 ? o.big_step_outs_log2 : kBigOutsLog2, 24);
   k.lds_bytes = o.lds_bytes > 0 ? o.lds_bytes : 24576;
   k.split_est = std::ldexp(1.0, o.split_serial_log2 > 0 ? o.split_serial_log2 : kSplitSerialLog2);
+  k.fork_est = std::ldexp(1.0, o.fork_serial_log2 > 0 ? o.fork_serial_log2 : kForkSerialLog2);
   {
     double qq = q;
     if (q < 4) {
@@ -1529,6 +1631,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (o.gradient && (o.simplify & 6)) return KN_E_INVALID;
   if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
   if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
+  if (o.fork_serial_log2 < 0 || o.fork_serial_log2 > 40) return KN_E_INVALID;
   if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;
   if (o.gemm64_pct < 0 || o.gemm64_pct > 100000) return KN_E_INVALID;
   if (o.big_step_outs_log2 < 0 || o.big_step_outs_log2 > 31) return KN_E_INVALID;

@@ -160,6 +160,24 @@ def run(raw: bytes, J=None, want_grad=False):
     def home(t):
         return int(im.tensors[t]["lds_off"])
 
+    # the serial tasks of one group run at once on different workgroups: every
+    # global-arena range each of them reads or writes, checked against the
+    # others' when the group completes, and their outputs visible to other
+    # tasks only after the whole group
+    group_acc = {}
+    group_made = {}
+
+    def concurrent_group():
+        g = int(im.tasks[cur_task[0]]["group"])
+        multi = (int(im.tasks[cur_task[0]]["kind"]) == TASK_SERIAL
+                 and int(im.groups[g]["n_tasks"]) > 1)
+        return g if multi else None
+
+    def record(write, off, size):
+        g = concurrent_group()
+        if g is not None:
+            group_acc.setdefault(g, []).append((cur_task[0], write, off, size))
+
     def write_tensor(t, data, task_local):
         size = int(im.tensors[t]["size"])
         assert data.size == size
@@ -178,6 +196,7 @@ def run(raw: bytes, J=None, want_grad=False):
                     raise AssertionError(f"tensor {t} overwrites live tensor {u}")
             arena[off:off + size] = data
             live_g[t] = (off, size)
+            record(True, off, size)
 
     def read(t, local):
         size = int(im.tensors[t]["size"])
@@ -187,6 +206,7 @@ def run(raw: bytes, J=None, want_grad=False):
             return state["lds"][lo:lo + size]
         assert t in local or finished[t], f"tensor {t} read before its producer finished"
         off = int(im.tensors[t]["off"])
+        record(False, off, size)
         return arena[off:off + size]
 
     def sh(t):
@@ -499,9 +519,13 @@ def run(raw: bytes, J=None, want_grad=False):
             assert local == made, "state range differs from the tensors the task produced"
             # LDS contents die with the task: nothing homed there may outlive it
             assert not live_l, f"LDS tensors {list(live_l)} still live when their task ends"
+            g_ = concurrent_group()
             for t in local:
                 if home(t) < 0:
-                    finished[t] = True
+                    if g_ is None:
+                        finished[t] = True
+                    else:
+                        group_made.setdefault(g_, []).append(t)
         elif task["kind"] == TASK_TILE:
             sd = im.steps[int(task["first"])]
             assert int(sd["mode"]) in (STEP_TILES, STEP_GEMM, STEP_GEMM64)
@@ -542,6 +566,15 @@ def run(raw: bytes, J=None, want_grad=False):
         g = int(task["group"])
         done_in_group[g] = done_in_group.get(g, 0) + 1
         if done_in_group[g] == int(im.groups[g]["n_tasks"]):
+            acc = group_acc.pop(g, [])
+            for x in range(len(acc)):
+                for y in range(x + 1, len(acc)):
+                    (t1, w1, o1, s1), (t2, w2, o2, s2) = acc[x], acc[y]
+                    if t1 != t2 and (w1 or w2) and o1 < o2 + s2 and o2 < o1 + s1:
+                        raise AssertionError(f"concurrent tasks {t1} and {t2} of group {g} "
+                                             "touch overlapping arena ranges")
+            for t in group_made.pop(g, []):
+                finished[t] = True
             if task["kind"] != TASK_SERIAL:
                 sd = im.steps[int(task["first"])]
                 if task["kind"] == TASK_REDUCE or int(sd["n_ks"]) == 1:

@@ -1,6 +1,6 @@
 """GPU parity of a plan whose spin groups need the full int32 index range of
 the engine's decode (csrc/decode.h): a paper-model grid-walk knot (Sec. III.A)
-of 770 crossings at q = 2, unsliced, whose plan holds a tensor of 2^28 entries
+of 770 crossings at q = 2, unsliced, whose min-fill plan holds a tensor of 2^28 entries
 and a step contracting a group of 2^27 values (indices far past q * 2^24).
 Checked against the sliced plan of the same knot (every tensor <= 2^20
 entries, relative error <= 1e-10) and against the exact value V(i) = +-1 that
@@ -34,7 +34,9 @@ def test_group_of_2_27_values_q2():
     rng = np.random.default_rng(1000 * 86 + 1)
     d = gen.random_grid_diagram(rng, 86)
     t = kn.Tait(d.pd)
-    p = kn.Plan(t, 2)
+    # the min-fill order: its plan holds the wide group this test needs (the
+    # auto order, which also tries separator hierarchies, stays below 2^25)
+    p = kn.Plan(t, 2, strategy=2)
     steps = im.Image(p.image()).steps
     widest = max(int(max(s["nb"], s["nm"], s["nn"], s["nk"])) for s in steps)
     assert widest >= 2**27 and p.stats["log2_max_entries"] >= 27

@@ -283,6 +283,32 @@ def test_batch_parity():
     assert torch.equal(z.view(torch.int64), z2.view(torch.int64))
 
 
+def test_forked_runs_parity():
+    """Long serial runs forked into concurrent subtree tasks (the vertex
+    tensors, up to 8 subtree tasks on their own workgroups, the steps above
+    them), alone and in a batch, complex128 and complex64, against the
+    oracle; a second launch gives identical bits."""
+    knots = gen.config_knots("q3_200_600", 0, count=24)
+    for prec, tol in ((0, TOL), (1, TOL32)):
+        for fork in (6, 9):
+            _log(f"forked runs: 2^{fork}, precision {prec}")
+            plans = [kn.Plan(kn.Tait(d.pd), q, fork_serial_log2=fork, precision=prec)
+                     for d, q in knots]
+            b = kn.Batch(plans)
+            z = b.contract()
+            torch.cuda.synchronize()
+            for (d, q), (m, e) in zip(knots, kn.scalars_from_device(z)):
+                tg, mo, eo = oracle_z(d, q)
+                assert rel_err(m * 2.0 ** (e - eo), mo) <= tol, (d.label, fork, prec)
+            z2 = b.contract()
+            torch.cuda.synchronize()
+            assert torch.equal(z.view(torch.int64), z2.view(torch.int64))
+    d, q = knots[3]
+    t, p, m, e = gpu_z(d, q, fork_serial_log2=5)
+    tg, mo, eo = oracle_z(d, q)
+    assert z_close(m, e, mo, eo)
+
+
 def test_bench_configuration_parity():
     """The batch exactly as bench.py times it: the 256 knots of the 200-600
     crossing workload planned as one PlanSet (min-fill orders, the tuned

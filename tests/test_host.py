@@ -783,3 +783,64 @@ def test_slice_loop_on_the_device_model():
         assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, q)
         done += 1
     assert done >= 3
+
+
+def test_forked_runs_on_the_device_model():
+    """Long serial runs forked into concurrent subtree tasks: a task for the
+    vertex tensors, a group of up to 8 subtree tasks, and the steps above
+    them.  The CPU model runs each group's tasks as concurrent (their global
+    ranges may not overlap, their outputs are visible only after the group)
+    and matches the oracle, also sliced, in complex64 and in a batch."""
+    knots = [gen.lattice_knot((44, k), 100, 200) for k in range(4)]
+    forked = 0
+    for d in knots:
+        t = kn.Tait(d.pd)
+        tg, m, e = oracle_z(d, 3)
+        for kw in (dict(fork_serial_log2=4), dict(fork_serial_log2=6),
+                   dict(fork_serial_log2=5, slice_log2_budget=5),
+                   dict(fork_serial_log2=3, split_serial_log2=3)):
+            p = kn.Plan(t, 3, **kw)
+            img = image_model.Image(p.image())
+            sizes = [int(g["n_tasks"]) for g in img.groups]
+            if p.stats["n_slices"] == 1 and len(sizes) == 3:
+                forked += 1
+                assert sizes[0] == 1 and 2 <= sizes[1] <= 8 and sizes[2] == 1, sizes
+            (zm, ze), = image_model.run(p.image())
+            assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12, (d.label, kw)
+        p32 = kn.Plan(t, 3, fork_serial_log2=4, precision=1)
+        (zm, ze), = image_model.run(p32.image())
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-5
+    assert forked >= 4
+    b = kn.Batch([kn.Plan(kn.Tait(d.pd), 3, fork_serial_log2=5) for d in knots])
+    for (zm, ze), d in zip(image_model.run(b.image()), knots):
+        tg, m, e = oracle_z(d, 3)
+        assert rel_err(zm * 2.0 ** (ze - e), m) < 1e-12
+    # gradient plans are never forked (their tensors are read twice)
+    g = kn.Plan(kn.Tait(knots[0].pd), 3, fork_serial_log2=2, gradient=True, jones_only=False)
+    assert all(int(x["n_tasks"]) == 1 for x in image_model.Image(g.image()).groups
+               if int(image_model.Image(g.image()).tasks[int(x["first_task"])]["kind"]) == 0)
+
+
+def test_model_catches_overlapping_concurrent_tasks():
+    """A planted fault in a copy of a forked image: the output of one subtree
+    task moved onto a tensor that another subtree task of the same group
+    writes.  The CPU model must reject it."""
+    d = gen.lattice_knot((44, 0), 100, 200)
+    raw = bytearray(kn.Plan(kn.Tait(d.pd), 3, fork_serial_log2=4).image())
+    img = image_model.Image(bytes(raw))
+    grp = img.groups[1]
+    tasks = [img.tasks[i] for i in range(int(grp["first_task"]), int(grp["first_task"]) + int(grp["n_tasks"]))]
+    assert len(tasks) >= 2
+    last = lambda task: int(img.steps[int(task["first"]) + int(task["count"]) - 1]["c"])
+    a, b = last(tasks[0]), last(tasks[1])
+    assert int(img.tensors[a]["lds_off"]) < 0 and int(img.tensors[b]["lds_off"]) < 0
+    h = img.h
+    tens = np.frombuffer(raw, image_model.TENSOR, int(h["n_tensors"]), int(h["o_tensors"]))
+    steps = np.frombuffer(raw, image_model.STEP, int(h["n_steps"]), int(h["o_steps"]))
+    tens[b]["off"] = tens[a]["off"]
+    for s in steps:  # keep the step homes consistent with the moved tensor
+        for f, t in (("home_a", "a"), ("home_b", "b"), ("home_c", "c")):
+            if int(s[t]) == b:
+                s[f] = int(tens[a]["off"])
+    with pytest.raises(AssertionError, match="overlap|overwrites"):
+        image_model.run(bytes(raw))
