@@ -606,47 +606,29 @@ struct Orderer {
     std::vector<uint64_t> xm(W, 0);  // N(x) + x as a bit set
     uint32_t ts = 0;
     // next spin: lowest rank, then least fill, then least degree, then
-    // lowest id, from packed keys (rank 10 bits, fill 22, degree 11, id 21;
-    // fill and degree saturate) in a binary min-heap: a spin whose key
-    // changes is pushed again, and entries that no longer equal their spin's
-    // current key (or whose spin is gone) are skipped when they surface.
-    // Keys are unique, so the order is that of a scan for the least key.
-    constexpr uint64_t kIdMask = (uint64_t(1) << 21) - 1;
-    std::vector<uint64_t> cur(n), heap;
-    std::vector<uint8_t> gone(n, 0);
-    heap.reserve(4 * (size_t)n);
-    auto key_of = [&](int32_t v) {
+    // lowest id (a linear scan over packed keys, which for a few hundred
+    // spins measured faster than a heap) over the spins still in the graph,
+    // kept packed: key[slot[v]] is v's.  Fields: rank 10 bits, fill 22,
+    // degree 11, id 21 (fill and degree saturate).
+    std::vector<uint64_t> key(n);
+    std::vector<int32_t> slot(n);
+    int32_t live = n;
+    auto pack = [&](int32_t v) {
       const uint64_t r = rank ? (uint64_t)std::min((*rank)[v], 1023) : 0;
       const uint64_t f = (uint64_t)std::min(fill[v], (1 << 22) - 1);
       const uint64_t d = (uint64_t)std::min(deg[v], (1 << 11) - 1);
-      return r << 54 | f << 32 | d << 21 | (uint64_t)v;
-    };
-    auto pack = [&](int32_t v) {
-      const uint64_t k = key_of(v);
-      if (k == cur[v]) return;
-      cur[v] = k;
-      heap.push_back(k);
-      std::push_heap(heap.begin(), heap.end(), std::greater<uint64_t>());
+      key[slot[v]] = r << 54 | f << 32 | d << 21 | (uint64_t)v;
     };
     for (int32_t v = 0; v < n; ++v) {
-      cur[v] = key_of(v);
-      heap.push_back(cur[v]);
+      slot[v] = v;
+      pack(v);
     }
-    std::make_heap(heap.begin(), heap.end(), std::greater<uint64_t>());
+    constexpr uint64_t kIdMask = (uint64_t(1) << 21) - 1;
     for (int32_t it = 0; it < n; ++it) {
-      int32_t x = -1;
-      while (!heap.empty()) {
-        const uint64_t top = heap.front();
-        std::pop_heap(heap.begin(), heap.end(), std::greater<uint64_t>());
-        heap.pop_back();
-        const int32_t v = (int32_t)(top & kIdMask);
-        if (!gone[v] && cur[v] == top) {
-          x = v;
-          break;
-        }
-      }
+      uint64_t best = UINT64_MAX;
+      for (int32_t i = 0; i < live; ++i) best = std::min(best, key[i]);
+      const int32_t x = best == UINT64_MAX ? -1 : (int32_t)(best & kIdMask);
       if (x < 0) break;
-      gone[x] = 1;
       // contract the holders of x pairwise, smallest first
       if (cnt[x] > 0) {
         for (;;) {
@@ -711,6 +693,12 @@ struct Orderer {
         adj[(size_t)a * W + (x >> 6)] &= ~(uint64_t(1) << (x & 63));
       }
       for (int32_t w = 0; w < W; ++w) adj[(size_t)x * W + w] = 0;
+      {  // x leaves the packed keys: the last one takes its place
+        const int32_t i = slot[x], last = (int32_t)(key[live - 1] & kIdMask);
+        key[i] = key[live - 1];
+        slot[last] = i;
+        --live;
+      }
       for (int32_t z : touched)
         if (z != x) pack(z);
       for (int32_t a : nv) pack(a);

@@ -2,8 +2,8 @@
 are checked on the device before they run (checks.h) and the guard zone after
 the arena is checked after each launch.  Over plans of every kind -- serial
 runs, tiles, 32- and 64-blocks, split contracted ranges, slices run as
-device-side loops, the adjoint with recomputation, complex64 and a mixed
-batch -- every check passes (kn_workspace_status reads 0) and the results
+device-side loops, forked runs, the adjoint with recomputation, complex64 and
+a mixed batch -- every check passes (kn_workspace_status reads 0) and the results
 equal the oracle's.  The checking library runs in a child process of its own
 (KN_LIBRARY selects it), printing one line per case."""
 
@@ -59,6 +59,8 @@ run("split", d5, 3, big_step_macs_log2=4, tile_macs_log2=3)
 run("complex64", d5, 3, tol=TOL32, precision=1)
 run("sliced", gen.lattice_knot((82, 1), 40, 120), 3, slice_log2_budget=4)
 run("separator", work[7][0], 3, strategy=4)
+run("forked", d5, 3, fork_serial_log2=6)
+run("forked sliced", gen.lattice_knot((82, 1), 40, 120), 3, slice_log2_budget=4, fork_serial_log2=3)
 for label, d, q, kw in gemm64_cases()[:3]:
     run(label, d, q, **kw)
 
