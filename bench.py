@@ -24,9 +24,10 @@ import hashlib
 import json
 import math
 import os
+import queue
 import sys
+import threading
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -50,8 +51,6 @@ def parse():
                          "default min-fill only: the pipeline is bound by host planning, and "
                          "the greedy alternative that auto also builds for the heaviest knots "
                          "costs more host time than it saves on the device")
-    ap.add_argument("--prefetch", type=int, default=2, choices=(1, 2, 3),
-                    help="batches the helper thread prepares ahead of the launch thread")
     ap.add_argument("--kernel-reps", type=int, default=20,
                     help="launches of the contraction kernel timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -281,18 +280,26 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---------------------------------------------------------------- pipeline
-    # Three threads.  Two helper stages prepare batches i+1 .. i+prefetch: the
-    # planner makes their Tait graphs and plans on the library's thread pool,
-    # the builder their batch device programs and uploads on a side stream
-    # into one of prefetch + 1 workspaces in turn (batch j's program is built
-    # while the planner works on batch j + 1).  Meanwhile the launch thread
-    # contracts batch i and, while the GPU runs it, forms V = A Z of batch
-    # i - 1 and releases that batch.  The library calls release the GIL.
+    # Three threads joined by bounded queues.  The planner thread makes the
+    # Tait graphs and plans of one batch after another on the library's thread
+    # pool; between two plan sets it frees the batches the launch thread is
+    # done with (freed while the planning threads allocate, their many blocks
+    # would contend for the allocator's locks).  The builder thread makes each
+    # batch's device program and uploads it on a side stream into one of
+    # N_SLOTS workspaces in turn.  The launch thread queues batch i + 1's
+    # contraction behind batch i's on the stream, forms V = A Z of batch i - 1
+    # while the GPU works, then waits for batch i.  The library calls release
+    # the GIL.
+    #
+    # Workspace slots: the builder starts batch j only once batch j - 1 is in
+    # the (one-deep) built queue, so batch j - 2 has been taken and batch
+    # j - 3, the last user of slot j % 3, launched: the upload waits (on the
+    # GPU) for that launch's contraction.  Batch j's Z buffer (one per slot)
+    # is written by a launch that comes after batch j - 3's Z was read.
+    N_SLOTS = 3
     state = {}
     # the threads hand the interpreter lock to each other often: switch fast
     sys.setswitchinterval(1e-4)
-    pool = ThreadPoolExecutor(max_workers=1)     # builder: device programs, uploads, releases
-    planner = ThreadPoolExecutor(max_workers=1)  # planner: plan sets (library thread pool)
     up_stream = torch.cuda.Stream()
 
     # knob settings recorded by the autotuner for this workload (plan options
@@ -300,9 +307,8 @@ def main():
     tuned = {p: tune.load("q3_200_600", p) for p in (0, 1)} if not args.untuned else {0: {}, 1: {}}
 
     # wall time of each part of the pipeline, summed over the timed steps
-    phase = {k: 0.0 for k in ("prepare", "plan", "batch", "upload", "handoff", "device", "launch",
-                              "submit", "finish", "wait", "jones", "release", "gpu")}
-    counter = [0]
+    phase = {k: 0.0 for k in ("plan", "plan_blocked", "free", "prepare", "batch", "upload",
+                              "handoff", "launch", "finish", "wait", "jones", "gpu", "gpu_start")}
 
     def workspace(slot, need, precision):
         ws = state.get(("ws", precision, slot))
@@ -312,31 +318,19 @@ def main():
         return ws
 
     def plan_stage(precision=0):
-        tp = time.perf_counter()
         opts = {k: v for k, v in tuned[precision].items() if k != "grid"}
         opts["strategy"] = args.strategy
-        plans = kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, precision=precision,
-                            **opts)
-        phase["plan"] += time.perf_counter() - tp
-        return plans
+        return kn.plan_set(ncr_arr, flat_pd, q, n_threads=args.threads, precision=precision,
+                           **opts)
 
-    def prepare(precision=0, planned=None):
-        """Plans (or the plan stage's future), then the batch device program
-        and its upload."""
-        tp = time.perf_counter()
-        plans = plan_stage(precision) if planned is None else planned.result()
-        taits = plans  # the set holds the Tait graphs too
+    def build_stage(plans, slot, precision=0):
+        """A plan set's batch device program, uploaded into workspace `slot`
+        behind the contraction that used that workspace last."""
         t1 = time.perf_counter()
         batch = kn.Batch(plans)
         if tuned[precision].get("grid"):
             batch.set_grid(int(tuned[precision]["grid"]))
         t2 = time.perf_counter()
-        # prefetch + 1 workspaces in turn: the upload into this one waits (on
-        # the GPU, not here) for the contraction that used it last, prefetch + 1
-        # batches ago; that contraction's launch came before this preparation
-        # was queued
-        slot = counter[0] % (args.prefetch + 1)
-        counter[0] += 1
         ws = workspace(slot, batch.workspace_bytes, precision)
         last = state.get(("done", precision, slot))
         if last is not None:
@@ -348,91 +342,156 @@ def main():
         phase["batch"] += t2 - t1
         phase["upload"] += t3 - t2
         phase["prepare"] += t3 - t1
-        return taits, plans, batch, uploaded, slot
+        return plans, plans, batch, uploaded, slot  # the set holds the Tait graphs too
+
+    def prepare(precision=0):
+        """One batch planned, built and uploaded on the calling thread (into a
+        workspace of its own)."""
+        return build_stage(plan_stage(precision), "host", precision)
 
     def launch(prepared, precision=0):
-        """Queue batch i's contraction behind its upload."""
+        """Queue batch i's contraction behind its upload (and behind what the
+        stream already holds: batch i - 1's contraction)."""
         taits, plans, batch, uploaded, slot = prepared
-        z = state.get(("z", precision))
+        z = state.get(("z", precision, slot))
         if z is None:
             z = kn.alloc_scalars(B)
-            state[("z", precision)] = z
+            state[("z", precision, slot)] = z
         t1 = time.perf_counter()
+        pre = torch.cuda.Event(enable_timing=True)
+        pre.record(stream)
         stream.wait_event(uploaded)
         start = torch.cuda.Event(enable_timing=True)
         start.record(stream)
         batch.contract(stream=stream, z=z)
         done = torch.cuda.Event(enable_timing=True)
         done.record(stream)
-        state["start"] = start
         state[("done", precision, slot)] = done
         phase["launch"] += time.perf_counter() - t1
-        return done, z
+        return dict(z=z, pre=pre, start=start, done=done)
 
-    def release(box):
-        box.pop()
-
-    def finish(prepared, done, z, hand=None):
-        """While the GPU runs batch i: form V = A Z of batch i - 1 (handed over
-        in the list `hand`, which holds the only reference) and release that
-        batch; then wait for batch i's Z."""
+    def finish(prepared, launched, to_free, hand=None):
+        """While the device runs batch i (and has batch i + 1 queued): form
+        V = A Z of batch i - 1 (handed over in the list `hand`, which holds
+        the only reference) and pass that batch on to be freed; then wait for
+        batch i's Z."""
         taits, plans, batch = prepared[:3]
+        done, z = launched["done"], launched["z"]
         previous = hand.pop() if hand else None
         t2 = time.perf_counter()
         if previous is not None:
             kn.jones_many(q, previous[0], previous[3])
-        t21 = time.perf_counter()
-        # batch i - 1 (plans, Tait graphs, device program) is released by the
-        # helper thread between two preparations: freed while the planning
-        # threads allocate, its many small blocks would contend for the
-        # allocator's locks (several ms instead of a fraction of one)
-        if previous is not None:
-            pool.submit(release, [previous])
+            to_free.put([previous])
         del previous
         t3 = time.perf_counter()
-        phase["release"] += t3 - t21
         # wait without spinning: the planning threads need every core
         while not done.query():
             time.sleep(50e-6)
         zh = z.cpu().numpy()
         t4 = time.perf_counter()
-        # the contraction's own time inside the pipeline (device clock)
-        phase["gpu"] += state["start"].elapsed_time(done) / 1e3
-        phase["jones"] += t21 - t2
+        # the contraction's own time inside the pipeline (device clock), and
+        # how long it waited on the device for its upload once the stream
+        # reached it
+        phase["gpu"] += launched["start"].elapsed_time(done) / 1e3
+        phase["gpu_start"] += launched["pre"].elapsed_time(launched["start"]) / 1e3
+        phase["jones"] += t3 - t2
         phase["wait"] += t4 - t3
         return taits, plans, batch, zh
 
     def run_steps(n, precision=0):
-        """n whole batches, host preparation (and upload) of batch i+1
-        overlapped with the device work of batch i; returns the last batch's
+        """n whole batches through the three threads; returns the last batch's
         results (every batch's V is formed before this returns)."""
-        # two helper stages run up to `prefetch` batches ahead: the planner
-        # plans batch j + 1 on the library's thread pool while the builder
-        # makes batch j's device program and uploads it, so a step costs the
-        # longer of the two stages rather than their sum
-        def submit():
-            return pool.submit(prepare, precision, planner.submit(plan_stage, precision))
+        plan_q = queue.Queue(maxsize=1)   # planned, not yet being built
+        built_q = queue.Queue(maxsize=1)  # built and uploaded, not yet launched
+        free_q = queue.SimpleQueue()      # done with: freed by the planner thread
+        stop = threading.Event()
 
-        futs = [submit() for _ in range(min(args.prefetch, n))]
-        cur = None
-        for i in range(n):
+        def put(dst, item):
+            """Blocking put that gives up once the run has stopped."""
+            while not stop.is_set():
+                try:
+                    dst.put(item, timeout=0.05)
+                    return True
+                except queue.Full:
+                    pass
+            return False
+
+        def get(src):
+            while True:
+                try:
+                    item = src.get(timeout=0.05)
+                except queue.Empty:
+                    if stop.is_set():
+                        raise RuntimeError("pipeline stopped")
+                    continue
+                if isinstance(item, BaseException):
+                    raise item
+                return item
+
+        def drain_free():
+            while True:
+                try:
+                    free_q.get_nowait().clear()
+                except queue.Empty:
+                    return
+
+        def planner():
+            try:
+                for _ in range(n):
+                    t0 = time.perf_counter()
+                    drain_free()
+                    t1 = time.perf_counter()
+                    plans = plan_stage(precision)
+                    t2 = time.perf_counter()
+                    ok = put(plan_q, plans)
+                    del plans
+                    phase["free"] += t1 - t0
+                    phase["plan"] += t2 - t1
+                    phase["plan_blocked"] += time.perf_counter() - t2
+                    if not ok:
+                        return
+            except BaseException as e:  # handed to the launch thread
+                put(plan_q, e)
+
+        def builder():
+            try:
+                for j in range(n):
+                    prepared = build_stage(get(plan_q), j % N_SLOTS, precision)
+                    ok = put(built_q, prepared)
+                    del prepared
+                    if not ok:
+                        return
+            except BaseException as e:
+                put(built_q, e)
+
+        helpers = [threading.Thread(target=planner, daemon=True),
+                   threading.Thread(target=builder, daemon=True)]
+        for t in helpers:
+            t.start()
+
+        def take_and_launch():
             t0 = time.perf_counter()
-            prepared = futs.pop(0).result()
-            t1 = time.perf_counter()
-            done, z = launch(prepared, precision)
-            ts = time.perf_counter()
-            if i + args.prefetch < n:
-                futs.append(submit())
-            hand = [cur] if cur is not None else None
+            prepared = get(built_q)
+            phase["handoff"] += time.perf_counter() - t0
+            return prepared, launch(prepared, precision)
+
+        try:
             cur = None
-            tf = time.perf_counter()
-            cur = finish(prepared, done, z, hand)
-            del prepared
-            te = time.perf_counter()
-            phase["handoff"] += t1 - t0
-            phase["submit"] += tf - ts
-            phase["finish"] += te - tf
-            phase["device"] += te - t1
+            nxt = take_and_launch()
+            for i in range(n):
+                prepared, launched = nxt
+                nxt = take_and_launch() if i + 1 < n else None
+                hand = [cur] if cur is not None else None
+                cur = None
+                tf = time.perf_counter()
+                cur = finish(prepared, launched, free_q, hand)
+                del prepared, launched
+                phase["finish"] += time.perf_counter() - tf
+        finally:
+            stop.set()
+            for t in helpers:
+                t.join()
+        drain_free()
         taits, plans, batch, zh = cur
         v, l2, ar = kn.jones_many(q, taits, zh)
         return taits, plans, batch, zh, v, l2, ar
@@ -528,8 +587,9 @@ def main():
         "host_plan_ms": ms_plan,
         "host_prepare_ms": ms_prepare,
         "host_threads": args.threads if args.threads > 0 else len(os.sched_getaffinity(0)),
-        "pipelined": f"host preparation of batches i+1..i+{args.prefetch} overlaps the GPU work "
-                     "of batch i; planning batch j+1 overlaps building batch j's device program",
+        "pipelined": "three threads: planning batch i+2 and building and uploading batch i+1 "
+                     "overlap the GPU work of batch i; batch i+1 is queued on the stream "
+                     "behind batch i",
         "pipeline_ms": pipeline_ms,
         "tuned": tuned[0] or None,
         "gpu_contract": {

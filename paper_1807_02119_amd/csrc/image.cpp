@@ -76,9 +76,36 @@ constexpr int32_t kSplitMaxChunks = 16;
 
 }  // namespace
 
+void Section::assign(const SectionBuild& b) {
+  size_t words = 0;
+  auto count = [&](const auto& v) {
+    words += (v.size() * sizeof(v[0]) + 7) / 8;
+  };
+  count(b.td), count(b.sd), count(b.vd), count(b.vslot), count(b.md), count(b.members);
+  count(b.fac), count(b.strides), count(b.comps), count(b.pins), count(b.consts);
+  count(b.tasks), count(b.groups);
+  block.reset(new uint64_t[std::max<size_t>(1, words)]);
+  uint64_t* at = block.get();
+  auto take = [&](auto& dst, const auto& v) {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    static_assert(alignof(T) <= 8, "section arrays are 8-byte aligned");
+    const size_t bytes = v.size() * sizeof(T);
+    if (bytes) std::memcpy(at, v.data(), bytes);
+    dst.p = reinterpret_cast<const T*>(at);
+    dst.n = v.size();
+    at += (bytes + 7) / 8;
+  };
+  take(td, b.td), take(sd, b.sd), take(vd, b.vd), take(vslot, b.vslot), take(md, b.md);
+  take(members, b.members), take(fac, b.fac), take(strides, b.strides), take(comps, b.comps);
+  take(pins, b.pins), take(consts, b.consts), take(tasks, b.tasks), take(groups, b.groups);
+  kd = b.kd;
+  est = b.est;
+  lds_used = b.lds_used;
+  arena_elems = b.arena_elems;
+}
+
 void make_section(PlanKnot& k) {
-  Section& S = k.sec;
-  S = Section();
+  SectionBuild S;
   const int32_t q = k.q;
   KnotDesc& d = S.kd;
   std::memset(&d, 0, sizeof(d));
@@ -423,6 +450,7 @@ void make_section(PlanKnot& k) {
     }
     S.groups.push_back(G);
   }
+  k.sec.assign(S);
 }
 
 int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
@@ -693,16 +721,14 @@ int64_t build_image_into(const std::vector<const PlanKnot*>& knots,
     const double per_chain = (double)((k.n_slices - slice + chains - 1) / chains);
     roots[ui] = {-S.est * per_chain, tk0 + S.groups[0].first_task};
   };
-  // a few units per thread; small images are laid out on the calling thread
+  // a few units per thread on the host pool when it is idle; small images,
+  // and images built while the pool plans, are laid out on the calling thread
   const size_t nth = std::min<size_t>(std::max<size_t>(1, nU / 16), (size_t)usable_cpus());
-  if (nth <= 1) {
-    for (size_t ui = 0; ui < nU; ++ui) place(ui);
-  } else {
-    std::atomic<size_t> next{0};
-    parallel_run((int32_t)std::min<size_t>(nth, 16), [&] {
-      for (size_t ui; (ui = next.fetch_add(1)) < nU;) place(ui);
-    });
-  }
+  std::atomic<size_t> next{0};
+  auto worker = [&] {
+    for (size_t ui; (ui = next.fetch_add(1)) < nU;) place(ui);
+  };
+  if (!parallel_run_idle((int32_t)std::min<size_t>(nth, 16), worker)) worker();
   {
     std::vector<std::pair<double, int32_t>> rs;
     rs.reserve(n_roots);

@@ -133,7 +133,9 @@ class SpinList {
 
 // One knot's part of a device program with knot-local ids and offsets; an
 // image is the concatenation of sections with the ids shifted (build_image).
-struct Section {
+// make_section fills a SectionBuild; the Section kept with the plan holds the
+// same arrays in one allocation (a batch frees hundreds of plans at once).
+struct SectionBuild {
   KnotDesc kd;                      // offsets relative to the section
   std::vector<TensorDesc> td;       // off relative to the knot's arena base
   std::vector<StepDesc> sd;         // a, b, c knot-local; str relative to `strides`
@@ -151,6 +153,43 @@ struct Section {
   double est = 0;                   // estimated chain time (start priority)
   int32_t lds_used = 0;             // bytes of LDS arena the knot needs
   int64_t arena_elems = 0;
+};
+
+// A read-only array inside a Section's block.
+template <class T>
+struct SecArr {
+  const T* p = nullptr;
+  size_t n = 0;
+  size_t size() const { return n; }
+  bool empty() const { return n == 0; }
+  const T* data() const { return p; }
+  const T& operator[](size_t i) const { return p[i]; }
+  const T* begin() const { return p; }
+  const T* end() const { return p + n; }
+};
+
+struct Section {
+  KnotDesc kd;
+  SecArr<TensorDesc> td;
+  SecArr<StepDesc> sd;
+  SecArr<VtxDesc> vd;
+  SecArr<int32_t> vslot;
+  SecArr<MEdge> md;
+  SecArr<int32_t> members;
+  SecArr<Factor> fac;
+  SecArr<int32_t> strides;
+  SecArr<int32_t> comps;
+  SecArr<int32_t> pins;
+  SecArr<double> consts;
+  SecArr<TaskDesc> tasks;
+  SecArr<GroupDesc> groups;
+  double est = 0;
+  int32_t lds_used = 0;
+  int64_t arena_elems = 0;
+  std::unique_ptr<uint64_t[]> block;  // every array above, 8-byte aligned
+
+  // Copy a built section into one block (replacing what was held).
+  void assign(const SectionBuild& b);
 };
 
 // How one step runs: inside a serial task, or as tiles over workgroups.
@@ -239,7 +278,7 @@ struct PlanKnot {
     std::vector<PTiling>().swap(tiling);
     std::vector<int32_t>().swap(comps);
     std::vector<Factor>().swap(factors);
-    std::vector<int32_t>{0}.swap(medge_off);
+    std::vector<int32_t>().swap(medge_off);
     std::vector<int32_t>().swap(medge_mem);
     std::vector<int32_t>().swap(medge_const);
     std::vector<std::complex<double>>().swap(consts);
@@ -315,6 +354,10 @@ struct FitAlloc {
 // callers in a process forked after the pool started, get threads of their
 // own for the call.
 void parallel_run(int32_t n_threads, const std::function<void()>& f);
+// f on up to n_threads threads of the pool (the caller's among them) when no
+// other call holds it; otherwise false, with f not run (the caller runs it
+// alone rather than adding threads to cores the other call keeps busy).
+bool parallel_run_idle(int32_t n_threads, const std::function<void()>& f);
 
 // CPUs this process may run on (its affinity mask), at least 1.
 int32_t usable_cpus();

@@ -108,6 +108,15 @@ void parallel_run(int32_t n_threads, const std::function<void()>& f) {
   for (auto& th : extra) th.join();
 }
 
+bool parallel_run_idle(int32_t n_threads, const std::function<void()>& f) {
+  if (n_threads <= 1) return false;
+  Pool* pl = pool();
+  std::unique_lock<std::mutex> lock(pl->call_mu, std::try_to_lock);
+  if (!lock.owns_lock()) return false;
+  pl->run(std::min(n_threads, pl->size() + 1) - 1, f);
+  return true;
+}
+
 }  // namespace kn
 
 using kn::usable_cpus;
