@@ -206,6 +206,16 @@ void kn_tait_free(kn_tait* g);
  *               the knot's vertex tensors (if the run starts the knot) and
  *               one for the steps above them.  Not applied to gradient plans
  *               (their tensors are read twice).  0 = default 10; 40 = never.
+ * split_min_log2  a step split into tiles over workgroups whose tiles are
+ *               few (fewer than 256) while its contracted index is long has
+ *               that index split as well: each split computes partial sums
+ *               over one segment and a reduce task adds them in split order.
+ *               An index of nk entries has at most nk / 2^split_min_log2
+ *               segments, rounded up (and at most 256), of equal length.
+ *               Every task costs a few microseconds
+ *               of claiming, descriptor loads and release whatever its size,
+ *               so short segments make many tasks that each do little.
+ *               0 = default 12.
  * paper_stats   1: also compute delta_h_paper (costs about as much as the
  *               plan itself); 0: delta_h_paper = -1.
  * lds_bytes     per-workgroup LDS for tensors that live inside one serial task
@@ -256,6 +266,7 @@ typedef struct {
   kn_bucket_opts bucket[KN_N_BUCKETS];
   int32_t order_trials;
   int32_t fork_serial_log2;
+  int32_t split_min_log2;
 } kn_plan_opts;
 
 /* Statistics of a plan (algorithmic, from the plan itself).

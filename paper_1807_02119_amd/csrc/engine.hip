@@ -398,9 +398,10 @@ struct GenIx {
   const int32_t *tab[6];  // A_b A_m A_k B_b B_k B_n (nullptr: decode)
   const int32_t *str[6];
   int32_t rank[6];
+  int32_t lo[6];          // first index a table holds (a contracted segment)
   QDiv D;
   __device__ inline int32_t off(int g, int32_t i) const {
-    return tab[g] ? tab[g][i] : group_off(i, str[g], rank[g], D);
+    return tab[g] ? tab[g][i - lo[g]] : group_off(i, str[g], rank[g], D);
   }
   __device__ inline int32_t a_row(int32_t b, int32_t m) const { return off(0, b) + off(1, m); }
   __device__ inline int32_t b_col(int32_t b, int32_t n) const { return off(3, b) + off(5, n); }
@@ -787,41 +788,75 @@ __device__ inline GenIx step_ix(const DevProg& p, const StepDesc& s, int32_t q) 
                {sp, sp + rb, sp + rb + rm, sp + rb + rm + rk, sp + 2 * rb + rm + rk,
                 sp + 2 * rb + rm + 2 * rk},
                {rb, rm, rk, rb, rk, rn},
+               {0, 0, 0, 0, 0, 0},
                QDiv(q)};
 }
 
 // STEP_TILES: `tile` consecutive outputs of C (row-major over b, m, n), over
 // contracted range ks of the split.  Tile tasks use none of the serial-task
 // LDS areas, so the whole dynamic LDS (tab_cap entries) holds generated offset
-// tables: contracted group first, then columns, rows, batch.
+// tables: contracted group first (only this task's segment of it when the
+// contracted index is split), then columns, rows, batch; the last 16 entries
+// are kept for the partial sums of a one-output tile.
+//
+// A tile of one output over a long segment (the scalar product that ends a
+// knot's contraction, split over many tasks) is summed by all four
+// wavefronts, a quarter of the segment each; wavefront 0's thread 0 adds the
+// four partial sums in wavefront order.
 template <class T>
 __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* arena, int32_t* s_tab, int32_t tab_cap, const States& st,
                           T* s_red) {
   GenIx ix = step_ix(p, s, q);
-  const int32_t n_of[6] = {s.nb, s.nm, s.nk, s.nb, s.nk, s.nn};
-  int32_t used = 0;
-  for (int g : {2, 4, 5, 1, 0, 3}) {
-    if (used + n_of[g] > tab_cap) continue;
-    int32_t* t = s_tab + used;
-    for (int32_t i = threadIdx.x; i < n_of[g]; i += kBlock) t[i] = group_off(i, ix.str[g], ix.rank[g], ix.D);
-    ix.tab[g] = t;
-    used += n_of[g];
-  }
-  int64_t ec;
-  const T scale = step_scale<T>(st, s.a, s.b, ec);
-  __syncthreads();
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
   const int32_t base = s.n_tiles / s.n_ks;
   const int32_t ks = tile_id / base, t = tile_id - ks * base;
   const int32_t k0 = ks * s.kseg, k1 = min(s.nk, k0 + s.kseg);
   const int64_t o0 = (int64_t)t * s.tile;
   const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
-  const int32_t L = lanes_per_output(o1 - o0, k1 - k0);
+  constexpr int32_t kPartials = 16;  // 4 complex partial sums (64 bytes)
+  const int32_t lo_of[6] = {0, 0, k0, 0, k0, 0};
+  const int32_t n_of[6] = {s.nb, s.nm, k1 - k0, s.nb, k1 - k0, s.nn};
+  int32_t used = 0;
+  for (int g : {2, 4, 5, 1, 0, 3}) {
+    if (used + n_of[g] > tab_cap - 2 * kPartials) continue;
+    int32_t* tb = s_tab + used;
+    for (int32_t i = threadIdx.x; i < n_of[g]; i += kBlock)
+      tb[i] = group_off(lo_of[g] + i, ix.str[g], ix.rank[g], ix.D);
+    ix.tab[g] = tb;
+    ix.lo[g] = lo_of[g];
+    used += n_of[g];
+  }
+  int64_t ec;
+  const T scale = step_scale<T>(st, s.a, s.b, ec);
+  __syncthreads();
   Cx<T>* pc = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
-  T lm = step_outputs<T>((const GlbCx<T>*)(arena + s.home_a), (const GlbCx<T>*)(arena + s.home_b),
-                         GlbOut<T>((GlbCx<T>*)pc + o0), ix, s.nm, s.nn, k0, k1, o0, o1, scale,
-                         L, (int32_t)threadIdx.x, kBlock);
+  const GlbCx<T>* pa = (const GlbCx<T>*)(arena + s.home_a);
+  const GlbCx<T>* pb = (const GlbCx<T>*)(arena + s.home_b);
+  T lm = 0;
+  if (o1 - o0 == 1 && k1 - k0 >= 2 * kBlock) {
+    LdsCx<T>* part = (LdsCx<T>*)(s_tab + ((used + 3) & ~3));  // 16-byte aligned
+    const int32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t quarter = (k1 - k0 + 3) / 4;
+    const int32_t kw0 = min(k1, k0 + w * quarter), kw1 = min(k1, kw0 + quarter);
+    step_outputs<T>(pa, pb, part + w, ix, s.nm, s.nn, kw0, kw1, o0, o1, T(1), 64, lane, 64);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T re = 0, im = 0;
+      for (int i = 0; i < 4; ++i) {
+        re += part[i].re;
+        im += part[i].im;
+      }
+      re *= scale;
+      im *= scale;
+      put(GlbOut<T>((GlbCx<T>*)pc + o0), 0, Cx<T>{re, im});
+      lm = fmax(fabs(re), fabs(im));
+    }
+  } else {
+    const int32_t L = lanes_per_output(o1 - o0, k1 - k0);
+    lm = step_outputs<T>(pa, pb, GlbOut<T>((GlbCx<T>*)pc + o0), ix, s.nm, s.nn, k0, k1, o0, o1,
+                         scale, L, (int32_t)threadIdx.x, kBlock);
+  }
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
 }
 

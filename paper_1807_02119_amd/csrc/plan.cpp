@@ -58,8 +58,14 @@ inline int32_t bucket_of(double outs) {
   for (double lim = 256.0; b < KN_N_BUCKETS - 1 && outs > lim; lim *= 16.0) ++b;
   return b;
 }
-// Steps with fewer tiles than this split a long contracted index.
+// Steps with fewer tiles than this split a long contracted index of nk
+// entries, into at most nk / 2^kSplitMinLog2 segments: a task costs a few
+// microseconds of claim, descriptor loads and release whatever its size, and
+// the scalar products that end the workload's knots (3^9 to 3^12 contracted
+// entries) ran fastest as segments of 2^12 to 2^13 (one 256-knot batch: 2.06
+// ms with segments of 128 entries, 1.66 ms with 2^11, 1.64 ms with 2^12).
 constexpr double kSplitBelow = 256;
+constexpr int32_t kSplitMinLog2 = 12;
 // Auto ordering also tries the greedy plan when the min-fill plan has at least
 // this many flops (below it the greedy plan rarely wins and planning time
 // matters more).
@@ -1338,7 +1344,8 @@ kn_status lay_out(PlanKnot& k, const kn_plan_opts& o, kn_plan_stats& st, int32_t
     t.n_ks = 1;
     t.kseg = (int32_t)nk;
     if (nk >= 256 && base < kSplitBelow) {
-      double want = std::ceil(kSplitBelow / base), most = std::ceil(nk / 128.0);
+      const double seg = std::ldexp(1.0, o.split_min_log2 > 0 ? o.split_min_log2 : kSplitMinLog2);
+      double want = std::ceil(kSplitBelow / base), most = std::ceil(nk / seg);
       double ks = std::min(std::min(want, most), 256.0);
       if (ks > 1) {
         int64_t kseg = (int64_t)std::ceil(nk / ks);
@@ -1620,6 +1627,7 @@ extern "C" kn_status kn_plan_create(const kn_tait* g, int32_t q, const kn_plan_o
   if (o.slice_log2_budget < 0 || o.slice_log2_budget > 40) return KN_E_INVALID;
   if (o.split_serial_log2 < 0 || o.split_serial_log2 > 40) return KN_E_INVALID;
   if (o.fork_serial_log2 < 0 || o.fork_serial_log2 > 40) return KN_E_INVALID;
+  if (o.split_min_log2 < 0 || o.split_min_log2 > 30) return KN_E_INVALID;
   if (o.gemm_tasks_log2 < 0 || o.gemm_tasks_log2 > 30) return KN_E_INVALID;
   if (o.gemm64_pct < 0 || o.gemm64_pct > 100000) return KN_E_INVALID;
   if (o.big_step_outs_log2 < 0 || o.big_step_outs_log2 > 31) return KN_E_INVALID;

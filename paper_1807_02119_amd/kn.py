@@ -49,14 +49,15 @@ class PlanOpts(ctypes.Structure):
                 ("split_serial_log2", ctypes.c_int32), ("gemm_tasks_log2", ctypes.c_int32),
                 ("gemm64_pct", ctypes.c_int32), ("big_step_outs_log2", ctypes.c_int32),
                 ("tile_outs_log2", ctypes.c_int32), ("bucket", BucketOpts * N_BUCKETS),
-                ("order_trials", ctypes.c_int32), ("fork_serial_log2", ctypes.c_int32)]
+                ("order_trials", ctypes.c_int32), ("fork_serial_log2", ctypes.c_int32),
+                ("split_min_log2", ctypes.c_int32)]
 
 
 def plan_opts(strategy=3, precision=0, simplify=None, jones_only=True, mem_budget_bytes=0,
               tile_outputs=0, big_step_macs_log2=0, paper_stats=False, lds_bytes=0,
               gradient=False, tile_macs_log2=0, slice_log2_budget=0, split_serial_log2=0,
               gemm_tasks_log2=0, gemm64_pct=0, big_step_outs_log2=0, tile_outs_log2=0,
-              buckets=None, order_trials=0, fork_serial_log2=0):
+              buckets=None, order_trials=0, fork_serial_log2=0, split_min_log2=0):
     """kn_plan_opts from keyword arguments (0 = the library default).
     ``buckets``: {bucket index: {knob: value}} overrides of the tile-shape knobs
     (BUCKET_KNOBS) per intermediate-size bucket (keys may be strings)."""
@@ -72,7 +73,7 @@ def plan_opts(strategy=3, precision=0, simplify=None, jones_only=True, mem_budge
                     ("split_serial_log2", split_serial_log2), ("gemm_tasks_log2", gemm_tasks_log2),
                     ("gemm64_pct", gemm64_pct), ("big_step_outs_log2", big_step_outs_log2),
                     ("tile_outs_log2", tile_outs_log2), ("order_trials", order_trials),
-                    ("fork_serial_log2", fork_serial_log2)):
+                    ("fork_serial_log2", fork_serial_log2), ("split_min_log2", split_min_log2)):
         setattr(o, name, int(v))
     for b, knobs in (buckets or {}).items():
         for name, v in knobs.items():

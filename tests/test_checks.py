@@ -30,7 +30,7 @@ def _plans():
     t = kn.Tait(work[5][0].pd)
     out.append(("fp32", kn.Plan(t, 3, precision=1)))
     out.append(("tiles", kn.Plan(t, 3, big_step_macs_log2=4, tile_outputs=8)))
-    out.append(("split", kn.Plan(t, 3, big_step_macs_log2=4, tile_macs_log2=3)))
+    out.append(("split", kn.Plan(t, 3, big_step_macs_log2=4, tile_macs_log2=3, split_min_log2=7)))
     out.append(("sliced", kn.Plan(t, 3, slice_log2_budget=6)))
     out.append(("separator", kn.Plan(t, 3, strategy=4)))
     g = kn.Tait(gen.lattice_knot((45, 1), 60, 120).pd)

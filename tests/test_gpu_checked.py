@@ -55,7 +55,7 @@ for d, q in gen.config_knots("tiny", 0)[:4]:
 d5 = work[5][0]
 run("default", d5, 3)
 run("tiles", d5, 3, big_step_macs_log2=4, tile_outputs=8)
-run("split", d5, 3, big_step_macs_log2=4, tile_macs_log2=3)
+run("split", d5, 3, big_step_macs_log2=4, tile_macs_log2=3, split_min_log2=7)
 run("complex64", d5, 3, tol=TOL32, precision=1)
 run("sliced", gen.lattice_knot((82, 1), 40, 120), 3, slice_log2_budget=4)
 run("separator", work[7][0], 3, strategy=4)

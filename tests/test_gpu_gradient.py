@@ -85,7 +85,8 @@ def test_gradient_tiled_steps():
         t = kn.Tait(d.pd)
         J, Jd = _couplings(t, rng)
         mo, eo, go = _oracle(t, J, 3)
-        for kw in (dict(big_step_macs_log2=4), dict(big_step_macs_log2=6, tile_outputs=16)):
+        for kw in (dict(big_step_macs_log2=4, split_min_log2=7),
+                   dict(big_step_macs_log2=6, tile_outputs=16)):
             _log(f"gradient tiled {d.label} {kw}")
             p = kn.Plan(t, 3, jones_only=False, gradient=True, **kw)
             m, e, g = _gpu_grad(p, Jd)

@@ -170,6 +170,7 @@ def test_gemm_and_split_parity():
     cases.append(("lattice0", gen.lattice_knot((63, 0), 100, 400),
                   dict(big_step_macs_log2=4, gemm_tasks_log2=2)))
     for name, d, kw in cases:
+        kw = dict(kw, split_min_log2=7)  # segments of 128 entries: GEMM steps split too
         _log(f"gemm/split case {name} {kw}")
         tg, mo, eo = oracle_z(d, 3)
         for prec in (0, 1):
@@ -200,7 +201,9 @@ def test_gemm64_split_ragged_full_size():
     d = gen.config_knots("q3_200_600", 0, count=79)[78][0]
     tg = oracle_tait(d)
     dd, unit = invariants.q3_class(tg.n_vertices, tg.edges, tg.eps)
-    for kw in (dict(gemm64_pct=100000, gemm_tasks_log2=30), dict(gemm64_pct=100000, gemm_tasks_log2=1)):
+    for kw in (dict(gemm64_pct=100000, gemm_tasks_log2=30, split_min_log2=7),
+               dict(gemm64_pct=100000, gemm_tasks_log2=1, split_min_log2=7),
+               dict(gemm64_pct=100000)):
         _log(f"gemm64 knot 78 {kw}")
         t, p, m, e = gpu_z(d, 3, **kw)
         v, l2, ar = kn.jones(3, t, m, e)

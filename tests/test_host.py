@@ -162,14 +162,46 @@ def _split_gemm_cases():
              (work[11][0], {})]
     for k in range(2):
         cases.append((gen.lattice_knot((63, k), 100, 400), dict(big_step_macs_log2=4)))
-    return cases
+    # segments of 128 contracted entries, so that GEMM steps split too
+    return [(d, dict(kw, split_min_log2=7)) for d, kw in cases]
+
+
+def test_default_split_segments():
+    """By default a contracted index of nk entries is split into at most
+    nk / 2^12 segments, rounded up (split_min_log2), and the workload's plans
+    end with scalar
+    products split that way: one output summed over segments of thousands of
+    entries, which the engine shares out to the four wavefronts of a task.
+    The parity tests of the workload on the GPU run such steps.  The model
+    evaluates the default plans of a few of them to the oracle's Z."""
+    work = gen.config_knots("q3_200_600", 0, count=24)
+    one_output = []
+    for i, (d, q) in enumerate(work):
+        p = kn.Plan(kn.Tait(d.pd), q)
+        for s in image_model.Image(p.image()).steps:
+            if int(s["mode"]) == image_model.STEP_SERIAL or int(s["n_ks"]) < 2:
+                continue
+            nk = int(s["nk"])
+            assert int(s["n_ks"]) <= -(-nk // 4096), (i, nk, int(s["n_ks"]))
+            if int(s["nb"]) * int(s["nm"]) * int(s["nn"]) == 1:
+                one_output.append(i)
+    assert len(set(one_output)) >= 2
+    for i in sorted(set(one_output))[:2]:
+        _check_model(work[i][0], 3)
+    # split_min_log2 = 7: segments of 128 entries again, more of them
+    d = work[one_output[0]][0]
+    fine = kn.Plan(kn.Tait(d.pd), 3, split_min_log2=7)
+    assert fine.stats["n_tasks"] > kn.Plan(kn.Tait(d.pd), 3).stats["n_tasks"]
+    with pytest.raises(kn.KnError):
+        kn.Plan(kn.Tait(d.pd), 3, split_min_log2=31)
 
 
 def gemm64_cases():
     """(label, knot, q, plan options) whose plans hold 64 x 64 GEMM steps:
     ragged sides, several blocks per task, and a split contracted range."""
     work = gen.config_knots("q3_200_600", 0, count=103)
-    wide = dict(gemm64_pct=100000)
+    # segments of 128 contracted entries, so that GEMM steps split too
+    wide = dict(gemm64_pct=100000, split_min_log2=7)
     return [("work71", work[71][0], 3, dict(strategy=0, simplify=3, **wide)),
             ("work94", work[94][0], 3, dict(gemm_tasks_log2=1, **wide)),
             ("work102", work[102][0], 3, dict(strategy=0, simplify=3, **wide)),
@@ -206,7 +238,7 @@ def test_plan_model_gemm64_split_ragged_full_size():
     from oracle import invariants
     d = gen.config_knots("q3_200_600", 0, count=79)[78][0]
     t = kn.Tait(d.pd)
-    p = kn.Plan(t, 3, gemm64_pct=100000, gemm_tasks_log2=1)
+    p = kn.Plan(t, 3, gemm64_pct=100000, gemm_tasks_log2=1, split_min_log2=7)
     steps = image_model.Image(p.image()).steps
     assert any(int(s["mode"]) == image_model.STEP_GEMM64 and int(s["n_ks"]) > 1
                and int(s["nm"]) % 64 != 0 for s in steps)
