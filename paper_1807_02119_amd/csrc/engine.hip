@@ -398,15 +398,18 @@ struct GenIx {
   const int32_t *tab[6];  // A_b A_m A_k B_b B_k B_n (nullptr: decode)
   const int32_t *str[6];
   int32_t rank[6];
-  int32_t lo[6];          // first index a table holds (a contracted segment)
+  int32_t klo;            // first contracted index the A_k and B_k tables hold
   QDiv D;
   __device__ inline int32_t off(int g, int32_t i) const {
-    return tab[g] ? tab[g][i - lo[g]] : group_off(i, str[g], rank[g], D);
+    return tab[g] ? tab[g][i] : group_off(i, str[g], rank[g], D);
+  }
+  __device__ inline int32_t off_k(int g, int32_t k) const {
+    return tab[g] ? tab[g][k - klo] : group_off(k, str[g], rank[g], D);
   }
   __device__ inline int32_t a_row(int32_t b, int32_t m) const { return off(0, b) + off(1, m); }
   __device__ inline int32_t b_col(int32_t b, int32_t n) const { return off(3, b) + off(5, n); }
-  __device__ inline int32_t a_k(int32_t k) const { return off(2, k); }
-  __device__ inline int32_t b_k(int32_t k) const { return off(4, k); }
+  __device__ inline int32_t a_k(int32_t k) const { return off_k(2, k); }
+  __device__ inline int32_t b_k(int32_t k) const { return off_k(4, k); }
 };
 
 // This lane's part of sum_k A[row, k] B[k, col] over k = k_first, k_first + L,
@@ -788,7 +791,7 @@ __device__ inline GenIx step_ix(const DevProg& p, const StepDesc& s, int32_t q) 
                {sp, sp + rb, sp + rb + rm, sp + rb + rm + rk, sp + 2 * rb + rm + rk,
                 sp + 2 * rb + rm + 2 * rk},
                {rb, rm, rk, rb, rk, rn},
-               {0, 0, 0, 0, 0, 0},
+               0,
                QDiv(q)};
 }
 
@@ -815,16 +818,16 @@ __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const
   const int64_t o0 = (int64_t)t * s.tile;
   const int64_t o1 = o0 + s.tile < outs ? o0 + s.tile : outs;
   constexpr int32_t kPartials = 16;  // 4 complex partial sums (64 bytes)
-  const int32_t lo_of[6] = {0, 0, k0, 0, k0, 0};
   const int32_t n_of[6] = {s.nb, s.nm, k1 - k0, s.nb, k1 - k0, s.nn};
+  ix.klo = k0;
   int32_t used = 0;
   for (int g : {2, 4, 5, 1, 0, 3}) {
     if (used + n_of[g] > tab_cap - 2 * kPartials) continue;
+    const int32_t lo = g == 2 || g == 4 ? k0 : 0;
     int32_t* tb = s_tab + used;
     for (int32_t i = threadIdx.x; i < n_of[g]; i += kBlock)
-      tb[i] = group_off(lo_of[g] + i, ix.str[g], ix.rank[g], ix.D);
+      tb[i] = group_off(lo + i, ix.str[g], ix.rank[g], ix.D);
     ix.tab[g] = tb;
-    ix.lo[g] = lo_of[g];
     used += n_of[g];
   }
   int64_t ec;
@@ -839,7 +842,15 @@ __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const
     const int32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t quarter = (k1 - k0 + 3) / 4;
     const int32_t kw0 = min(k1, k0 + w * quarter), kw1 = min(k1, kw0 + quarter);
-    step_outputs<T>(pa, pb, part + w, ix, s.nm, s.nn, kw0, kw1, o0, o1, T(1), 64, lane, 64);
+    const int32_t mn = s.nm * s.nn, o = (int32_t)o0;
+    const int32_t b = o / mn, m = (o - b * mn) / s.nn, n = o - b * mn - m * s.nn;
+    T cr, ci;
+    lane_dot<T>(pa + ix.a_row(b, m), pb + ix.b_col(b, n), ix, kw0 + lane, kw1, 64, cr, ci);
+    for (int32_t off = 32; off >= 1; off >>= 1) {
+      cr += __shfl_xor(cr, off, 64);
+      ci += __shfl_xor(ci, off, 64);
+    }
+    if (lane == 0) put(part, w, Cx<T>{cr, ci});
     __syncthreads();
     if (threadIdx.x == 0) {
       T re = 0, im = 0;
