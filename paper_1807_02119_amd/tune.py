@@ -13,7 +13,9 @@ How a step runs is decided by planner knobs:
 - gemm64_pct: how much padding a step accepts to use 64 x 64 output blocks
   instead of 32 x 32 ones;
 - split_serial_log2: from which estimated length a run of small steps is
-  executed level by level over several workgroups.
+  executed level by level over several workgroups;
+- split_min_log2: how many contracted entries (at least) one segment of a
+  split contracted index holds.
 The persistent kernel's grid is one more knob.  The tile-shape knobs
 (tile_macs_log2, tile_outs_log2, gemm64_pct, gemm_tasks_log2) can also be
 set per intermediate-size bucket (steps whose output has at most 2^8, 2^12,
@@ -49,6 +51,7 @@ SPACE = {
     "gemm_tasks_log2": [4, 5, 6, 7, 30],
     "gemm64_pct": [1, 150, 300],
     "split_serial_log2": [8, 10, 12, 40],
+    "split_min_log2": [9, 10, 11, 12, 13, 14],
 }
 BUCKET_SPACE = {
     "tile_macs_log2": [12, 13, 14, 15, 16, 17],
@@ -59,7 +62,8 @@ BUCKET_SPACE = {
 N_BUCKETS = 5
 DEFAULTS = {"big_step_macs_log2": 16, "big_step_outs_log2": 12, "tile_macs_log2": 15,
             "tile_outs_log2": 10, "lds_bytes": 24576, "gemm_tasks_log2": 5, "gemm64_pct": 300,
-            "split_serial_log2": 40, "grid": 0}
+            "split_serial_log2": 40, "split_min_log2": 12, "grid": 0}
+DEFAULTS_KEY = json.dumps(DEFAULTS, sort_keys=True)
 TUNED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
 
 
@@ -156,8 +160,24 @@ def make_measure(pds, qs, precision=0, reps=5, threads=0, strategy=3):
     return measure
 
 
+def flat_setting(setting):
+    """A setting as ``load`` returns it (plan-wide knobs and ``buckets``) as a
+    flat setting over every coordinate the search moves: knobs it lacks take
+    the defaults, bucket coordinates it lacks 0 (the plan-wide value)."""
+    flat = dict(DEFAULTS)
+    flat.update({k: v for k, v in setting.items() if k != "buckets" and k in DEFAULTS})
+    flat.update({k: 0 for k in bucket_space()})
+    for b, knobs in (setting.get("buckets") or {}).items():
+        for knob, v in knobs.items():
+            flat[f"{knob}@{int(b)}"] = v
+    return flat
+
+
 def tune(pds, qs, precision=0, reps=5, space=None, grids=None, buckets=True, threads=0,
-         confirm=5, strategy=3, log=print):
+         confirm=5, strategy=3, start=None, log=print):
+    """Coordinate descent from the defaults, or from ``start`` (a setting as
+    ``load`` returns it, e.g. the one recorded before); the confirmation
+    times the defaults, the start and the best alternately."""
     space = dict(SPACE if space is None else space)
     measure = make_measure(pds, qs, precision=precision, reps=reps, threads=threads,
                            strategy=strategy)
@@ -167,31 +187,37 @@ def tune(pds, qs, precision=0, reps=5, space=None, grids=None, buckets=True, thr
         log(f"  {json.dumps(split_setting(s), sort_keys=True)}: {v:.4f} ms")
         return v
 
-    start = dict(DEFAULTS)
-    best, best_v, seen = coordinate_descent(logged, space, start)
+    first = dict(DEFAULTS) if start is None else flat_setting(start)
+    best, best_v, seen = coordinate_descent(logged, space, first)
     if grids:
         best, best_v, more = coordinate_descent(logged, {"grid": list(grids)}, best, passes=1)
         seen.update(more)
-    plan_wide = dict(best)
+    plan_wide = {k: v for k, v in best.items() if "@" not in k}
     if buckets:
         bspace = bucket_space()
-        flat = dict(best, **{k: 0 for k in bspace})
+        flat = dict({k: 0 for k in bspace}, **best)
         best, best_v, more = coordinate_descent(logged, bspace, flat, passes=1)
         seen.update(more)
-    # defaults against the best, timed alternately
-    d_ms, b_ms = [], []
+    # defaults (and the start) against the best, timed alternately
+    d_ms, b_ms, s_ms = [], [], []
     for _ in range(confirm):
         d_ms.append(measure(dict(DEFAULTS)))
+        if start is not None:
+            s_ms.append(measure(dict(first)))
         b_ms.append(measure(dict(best)))
+    if DEFAULTS_KEY not in seen:
+        seen[DEFAULTS_KEY] = statistics.median(d_ms)
     table = [dict(split_setting(json.loads(k)), ms=v)
              for k, v in sorted(seen.items(), key=lambda kv: kv[1])]
     return {"best": split_setting(best), "best_ms": best_v, "plan_wide": split_setting(plan_wide),
-            "default_ms": seen[json.dumps(DEFAULTS, sort_keys=True)],
-            "confirm": {"default_ms": d_ms, "best_ms": b_ms,
-                        "default_median_ms": statistics.median(d_ms),
-                        "best_median_ms": statistics.median(b_ms),
-                        "default_spread_ms": max(d_ms) - min(d_ms),
-                        "best_spread_ms": max(b_ms) - min(b_ms)},
+            "default_ms": seen[DEFAULTS_KEY],
+            "confirm": dict({"default_ms": d_ms, "best_ms": b_ms,
+                             "default_median_ms": statistics.median(d_ms),
+                             "best_median_ms": statistics.median(b_ms),
+                             "default_spread_ms": max(d_ms) - min(d_ms),
+                             "best_spread_ms": max(b_ms) - min(b_ms)},
+                            **({"start": split_setting(first), "start_ms": s_ms,
+                                "start_median_ms": statistics.median(s_ms)} if s_ms else {})),
             "table": table}
 
 
@@ -225,6 +251,8 @@ def main():
     ap.add_argument("--strategy", type=int, default=3,
                     help="contraction-order strategy the plans are made with (kn_plan_opts)")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--from-tuned", action="store_true",
+                    help="start the search from the setting recorded for the workload")
     args = ap.parse_args()
 
     import numpy as np
@@ -246,12 +274,15 @@ def main():
            "when": time.strftime("%Y-%m-%d"), "by_precision": {}}
     for precision in (int(p) for p in args.precisions.split(",")):
         print(f"precision {precision}", flush=True)
+        start = load(args.workload, precision) if args.from_tuned else None
         res = tune(pds, qs, precision=precision, reps=args.reps,
                    grids=[0, cus, 2 * cus, 4 * cus], buckets=not args.no_buckets,
-                   strategy=args.strategy, log=lambda m: print(m, flush=True))
+                   strategy=args.strategy, start=start or None,
+                   log=lambda m: print(m, flush=True))
         c = res["confirm"]
         print(f"best {res['best']} {res['best_ms']:.4f} ms (defaults {res['default_ms']:.4f} ms); "
-              f"confirmed medians {c['best_median_ms']:.4f} vs {c['default_median_ms']:.4f} ms",
+              f"confirmed medians {c['best_median_ms']:.4f} vs {c['default_median_ms']:.4f} ms"
+              + (f", start {c['start_median_ms']:.4f} ms" if "start_median_ms" in c else ""),
               flush=True)
         out["by_precision"][str(precision)] = res
     path = args.out or os.path.join(TUNED_DIR, f"{args.workload}.json")

@@ -671,6 +671,13 @@ def test_tuner_space_is_valid():
             if workload == "q3_200_600" or rec:
                 assert rec, (workload, prec)
                 kn.Plan(t, 3, precision=prec, **tune.plan_options(rec))
+                # a recorded setting as a search start: every coordinate set,
+                # and back to the same setting (defaults filled in)
+                flat = tune.flat_setting(rec)
+                assert set(flat) == set(tune.DEFAULTS) | set(tune.bucket_space())
+                back = tune.split_setting(flat)
+                assert back.get("buckets", {}) == rec.get("buckets", {})
+                assert all(back[k] == rec.get(k, tune.DEFAULTS[k]) for k in tune.DEFAULTS)
 
 
 def test_bucket_knobs_change_only_their_bucket():
