@@ -15,7 +15,9 @@ How a step runs is decided by planner knobs:
 - split_serial_log2: from which estimated length a run of small steps is
   executed level by level over several workgroups;
 - split_min_log2: how many contracted entries (at least) one segment of a
-  split contracted index holds.
+  split contracted index holds;
+- fork_serial_log2: from which estimated length a run of small steps is
+  forked into concurrent subtree tasks.
 The persistent kernel's grid is one more knob.  The tile-shape knobs
 (tile_macs_log2, tile_outs_log2, gemm64_pct, gemm_tasks_log2) can also be
 set per intermediate-size bucket (steps whose output has at most 2^8, 2^12,
@@ -52,6 +54,7 @@ SPACE = {
     "gemm64_pct": [1, 150, 300],
     "split_serial_log2": [8, 10, 12, 40],
     "split_min_log2": [9, 10, 11, 12, 13, 14],
+    "fork_serial_log2": [8, 9, 10, 11, 40],
 }
 BUCKET_SPACE = {
     "tile_macs_log2": [12, 13, 14, 15, 16, 17],
@@ -62,7 +65,7 @@ BUCKET_SPACE = {
 N_BUCKETS = 5
 DEFAULTS = {"big_step_macs_log2": 16, "big_step_outs_log2": 12, "tile_macs_log2": 15,
             "tile_outs_log2": 10, "lds_bytes": 24576, "gemm_tasks_log2": 5, "gemm64_pct": 300,
-            "split_serial_log2": 40, "split_min_log2": 12, "grid": 0}
+            "split_serial_log2": 40, "split_min_log2": 12, "fork_serial_log2": 10, "grid": 0}
 DEFAULTS_KEY = json.dumps(DEFAULTS, sort_keys=True)
 TUNED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
 
