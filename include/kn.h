@@ -414,12 +414,7 @@ kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_
                        const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
                        int32_t n_threads, kn_tait** taits, kn_plan** plans, kn_status* status);
 /* Free n Tait graphs and n plans (as returned by kn_plan_many; null entries
- * are skipped; either array may be NULL).  The handles are invalid on return.
- * Those that kn_plan_many made go back to the planning threads: the next
- * kn_plan_many call's workers each free the ones they allocated before they
- * plan (in parallel, each from its own heap), and its caller frees the rest;
- * any others are freed here.  This keeps a pipeline's frees off the thread
- * that plans. */
+ * are skipped; either array may be NULL). */
 void kn_free_many(int32_t n, kn_tait** taits, kn_plan** plans);
 /* kn_jones for n knots: v (nullable) receives 2n doubles (re, im). */
 kn_status kn_jones_many(int32_t n, const int32_t* q, const kn_tait* const* g,

@@ -23,7 +23,6 @@ struct kn_tait {
   std::vector<int8_t> twist;  // twist sign per crossing
   int32_t writhe = 0;
   int32_t tau = 0;
-  uint32_t owner = 0;  // host thread of kn_plan_many that made it (0: none)
 };
 
 namespace kn {
@@ -450,7 +449,6 @@ struct kn_plan {
   // never need it); guarded for concurrent users of one plan
   mutable std::mutex image_mu;
   mutable kn::Bytes image;
-  uint32_t owner = 0;  // host thread of kn_plan_many that made it (0: none)
 };
 
 namespace kn {

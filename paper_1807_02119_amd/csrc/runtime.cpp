@@ -121,39 +121,6 @@ bool parallel_run_idle(int32_t n_threads, const std::function<void()>& f) {
 
 using kn::usable_cpus;
 
-namespace {
-
-// A unique id per host thread (0 is never used).
-std::atomic<uint32_t> g_next_thread_id{1};
-uint32_t this_thread_id() {
-  thread_local const uint32_t id = g_next_thread_id.fetch_add(1);
-  return id;
-}
-
-// Tait graphs and plans that kn_plan_many made, handed to kn_free_many: each
-// was allocated by one planning thread from that thread's heap.  They are
-// kept until the next kn_plan_many, whose workers each free the ones they
-// allocated, all at once and without waiting on other threads' heaps, before
-// they plan; what no worker of that call made is freed by its caller
-// afterwards.  Freed on the calling thread instead, a planning batch's few
-// thousand blocks cost a large part of a millisecond, and freed beside a
-// running kn_plan_many they contend for the planning threads' heaps.
-struct Pending {
-  kn_tait* t;
-  kn_plan* p;
-  uint32_t owner;
-};
-std::mutex g_pending_mu;
-std::vector<Pending> g_pending;
-constexpr size_t kMaxPending = size_t(1) << 16;
-
-void free_pending(const Pending& x) {
-  if (x.p) kn_plan_free(x.p);
-  if (x.t) kn_tait_free(x.t);
-}
-
-}  // namespace
-
 extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, const int32_t* pd,
                                   const int8_t* signs, const int32_t* q, const kn_plan_opts* opts,
                                   int32_t n_threads, kn_tait** taits, kn_plan** plans,
@@ -178,22 +145,7 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
                    [&](int32_t a, int32_t b) { return n_crossings[a] > n_crossings[b]; });
   std::atomic<int32_t> next{0};
   std::vector<kn_status> st(n_knots, KN_OK);
-  // sets freed since the last call (see Pending): each worker frees its own
-  std::vector<Pending> old;
-  {
-    std::lock_guard<std::mutex> lock(g_pending_mu);
-    old.swap(g_pending);
-  }
-  std::vector<uint32_t> ran(64, 0);  // ids of the threads that ran the worker
-  std::atomic<int32_t> n_ran{0};
   std::function<void()> worker = [&]() {
-    const uint32_t me = this_thread_id();
-    const int32_t w = n_ran.fetch_add(1);
-    if (w < (int32_t)ran.size()) {
-      ran[w] = me;
-      for (const Pending& x : old)
-        if (x.owner == me) free_pending(x);
-    }
     for (;;) {
       const int32_t j = next.fetch_add(1);
       if (j >= n_knots) return;
@@ -201,11 +153,9 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
       kn_tait* g = nullptr;
       kn_status rc = kn_build_tait(n_crossings[i], pd ? pd + 4 * off[i] : nullptr,
                                    signs ? signs + off[i] : nullptr, -1, 0, &g);
-      if (g) g->owner = me;
       if (rc == KN_OK) {
         kn_plan* p = nullptr;
         rc = kn_plan_create(g, q[i], opts, &p);
-        if (p) p->owner = me;
         plans[i] = p;  // also kept on KN_E_BUDGET (statistics)
       }
       taits[i] = g;
@@ -213,12 +163,6 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
     }
   };
   kn::parallel_run(nt, worker);
-  {
-    // what no worker of this call made (or a worker past the first 64)
-    const int32_t nr = std::min<int32_t>(n_ran.load(), (int32_t)ran.size());
-    for (const Pending& x : old)
-      if (std::find(ran.begin(), ran.begin() + nr, x.owner) == ran.begin() + nr) free_pending(x);
-  }
   kn_status first = KN_OK;
   for (int32_t i = 0; i < n_knots; ++i) {
     if (status) status[i] = st[i];
@@ -228,21 +172,10 @@ extern "C" kn_status kn_plan_many(int32_t n_knots, const int32_t* n_crossings, c
 }
 
 extern "C" void kn_free_many(int32_t n, kn_tait** taits, kn_plan** plans) {
-  std::vector<Pending> now;
-  {
-    std::lock_guard<std::mutex> lock(g_pending_mu);
-    for (int32_t i = 0; i < n; ++i) {
-      kn_plan* p = plans ? plans[i] : nullptr;
-      kn_tait* t = taits ? taits[i] : nullptr;
-      if (p) (p->owner ? g_pending : now).push_back({nullptr, p, p->owner});
-      if (t) (t->owner ? g_pending : now).push_back({t, nullptr, t->owner});
-    }
-    if (g_pending.size() > kMaxPending) {
-      now.insert(now.end(), g_pending.begin(), g_pending.end());
-      g_pending.clear();
-    }
+  for (int32_t i = 0; i < n; ++i) {
+    if (plans && plans[i]) kn_plan_free(plans[i]);
+    if (taits && taits[i]) kn_tait_free(taits[i]);
   }
-  for (const Pending& x : now) free_pending(x);
 }
 
 extern "C" kn_status kn_jones_many(int32_t n, const int32_t* q, const kn_tait* const* g,

@@ -166,36 +166,6 @@ def _split_gemm_cases():
     return [(d, dict(kw, split_min_log2=7)) for d, kw in cases]
 
 
-def test_plan_sets_handed_back_to_the_planning_threads():
-    """kn_free_many hands sets that kn_plan_many made back to the planning
-    threads, which free them at their next kn_plan_many: sets freed in turn,
-    sets freed on another thread while a kn_plan_many runs, and plans of
-    kn_plan_many freed one by one all leave every later plan intact (under
-    the sanitized build, any use after free or double free fails here)."""
-    import threading
-    knots = gen.config_knots("tiny", 0)[:12]
-    pds = [d.pd for d, _ in knots if d.n >= 2]
-    qs = [q for d, q in knots if d.n >= 2]
-    ncr = np.array([p.shape[0] for p in pds], np.int32)
-    flat = np.concatenate([p.reshape(-1) for p in pds])
-    ref = [kn.Plan(kn.Tait(p), q).image() for p, q in zip(pds, qs)]
-    sets = [kn.plan_set(ncr, flat, qs, n_threads=4) for _ in range(3)]
-    for ps in sets:
-        assert [ps.plan(i).image() for i in range(ps.n)] == ref
-    del sets[0]  # handed back; freed by the next call's workers
-    other = threading.Thread(target=lambda: sets.pop(0))
-    other.start()  # freed on another thread, maybe while the next call plans
-    ps = kn.plan_set(ncr, flat, qs, n_threads=4)
-    other.join()
-    assert [ps.plan(i).image() for i in range(ps.n)] == ref
-    taits, plans = kn.plan_many(pds, qs, n_threads=4)
-    assert [p.image() for p in plans] == ref
-    del taits, plans  # freed one by one, at once
-    del sets, ps
-    ps = kn.plan_set(ncr, flat, qs, n_threads=1)
-    assert [ps.plan(i).image() for i in range(ps.n)] == ref
-
-
 def test_default_split_segments():
     """By default a contracted index of nk entries is split into at most
     nk / 2^12 segments, rounded up (split_min_log2), and the workload's plans
