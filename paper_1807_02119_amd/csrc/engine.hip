@@ -619,10 +619,17 @@ __device__ inline Cx<T>* home_ptr(int32_t home, Cx<T>* arena, Cx<T>* lds) {
 // tables `tab` (A_b A_m A_k B_b B_k B_n, generated in LDS) and the states of
 // operands made before the task in ext[0..1].  Returns this thread's max |.|
 // and C's exponent.
+//
+// A step the whole workgroup computes (nthr = kBlock) first copies operands
+// that live in the global arena into the staging area (entries stage_off ..
+// stage_off + stage_elems - 1 of the LDS arena pointer), A first, each when it
+// fits: one burst of independent coalesced loads, after which the step's
+// gathers read LDS.  The products and their order are unchanged.
 template <class T>
 __device__ inline T serial_step(const StepDesc& d, const int32_t* tab, Cx<T>* arena, Cx<T>* lds,
                                 const States& st, const TensorState* ext, int32_t tid,
-                                int32_t nthr, int64_t& ec) {
+                                int32_t nthr, int32_t stage_off, int32_t stage_elems,
+                                int64_t& ec) {
   TabIx ix;
   ix.ab = tab;
   ix.am = ix.ab + d.nb;
@@ -641,8 +648,30 @@ __device__ inline T serial_step(const StepDesc& d, const int32_t* tab, Cx<T>* ar
   const T scale = (T)ldexp(1.0, -sh);
   const int64_t outs = (int64_t)d.nb * d.nm * d.nn;
   const int32_t L = lanes_per_output(outs, d.nk, nthr);
-  return step_outputs_homes<T>(d.home_a, d.home_b, d.home_c, arena, lds, ix, d.nm, d.nn, 0, d.nk,
-                               0, outs, scale, L, tid, nthr);
+  int32_t ha = d.home_a, hb = d.home_b;
+  if (nthr == kBlock && (ha >= 0 || hb >= 0)) {
+    // sizes of A (spins b, m, k) and B (spins b, k, n)
+    const int64_t na = (int64_t)d.nb * d.nm * d.nk, nbb = (int64_t)d.nb * d.nk * d.nn;
+    const bool sa = ha >= 0 && na <= stage_elems;
+    const int64_t used = sa ? na : 0;
+    const bool sb = hb >= 0 && used + nbb <= stage_elems;
+    if (sa || sb) {
+      LdsCx<T>* stg = (LdsCx<T>*)(lds + stage_off);
+      if (sa) {
+        const GlbCx<T>* g = (const GlbCx<T>*)(arena + ha);
+        for (int32_t i = tid; i < (int32_t)na; i += kBlock) put(stg, i, ldc(g + i));
+        ha = -1 - stage_off;
+      }
+      if (sb) {
+        const GlbCx<T>* g = (const GlbCx<T>*)(arena + hb);
+        for (int32_t i = tid; i < (int32_t)nbb; i += kBlock) put(stg + used, i, ldc(g + i));
+        hb = -1 - (stage_off + (int32_t)used);
+      }
+      __syncthreads();
+    }
+  }
+  return step_outputs_homes<T>(ha, hb, d.home_c, arena, lds, ix, d.nm, d.nn, 0, d.nk, 0, outs,
+                               scale, L, tid, nthr);
 }
 
 // Serial steps [first, first + count): descriptors are staged in LDS one
@@ -667,6 +696,9 @@ __device__ __attribute__((always_inline)) void serial_steps(const DevProg& p, in
   };
   constexpr int32_t kDescWords = (int32_t)(sizeof(StepDesc) / 4);
   const QDiv D(q);
+  // the staging area follows the tensor arena
+  const int32_t stage_off = p.h->lds_bytes / (int32_t)sizeof(Cx<T>);
+  const int32_t stage_elems = stage_bytes(p.h->lds_bytes) / (int32_t)sizeof(Cx<T>);
   int32_t s = first;
   const int32_t end = first + count;
   while (s < end) {
@@ -739,7 +771,7 @@ __device__ __attribute__((always_inline)) void serial_steps(const DevProg& p, in
         if (je - j > 1 && (int64_t)d.nb * d.nm * d.nn * d.nk < kWaveMacs) continue;
         int64_t ec;
         T lm = serial_step<T>(d, s_tab + s_tb[u], arena, lds, st, s_ext + 2 * u,
-                              (int32_t)threadIdx.x, kBlock, ec);
+                              (int32_t)threadIdx.x, kBlock, stage_off, stage_elems, ec);
         lm = block_max<T>(lm, s_red);
         if (threadIdx.x == 0) st.set(d.c, frexp_shift<T>(lm), ec);
       }
@@ -754,7 +786,8 @@ __device__ __attribute__((always_inline)) void serial_steps(const DevProg& p, in
           if ((int64_t)d.nb * d.nm * d.nn * d.nk >= kWaveMacs) continue;
           if ((r++ & (kBlock / 64 - 1)) != wv) continue;
           int64_t ec;
-          T lm = serial_step<T>(d, s_tab + s_tb[u], arena, lds, st, s_ext + 2 * u, lane, 64, ec);
+          T lm = serial_step<T>(d, s_tab + s_tb[u], arena, lds, st, s_ext + 2 * u, lane, 64, 0, 0,
+                                ec);
           lm = wave_max(lm);
           if (lane == 0) st.set(d.c, frexp_shift<T>(lm), ec);
         }
@@ -1690,13 +1723,13 @@ int device_cus() {
 template <class T>
 kn_status launch_engine(const ImgHeader& h, uint8_t* ws, hipStream_t st, const double* J,
                         kn_scalar* z, double* grad, int32_t grid_override, TraceRec* trace) {
-  const size_t dyn = (size_t)kLdsArena + (size_t)h.lds_bytes;
+  const size_t dyn = (size_t)kLdsArena + (size_t)h.lds_bytes + (size_t)stage_bytes(h.lds_bytes);
   static std::once_flag once;
   static bool attr_ok = true;
   std::call_once(once, [] {
     attr_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(engine<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024 - 1024) == hipSuccess;
+                                  kLdsLimit) == hipSuccess;
   });
   if (!attr_ok) return KN_E_DEVICE;
   // default: one workgroup per compute unit (measured faster than filling

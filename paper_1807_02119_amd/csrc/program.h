@@ -227,6 +227,18 @@ constexpr int32_t kLdsShift = kLdsDesc + kDescBuf * (int32_t)sizeof(StepDesc);
 constexpr int32_t kLdsExp = (kLdsShift + kStateCap * 4 + 7) / 8 * 8;
 constexpr int32_t kLdsExt = (kLdsExp + kStateCap * 8 + 15) / 16 * 16;  // operand states
 constexpr int32_t kLdsArena = kLdsExt + 2 * kDescBuf * (int32_t)sizeof(TensorState);
+// Dynamic LDS the engine may use, and the staging area after the tensor arena
+// (lds_bytes of it): global operands of a serial step that the whole
+// workgroup computes are copied there when they fit, so that the step's
+// gathers read LDS.  Up to kStageMax bytes, within kLdsLimit.
+constexpr int32_t kLdsLimit = 160 * 1024 - 1024;
+constexpr int32_t kStageMax = 64 * 1024;
+constexpr int32_t stage_bytes(int32_t lds_bytes) {
+  return kLdsLimit - kLdsArena - lds_bytes >= kStageMax
+             ? kStageMax
+             : (kLdsLimit - kLdsArena - lds_bytes > 0 ? (kLdsLimit - kLdsArena - lds_bytes) / 256 * 256
+                                                      : 0);
+}
 
 // control words at the start of the runtime state
 // (CTRL_ERROR: first error code, CTRL_ERR_*: the task, step and detail of it)
