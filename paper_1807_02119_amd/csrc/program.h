@@ -230,8 +230,9 @@ constexpr int32_t kLdsArena = kLdsExt + 2 * kDescBuf * (int32_t)sizeof(TensorSta
 // Dynamic LDS the engine may use, and the staging area after the tensor arena
 // (lds_bytes of it): global operands of a serial step that the whole
 // workgroup computes are copied there when they fit, so that the step's
-// gathers read LDS.  Up to kStageMax bytes, within kLdsLimit.
-constexpr int32_t kLdsLimit = 160 * 1024 - 1024;
+// gathers read LDS.  Up to kStageMax bytes, within kLdsLimit (the 160 KiB
+// of a CU less 2 KiB for the engine's static shared variables).
+constexpr int32_t kLdsLimit = 160 * 1024 - 2048;
 constexpr int32_t kStageMax = 64 * 1024;
 constexpr int32_t stage_bytes(int32_t lds_bytes) {
   return kLdsLimit - kLdsArena - lds_bytes >= kStageMax
