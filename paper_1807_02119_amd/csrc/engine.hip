@@ -839,10 +839,14 @@ __device__ inline GenIx step_ix(const DevProg& p, const StepDesc& s, int32_t q) 
 // knot's contraction, split over many tasks) is summed by all four
 // wavefronts, a quarter of the segment each; wavefront 0's thread 0 adds the
 // four partial sums in wavefront order.
+//
+// ph (traced launches, thread 0; else null; ph[3] holds the task's start):
+// from the start to the end of the tables and operand states, then the
+// products, then the publish.
 template <class T>
 __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* arena, int32_t* s_tab, int32_t tab_cap, const States& st,
-                          T* s_red) {
+                          T* s_red, int64_t* ph) {
   GenIx ix = step_ix(p, s, q);
   const int64_t outs = (int64_t)s.nb * s.nm * s.nn;
   const int32_t base = s.n_tiles / s.n_ks;
@@ -866,6 +870,11 @@ __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const
   int64_t ec;
   const T scale = step_scale<T>(st, s.a, s.b, ec);
   __syncthreads();
+  int64_t tk = 0;
+  if (ph) {
+    tk = wall_clock64();
+    ph[0] = tk - ph[3];
+  }
   Cx<T>* pc = s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c;
   const GlbCx<T>* pa = (const GlbCx<T>*)(arena + s.home_a);
   const GlbCx<T>* pb = (const GlbCx<T>*)(arena + s.home_b);
@@ -901,7 +910,13 @@ __device__ __attribute__((always_inline)) void tile_step(const DevProg& p, const
     lm = step_outputs<T>(pa, pb, GlbOut<T>((GlbCx<T>*)pc + o0), ix, s.nm, s.nn, k0, k1, o0, o1,
                          scale, L, (int32_t)threadIdx.x, kBlock);
   }
+  if (ph) {
+    const int64_t t = wall_clock64();
+    ph[1] = t - tk;
+    tk = t;
+  }
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
+  if (ph) ph[2] = wall_clock64() - tk;
 }
 
 // Matrix-core products for the GEMM blocks: D = A B + C on one 16 x 16
@@ -945,7 +960,7 @@ struct Mfma<float> {
 template <class T, int TM>
 __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const StepDesc& s, int32_t tile_id, int32_t q,
                           Cx<T>* __restrict__ arena, uint8_t* smem, int32_t smem_bytes,
-                          const States& st, T* s_red) {
+                          const States& st, T* s_red, int64_t* ph) {
   constexpr int32_t BM = 16 * TM, BK = kGemmChunk, P = BM + 1;
   constexpr int32_t WT = TM / 2;             // 16 x 16 tiles per wavefront side
   constexpr int32_t NS = WT == 1 ? 2 : 1;    // accumulator chains per part
@@ -997,6 +1012,11 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
   GlbCx<T>* C = (GlbCx<T>*)(s.n_ks > 1 ? arena + s.partial + (int64_t)ks * outs : arena + s.home_c);
   T lm = 0;
   __syncthreads();
+  int64_t tk = 0;
+  if (ph) {
+    tk = wall_clock64();
+    ph[0] = tk - ph[3];
+  }
 
   struct Ops {
     Cx<T> a[TM], b[TM];
@@ -1119,7 +1139,13 @@ __device__ __attribute__((always_inline)) void gemm_tile(const DevProg& p, const
         }
       }
   }
+  if (ph) {
+    const int64_t t = wall_clock64();
+    ph[1] = t - tk;
+    tk = t;
+  }
   if (s.n_ks == 1) tile_publish<T>(p, s.c, tile_id, lm, ec, s_red);
+  if (ph) ph[2] = wall_clock64() - tk;
 }
 
 // Outputs [part * kReduceChunk, ...) of a split step: C = sum over the n_ks
@@ -1600,19 +1626,24 @@ __global__ __launch_bounds__(kBlock, 2) void engine(const uint8_t* __restrict__ 
       }
     } else {
       const States st{p.ts, s_shift, s_exp, 0, 0};
-      if (tid == 0)
-        for (int i = 0; i < 4; ++i) s_ph[i] = 0;
+      // traced launches: thread 0 writes the phases straight into s_ph
+      int64_t* ph = (trace && tid == 0) ? s_ph : nullptr;
+      if (ph) {
+        for (int i = 0; i < 3; ++i) ph[i] = 0;
+        ph[3] = t_start;
+      }
       const StepDesc sd = p.steps[td.first];
       const int32_t q = p.knots[td.knot].q;
       const int32_t dyn = kLdsArena + p.h->lds_bytes;
       if (td.kind == TASK_REDUCE)
         reduce_step<T>(p, sd, td.count, arena, st, s_red);
       else if (sd.mode == STEP_GEMM)
-        gemm_tile<T, 2>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
+        gemm_tile<T, 2>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red, ph);
       else if (sd.mode == STEP_GEMM64)
-        gemm_tile<T, 4>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red);
+        gemm_tile<T, 4>(p, sd, td.count, q, arena, kn_dyn_smem, dyn, st, s_red, ph);
       else
-        tile_step<T>(p, sd, td.count, q, arena, s_tab, dyn / 4, st, s_red);
+        tile_step<T>(p, sd, td.count, q, arena, s_tab, dyn / 4, st, s_red, ph);
+      if (ph) ph[3] = 0;
     }
     // ---- publish; the last task of a group releases the knot's next group
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -214,7 +214,9 @@ struct TraceRec {
   int32_t task;
   int32_t wg;
   // serial tasks: time in setup, in staging descriptors and generating
-  // tables, in the step products, in reductions and barriers
+  // tables, in the step products, in reductions and barriers; tile tasks:
+  // from the start to the end of tables and operand states (descriptor loads
+  // included), the products, the publish of C's shift (0 for reduce tasks)
   int64_t ph[4];
 };
 

@@ -124,6 +124,13 @@ def report(t, launch_ms, n_wg=256):
         if m.any():
             out.append(f"| tile, {_MODES[md]} | {m.sum()} | {busy[m].sum() / 1e3:.1f} | "
                        f"{busy[m].mean():.1f} |")
+    m = kind == 1
+    if m.any():
+        ph = t["ph"][m]
+        rest = busy[m] - ph[:, :3].sum(axis=1)
+        out += ["", "Tile tasks, mean us: descriptors, tables and operand states "
+                f"{ph[:, 0].mean():.1f}; products {ph[:, 1].mean():.1f}; publish of C's shift "
+                f"{ph[:, 2].mean():.1f}; release and enqueue {rest.mean():.1f}"]
     nk = int(knot.max()) + 1
     kend = np.zeros(nk)
     np.maximum.at(kend, knot, te)
