@@ -421,3 +421,45 @@ def test_api_errors():
     with pytest.raises(kn.KnError) as e:
         kn.contract(p, workspace=small)
     assert e.value.code == -3
+
+
+def test_staged_serial_steps_same_bits():
+    """Serial steps that the whole workgroup computes copy their global
+    operands into the LDS staging area after the tensor arena when they fit.
+    The staging changes where a step reads its operands, not what it adds:
+    the same knots planned with a 48 KiB tensor arena (a 64 KiB staging area)
+    and with a 128 KiB one (a 1.75 KiB staging area, so that almost nothing
+    is staged) give the same bits, in complex128 and complex64, and the first
+    knots match the oracle."""
+    from tests import image_model as im
+
+    knots = gen.config_knots("q3_200_600", 5, count=32)
+    ncr = np.array([d.n for d, _ in knots], np.int32)
+    flat = np.concatenate([np.asarray(d.pd, np.int32).reshape(-1) for d, _ in knots])
+    oracle = {i: oracle_z(knots[i][0], 3) for i in range(4)}
+    for prec in (0, 1):
+        bits = []
+        for lds in (49152, 131072):
+            ps = kn.plan_set(ncr, flat, 3, strategy=2, precision=prec, lds_bytes=lds)
+            b = kn.Batch(ps)
+            if lds == 49152:
+                # whole-workgroup serial steps (one step in its level, or at
+                # least 2048 products) with a global operand that fits 4096
+                # entries: steps that take the staging path
+                img = im.Image(b.image())
+                st = img.steps
+                ser = st[st["mode"] == 0]
+                macs = ser["nb"].astype(np.int64) * ser["nm"] * ser["nn"] * ser["nk"]
+                na = ser["nb"].astype(np.int64) * ser["nm"] * ser["nk"]
+                glob_a = (ser["home_a"] >= 0) & (na <= 4096)
+                assert int((glob_a & (macs >= 2048)).sum()) > 0
+            _log(f"staging: precision {prec}, lds_bytes {lds}")
+            z = b.contract()
+            torch.cuda.synchronize()
+            bits.append(z.cpu().numpy().view(np.int64).copy())
+            out = kn.scalars_from_device(z)
+            tol = TOL if prec == 0 else TOL32
+            for i, (tg, mo, eo) in oracle.items():
+                m, e = out[i]
+                assert z_close(m, e, mo, eo, tol), (i, prec, lds)
+        assert np.array_equal(bits[0], bits[1]), prec
