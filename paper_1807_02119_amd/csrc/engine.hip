@@ -249,6 +249,14 @@ __device__ inline T block_max(T v, T* red) {
 
 // ------------------------------------------------------------------ setup
 
+// Lane u's value of a double held per lane (uniform result).
+__device__ inline double rl_double(double x, int u) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(b >> 32), u);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <class T>
 __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, const KnotDesc& kd, Cx<T>* arena, Cx<T>* lds,
                            const double* J, const States& st, int32_t slice) {
@@ -304,10 +312,17 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
       my_size = t.size;
       my_lds = t.lds_off;
     }
-    // the slot lists of the block, one merged-edge id per slot
+    // the slot lists of the block, one merged-edge id per slot, and the
+    // weights x_m of those slots: loaded once per block, so that the entry
+    // loop of a vertex reads no global memory (a load there would also wait
+    // for the entries stored before it)
     int32_t sl[kSlots];
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) sl[j] = have && j < my.n_slots ? p.vslot[my.slot_off + j] : 0;
+    Cx<double> wl[kSlots];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j)
+      wl[j] = have && j < my.n_slots ? xm[sl[j]] : Cx<double>{1.0, 0.0};
     const int nv = min(64, kd.n_vtx - v0);
     for (int u = 0; u < nv; ++u) {
       // uniform values of vertex v0 + u, read from its lane
@@ -321,9 +336,9 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
       const int32_t lds_off = from(my_lds);
       const int64_t off = (int64_t)(((uint64_t)(uint32_t)from((int32_t)(my_off >> 32)) << 32) |
                                     (uint32_t)from((int32_t)my_off));
-      int32_t slot[kSlots];
+      Cx<double> w[kSlots];
 #pragma unroll
-      for (int j = 0; j < kSlots; ++j) slot[j] = __builtin_amdgcn_readlane(sl[j], u);
+      for (int j = 0; j < kSlots; ++j) w[j] = {rl_double(wl[j].re, u), rl_double(wl[j].im, u)};
       const bool in_lds = lds_off >= 0;
       Cx<T>* out = in_lds ? lds + lds_off : arena + off;
       const GlbOut<T> gout((GlbCx<T>*)(in_lds ? arena : out));
@@ -352,7 +367,7 @@ __device__ __attribute__((always_inline)) void knot_setup(const DevProg& p, cons
           Cx<double> prod{1.0, 0.0};
 #pragma unroll
           for (int j = kSlots - 1; j >= 0; --j)
-            if (dig[j] == a) prod = cmul(prod, xm[slot[j]]);
+            if (dig[j] == a) prod = cmul(prod, w[j]);
           // slices: an edge to a fixed spin contributes x_m where this spin
           // takes the fixed value (digit j of the slice number, base q)
           for (int j = 0; j < n_pins; ++j) {
